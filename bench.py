@@ -1,0 +1,205 @@
+#!/usr/bin/env python3
+"""Benchmark of the H' build (and its batched and projector forms) on one GPU.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+
+Prints ONE JSON line.  A step is one pass of the hot path over its synthetic
+input, already resident in HBM: one lfbp_compute_Ht call (plain workloads), one
+lfbp_compute_Ht_batched call over the 16-set table (batched), or one forward
+plus one backward projection (projector).  K steps are timed with HIP events
+on the stream the kernels run on, bracketed by device synchronisation.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "H' build GB/s & % HBM peak (bit-exact); batched vs per-PSF speedup"
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, public spec
+FP32_PEAK_TFLOPS = 157.3       # MI355X dense FP32 (vector and matrix)
+PLAIN = {"tiny": ("TINY", "f32"), "microscope": ("MICROSCOPE", "f32"), "camera": ("CAMERA", "f32"),
+         "camera-f16": ("CAMERA", "f16")}
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="microscope",
+                    choices=sorted(PLAIN) + ["batched", "projector"])
+    ap.add_argument("--variant", default=None, choices=[None, "direct", "staged"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="approximate CPU time budget of the oracle baseline")
+    return ap.parse_args()
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for f in ("lfbp_gather.hip", "lfbp_internal.h"):
+        with open(os.path.join(ROOT, "paper_2003_09133_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(workload: str):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"gather_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def cores_used() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def time_steps(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record(stream)
+    for _ in range(steps):
+        fn()
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return start.elapsed_time(stop) / 1000.0, wall
+
+
+def cpu_oracle_rate(H, nthreads, budget_s):
+    """Oracle H' on the host: GB/s of (read + write) on whole passes over H."""
+    import numpy as np
+    import oracle
+    out = np.empty_like(H)
+    t0 = time.perf_counter()
+    oracle.Ht_rows(H, nthreads=nthreads, out=out)
+    one = time.perf_counter() - t0
+    reps = max(1, min(10, int(budget_s / max(one, 1e-3)) - 1))
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        oracle.Ht_rows(H, nthreads=nthreads, out=out)
+    dt = (time.perf_counter() - t0) / reps
+    return 2.0 * H.nbytes / dt / 1e9, reps + 1, dt
+
+
+def bench_plain(args, torch):
+    import numpy as np
+    import lfsynth
+    import paper_2003_09133_amd as lf
+
+    wname, dt = PLAIN[args.workload]
+    w = getattr(lfsynth, wname)
+    npdt = np.float32 if dt == "f32" else np.float16
+    H, zf = lfsynth.make_H(w, npdt)
+    dev = torch.device("cuda:0")
+    dH = torch.from_numpy(H).to(dev)
+    dHt = torch.empty_like(dH)
+    cfg = None
+    if args.variant:
+        cfg = {"variant": lf.GATHER_DIRECT if args.variant == "direct" else lf.GATHER_STAGED}
+    resolved = lf.default_config(w.shape, dH.dtype)
+    if cfg:
+        resolved.update(cfg)
+    elapsed, wall = time_steps(lambda: lf.compute_Ht_into(dH, dHt, config=cfg), args.steps, args.warmup, torch)
+    bytes_step = 2 * H.nbytes
+    sec_step = elapsed / args.steps
+    gbs = bytes_step / sec_step / 1e9
+    out = {
+        "metric": METRIC, "value": round(gbs, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(sec_step * 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": dt, "data": "synthetic",
+        "config": {"workload": f"{w.name} H{list(w.shape)} {dt}", "shape": list(w.shape),
+                   "bytes_per_step": bytes_step, "zero_fraction": round(zf, 4),
+                   "kernel": resolved, "wall_s": round(wall, 3)},
+        "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile(args.workload)},
+    }
+    if not args.no_cpu_baseline:
+        nth = cores_used()
+        rate, passes, per = cpu_oracle_rate(H, nth, args.cpu_seconds)
+        out["cpu_baseline"] = {"value": round(rate, 3), "unit": "GB/s", "cores": nth, "kind": "oracle",
+                               "sample": f"{passes} full passes of the oracle over the same H "
+                                         f"({per:.2f} s each)"}
+    return out
+
+
+def bench_batched(args, torch):
+    import numpy as np
+    import lfsynth
+    import paper_2003_09133_amd as lf
+
+    dev = torch.device("cuda:0")
+    Hs, Hts = [], []
+    for w in lfsynth.BATCHED_SETS:
+        H, _ = lfsynth.make_H(w)
+        Hs.append(torch.from_numpy(H).to(dev))
+        Hts.append(torch.empty_like(Hs[-1]))
+        del H
+    bytes_step = sum(2 * h.numel() * 4 for h in Hs)
+
+    def batched():
+        lf.compute_Ht_batched(Hs, Hts)
+
+    def sequential():
+        for h, o in zip(Hs, Hts):
+            lf.compute_Ht_into(h, o)
+
+    t_seq, _ = time_steps(sequential, args.steps, args.warmup, torch)
+    t_bat, wall = time_steps(batched, args.steps, args.warmup, torch)
+    sec = t_bat / args.steps
+    gbs = bytes_step / sec / 1e9
+    out = {
+        "metric": METRIC, "value": round(gbs, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batched 16 PSF sets f32 (Nnum 7-19, 9-25 lenslets, nz 9-41)",
+                   "bytes_per_step": bytes_step, "sets": [list(w.shape) for w in lfsynth.BATCHED_SETS],
+                   "sequential_ms_per_step": round(t_seq / args.steps * 1e3, 4),
+                   "batched_vs_sequential_speedup": round(t_seq / t_bat, 4), "wall_s": round(wall, 3)},
+        "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None},
+    }
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}), flush=True)
+        sys.exit(1)
+    if args.workload == "batched":
+        out = bench_batched(args, torch)
+    elif args.workload == "projector":
+        raise SystemExit("projector benchmark: not built yet")
+    else:
+        out = bench_plain(args, torch)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,188 @@
+/*
+ * lfbp.h -- light-field backprojection arrays on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of liblfbp.so.  Every data pointer is DEVICE memory owned by the
+ * caller (for example a torch allocation); the library never frees it.  Every
+ * call is ordered on `stream` (a hipStream_t passed as void*; NULL means the
+ * null stream), returns as soon as the work is queued and never synchronises.
+ * Arguments are validated on the host before any HIP call: on an error nothing
+ * is launched and the status says why.  No C++ exception and no abort crosses
+ * this interface.  Calls may be made from several threads at once.
+ *
+ * Arrays are row-major with the last axis fastest:
+ *   PSF array H and backprojection array H'   [ns][nt][nx][ny][nz]
+ *       s,t = pixel row/column inside a pattern cut-out (ns x nt pixels),
+ *       x,y = source position inside the elementary cell (nx x ny positions),
+ *       z   = depth plane.
+ *   Volume g  [nz][R][C]   and   image f  [R][C]   share the lateral grid.
+ * In H' the roles of the axes are swapped (Sec. 3, Fig. 6 discussion): axes 3-4
+ * hold the class (position inside a lenslet period) of an image pixel and axes
+ * 1-2 the offset of a voxel from that pixel, so H'[.,.,x',y',z] is the
+ * backprojection of a pixel of class (x',y') into depth plane z.
+ */
+#ifndef LFBP_H
+#define LFBP_H
+
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define LFBP_API __attribute__((visibility("default")))
+#else
+#define LFBP_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LFBP_OK = 0,
+    LFBP_EINVAL = -1,  /* null pointer, count <= 0, image size < 1, bad config field */
+    LFBP_ESHAPE = -2,  /* a dimension < 1, an even ns/nt/nx/ny, or a size beyond the limits below */
+    LFBP_EDTYPE = -3,  /* unknown element type, or one the call does not support */
+    LFBP_EALIAS = -4,  /* input and output ranges overlap (in-place is not supported) */
+    LFBP_EDEVICE = -5, /* a HIP call failed (launch error, no device) */
+    LFBP_ENOMEM = -6,  /* the library could not allocate its own device or host memory */
+    LFBP_EALIGN = -7   /* a pointer is not aligned to its element size */
+} lfbp_status;
+
+typedef enum { LFBP_F32 = 0, LFBP_F16 = 1 } lfbp_dtype;
+
+typedef struct {
+    int64_t ns, nt, nx, ny, nz;
+} lfbp_shape;
+
+/*
+ * lfbp_compute_Ht -- the backprojection array H' from the PSF array H by pure
+ * re-arrangement (Sec. 4, Eq. 3 with the index relations of Eqs. 4-9; Fig. 10).
+ *
+ *   H'[s'][t'][x'][y'][z] = H[ns-1-s'][nt-1-t'][(x'+s'-hs) mod nx][(y'+t'-ht) mod ny][z]
+ *
+ * with hs = (ns-1)/2, ht = (nt-1)/2 and mod the non-negative remainder.  This
+ * is the paper's relation with the periodic extension of H (Sec. 4, Figs. 8-9)
+ * applied to every entry, i.e. H' is exactly the adjoint of the forward model
+ * f = H g (Sec. 2.1, Eq. 1) in convolutional form; the map is its own inverse
+ * (Sec. 3: the transformation is reversible).
+ *
+ * H, Ht   device pointers to ns*nt*nx*ny*nz elements of `dtype`, aligned to the
+ *         element size, non-overlapping.  H is read, Ht is overwritten.
+ * shape   ns, nt, nx, ny odd (Sec. 4 requires odd nx, ny; the reflection of
+ *         Eqs. 8-9 needs odd ns, nt), all >= 1; nz >= 1.  ns*nt*nx < 2^31,
+ *         nx*ny*nz < 2^31, total bytes < 2^62.
+ * dtype   LFBP_F32 or LFBP_F16; values move as raw bits (NaN payloads, -0 and
+ *         denormals are preserved).
+ * Errors  EINVAL, ESHAPE, EDTYPE, EALIAS, EALIGN before launch; EDEVICE if the
+ *         launch fails.  Allocates nothing.
+ */
+LFBP_API lfbp_status lfbp_compute_Ht(const void* H, void* Ht, lfbp_shape shape, lfbp_dtype dtype, void* stream);
+
+/*
+ * Kernel choice for the re-arrangement.  variant:
+ *   LFBP_GATHER_AUTO   -- the library's tuned choice for the shape (default)
+ *   LFBP_GATHER_DIRECT -- each wavefront copies whole x-rows (ny*nz contiguous
+ *                         elements) straight from H to H' with the rotation
+ *                         applied to the read addresses
+ *   LFBP_GATHER_STAGED -- rows are rotated into an LDS tile, which is then
+ *                         written to H' with 16-byte stores
+ * Zero in any other field selects the tuned value.
+ */
+enum { LFBP_GATHER_AUTO = 0, LFBP_GATHER_DIRECT = 1, LFBP_GATHER_STAGED = 2 };
+
+typedef struct {
+    int32_t variant;      /* LFBP_GATHER_* */
+    int32_t block_threads;/* 64..512, multiple of 64 */
+    int32_t rows_in_flight;/* x-rows a wavefront loads before it stores: 1 or 2 */
+    int32_t tile_bytes;   /* STAGED: LDS tile per workgroup, bytes (<= 65536) */
+    int32_t nontemporal;  /* 1: streaming stores that bypass cache retention, 2: regular stores */
+    int32_t grid;         /* >0: persistent grid of this many workgroups; 0: one per work unit */
+} lfbp_gather_config;
+
+/* lfbp_compute_Ht with an explicit kernel choice (used by the autotuner and by
+ * tests that cover each variant).  cfg may be NULL (same as lfbp_compute_Ht).
+ * Errors as lfbp_compute_Ht, plus EINVAL for an out-of-range cfg field. */
+LFBP_API lfbp_status lfbp_compute_Ht_config(const void* H, void* Ht, lfbp_shape shape, lfbp_dtype dtype,
+                                   const lfbp_gather_config* cfg, void* stream);
+
+/* The configuration lfbp_compute_Ht uses for this shape and dtype (every field
+ * resolved, none zero).  Errors: EINVAL (cfg NULL), ESHAPE, EDTYPE. */
+LFBP_API lfbp_status lfbp_default_config(lfbp_shape shape, lfbp_dtype dtype, lfbp_gather_config* cfg);
+
+typedef struct {
+    const void* H;
+    void* Ht;
+    lfbp_shape shape;
+} lfbp_problem;
+
+/*
+ * lfbp_compute_Ht_batched -- H' for `count` independent PSF arrays (for
+ * example a depth sweep, or several lens/MLA configurations) in ONE persistent
+ * kernel launch (Sec. 3.1: PSF updates inside iterative reconstruction need
+ * H' recomputed often).  Each problem obeys the rules of lfbp_compute_Ht; all
+ * share `dtype`.  Results are bit-identical to count separate calls.
+ *
+ * problems  HOST array of `count` descriptors (copied; may be freed on return).
+ * Ownership The library keeps a plan per distinct problem table (device
+ *           descriptor table plus a captured hipGraph of the launch), reused
+ *           when the same table is submitted again; lfbp_release_plans()
+ *           frees all plans.  A plan is created on first use (hipMalloc,
+ *           stream capture), so the first call with a new table allocates.
+ * Errors    EINVAL (problems NULL, count <= 0, or any pointer NULL), ESHAPE,
+ *           EDTYPE, EALIGN, EALIAS (any input overlapping any output) -- all
+ *           checked before anything is launched; ENOMEM, EDEVICE.
+ */
+LFBP_API lfbp_status lfbp_compute_Ht_batched(const lfbp_problem* problems, int32_t count, lfbp_dtype dtype,
+                                    void* stream);
+
+/* Same as lfbp_compute_Ht_batched with an explicit kernel choice for every
+ * problem (variant must be DIRECT or STAGED or AUTO) and graph use: use_graph
+ * = 1 replays a captured graph, 0 launches the kernel directly. */
+LFBP_API lfbp_status lfbp_compute_Ht_batched_config(const lfbp_problem* problems, int32_t count, lfbp_dtype dtype,
+                                           const lfbp_gather_config* cfg, int32_t use_graph, void* stream);
+
+/*
+ * lfbp_forward -- forward projection f = H g (Sec. 2.1, Eq. 1): every voxel
+ * adds its pattern, scaled by its value and centred on it, to the image;
+ * voxel (z,P,Q) uses the pattern H[.,.,P mod nx, Q mod ny, z] and reaches
+ * pixel (P+s-hs, Q+t-ht) with weight H[s][t][P mod nx][Q mod ny][z]:
+ *
+ *   f[p][q] = sum_z sum_{s,t} H[s][t][P mod nx][Q mod ny][z] g[z][P][Q],
+ *             P = p-s+hs, Q = q-t+ht, terms with P, Q outside the image dropped.
+ *
+ * H  float32 [ns][nt][nx][ny][nz];  g float32 [nz][R][C];  f float32 [R][C],
+ * overwritten.  Float32 arithmetic with float32 accumulation.
+ * Errors EINVAL (null, R or C < 1), ESHAPE, EALIAS (f overlapping H or g),
+ * EALIGN, EDEVICE.  Allocates nothing.
+ */
+LFBP_API lfbp_status lfbp_forward(const float* H, lfbp_shape shape, const float* g, int64_t R, int64_t C, float* f,
+                         void* stream);
+
+/*
+ * lfbp_backward -- backprojection of an image into the volume with H'
+ * (the bracketed term of Eq. 2, Sec. 3): every pixel adds its slice of H',
+ * scaled by its value, to the voxels it receives light from:
+ *
+ *   g[z][P][Q] = sum_{p,q} f[p][q] Ht[P-p+hs][Q-q+ht][p mod nx][q mod ny][z],
+ *
+ * terms with the H' index outside 0..ns-1 / 0..nt-1 dropped.  With Ht from
+ * lfbp_compute_Ht(H) this is exactly the adjoint of lfbp_forward(H).
+ * Ht float32 [ns][nt][nx][ny][nz]; f float32 [R][C]; g float32 [nz][R][C],
+ * overwritten.  Errors as lfbp_forward.  Allocates nothing.
+ */
+LFBP_API lfbp_status lfbp_backward(const float* Ht, lfbp_shape shape, const float* f, int64_t R, int64_t C, float* g,
+                          void* stream);
+
+/* Static text for a status code (never NULL). */
+LFBP_API const char* lfbp_status_string(lfbp_status s);
+
+/* Frees every batched plan (device descriptor tables and graph executables).
+ * The caller must make sure no launched batch is still running. */
+LFBP_API void lfbp_release_plans(void);
+
+/* Library version string, e.g. "lfbp 0.1 gfx950". */
+LFBP_API const char* lfbp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LFBP_H */

@@ -1,0 +1,185 @@
+"""Light-field backprojection arrays on AMD Instinct MI355X (gfx950).
+
+Python binding of liblfbp.so.  Every function here only marshals arguments
+(device pointers, shapes, the current HIP stream) into the C ABI of
+include/lfbp.h; all computation runs in the library's HIP kernels.  PyTorch
+provides device memory and streams.
+
+    compute_Ht(H)              H' from H by pure re-arrangement (Sec. 4)
+    compute_Ht_batched([H..])  many PSF arrays in one persistent launch
+    forward(H, g)              f = H g (Sec. 2.1, Eq. 1)
+    backward(Ht, f)            g = H' f (Eq. 2, backprojection)
+    LFProject                  torch.autograd.Function: forward by H, gradient by H'
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _abi
+from ._abi import (F16, F32, GATHER_AUTO, GATHER_DIRECT, GATHER_STAGED, GatherConfig, LfbpError,
+                   Problem, Shape)
+
+__all__ = ["compute_Ht", "compute_Ht_into", "compute_Ht_batched", "forward", "backward", "LFProject",
+           "project", "default_config", "GatherConfig", "LfbpError", "release_plans", "version",
+           "GATHER_AUTO", "GATHER_DIRECT", "GATHER_STAGED"]
+
+_DTYPES = {torch.float32: F32, torch.float16: F16}
+
+
+def _stream(stream=None) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def _check_psf(H: torch.Tensor, name: str = "H"):
+    if not isinstance(H, torch.Tensor) or H.dim() != 5:
+        raise ValueError(f"{name} must be a 5-D tensor [ns, nt, nx, ny, nz]")
+    if not H.is_cuda:
+        raise ValueError(f"{name} must live on a GPU")
+    if not H.is_contiguous():
+        raise ValueError(f"{name} must be contiguous (row-major, depth fastest)")
+    if H.dtype not in _DTYPES:
+        raise TypeError(f"{name} must be float32 or float16, got {H.dtype}")
+
+
+def _config(cfg) -> GatherConfig | None:
+    if cfg is None:
+        return None
+    if isinstance(cfg, GatherConfig):
+        return cfg
+    c = GatherConfig()
+    for k, v in dict(cfg).items():
+        setattr(c, k, int(v))
+    return c
+
+
+def compute_Ht_into(H: torch.Tensor, Ht: torch.Tensor, config=None, stream=None) -> torch.Tensor:
+    """Write H' of H into the preallocated tensor Ht (same shape and dtype)."""
+    _check_psf(H)
+    _check_psf(Ht, "Ht")
+    if Ht.shape != H.shape or Ht.dtype != H.dtype:
+        raise ValueError("Ht must have the shape and dtype of H")
+    cfg = _config(config)
+    L = _abi.lib()
+    if cfg is None:
+        st = L.lfbp_compute_Ht(H.data_ptr(), Ht.data_ptr(), Shape.of(H.shape), _DTYPES[H.dtype],
+                               _stream(stream))
+    else:
+        st = L.lfbp_compute_Ht_config(H.data_ptr(), Ht.data_ptr(), Shape.of(H.shape), _DTYPES[H.dtype],
+                                      ctypes.byref(cfg), _stream(stream))
+    _abi.check(st, "lfbp_compute_Ht")
+    return Ht
+
+
+def compute_Ht(H: torch.Tensor, config=None, stream=None) -> torch.Tensor:
+    """H' of H (Sec. 4): a new tensor of the same shape and dtype."""
+    _check_psf(H)
+    return compute_Ht_into(H, torch.empty_like(H), config, stream)
+
+
+def compute_Ht_batched(Hs, outs=None, config=None, use_graph: bool = True, stream=None):
+    """H' of every tensor in Hs with one persistent kernel launch (replayed
+    from a captured hipGraph when use_graph).  All tensors share one dtype."""
+    Hs = list(Hs)
+    if not Hs:
+        raise ValueError("empty batch")
+    for i, H in enumerate(Hs):
+        _check_psf(H, f"Hs[{i}]")
+    if len({H.dtype for H in Hs}) != 1:
+        raise TypeError("all PSF arrays of a batch must share one dtype")
+    outs = [torch.empty_like(H) for H in Hs] if outs is None else list(outs)
+    if len(outs) != len(Hs):
+        raise ValueError("outs must match Hs")
+    for i, (H, o) in enumerate(zip(Hs, outs)):
+        _check_psf(o, f"outs[{i}]")
+        if o.shape != H.shape or o.dtype != H.dtype:
+            raise ValueError(f"outs[{i}] must have the shape and dtype of Hs[{i}]")
+    probs = (Problem * len(Hs))(*[Problem(H.data_ptr(), o.data_ptr(), Shape.of(H.shape))
+                                  for H, o in zip(Hs, outs)])
+    cfg = _config(config)
+    L = _abi.lib()
+    if cfg is None and use_graph:
+        st = L.lfbp_compute_Ht_batched(probs, len(Hs), _DTYPES[Hs[0].dtype], _stream(stream))
+    else:
+        st = L.lfbp_compute_Ht_batched_config(probs, len(Hs), _DTYPES[Hs[0].dtype],
+                                              ctypes.byref(cfg) if cfg is not None else None,
+                                              1 if use_graph else 0, _stream(stream))
+    _abi.check(st, "lfbp_compute_Ht_batched")
+    return outs
+
+
+def default_config(shape, dtype=torch.float32) -> dict:
+    """The kernel configuration compute_Ht uses for this shape and dtype."""
+    c = GatherConfig()
+    _abi.check(_abi.lib().lfbp_default_config(Shape.of(shape), _DTYPES[dtype], ctypes.byref(c)),
+               "lfbp_default_config")
+    return c.as_dict()
+
+
+def _check_f32(t: torch.Tensor, name: str, dim: int):
+    if not isinstance(t, torch.Tensor) or t.dim() != dim:
+        raise ValueError(f"{name} must be a {dim}-D tensor")
+    if not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float32 GPU tensor")
+
+
+def forward(H: torch.Tensor, g: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Forward projection f = H g: g [nz, R, C] -> f [R, C] (float32)."""
+    _check_f32(H, "H", 5)
+    _check_f32(g, "g", 3)
+    nz, R, C = g.shape
+    if nz != H.shape[4]:
+        raise ValueError("g must have nz depth planes")
+    f = torch.empty((R, C), dtype=torch.float32, device=g.device) if out is None else out
+    _check_f32(f, "out", 2)
+    _abi.check(_abi.lib().lfbp_forward(H.data_ptr(), Shape.of(H.shape), g.data_ptr(), R, C, f.data_ptr(),
+                                       _stream(stream)), "lfbp_forward")
+    return f
+
+
+def backward(Ht: torch.Tensor, f: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Backprojection g = H' f: f [R, C] -> g [nz, R, C] (float32)."""
+    _check_f32(Ht, "Ht", 5)
+    _check_f32(f, "f", 2)
+    R, C = f.shape
+    g = torch.empty((Ht.shape[4], R, C), dtype=torch.float32, device=f.device) if out is None else out
+    _check_f32(g, "out", 3)
+    _abi.check(_abi.lib().lfbp_backward(Ht.data_ptr(), Shape.of(Ht.shape), f.data_ptr(), R, C, g.data_ptr(),
+                                        _stream(stream)), "lfbp_backward")
+    return g
+
+
+class LFProject(torch.autograd.Function):
+    """f = H g with the gradient g_grad = H' f_grad.
+
+    The projector is linear, so its vector-Jacobian product is the adjoint,
+    which is exactly the backprojection with H' (Sec. 3).  Nothing of the
+    forward pass is saved except the H' handle; H and H' get no gradient."""
+
+    @staticmethod
+    def forward(ctx, g, H, Ht):
+        ctx.save_for_backward(Ht)
+        return forward(H, g.contiguous())
+
+    @staticmethod
+    def backward(ctx, grad_f):
+        (Ht,) = ctx.saved_tensors
+        return backward(Ht, grad_f.contiguous()), None, None
+
+
+def project(g: torch.Tensor, H: torch.Tensor, Ht: torch.Tensor | None = None) -> torch.Tensor:
+    """Differentiable f = H g; H' is built on the GPU when not given."""
+    if Ht is None:
+        Ht = compute_Ht(H)
+    return LFProject.apply(g, H, Ht)
+
+
+def release_plans():
+    _abi.lib().lfbp_release_plans()
+
+
+def version() -> str:
+    return _abi.lib().lfbp_version().decode()

@@ -1,0 +1,86 @@
+// Internal definitions shared by the HIP kernels and the host runtime of
+// liblfbp.so.  Not part of the public ABI.
+#pragma once
+
+#include <stdint.h>
+
+#include "lfbp.h"
+
+#if defined(__HIPCC__)
+#define LFBP_HD __host__ __device__
+#else
+#define LFBP_HD
+#endif
+
+namespace lfbp {
+
+// Unsigned 32-bit division by a run-time invariant divisor with one multiply-
+// high, one subtract and two shifts (Granlund & Montgomery, "Division by
+// invariant integers using multiplication", PLDI 1994, Fig. 4.1): exact for
+// every 32-bit dividend n and every divisor d >= 1.
+struct FastDiv {
+    uint32_t d, m, s1, s2;
+};
+
+inline FastDiv make_fastdiv(uint32_t d)
+{
+    uint32_t l = 0;
+    while (l < 32 && (uint64_t(1) << l) < d) ++l;  // l = ceil(log2 d)
+    FastDiv f;
+    f.d = d;
+    const uint64_t two32 = uint64_t(1) << 32;
+    // m = floor(2^32 * (2^l - d) / d) + 1  (fits in 32 bits)
+    f.m = uint32_t((two32 * ((uint64_t(1) << l) - d)) / d + 1);
+    f.s1 = l < 1 ? l : 1;
+    f.s2 = l > 1 ? l - 1 : 0;
+    return f;
+}
+
+LFBP_HD inline uint32_t mulhi32(uint32_t a, uint32_t b)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __umulhi(a, b);
+#else
+    return uint32_t((uint64_t(a) * b) >> 32);
+#endif
+}
+
+LFBP_HD inline uint32_t fdiv(uint32_t n, const FastDiv& f)
+{
+    const uint32_t t = mulhi32(f.m, n);
+    return (t + ((n - t) >> f.s1)) >> f.s2;
+}
+
+// Everything a gather kernel needs about one H -> H' problem.
+// Output x-row R (R = (s'*nt + t')*nx + x', W elements) is input x-row
+//   ((ns-1-s')*nt + (nt-1-t'))*nx + ((x' + a(s')) mod nx)
+// rotated left by rot(t') = b(t')*nz elements, with
+//   a(s') = (s' - hs) mod nx,  b(t') = (t' - ht) mod ny.
+struct GatherDesc {
+    const void* H;
+    void* Ht;
+    uint32_t ns, nt, nx, ny, nz;
+    uint32_t W;          // ny*nz, elements per x-row
+    uint32_t NB;         // ns*nt, number of blocks of nx x-rows
+    uint32_t nrows;      // NB*nx
+    uint32_t a_off;      // a(s') = (s' + a_off) mod nx
+    uint32_t b_off;      // b(t') = (t' + b_off) mod ny
+    FastDiv fnx, fny, fnt;
+    // work decomposition
+    uint32_t rows_per_unit;  // output x-rows per work unit
+    uint32_t nunits;         // ceil(nrows / rows_per_unit)
+    uint32_t phase_out;      // (address of Ht / element size) mod (16 / element size)
+    uint32_t pad;
+};
+
+// Kernel selection resolved by the host runtime.
+struct LaunchPlan {
+    int variant;        // LFBP_GATHER_DIRECT or LFBP_GATHER_STAGED
+    int threads;        // workgroup size
+    int rows_in_flight; // rows per wavefront step (DIRECT) or per wave load batch (STAGED)
+    int tile_bytes;     // STAGED LDS bytes
+    int nontemporal;    // 1 or 2
+    int grid;           // workgroups launched
+};
+
+}  // namespace lfbp

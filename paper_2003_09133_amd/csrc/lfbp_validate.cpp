@@ -1,0 +1,99 @@
+// Host-only argument checks of the C ABI (no HIP calls, no HIP headers).
+#include "lfbp_validate.h"
+
+#include <initializer_list>
+
+namespace lfbp {
+
+namespace {
+constexpr uint64_t LIM31 = uint64_t(1) << 31;
+constexpr uint64_t LIM62 = uint64_t(1) << 62;
+
+// a*b, saturating at 2^63 (enough to test against the limits used here).
+uint64_t mul_sat(uint64_t a, uint64_t b)
+{
+    const uint64_t cap = uint64_t(1) << 63;
+    if (a != 0 && b > cap / a) return cap;
+    return a * b;
+}
+}  // namespace
+
+int dtype_size(lfbp_dtype dt)
+{
+    switch (dt) {
+        case LFBP_F32: return 4;
+        case LFBP_F16: return 2;
+        default: return 0;
+    }
+}
+
+uint64_t shape_elems(const lfbp_shape& s)
+{
+    uint64_t e = 1;
+    for (int64_t v : {s.ns, s.nt, s.nx, s.ny, s.nz}) e = mul_sat(e, v > 0 ? uint64_t(v) : 0);
+    return e;
+}
+
+lfbp_status check_shape(const lfbp_shape& s, int esize)
+{
+    if (s.ns < 1 || s.nt < 1 || s.nx < 1 || s.ny < 1 || s.nz < 1) return LFBP_ESHAPE;
+    // Odd cell sides (Sec. 4); odd patch sides so that the reflection of
+    // Eqs. 8-9 maps 1..ns onto itself and the patch has a centre pixel.
+    if (s.ns % 2 == 0 || s.nt % 2 == 0 || s.nx % 2 == 0 || s.ny % 2 == 0) return LFBP_ESHAPE;
+    const uint64_t rows = mul_sat(mul_sat(uint64_t(s.ns), uint64_t(s.nt)), uint64_t(s.nx));
+    const uint64_t block = mul_sat(mul_sat(uint64_t(s.nx), uint64_t(s.ny)), uint64_t(s.nz));
+    if (rows >= LIM31 || block >= LIM31) return LFBP_ESHAPE;
+    if (mul_sat(shape_elems(s), uint64_t(esize > 0 ? esize : 1)) >= LIM62) return LFBP_ESHAPE;
+    return LFBP_OK;
+}
+
+bool ranges_overlap(const void* a, uint64_t na, const void* b, uint64_t nb)
+{
+    const uint64_t pa = reinterpret_cast<uint64_t>(a), pb = reinterpret_cast<uint64_t>(b);
+    return pa < pb + nb && pb < pa + na;
+}
+
+lfbp_status check_gather(const void* H, const void* Ht, const lfbp_shape& s, lfbp_dtype dt)
+{
+    if (!H || !Ht) return LFBP_EINVAL;
+    const int es = dtype_size(dt);
+    if (es == 0) return LFBP_EDTYPE;
+    const lfbp_status st = check_shape(s, es);
+    if (st != LFBP_OK) return st;
+    if (reinterpret_cast<uint64_t>(H) % es || reinterpret_cast<uint64_t>(Ht) % es) return LFBP_EALIGN;
+    const uint64_t bytes = shape_elems(s) * uint64_t(es);
+    if (ranges_overlap(H, bytes, Ht, bytes)) return LFBP_EALIAS;
+    return LFBP_OK;
+}
+
+lfbp_status check_config(const lfbp_gather_config* c)
+{
+    if (!c) return LFBP_OK;
+    if (c->variant < 0 || c->variant > LFBP_GATHER_STAGED) return LFBP_EINVAL;
+    if (c->block_threads != 0 && (c->block_threads < 64 || c->block_threads > 512 || c->block_threads % 64))
+        return LFBP_EINVAL;
+    if (c->rows_in_flight != 0 && c->rows_in_flight != 1 && c->rows_in_flight != 2) return LFBP_EINVAL;
+    if (c->tile_bytes < 0 || c->tile_bytes > 65536) return LFBP_EINVAL;
+    if (c->nontemporal < 0 || c->nontemporal > 2) return LFBP_EINVAL;
+    if (c->grid < 0) return LFBP_EINVAL;
+    return LFBP_OK;
+}
+
+lfbp_status check_project(const float* psf, const lfbp_shape& s, const float* in2, int64_t in2_elems, int64_t R,
+                          int64_t C, const float* out, int64_t out_elems)
+{
+    if (!psf || !in2 || !out) return LFBP_EINVAL;
+    if (R < 1 || C < 1) return LFBP_EINVAL;
+    const lfbp_status st = check_shape(s, 4);
+    if (st != LFBP_OK) return st;
+    if (mul_sat(mul_sat(uint64_t(R), uint64_t(C)), uint64_t(s.nz)) >= LIM31) return LFBP_ESHAPE;
+    const uintptr_t a = reinterpret_cast<uintptr_t>(psf), b = reinterpret_cast<uintptr_t>(in2),
+                    c = reinterpret_cast<uintptr_t>(out);
+    if (a % 4 || b % 4 || c % 4) return LFBP_EALIGN;
+    const uint64_t ob = uint64_t(out_elems) * 4;
+    if (ranges_overlap(out, ob, psf, shape_elems(s) * 4) || ranges_overlap(out, ob, in2, uint64_t(in2_elems) * 4))
+        return LFBP_EALIAS;
+    return LFBP_OK;
+}
+
+}  // namespace lfbp

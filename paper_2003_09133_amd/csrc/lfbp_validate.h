@@ -1,0 +1,33 @@
+// Host-only argument checks of the C ABI.  No HIP header is included here:
+// every check runs before the first HIP call of an entry point.
+#pragma once
+
+#include <stdint.h>
+
+#include "lfbp.h"
+
+namespace lfbp {
+
+// Element size of a dtype, 0 if unknown.
+int dtype_size(lfbp_dtype dt);
+
+// Shape rules of the re-arrangement (odd ns, nt, nx, ny; all >= 1; size limits).
+lfbp_status check_shape(const lfbp_shape& s, int esize);
+
+// Full check of one lfbp_compute_Ht call.
+lfbp_status check_gather(const void* H, const void* Ht, const lfbp_shape& s, lfbp_dtype dt);
+
+// Configuration fields (0 = tuned default is always accepted).
+lfbp_status check_config(const lfbp_gather_config* cfg);
+
+// Full check of one projector call: in1 (H or Ht), in2 (g or f) read, out written.
+// in2_elems and out_elems are the element counts of the second input and the output.
+lfbp_status check_project(const float* psf, const lfbp_shape& s, const float* in2, int64_t in2_elems, int64_t R,
+                          int64_t C, const float* out, int64_t out_elems);
+
+// True when [a, a+na) and [b, b+nb) (bytes) overlap.
+bool ranges_overlap(const void* a, uint64_t na, const void* b, uint64_t nb);
+
+uint64_t shape_elems(const lfbp_shape& s);
+
+}  // namespace lfbp

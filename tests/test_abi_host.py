@@ -1,0 +1,158 @@
+"""The C ABI on a host without a GPU: the library loads, exports every symbol
+the header declares, and rejects bad arguments before any HIP call."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2003_09133_amd import _abi
+from paper_2003_09133_amd._abi import GatherConfig, Problem, Shape
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lfbp.h")
+GOOD = Shape(15, 15, 3, 3, 3)
+P1, P2 = 0x10000, 0x20000000          # fake device addresses, never dereferenced
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^LFBP_API\s+[\w\s\*]+?\b(lfbp_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_four_calls():
+    names = declared_functions()
+    for n in ("lfbp_compute_Ht", "lfbp_compute_Ht_batched", "lfbp_forward", "lfbp_backward"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = _abi.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", _abi.LIB_PATH], capture_output=True, text=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    assert set(declared_functions()) <= exported
+    # only the ABI is exported
+    assert {s for s in exported if s.startswith("lfbp")} == set(declared_functions())
+
+
+def test_status_strings():
+    L = _abi.lib()
+    for code in range(0, -8, -1):
+        assert L.lfbp_status_string(code)
+    assert b"unknown" in L.lfbp_status_string(-99)
+    assert L.lfbp_version().startswith(b"lfbp")
+
+
+def call(H=P1, Ht=P2, shape=GOOD, dt=_abi.F32):
+    return _abi.lib().lfbp_compute_Ht(H, Ht, shape, dt, None)
+
+
+@pytest.mark.parametrize("shape", [Shape(0, 15, 3, 3, 3), Shape(15, 15, 3, 3, 0), Shape(14, 15, 3, 3, 3),
+                                   Shape(15, 16, 3, 3, 3), Shape(15, 15, 4, 3, 3), Shape(15, 15, 3, 2, 3),
+                                   Shape(-1, 15, 3, 3, 3), Shape(65537, 65537, 1, 1, 1),
+                                   Shape(1, 1, 3, 3, 1 << 28), Shape(1 << 40, 1, 1, 1, 1)])
+def test_bad_shapes(shape):
+    assert call(shape=shape) == _abi.ESHAPE
+
+
+def test_null_dtype_alias_align():
+    assert call(H=None) == _abi.EINVAL
+    assert call(Ht=None) == _abi.EINVAL
+    assert call(dt=7) == _abi.EDTYPE
+    assert call(Ht=P1) == _abi.EALIAS
+    nbytes = 15 * 15 * 3 * 3 * 3 * 4
+    assert call(Ht=P1 + nbytes - 4) == _abi.EALIAS
+    assert call(H=P1 + 2) == _abi.EALIGN
+    assert call(Ht=P2 + 1, dt=_abi.F16) == _abi.EALIGN
+
+
+def test_bad_config_fields():
+    L = _abi.lib()
+    for field, val in [("variant", 3), ("block_threads", 96), ("block_threads", 1024),
+                       ("rows_in_flight", 3), ("tile_bytes", 70000), ("nontemporal", 3), ("grid", -1)]:
+        c = GatherConfig()
+        setattr(c, field, val)
+        assert L.lfbp_compute_Ht_config(P1, P2, GOOD, _abi.F32, ctypes.byref(c), None) == _abi.EINVAL, field
+
+
+def test_default_config_resolves_every_field():
+    L = _abi.lib()
+    for shape, dt in [(GOOD, _abi.F32), (Shape(165, 165, 15, 15, 21), _abi.F32),
+                      (Shape(345, 345, 15, 15, 51), _abi.F16), (Shape(181, 181, 95, 55, 11), _abi.F32),
+                      (Shape(3, 3, 1, 1, 40000), _abi.F32)]:
+        c = GatherConfig()
+        assert L.lfbp_default_config(shape, dt, ctypes.byref(c)) == _abi.OK
+        d = c.as_dict()
+        assert all(v > 0 for v in d.values()), d
+        assert d["variant"] in (_abi.GATHER_DIRECT, _abi.GATHER_STAGED)
+    c = GatherConfig()
+    assert L.lfbp_default_config(Shape(4, 3, 3, 3, 3), _abi.F32, ctypes.byref(c)) == _abi.ESHAPE
+    assert L.lfbp_default_config(GOOD, 9, ctypes.byref(c)) == _abi.EDTYPE
+    assert L.lfbp_default_config(GOOD, _abi.F32, None) == _abi.EINVAL
+
+
+def batch(*probs):
+    return (Problem * len(probs))(*probs)
+
+
+def test_batched_validation_before_launch():
+    L = _abi.lib()
+    ok = Problem(P1, P2, GOOD)
+    assert L.lfbp_compute_Ht_batched(None, 1, _abi.F32, None) == _abi.EINVAL
+    assert L.lfbp_compute_Ht_batched(batch(ok), 0, _abi.F32, None) == _abi.EINVAL
+    assert L.lfbp_compute_Ht_batched(batch(ok), 1, 5, None) == _abi.EDTYPE
+    bad_shape = Problem(P1 + 0x100000, P2 + 0x100000, Shape(15, 15, 2, 3, 3))
+    assert L.lfbp_compute_Ht_batched(batch(ok, bad_shape), 2, _abi.F32, None) == _abi.ESHAPE
+    null = Problem(None, P2 + 0x100000, GOOD)
+    assert L.lfbp_compute_Ht_batched(batch(ok, null), 2, _abi.F32, None) == _abi.EINVAL
+    # output of one problem overlapping the input of another
+    cross = Problem(P2 + 0x100000, P1 + 64, GOOD)
+    assert L.lfbp_compute_Ht_batched(batch(ok, cross), 2, _abi.F32, None) == _abi.EALIAS
+    # two outputs overlapping
+    twin = Problem(P1 + 0x100000, P2 + 8, GOOD)
+    assert L.lfbp_compute_Ht_batched(batch(ok, twin), 2, _abi.F32, None) == _abi.EALIAS
+    assert L.lfbp_compute_Ht_batched_config(batch(ok), 1, _abi.F32, None, 2, None) == _abi.EINVAL
+
+
+def test_projector_validation_before_launch():
+    L = _abi.lib()
+    assert L.lfbp_forward(None, GOOD, P2, 30, 30, P2 + 0x100000, None) == _abi.EINVAL
+    assert L.lfbp_forward(P1, GOOD, P2, 0, 30, P2 + 0x100000, None) == _abi.EINVAL
+    assert L.lfbp_forward(P1, Shape(15, 14, 3, 3, 3), P2, 30, 30, P2 + 0x100000, None) == _abi.ESHAPE
+    assert L.lfbp_forward(P1, GOOD, P2, 30, 30, P2 + 8, None) == _abi.EALIAS
+    assert L.lfbp_forward(P1, GOOD, P2, 30, 30, P2 + 0x100002, None) == _abi.EALIGN
+    assert L.lfbp_backward(P1, GOOD, P2, 30, 30, P1 + 16, None) == _abi.EALIAS
+    assert L.lfbp_backward(P1, GOOD, P2, 1 << 20, 1 << 20, P2 + 0x100000, None) == _abi.ESHAPE
+
+
+def test_fastdiv_exact(tmp_path):
+    """The division-by-invariant-integer helper of the kernels, compiled for
+    the host: exact against '/' for edge and random dividends."""
+    src = tmp_path / "fd.cpp"
+    src.write_text(r'''
+#include "lfbp_internal.h"
+#include <cstdio>
+#include <random>
+int main() {
+  std::mt19937_64 rng(1);
+  const uint32_t ds[] = {1,2,3,5,7,11,15,19,21,51,55,95,165,345,765,4725,11475,65535,65536,1u<<20,(1u<<31)-1,1u<<31,0xffffffffu};
+  for (uint32_t d : ds) {
+    lfbp::FastDiv f = lfbp::make_fastdiv(d);
+    for (int i = 0; i < 200000; ++i) {
+      uint32_t n = (i < 1000) ? uint32_t(i) : (i < 2000 ? 0xffffffffu - uint32_t(i - 1000) : uint32_t(rng()));
+      if (lfbp::fdiv(n, f) != n / d) { std::printf("FAIL %u %u\n", n, d); return 1; }
+      uint32_t m = d * (n / d);  // multiples and their neighbours
+      if (lfbp::fdiv(m, f) != m / d || (m && lfbp::fdiv(m - 1, f) != (m - 1) / d)) { std::printf("FAIL m %u %u\n", m, d); return 1; }
+    }
+  }
+  std::printf("ok\n");
+  return 0;
+}
+''')
+    exe = tmp_path / "fd"
+    subprocess.run(["g++", "-O2", "-std=c++17", f"-I{ROOT}/include", f"-I{ROOT}/paper_2003_09133_amd/csrc",
+                    str(src), "-o", str(exe)], check=True)
+    assert subprocess.run([str(exe)], capture_output=True, text=True).stdout.strip() == "ok"

@@ -1,0 +1,171 @@
+"""H' on the GPU against the CPU oracle, bit for bit.
+
+Inputs are random 32/16-bit payloads (every element distinct with high
+probability, NaN payloads, -0, infinities and denormals mixed in) and the
+Gaussian-envelope workloads.  Sizes run from single elements through shapes
+that span many work units with ragged tails, up to the full microscope and
+camera workloads in the launch configuration the benchmark times.
+"""
+import numpy as np
+import pytest
+import torch
+
+import lfsynth
+import oracle
+import paper_2003_09133_amd as lf
+from gpu_util import DEV, assert_same_bits, gpu_equal_bits, sample_indices, to_dev
+
+pytestmark = pytest.mark.gpu
+
+CONFIGS = [
+    None,
+    {"variant": lf.GATHER_DIRECT, "rows_in_flight": 1},
+    {"variant": lf.GATHER_DIRECT, "rows_in_flight": 2, "block_threads": 128},
+    {"variant": lf.GATHER_STAGED, "tile_bytes": 4096, "rows_in_flight": 1},
+    {"variant": lf.GATHER_STAGED, "tile_bytes": 65536, "block_threads": 512},
+    {"variant": lf.GATHER_STAGED, "nontemporal": 2, "grid": 3},
+    {"variant": lf.GATHER_DIRECT, "nontemporal": 2, "grid": 5, "block_threads": 64},
+]
+
+
+def random_shapes(n, seed):
+    rng = np.random.default_rng(seed)
+    odd = lambda lo, hi: int(rng.integers(lo, hi + 1)) | 1
+    out = []
+    for _ in range(n):
+        out.append((odd(1, 41), odd(1, 41), odd(1, 11), odd(1, 11), int(rng.integers(1, 10))))
+    return out
+
+
+EDGE_SHAPES = [(1, 1, 1, 1, 1), (1, 1, 1, 1, 5), (3, 3, 7, 5, 2), (3, 5, 5, 3, 1), (15, 15, 3, 3, 3),
+               (5, 7, 1, 1, 1), (9, 9, 9, 9, 1), (3, 3, 1, 3, 400), (3, 1, 3, 1, 1100), (7, 5, 3, 5, 33)]
+
+
+def run(H: np.ndarray, cfg=None) -> np.ndarray:
+    Ht = lf.compute_Ht(to_dev(H), config=cfg)
+    torch.cuda.synchronize()
+    return Ht.cpu().numpy()
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float16])
+def test_tiny_workload(dtype):
+    w = lfsynth.TINY
+    H, _ = lfsynth.make_H(w, dtype)
+    ref = oracle.Ht_rows(H)
+    for cfg in CONFIGS:
+        assert_same_bits(run(H, cfg), ref, f"tiny gauss {cfg}")
+    Hb = lfsynth.bits(w.shape, 3, dtype)
+    refb = oracle.Ht_rows(Hb)
+    for cfg in CONFIGS:
+        assert_same_bits(run(Hb, cfg), refb, f"tiny bits {cfg}")
+
+
+@pytest.mark.parametrize("shape", EDGE_SHAPES + random_shapes(40, 7))
+def test_shapes_all_variants(shape):
+    for dtype in (np.float32, np.float16):
+        H = lfsynth.bits(shape, sum(shape), dtype)
+        ref = oracle.Ht_rows(H)
+        for cfg in CONFIGS:
+            assert_same_bits(run(H, cfg), ref, f"{shape} {np.dtype(dtype).name} {cfg}")
+
+
+def test_row_too_wide_for_a_tile_falls_back_to_direct():
+    """ny*nz*4 bytes beyond the largest LDS tile: the staged request is served
+    by the direct kernel and stays exact."""
+    shape = (3, 3, 3, 3, 6000)
+    H = lfsynth.bits(shape, 5, np.float32)
+    ref = oracle.Ht_rows(H)
+    assert_same_bits(run(H, {"variant": lf.GATHER_STAGED}), ref, "wide rows")
+    assert_same_bits(run(H), ref, "wide rows default")
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float16])
+def test_unaligned_views_and_no_writes_outside(dtype):
+    """Tensors that start at every element offset inside a 16-byte vector, with
+    canary regions on both sides of the output that must stay untouched."""
+    shape = (13, 11, 5, 3, 7)
+    H = lfsynth.bits(shape, 9, dtype)
+    ref = oracle.Ht_rows(H)
+    E = H.size
+    tdt = torch.float32 if dtype == np.float32 else torch.float16
+    ve = 16 // np.dtype(dtype).itemsize
+    for off_in in range(ve):
+        for off_out in range(ve):
+            src = torch.zeros(E + 2 * ve, dtype=tdt, device=DEV)
+            src[off_in:off_in + E] = to_dev(H).view(-1)
+            canary = torch.full((E + 2 * ve + 64,), -7.0, dtype=tdt, device=DEV)
+            dst = canary[32 + off_out:32 + off_out + E].view(shape)
+            hin = src[off_in:off_in + E].view(shape)
+            for cfg in (None, {"variant": lf.GATHER_DIRECT}, {"variant": lf.GATHER_STAGED, "tile_bytes": 2048}):
+                canary.fill_(-7.0)
+                lf.compute_Ht_into(hin, dst, config=cfg)
+                torch.cuda.synchronize()
+                assert_same_bits(dst.cpu().numpy(), ref, f"offsets {off_in},{off_out} {cfg}")
+                c = canary.cpu().numpy()
+                assert (c[:32 + off_out] == -7.0).all() and (c[32 + off_out + E:] == -7.0).all()
+
+
+def test_reversible_on_gpu():
+    """Sec. 3: applying the map to H' restores H (here on the GPU, all variants)."""
+    H = to_dev(lfsynth.bits((31, 27, 7, 5, 6), 4, np.float32))
+    for cfg in CONFIGS:
+        assert gpu_equal_bits(lf.compute_Ht(lf.compute_Ht(H, config=cfg), config=cfg), H)
+
+
+def test_stream_ordering():
+    """Work is queued on the given stream and never synchronises by itself."""
+    H = to_dev(lfsynth.bits((41, 41, 11, 11, 9), 8, np.float32))
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        Ht = lf.compute_Ht(H)
+        back = lf.compute_Ht(Ht)
+    s.synchronize()
+    assert gpu_equal_bits(back, H)
+
+
+# ------------------------------------------------------------------ full size
+
+def _full_size_check(w, dtype, full_compare: bool):
+    H, zf = lfsynth.make_H(w, dtype)
+    cfg = lf.default_config(w.shape, torch.float32 if dtype == np.float32 else torch.float16)
+    print(f"\n{w.name} {np.dtype(dtype).name} zero fraction {zf:.3f} config {cfg}", flush=True)
+    dH = to_dev(H)
+    Ht = lf.compute_Ht(dH)                              # the benchmark's launch configuration
+    torch.cuda.synchronize()
+    if full_compare:
+        got = Ht.cpu().numpy()
+        assert_same_bits(got, oracle.Ht_rows(H), f"{w.name} full")
+    else:
+        idx = sample_indices(H.size, 2_000_000, 1)
+        flat = Ht.view(-1)
+        got = flat[torch.from_numpy(idx).to(DEV)].cpu().numpy()
+        assert_same_bits(got, oracle.Ht_at(H, idx), f"{w.name} sampled")
+        # three whole output rows s' (first, middle, last): every (t', x', y', z)
+        ns = w.shape[0]
+        per = H.size // ns
+        for sp in (0, ns // 2, ns - 1):
+            ridx = np.arange(sp * per, (sp + 1) * per, dtype=np.int64)
+            assert_same_bits(flat[sp * per:(sp + 1) * per].cpu().numpy(), oracle.Ht_at(H, ridx), f"row {sp}")
+    # reversibility holds at any size
+    assert gpu_equal_bits(lf.compute_Ht(Ht), dH)
+    # random payloads: every element distinct with high probability
+    Hb = lfsynth.bits(w.shape, 99, dtype)
+    dHb = to_dev(Hb)
+    Htb = lf.compute_Ht(dHb)
+    torch.cuda.synchronize()
+    if full_compare:
+        assert_same_bits(Htb.cpu().numpy(), oracle.Ht_rows(Hb), f"{w.name} bits full")
+    else:
+        idx = sample_indices(Hb.size, 2_000_000, 2)
+        got = Htb.view(-1)[torch.from_numpy(idx).to(DEV)].cpu().numpy()
+        assert_same_bits(got, oracle.Ht_at(Hb, idx), f"{w.name} bits sampled")
+    assert gpu_equal_bits(lf.compute_Ht(Htb), dHb)
+
+
+def test_microscope_full_size():
+    _full_size_check(lfsynth.MICROSCOPE, np.float32, full_compare=True)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float16])
+def test_camera_full_size(dtype):
+    _full_size_check(lfsynth.CAMERA, dtype, full_compare=False)
