@@ -37,6 +37,8 @@ def parse():
                     choices=sorted(PLAIN) + ["batched", "projector"])
     ap.add_argument("--variant", default=None, choices=[None, "direct", "staged"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy", action="store_true",
+                    help="time a plain device-to-device copy of the same bytes instead (reference ceiling)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="approximate CPU time budget of the oracle baseline")
     return ap.parse_args()
@@ -120,7 +122,8 @@ def bench_plain(args, torch):
     resolved = lf.default_config(w.shape, dH.dtype)
     if cfg:
         resolved.update(cfg)
-    elapsed, wall = time_steps(lambda: lf.compute_Ht_into(dH, dHt, config=cfg), args.steps, args.warmup, torch)
+    step = (lambda: dHt.copy_(dH)) if args.copy else (lambda: lf.compute_Ht_into(dH, dHt, config=cfg))
+    elapsed, wall = time_steps(step, args.steps, args.warmup, torch)
     bytes_step = 2 * H.nbytes
     sec_step = elapsed / args.steps
     gbs = bytes_step / sec_step / 1e9
@@ -130,11 +133,11 @@ def bench_plain(args, torch):
         "scaling": "weak", "vs_baseline": None, "dtype": dt, "data": "synthetic",
         "config": {"workload": f"{w.name} H{list(w.shape)} {dt}", "shape": list(w.shape),
                    "bytes_per_step": bytes_step, "zero_fraction": round(zf, 4),
-                   "kernel": resolved, "wall_s": round(wall, 3)},
+                   "kernel": "torch copy_ (reference)" if args.copy else resolved, "wall_s": round(wall, 3)},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile(args.workload)},
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not args.copy:
         nth = cores_used()
         rate, passes, per = cpu_oracle_rate(H, nth, args.cpu_seconds)
         out["cpu_baseline"] = {"value": round(rate, 3), "unit": "GB/s", "cores": nth, "kind": "oracle",

@@ -81,20 +81,26 @@ LFBP_API lfbp_status lfbp_compute_Ht(const void* H, void* Ht, lfbp_shape shape, 
  *   LFBP_GATHER_AUTO   -- the library's tuned choice for the shape (default)
  *   LFBP_GATHER_DIRECT -- each wavefront copies whole x-rows (ny*nz contiguous
  *                         elements) straight from H to H' with the rotation
- *                         applied to the read addresses
- *   LFBP_GATHER_STAGED -- rows are rotated into an LDS tile, which is then
- *                         written to H' with 16-byte stores
- * Zero in any other field selects the tuned value.
+ *                         applied to the read addresses (4/2-byte accesses)
+ *   LFBP_GATHER_STAGED -- rows are read with 4/2-byte loads and rotated into
+ *                         an LDS tile laid out like H', which is written with
+ *                         16-byte stores
+ *   LFBP_GATHER_WIDE   -- as STAGED, but rows are also read with 16-byte
+ *                         loads (aligned supersets of each row)
+ * Zero in any field selects the tuned value for that field.
  */
-enum { LFBP_GATHER_AUTO = 0, LFBP_GATHER_DIRECT = 1, LFBP_GATHER_STAGED = 2 };
+enum { LFBP_GATHER_AUTO = 0, LFBP_GATHER_DIRECT = 1, LFBP_GATHER_STAGED = 2, LFBP_GATHER_WIDE = 3 };
 
 typedef struct {
-    int32_t variant;      /* LFBP_GATHER_* */
-    int32_t block_threads;/* 64..512, multiple of 64 */
-    int32_t rows_in_flight;/* x-rows a wavefront loads before it stores: 1 or 2 */
-    int32_t tile_bytes;   /* STAGED: LDS tile per workgroup, bytes (<= 65536) */
-    int32_t nontemporal;  /* 1: streaming stores that bypass cache retention, 2: regular stores */
-    int32_t grid;         /* >0: persistent grid of this many workgroups; 0: one per work unit */
+    int32_t variant;        /* LFBP_GATHER_* */
+    int32_t block_threads;  /* 64..512, multiple of 64 */
+    int32_t rows_in_flight; /* DIRECT, STAGED: x-rows a wavefront loads before it stores, 1 or 2 */
+    int32_t tile_bytes;     /* STAGED: LDS tile per workgroup, bytes (<= 65536) */
+    int32_t vec_per_thread; /* WIDE: 16-byte loads per thread per work unit, 2, 4 or 8 */
+    int32_t nontemporal;    /* 1: streaming stores, 2: regular stores */
+    int32_t persistent;     /* 1: `grid` workgroups loop over the work units (WIDE overlaps the loads of
+                               the next unit with the stores of the current one); 2: one workgroup per unit */
+    int32_t grid;           /* persistent grid size; 0 = every workgroup slot of the device */
 } lfbp_gather_config;
 
 /* lfbp_compute_Ht with an explicit kernel choice (used by the autotuner and by
@@ -133,9 +139,9 @@ typedef struct {
 LFBP_API lfbp_status lfbp_compute_Ht_batched(const lfbp_problem* problems, int32_t count, lfbp_dtype dtype,
                                     void* stream);
 
-/* Same as lfbp_compute_Ht_batched with an explicit kernel choice for every
- * problem (variant must be DIRECT or STAGED or AUTO) and graph use: use_graph
- * = 1 replays a captured graph, 0 launches the kernel directly. */
+/* Same as lfbp_compute_Ht_batched with an explicit kernel choice shared by
+ * every problem, and graph use: use_graph = 1 replays a captured graph,
+ * 0 launches the kernel directly.  cfg may be NULL. */
 LFBP_API lfbp_status lfbp_compute_Ht_batched_config(const lfbp_problem* problems, int32_t count, lfbp_dtype dtype,
                                            const lfbp_gather_config* cfg, int32_t use_graph, void* stream);
 

@@ -18,12 +18,12 @@ import ctypes
 import torch
 
 from . import _abi
-from ._abi import (F16, F32, GATHER_AUTO, GATHER_DIRECT, GATHER_STAGED, GatherConfig, LfbpError,
-                   Problem, Shape)
+from ._abi import (F16, F32, GATHER_AUTO, GATHER_DIRECT, GATHER_STAGED, GATHER_WIDE, GatherConfig,
+                   LfbpError, Problem, Shape)
 
 __all__ = ["compute_Ht", "compute_Ht_into", "compute_Ht_batched", "forward", "backward", "LFProject",
            "project", "default_config", "GatherConfig", "LfbpError", "release_plans", "version",
-           "GATHER_AUTO", "GATHER_DIRECT", "GATHER_STAGED"]
+           "GATHER_AUTO", "GATHER_DIRECT", "GATHER_STAGED", "GATHER_WIDE"]
 
 _DTYPES = {torch.float32: F32, torch.float16: F16}
 

@@ -13,7 +13,7 @@ LIB_PATH = os.environ.get("LFBP_LIB", os.path.join(HERE, "liblfbp.so"))
 
 OK, EINVAL, ESHAPE, EDTYPE, EALIAS, EDEVICE, ENOMEM, EALIGN = 0, -1, -2, -3, -4, -5, -6, -7
 F32, F16 = 0, 1
-GATHER_AUTO, GATHER_DIRECT, GATHER_STAGED = 0, 1, 2
+GATHER_AUTO, GATHER_DIRECT, GATHER_STAGED, GATHER_WIDE = 0, 1, 2, 3
 
 STATUS_NAMES = {OK: "LFBP_OK", EINVAL: "LFBP_EINVAL", ESHAPE: "LFBP_ESHAPE", EDTYPE: "LFBP_EDTYPE",
                 EALIAS: "LFBP_EALIAS", EDEVICE: "LFBP_EDEVICE", ENOMEM: "LFBP_ENOMEM", EALIGN: "LFBP_EALIGN"}
@@ -35,7 +35,8 @@ class Problem(ctypes.Structure):
 class GatherConfig(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("block_threads", ctypes.c_int32),
                 ("rows_in_flight", ctypes.c_int32), ("tile_bytes", ctypes.c_int32),
-                ("nontemporal", ctypes.c_int32), ("grid", ctypes.c_int32)]
+                ("vec_per_thread", ctypes.c_int32), ("nontemporal", ctypes.c_int32),
+                ("persistent", ctypes.c_int32), ("grid", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

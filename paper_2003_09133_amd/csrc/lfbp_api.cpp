@@ -1,11 +1,10 @@
-// Host runtime and C ABI of liblfbp.so: argument checks, kernel choice,
-// batched plans (device descriptor tables + captured hipGraphs).
+// Host runtime and C ABI of liblfbp.so: argument checks, kernel choice and work
+// decomposition, batched plans (device descriptor tables + captured hipGraphs).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
-#include <map>
 #include <memory>
 #include <mutex>
 #include <vector>
@@ -19,72 +18,111 @@ namespace lfbp {
 
 hipError_t launch_gather(const GatherDesc& d, int esize, const LaunchPlan& p, hipStream_t stream);
 hipError_t launch_gather_batched(const GatherDesc* descs_dev, const uint32_t* unit_start_dev, uint32_t count,
-                                 uint32_t maxW, int esize, const LaunchPlan& p, hipStream_t stream);
+                                 uint32_t maxW, uint32_t max_rows, int esize, const LaunchPlan& p,
+                                 hipStream_t stream);
 hipError_t set_gather_smem_limits(int max_bytes);
-int batched_occupancy(int variant, uint32_t maxW, int esize, int U, int threads, int smem);
+int gather_occupancy(const LaunchPlan& p, uint32_t W, int esize, bool batched);
 hipError_t launch_forward(const float* H, const lfbp_shape& s, const float* g, int64_t R, int64_t C, float* f,
                           hipStream_t stream);
 hipError_t launch_backward(const float* Ht, const lfbp_shape& s, const float* f, int64_t R, int64_t C, float* g,
                            hipStream_t stream);
-hipError_t project_init();
+hipError_t project_init(int max_lds);
 
 namespace {
 
-constexpr int kMaxTile = 65536;
+// ---------------------------------------------------------------- device setup
 
-// One-time per-process setup of kernel attributes (dynamic LDS limits).
 std::once_flag g_init_once;
 hipError_t g_init_err = hipSuccess;
+int g_max_lds = 65536;  // dynamic LDS a workgroup may use (device limit, read at init)
+int g_cus = 256;
 
 hipError_t ensure_init()
 {
     std::call_once(g_init_once, [] {
-        g_init_err = set_gather_smem_limits(kMaxTile);
-        if (g_init_err == hipSuccess) g_init_err = project_init();
+        int dev = 0, lds = 0, cus = 0;
+        g_init_err = hipGetDevice(&dev);
+        if (g_init_err != hipSuccess) return;
+        if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
+            g_max_lds = lds;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            g_cus = cus;
+        g_init_err = set_gather_smem_limits(g_max_lds);
+        if (g_init_err != hipSuccess && g_max_lds > 65536) {
+            (void)hipGetLastError();
+            g_max_lds = 65536;
+            g_init_err = set_gather_smem_limits(g_max_lds);
+        }
+        if (g_init_err == hipSuccess) g_init_err = project_init(g_max_lds);
     });
     return g_init_err;
 }
 
-// Rows of W elements that fit a tile of tile_bytes with the two alignment
-// vectors of slack.
-uint32_t rows_for_tile(uint32_t W, int esize, int tile_bytes)
-{
-    const int64_t usable = int64_t(tile_bytes) - 2 * 16;
-    const int64_t rows = usable / (int64_t(W) * esize);
-    return rows < 1 ? 0 : uint32_t(rows);
-}
+int round16(int64_t b) { return int((b + 15) / 16 * 16); }
 
-// Complete a (possibly partial) configuration for one problem.
-lfbp_gather_config resolve_config(const lfbp_shape& s, int esize, const lfbp_gather_config* user)
+// ---------------------------------------------------------------- work decomposition
+
+// Complete a (possibly partial) user configuration with the tuned values.
+lfbp_gather_config resolve_config(const lfbp_shape& s, int esize, const lfbp_gather_config* user, bool batched)
 {
-    lfbp_gather_config c = tuned_config(s, esize);  // never has zero fields
+    lfbp_gather_config c = tuned_config(s, esize, batched);  // every field set
     if (user) {
         if (user->variant) c.variant = user->variant;
         if (user->block_threads) c.block_threads = user->block_threads;
         if (user->rows_in_flight) c.rows_in_flight = user->rows_in_flight;
         if (user->tile_bytes) c.tile_bytes = user->tile_bytes;
+        if (user->vec_per_thread) c.vec_per_thread = user->vec_per_thread;
         if (user->nontemporal) c.nontemporal = user->nontemporal;
+        if (user->persistent) c.persistent = user->persistent;
         if (user->grid) c.grid = user->grid;
-        else if (user->variant || user->block_threads || user->rows_in_flight || user->tile_bytes)
-            c.grid = 0;  // a different work split: let the unit count decide
-    }
-    const uint32_t W = uint32_t(s.ny * s.nz);
-    // A staged tile must hold at least one row; otherwise copy rows directly.
-    if (c.variant == LFBP_GATHER_STAGED && rows_for_tile(W, esize, c.tile_bytes) == 0) {
-        if (int64_t(W) * esize + 32 <= kMaxTile)
-            c.tile_bytes = int(((int64_t(W) * esize + 32 + 15) / 16) * 16);
-        else
-            c.variant = LFBP_GATHER_DIRECT;
     }
     return c;
 }
 
-GatherDesc make_desc(const void* H, void* Ht, const lfbp_shape& s, int esize, const lfbp_gather_config& c)
+// Rows per work unit and dynamic LDS of config c for rows of W elements.
+// Falls back WIDE -> STAGED -> DIRECT when a row does not fit.  ntab = row
+// tables the WIDE kernel keeps (2 when pipelined).
+void decompose(uint32_t W, int es, lfbp_gather_config& c, uint32_t& rows, int& lds)
+{
+    const int64_t ve = 16 / es;
+    if (c.variant == LFBP_GATHER_WIDE) {
+        const int64_t vpr = (int64_t(W) + 2 * ve - 2) / ve;
+        const int ntab = c.persistent == 1 ? 2 : 1;
+        int64_t r = int64_t(c.vec_per_thread) * c.block_threads / vpr;
+        auto need = [&](int64_t rr) { return int64_t(ntab) * rr * 16 + round16((rr * W + 2 * ve) * es); };
+        while (r > 0 && need(r) > g_max_lds) --r;
+        if (r > 0) {
+            rows = uint32_t(r);
+            lds = int(need(r));
+            return;
+        }
+        c.variant = LFBP_GATHER_STAGED;
+    }
+    if (c.variant == LFBP_GATHER_STAGED) {
+        int tile = std::min(c.tile_bytes, g_max_lds);
+        int64_t r = (int64_t(tile) - 2 * 16) / (int64_t(W) * es);
+        if (r < 1 && int64_t(W) * es + 32 <= g_max_lds) {
+            tile = round16(int64_t(W) * es + 32);
+            r = 1;
+        }
+        if (r >= 1) {
+            rows = uint32_t(r);
+            lds = tile;
+            return;
+        }
+        c.variant = LFBP_GATHER_DIRECT;
+    }
+    rows = uint32_t(c.block_threads / 64 * c.rows_in_flight);
+    lds = 0;
+}
+
+GatherDesc make_desc(const void* H, void* Ht, const lfbp_shape& s, int es, uint32_t rows)
 {
     GatherDesc d;
     std::memset(&d, 0, sizeof(d));
     d.H = H;
     d.Ht = Ht;
+    d.E = shape_elems(s);
     d.ns = uint32_t(s.ns);
     d.nt = uint32_t(s.nt);
     d.nx = uint32_t(s.nx);
@@ -99,27 +137,38 @@ GatherDesc make_desc(const void* H, void* Ht, const lfbp_shape& s, int esize, co
     d.fnx = make_fastdiv(d.nx);
     d.fny = make_fastdiv(d.ny);
     d.fnt = make_fastdiv(d.nt);
-    if (c.variant == LFBP_GATHER_STAGED)
-        d.rows_per_unit = rows_for_tile(d.W, esize, c.tile_bytes);
-    else
-        d.rows_per_unit = uint32_t(c.block_threads / 64) * uint32_t(c.rows_in_flight);
-    d.rows_per_unit = std::max<uint32_t>(1, std::min(d.rows_per_unit, d.nrows));
+    d.rows_per_unit = std::max<uint32_t>(1, std::min(rows, d.nrows));
     d.nunits = (d.nrows + d.rows_per_unit - 1) / d.rows_per_unit;
-    const uint32_t ve = 16 / uint32_t(esize);
-    d.phase_out = uint32_t((reinterpret_cast<uintptr_t>(Ht) / uintptr_t(esize)) % ve);
+    const uint32_t ve = 16 / uint32_t(es);
+    d.phase_in = uint32_t((reinterpret_cast<uintptr_t>(H) / uintptr_t(es)) % ve);
+    d.phase_out = uint32_t((reinterpret_cast<uintptr_t>(Ht) / uintptr_t(es)) % ve);
+    d.vpr = (d.W + 2 * ve - 2) / ve;
+    d.fvpr = make_fastdiv(d.vpr);
+    d.xcd_remap = 1;
     return d;
 }
 
-LaunchPlan make_plan(const lfbp_gather_config& c, uint32_t units)
+LaunchPlan make_plan(const lfbp_gather_config& c, int lds)
 {
     LaunchPlan p;
     p.variant = c.variant;
     p.threads = c.block_threads;
     p.rows_in_flight = c.rows_in_flight;
-    p.tile_bytes = c.variant == LFBP_GATHER_STAGED ? c.tile_bytes : 0;
+    p.vec_per_thread = c.vec_per_thread;
+    p.lds_bytes = lds;
     p.nontemporal = c.nontemporal;
-    p.grid = c.grid > 0 ? int(std::min<uint32_t>(uint32_t(c.grid), units)) : int(units);
+    p.persistent = c.persistent;
+    p.grid = 0;
     return p;
+}
+
+// Grid of a launch over `units` work units.
+int grid_for(const lfbp_gather_config& c, LaunchPlan& p, uint32_t units, uint32_t W, int es, bool batched)
+{
+    if (c.persistent != 1) return int(units);
+    int g = c.grid;
+    if (g <= 0) g = g_cus * gather_occupancy(p, W, es, batched);
+    return int(std::min<uint64_t>(uint64_t(g), units));
 }
 
 // ---------------------------------------------------------------- batched plans
@@ -128,11 +177,11 @@ struct BatchPlan {
     int device = -1;
     std::vector<lfbp_problem> probs;
     lfbp_dtype dtype = LFBP_F32;
-    lfbp_gather_config cfg{};
+    lfbp_gather_config key{};
     int use_graph = 1;
     GatherDesc* descs_dev = nullptr;
     uint32_t* unit_start_dev = nullptr;
-    uint32_t count = 0, maxW = 0;
+    uint32_t count = 0, maxW = 0, max_rows = 0;
     LaunchPlan plan{};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -150,10 +199,10 @@ std::mutex g_plan_mu;
 std::vector<std::unique_ptr<BatchPlan>> g_plans;
 
 bool same_table(const BatchPlan& p, int dev, const lfbp_problem* probs, int32_t count, lfbp_dtype dt,
-                const lfbp_gather_config& cfg, int use_graph)
+                const lfbp_gather_config& key, int use_graph)
 {
     if (p.device != dev || p.dtype != dt || p.probs.size() != size_t(count) || p.use_graph != use_graph) return false;
-    if (std::memcmp(&p.cfg, &cfg, sizeof(cfg)) != 0) return false;
+    if (std::memcmp(&p.key, &key, sizeof(key)) != 0) return false;
     return std::memcmp(p.probs.data(), probs, sizeof(lfbp_problem) * size_t(count)) == 0;
 }
 
@@ -161,45 +210,50 @@ lfbp_status build_plan(BatchPlan& bp, const lfbp_problem* probs, int32_t count, 
                        const lfbp_gather_config* user, int use_graph)
 {
     const int es = dtype_size(dt);
-    // One variant, workgroup size and rows-in-flight for the whole batch: take
-    // the tuned choice of the largest problem, then size each problem's work
-    // unit for that choice.
+    // One kernel configuration for the whole batch: the tuned choice of the
+    // largest problem; each problem's work unit is then sized for it.
     int big = 0;
     for (int32_t i = 1; i < count; ++i)
         if (shape_elems(probs[i].shape) > shape_elems(probs[big].shape)) big = i;
-    lfbp_gather_config c = resolve_config(probs[big].shape, es, user);
-    std::vector<GatherDesc> descs(static_cast<size_t>(count));
-    std::vector<uint32_t> start(static_cast<size_t>(count) + 1, 0);
+    lfbp_gather_config c = resolve_config(probs[big].shape, es, user, true);
+    // Every problem must fit the chosen variant; the first one that does not
+    // moves the whole batch down (WIDE -> STAGED -> DIRECT).
     uint32_t maxW = 0;
-    int tile = 0;
     for (int32_t i = 0; i < count; ++i) {
         const uint32_t W = uint32_t(probs[i].shape.ny * probs[i].shape.nz);
         maxW = std::max(maxW, W);
-        if (c.variant == LFBP_GATHER_STAGED && rows_for_tile(W, es, c.tile_bytes) == 0) {
-            if (int64_t(W) * es + 32 <= kMaxTile)
-                c.tile_bytes = int(((int64_t(W) * es + 32 + 15) / 16) * 16);
-            else
-                c.variant = LFBP_GATHER_DIRECT;
-        }
+        uint32_t r;
+        int l;
+        decompose(W, es, c, r, l);
     }
+    std::vector<uint32_t> rows(static_cast<size_t>(count));
+    int lds = 0;
+    uint32_t max_rows = 0;
     for (int32_t i = 0; i < count; ++i) {
-        descs[size_t(i)] = make_desc(probs[i].H, probs[i].Ht, probs[i].shape, es, c);
+        const uint32_t W = uint32_t(probs[i].shape.ny * probs[i].shape.nz);
+        lfbp_gather_config ci = c;
+        int l = 0;
+        decompose(W, es, ci, rows[size_t(i)], l);
+        max_rows = std::max(max_rows, rows[size_t(i)]);
+        if (c.variant == LFBP_GATHER_WIDE) {
+            const int64_t ve = 16 / es;
+            l = round16((int64_t(rows[size_t(i)]) * W + 2 * ve) * es);  // tile only; tables added below
+        }
+        lds = std::max(lds, l);
+    }
+    if (c.variant == LFBP_GATHER_WIDE) lds += (c.persistent == 1 ? 2 : 1) * int(max_rows) * 16;
+    if (lds > g_max_lds) return LFBP_ESHAPE;
+    std::vector<GatherDesc> descs(static_cast<size_t>(count));
+    std::vector<uint32_t> start(static_cast<size_t>(count) + 1, 0);
+    for (int32_t i = 0; i < count; ++i) {
+        descs[size_t(i)] = make_desc(probs[i].H, probs[i].Ht, probs[i].shape, es, rows[size_t(i)]);
         const uint64_t next = uint64_t(start[size_t(i)]) + descs[size_t(i)].nunits;
         if (next >= (uint64_t(1) << 31)) return LFBP_ESHAPE;
         start[size_t(i) + 1] = uint32_t(next);
     }
-    tile = c.variant == LFBP_GATHER_STAGED ? c.tile_bytes : 0;
     const uint32_t total = start[size_t(count)];
-    LaunchPlan lp = make_plan(c, total);
-    lp.tile_bytes = tile;
-    if (c.grid <= 0) {
-        // persistent grid: every workgroup slot of the device, once
-        int dev = 0, cus = 0;
-        if (hipGetDevice(&dev) != hipSuccess) return LFBP_EDEVICE;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return LFBP_EDEVICE;
-        const int per_cu = std::max(1, batched_occupancy(c.variant, maxW, es, c.rows_in_flight, c.block_threads, tile));
-        lp.grid = int(std::min<uint64_t>(uint64_t(cus) * uint64_t(per_cu), total));
-    }
+    LaunchPlan lp = make_plan(c, lds);
+    lp.grid = grid_for(c, lp, total, maxW, es, true);
     if (hipMalloc(reinterpret_cast<void**>(&bp.descs_dev), sizeof(GatherDesc) * size_t(count)) != hipSuccess)
         return LFBP_ENOMEM;
     if (hipMalloc(reinterpret_cast<void**>(&bp.unit_start_dev), sizeof(uint32_t) * (size_t(count) + 1)) != hipSuccess)
@@ -211,6 +265,7 @@ lfbp_status build_plan(BatchPlan& bp, const lfbp_problem* probs, int32_t count, 
         return LFBP_EDEVICE;
     bp.count = uint32_t(count);
     bp.maxW = maxW;
+    bp.max_rows = max_rows;
     bp.plan = lp;
     bp.dtype = dt;
     bp.use_graph = use_graph;
@@ -220,7 +275,8 @@ lfbp_status build_plan(BatchPlan& bp, const lfbp_problem* probs, int32_t count, 
         if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return LFBP_EDEVICE;
         hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            const hipError_t le = launch_gather_batched(bp.descs_dev, bp.unit_start_dev, bp.count, bp.maxW, es, lp, cs);
+            const hipError_t le =
+                launch_gather_batched(bp.descs_dev, bp.unit_start_dev, bp.count, bp.maxW, bp.max_rows, es, lp, cs);
             e = hipStreamEndCapture(cs, &bp.graph);
             if (le != hipSuccess) e = le;
         }
@@ -275,7 +331,7 @@ const char* lfbp_status_string(lfbp_status s)
     }
 }
 
-const char* lfbp_version(void) { return "lfbp 0.1 gfx950"; }
+const char* lfbp_version(void) { return "lfbp 0.2 gfx950"; }
 
 lfbp_status lfbp_default_config(lfbp_shape shape, lfbp_dtype dtype, lfbp_gather_config* cfg)
 {
@@ -284,11 +340,15 @@ lfbp_status lfbp_default_config(lfbp_shape shape, lfbp_dtype dtype, lfbp_gather_
     if (es == 0) return LFBP_EDTYPE;
     const lfbp_status st = check_shape(shape, es);
     if (st != LFBP_OK) return st;
-    *cfg = resolve_config(shape, es, nullptr);
-    if (cfg->grid == 0) {
-        const GatherDesc d = make_desc(nullptr, nullptr, shape, es, *cfg);
-        cfg->grid = int(d.nunits);
+    lfbp_gather_config c = resolve_config(shape, es, nullptr, false);
+    uint32_t rows = 0;
+    int lds = 0;
+    decompose(uint32_t(shape.ny * shape.nz), es, c, rows, lds);
+    if (c.grid == 0) {
+        const GatherDesc d = make_desc(nullptr, nullptr, shape, es, rows);
+        c.grid = c.persistent == 1 ? g_cus : int(d.nunits);
     }
+    *cfg = c;
     return LFBP_OK;
 }
 
@@ -301,9 +361,14 @@ lfbp_status lfbp_compute_Ht_config(const void* H, void* Ht, lfbp_shape shape, lf
     if (st != LFBP_OK) return st;
     if (ensure_init() != hipSuccess) return LFBP_EDEVICE;
     const int es = dtype_size(dtype);
-    const lfbp_gather_config c = resolve_config(shape, es, cfg);
-    const GatherDesc d = make_desc(H, Ht, shape, es, c);
-    const LaunchPlan p = make_plan(c, d.nunits);
+    lfbp_gather_config c = resolve_config(shape, es, cfg, false);
+    uint32_t rows = 0;
+    int lds = 0;
+    const uint32_t W = uint32_t(shape.ny * shape.nz);
+    decompose(W, es, c, rows, lds);
+    const GatherDesc d = make_desc(H, Ht, shape, es, rows);
+    LaunchPlan p = make_plan(c, lds);
+    p.grid = grid_for(c, p, d.nunits, W, es, false);
     return launch_gather(d, es, p, static_cast<hipStream_t>(stream)) == hipSuccess ? LFBP_OK : LFBP_EDEVICE;
 }
 
@@ -335,7 +400,7 @@ lfbp_status lfbp_compute_Ht_batched_config(const lfbp_problem* problems, int32_t
     if (!plan) {
         auto bp = std::make_unique<BatchPlan>();
         bp->device = dev;
-        bp->cfg = key;
+        bp->key = key;
         st = build_plan(*bp, problems, count, dtype, cfg, use_graph);
         if (st != LFBP_OK) return st;
         g_plans.push_back(std::move(bp));
@@ -346,7 +411,7 @@ lfbp_status lfbp_compute_Ht_batched_config(const lfbp_problem* problems, int32_t
     if (plan->use_graph)
         e = hipGraphLaunch(plan->exec, s);
     else
-        e = launch_gather_batched(plan->descs_dev, plan->unit_start_dev, plan->count, plan->maxW,
+        e = launch_gather_batched(plan->descs_dev, plan->unit_start_dev, plan->count, plan->maxW, plan->max_rows,
                                   dtype_size(dtype), plan->plan, s);
     return e == hipSuccess ? LFBP_OK : LFBP_EDEVICE;
 }
@@ -365,7 +430,7 @@ void lfbp_release_plans(void)
 lfbp_status lfbp_forward(const float* H, lfbp_shape shape, const float* g, int64_t R, int64_t C, float* f,
                          void* stream)
 {
-    const lfbp_status st = check_project(H, shape, g, shape.nz * R * C, R, C, f, R * C);
+    const lfbp_status st = check_project(H, shape, g, R, C, f, true);
     if (st != LFBP_OK) return st;
     if (ensure_init() != hipSuccess) return LFBP_EDEVICE;
     return launch_forward(H, shape, g, R, C, f, static_cast<hipStream_t>(stream)) == hipSuccess ? LFBP_OK
@@ -375,7 +440,7 @@ lfbp_status lfbp_forward(const float* H, lfbp_shape shape, const float* g, int64
 lfbp_status lfbp_backward(const float* Ht, lfbp_shape shape, const float* f, int64_t R, int64_t C, float* g,
                           void* stream)
 {
-    const lfbp_status st = check_project(Ht, shape, f, R * C, R, C, g, shape.nz * R * C);
+    const lfbp_status st = check_project(Ht, shape, f, R, C, g, false);
     if (st != LFBP_OK) return st;
     if (ensure_init() != hipSuccess) return LFBP_EDEVICE;
     return launch_backward(Ht, shape, f, R, C, g, static_cast<hipStream_t>(stream)) == hipSuccess ? LFBP_OK

@@ -9,28 +9,43 @@
 // is written exactly once.  z is the contiguous axis (depth planes are
 // independent, Sec. 4), so the map moves whole "x-rows" of W = ny*nz
 // contiguous elements: output x-row (s',t',x') is input x-row
-// (ns-1-s', nt-1-t', (x'+a) mod nx) rotated left by b*nz elements.  All index
-// work is per row and wave-uniform (scalar unit); per element only the
-// rotation wraps.  No arithmetic touches the payloads: float32 and float16
-// both move as raw 32/16-bit words.
+// (ns-1-s', nt-1-t', (x'+a) mod nx) rotated left by b*nz elements.  Row index
+// work is per row (wave-uniform, or once per row in a small LDS table); per
+// element only the rotation wraps.  No arithmetic touches the payloads:
+// float32 and float16 both move as raw 32/16-bit words.
 //
-// Two kernels:
-//   direct  -- a wavefront copies U whole x-rows, reading H at rotated
-//              addresses and writing H' contiguously (dword/short accesses,
-//              each wave instruction covers 64 consecutive elements).
-//   staged  -- a workgroup rotates a run of consecutive output x-rows into an
-//              LDS tile laid out exactly like that stretch of H', then writes
-//              the tile to HBM with aligned 16-byte stores (full cache lines).
-// Each has a plain entry (descriptor passed by value, nothing allocated) and a
-// batched entry (descriptor table in device memory, one persistent launch for
-// many problems).
+// Kernel families (all write every element of H' exactly once):
+//   DIRECT  a wavefront copies whole x-rows, reading H at rotated addresses and
+//           writing H' contiguously with 4/2-byte accesses.
+//   STAGED  4/2-byte row loads, rotated into an LDS tile that is laid out like
+//           the stretch of H' it covers, written out with aligned 16-byte
+//           stores (full cache lines).
+//   WIDE    as STAGED, with the rows also read as aligned 16-byte vectors (a
+//           row's superset; the few elements of neighbouring rows are
+//           dropped).  Its persistent form keeps the 16-byte loads of the next
+//           unit in flight while the current tile is written (LDS-only
+//           barriers do not drain outstanding global loads), and gives each
+//           workgroup a contiguous range of units so that the cache lines two
+//           consecutive units share stay in one XCD's L2.
+// Each has a plain entry (descriptor by value, nothing allocated) and a
+// batched entry (descriptor table in device memory, one launch for many
+// problems).
 #include <hip/hip_runtime.h>
+
+#include <iterator>
+#include <vector>
 
 #include "lfbp_internal.h"
 
 namespace lfbp {
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+union Pack16 {
+    u32x4 v;
+    T e[16 / sizeof(T)];
+};
 
 template <typename T>
 __device__ __forceinline__ void put(T* p, T v, bool nt)
@@ -49,10 +64,18 @@ __device__ __forceinline__ void put16(void* p, u32x4 v, bool nt)
         *static_cast<u32x4*>(p) = v;
 }
 
-// Source of output x-row R: pointer to the start of the input x-row and the
-// left rotation in elements.
-template <typename T>
-__device__ __forceinline__ void row_source(const GatherDesc& d, uint32_t R, const T*& src, uint32_t& rot)
+// Workgroup barrier ordering LDS accesses only: outstanding global loads and
+// stores of the waves stay in flight across it.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Source of output x-row R: element offset of the input x-row and its left
+// rotation in elements.
+__device__ __forceinline__ void row_source(const GatherDesc& d, uint32_t R, uint64_t& src, uint32_t& rot)
 {
     const uint32_t O = fdiv(R, d.fnx);  // block index s'*nt + t'
     const uint32_t xo = R - O * d.nx;   // x'
@@ -63,12 +86,47 @@ __device__ __forceinline__ void row_source(const GatherDesc& d, uint32_t R, cons
     const uint32_t b = ub - fdiv(ub, d.fny) * d.ny;
     uint32_t xs = xo + a;
     if (xs >= d.nx) xs -= d.nx;
-    const uint64_t in_row = uint64_t(d.NB - 1 - O) * d.nx + xs;  // block reversal (Eqs. 8-9)
-    src = static_cast<const T*>(d.H) + in_row * d.W;
+    src = (uint64_t(d.NB - 1 - O) * d.nx + xs) * d.W;  // block reversal (Eqs. 8-9)
     rot = b * d.nz;
 }
 
-// ---------------------------------------------------------------- direct
+// Unit index of workgroup b when one workgroup serves each unit: workgroups
+// are dealt to the 8 XCDs round-robin, so hand each XCD a contiguous range of
+// units (bijective on [0, n)).
+__device__ __forceinline__ uint32_t unit_of_block(uint32_t b, uint32_t n, bool remap)
+{
+    if (!remap) return b;
+    const uint32_t x = b & 7u, l = b >> 3, per = n >> 3, rem = n & 7u;
+    return x * per + min(x, rem) + l;
+}
+
+// Emit a tile that holds H'[O0, O0+L) starting at LDS slot `lead`:
+// 16-byte stores at 16-byte aligned addresses, partial vectors at the ends
+// element by element.
+template <typename T>
+__device__ __forceinline__ void emit_tile(const GatherDesc& d, uint64_t O0, uint32_t L, uint32_t lead, const T* tile,
+                                          bool nt)
+{
+    constexpr uint32_t VE = 16 / sizeof(T);
+    T* out = static_cast<T*>(d.Ht);
+    const uint64_t g0 = O0 + d.phase_out;
+    const uint64_t u0 = g0 / VE, u1 = (g0 + L + VE - 1) / VE;
+    for (uint64_t u = u0 + threadIdx.x; u < u1; u += blockDim.x) {
+        const uint32_t li = uint32_t((u - u0) * VE);     // LDS index of the vector
+        const int64_t rel = int64_t(li) - int64_t(lead);  // position in the unit
+        if (rel >= 0 && rel + VE <= L) {
+            put16(out + (O0 + rel), *reinterpret_cast<const u32x4*>(tile + li), nt);
+        } else {
+#pragma unroll
+            for (uint32_t e = 0; e < VE; ++e) {
+                const int64_t p = rel + e;
+                if (p >= 0 && p < int64_t(L)) put<T>(out + (O0 + p), tile[li + e], nt);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- DIRECT
 
 // U consecutive output x-rows starting at R0, S 64-element segments per row
 // per step, all U*S loads of a step in flight before the stores.
@@ -84,7 +142,9 @@ __device__ __forceinline__ void direct_rows(const GatherDesc& d, uint32_t R0, ui
         const uint32_t R = R0 + u;
         live[u] = R < d.nrows;
         const uint32_t Rc = live[u] ? R : R0;
-        row_source<T>(d, Rc, src[u], rot[u]);
+        uint64_t so;
+        row_source(d, Rc, so, rot[u]);
+        src[u] = static_cast<const T*>(d.H) + so;
         dst[u] = static_cast<T*>(d.Ht) + uint64_t(Rc) * d.W;
     }
     const uint32_t W = d.W;
@@ -111,8 +171,6 @@ __device__ __forceinline__ void direct_rows(const GatherDesc& d, uint32_t R0, ui
     }
 }
 
-// Work unit of the direct kernel = rows_per_unit consecutive output rows,
-// split over the wavefronts of the workgroup in steps of U rows.
 template <typename T, int S, int U>
 __device__ __forceinline__ void direct_unit(const GatherDesc& d, uint32_t unit, bool nt)
 {
@@ -130,23 +188,20 @@ __device__ __forceinline__ void direct_unit(const GatherDesc& d, uint32_t unit, 
     }
 }
 
-// ---------------------------------------------------------------- staged
+// ---------------------------------------------------------------- STAGED
 
 template <typename T, int S, int U>
 __device__ __forceinline__ void staged_unit(const GatherDesc& d, uint32_t unit, T* lds, bool nt)
 {
-    constexpr uint32_t VE = 16 / sizeof(T);  // elements per 16-byte vector
+    constexpr uint32_t VE = 16 / sizeof(T);
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t nw = blockDim.x >> 6;
     const uint32_t W = d.W;
     const uint32_t R0 = unit * d.rows_per_unit;
     const uint32_t nr = min(d.rows_per_unit, d.nrows - R0);
-    const uint64_t O0 = uint64_t(R0) * W;                       // first output element
-    const uint32_t lead = uint32_t((O0 + d.phase_out) % VE);    // LDS slot of O0
-    const uint32_t L = nr * W;
-
-    // 1. Load: input rows in, rotated into their output slots.
+    const uint64_t O0 = uint64_t(R0) * W;
+    const uint32_t lead = uint32_t((O0 + d.phase_out) % VE);
     for (uint32_t r0 = wave * U; r0 < nr; r0 += nw * U) {
         const T* src[U];
         uint32_t rot[U];
@@ -154,7 +209,9 @@ __device__ __forceinline__ void staged_unit(const GatherDesc& d, uint32_t unit, 
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             live[u] = r0 + u < nr;
-            row_source<T>(d, R0 + (live[u] ? r0 + u : r0), src[u], rot[u]);
+            uint64_t so;
+            row_source(d, R0 + (live[u] ? r0 + u : r0), so, rot[u]);
+            src[u] = static_cast<const T*>(d.H) + so;
         }
         for (uint32_t base = 0; base < W; base += 64 * S) {
             T v[U][S];
@@ -179,27 +236,154 @@ __device__ __forceinline__ void staged_unit(const GatherDesc& d, uint32_t unit, 
         }
     }
     __syncthreads();
+    emit_tile<T>(d, O0, nr * W, lead, lds, nt);
+    __syncthreads();
+}
 
-    // 2. Emit: the tile is H'[O0, O0+L) shifted by `lead`; write it with
-    //    16-byte stores at 16-byte aligned addresses, partial vectors at the
-    //    two ends element by element.
-    T* out = static_cast<T*>(d.Ht);
-    const uint64_t g0 = O0 + d.phase_out;
-    const uint64_t u0 = g0 / VE, u1 = (g0 + L + VE - 1) / VE;
-    for (uint64_t u = u0 + threadIdx.x; u < u1; u += blockDim.x) {
-        const uint32_t li = uint32_t((u - u0) * VE);            // LDS index of the vector
-        const int64_t rel = int64_t(li) - int64_t(lead);         // position in the unit
-        if (rel >= 0 && rel + VE <= L) {
-            put16(out + (O0 + rel), *reinterpret_cast<const u32x4*>(lds + li), nt);
-        } else {
+// ---------------------------------------------------------------- WIDE
+
+// Row table of the unit starting at output row R0 (nr rows).
+template <typename T>
+__device__ __forceinline__ void wide_table(const GatherDesc& d, uint32_t R0, uint32_t nr, RowEnt* tab)
+{
+    constexpr uint32_t VE = 16 / sizeof(T);
+    for (uint32_t r = threadIdx.x; r < nr; r += blockDim.x) {
+        uint64_t src;
+        uint32_t rot;
+        row_source(d, R0 + r, src, rot);
+        RowEnt e;
+        e.lead = uint32_t((src + d.phase_in) % VE);
+        e.vbase = int64_t(src) - int64_t(e.lead);
+        e.rot = rot;
+        tab[r] = e;
+    }
+}
+
+// Issue the 16-byte loads of a unit: slot m of thread t reads vector
+// idx = t + m*blockDim of the flattened (row, vector-in-row) space.
+template <typename T, int M>
+__device__ __forceinline__ void wide_load(const GatherDesc& d, uint32_t nr, const RowEnt* tab, u32x4 (&v)[M])
+{
+    constexpr uint32_t VE = 16 / sizeof(T);
+    const uint32_t nvec = nr * d.vpr;
+    const T* H = static_cast<const T*>(d.H);
 #pragma unroll
-            for (uint32_t e = 0; e < VE; ++e) {
-                const int64_t p = rel + e;
-                if (p >= 0 && p < int64_t(L)) put<T>(out + (O0 + p), lds[li + e], nt);
+    for (int m = 0; m < M; ++m) {
+        const uint32_t idx = threadIdx.x + uint32_t(m) * blockDim.x;
+        if (idx < nvec) {
+            const uint32_t r = fdiv(idx, d.fvpr);
+            const uint32_t k = idx - r * d.vpr;
+            const RowEnt e = tab[r];
+            if (k * VE < e.lead + d.W) {  // the vector holds part of the row
+                const int64_t g = e.vbase + int64_t(k * VE);
+                if (g >= 0 && uint64_t(g) + VE <= d.E) {
+                    v[m] = *reinterpret_cast<const u32x4*>(H + g);
+                } else {  // a vector sticking out of the array (its first or last)
+                    Pack16<T> p;
+#pragma unroll
+                    for (uint32_t q = 0; q < VE; ++q) {
+                        const int64_t gi = g + q;
+                        p.e[q] = (gi >= 0 && uint64_t(gi) < d.E) ? H[gi] : T(0);
+                    }
+                    v[m] = p.v;
+                }
             }
         }
     }
-    __syncthreads();
+}
+
+// Scatter the loaded vectors into the tile at their rotated output slots.
+template <typename T, int M>
+__device__ __forceinline__ void wide_scatter(const GatherDesc& d, uint32_t nr, const RowEnt* tab,
+                                             const u32x4 (&v)[M], T* tile, uint32_t lead_out)
+{
+    constexpr uint32_t VE = 16 / sizeof(T);
+    const uint32_t nvec = nr * d.vpr;
+    const int32_t W = int32_t(d.W);
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const uint32_t idx = threadIdx.x + uint32_t(m) * blockDim.x;
+        if (idx < nvec) {
+            const uint32_t r = fdiv(idx, d.fvpr);
+            const uint32_t k = idx - r * d.vpr;
+            const RowEnt e = tab[r];
+            const int32_t j0 = int32_t(k * VE) - int32_t(e.lead);  // row position of element 0
+            if (j0 < W) {
+                Pack16<T> p;
+                p.v = v[m];
+                T* row = tile + lead_out + r * d.W;
+                const int32_t rot = int32_t(e.rot);
+#pragma unroll
+                for (uint32_t q = 0; q < VE; ++q) {
+                    const int32_t j = j0 + int32_t(q);
+                    if (j >= 0 && j < W) row[j >= rot ? j - rot : j + W - rot] = p.e[q];
+                }
+            }
+        }
+    }
+}
+
+template <typename T, int M>
+__device__ __forceinline__ void wide_unit(const GatherDesc& d, uint32_t unit, RowEnt* tab, T* tile, bool nt)
+{
+    constexpr uint32_t VE = 16 / sizeof(T);
+    const uint32_t R0 = unit * d.rows_per_unit;
+    const uint32_t nr = min(d.rows_per_unit, d.nrows - R0);
+    const uint64_t O0 = uint64_t(R0) * d.W;
+    const uint32_t lead = uint32_t((O0 + d.phase_out) % VE);
+    wide_table<T>(d, R0, nr, tab);
+    lds_barrier();
+    u32x4 v[M];
+    wide_load<T, M>(d, nr, tab, v);
+    wide_scatter<T, M>(d, nr, tab, v, tile, lead);
+    lds_barrier();
+    emit_tile<T>(d, O0, nr * d.W, lead, tile, nt);
+    lds_barrier();
+}
+
+// Persistent, software-pipelined: units [u0, u1) of one descriptor source.
+// Get(u) returns the descriptor and local unit of global unit u.
+template <typename T, int M, class Get>
+__device__ __forceinline__ void wide_pipeline(uint32_t u0, uint32_t u1, Get get, RowEnt* tab0, RowEnt* tab1,
+                                              uint32_t tab_rows, T* tile, bool nt)
+{
+    constexpr uint32_t VE = 16 / sizeof(T);
+    if (u0 >= u1) return;
+    (void)tab_rows;
+    GatherDesc dc;
+    uint32_t lc;
+    get(u0, dc, lc);
+    uint32_t R0 = lc * dc.rows_per_unit;
+    uint32_t nr = min(dc.rows_per_unit, dc.nrows - R0);
+    wide_table<T>(dc, R0, nr, tab0);
+    lds_barrier();
+    u32x4 v[M];
+    wide_load<T, M>(dc, nr, tab0, v);
+    for (uint32_t u = u0; u < u1; ++u) {
+        RowEnt* tc = ((u - u0) & 1u) ? tab1 : tab0;
+        RowEnt* tn = ((u - u0) & 1u) ? tab0 : tab1;
+        const uint64_t O0 = uint64_t(R0) * dc.W;
+        const uint32_t lead = uint32_t((O0 + dc.phase_out) % VE);
+        wide_scatter<T, M>(dc, nr, tc, v, tile, lead);
+        GatherDesc dn;
+        uint32_t ln = 0, Rn = 0, nn = 0;
+        const bool more = u + 1 < u1;
+        if (more) {
+            get(u + 1, dn, ln);
+            Rn = ln * dn.rows_per_unit;
+            nn = min(dn.rows_per_unit, dn.nrows - Rn);
+            wide_table<T>(dn, Rn, nn, tn);
+        }
+        lds_barrier();                               // tile and next table complete
+        if (more) wide_load<T, M>(dn, nn, tn, v);    // next unit's loads in flight ...
+        emit_tile<T>(dc, O0, nr * dc.W, lead, tile, nt);  // ... while this tile is written
+        lds_barrier();                               // tile free again
+        if (more) {
+            dc = dn;
+            R0 = Rn;
+            nr = nn;
+        }
+    }
 }
 
 // ---------------------------------------------------------------- entries
@@ -218,8 +402,34 @@ __global__ void __launch_bounds__(512) k_staged(GatherDesc d, int nt)
     for (uint32_t unit = blockIdx.x; unit < d.nunits; unit += gridDim.x) staged_unit<T, S, U>(d, unit, lds, nt != 0);
 }
 
+template <typename T, int M>
+__global__ void __launch_bounds__(512) k_wide(GatherDesc d, int nt)
+{
+    extern __shared__ u32x4 smem[];
+    RowEnt* tab = reinterpret_cast<RowEnt*>(smem);
+    T* tile = reinterpret_cast<T*>(smem + d.rows_per_unit);
+    for (uint32_t b = blockIdx.x; b < d.nunits; b += gridDim.x)
+        wide_unit<T, M>(d, unit_of_block(b, d.nunits, d.xcd_remap && gridDim.x == d.nunits), tab, tile, nt != 0);
+}
+
+template <typename T, int M>
+__global__ void __launch_bounds__(512) k_wide_persist(GatherDesc d, int nt)
+{
+    extern __shared__ u32x4 smem[];
+    RowEnt* tab0 = reinterpret_cast<RowEnt*>(smem);
+    RowEnt* tab1 = tab0 + d.rows_per_unit;
+    T* tile = reinterpret_cast<T*>(smem + 2 * d.rows_per_unit);
+    const uint32_t n = d.nunits, g = gridDim.x, b = blockIdx.x;
+    const uint32_t u0 = uint32_t(uint64_t(b) * n / g), u1 = uint32_t(uint64_t(b + 1) * n / g);
+    auto get = [&](uint32_t u, GatherDesc& dd, uint32_t& lu) {
+        dd = d;
+        lu = u;
+    };
+    wide_pipeline<T, M>(u0, u1, get, tab0, tab1, d.rows_per_unit, tile, nt != 0);
+}
+
 // Batched entries: unit_start[p] = first global unit of problem p,
-// unit_start[count] = total.  The grid strides over all units of all problems.
+// unit_start[count] = total.
 __device__ __forceinline__ uint32_t find_problem(const uint32_t* unit_start, uint32_t count, uint32_t g)
 {
     uint32_t lo = 0, hi = count;  // unit_start[lo] <= g < unit_start[hi]
@@ -235,8 +445,9 @@ __device__ __forceinline__ uint32_t find_problem(const uint32_t* unit_start, uin
 
 template <typename T, int S, int U>
 __global__ void __launch_bounds__(512)
-    k_direct_batched(const GatherDesc* descs, const uint32_t* unit_start, uint32_t count, int nt)
+    k_direct_batched(const GatherDesc* descs, const uint32_t* unit_start, uint32_t count, uint32_t max_rows, int nt)
 {
+    (void)max_rows;
     const uint32_t total = unit_start[count];
     for (uint32_t g = blockIdx.x; g < total; g += gridDim.x) {
         const uint32_t p = find_problem(unit_start, count, g);
@@ -247,8 +458,9 @@ __global__ void __launch_bounds__(512)
 
 template <typename T, int S, int U>
 __global__ void __launch_bounds__(512)
-    k_staged_batched(const GatherDesc* descs, const uint32_t* unit_start, uint32_t count, int nt)
+    k_staged_batched(const GatherDesc* descs, const uint32_t* unit_start, uint32_t count, uint32_t max_rows, int nt)
 {
+    (void)max_rows;
     extern __shared__ u32x4 smem[];
     T* lds = reinterpret_cast<T*>(smem);
     const uint32_t total = unit_start[count];
@@ -259,26 +471,48 @@ __global__ void __launch_bounds__(512)
     }
 }
 
+// One workgroup per unit over all problems.  max_rows = largest rows_per_unit.
+template <typename T, int M>
+__global__ void __launch_bounds__(512)
+    k_wide_batched(const GatherDesc* descs, const uint32_t* unit_start, uint32_t count, uint32_t max_rows, int nt)
+{
+    extern __shared__ u32x4 smem[];
+    RowEnt* tab = reinterpret_cast<RowEnt*>(smem);
+    T* tile = reinterpret_cast<T*>(smem + max_rows);
+    const uint32_t total = unit_start[count];
+    for (uint32_t g = blockIdx.x; g < total; g += gridDim.x) {
+        const uint32_t p = find_problem(unit_start, count, g);
+        const GatherDesc d = descs[p];
+        wide_unit<T, M>(d, g - unit_start[p], tab, tile, nt != 0);
+    }
+}
+
+// Persistent and pipelined over all problems: workgroup b owns the contiguous
+// global units [b*total/grid, (b+1)*total/grid).
+template <typename T, int M>
+__global__ void __launch_bounds__(512) k_wide_batched_persist(const GatherDesc* descs, const uint32_t* unit_start,
+                                                              uint32_t count, uint32_t max_rows, int nt)
+{
+    extern __shared__ u32x4 smem[];
+    RowEnt* tab0 = reinterpret_cast<RowEnt*>(smem);
+    RowEnt* tab1 = tab0 + max_rows;
+    T* tile = reinterpret_cast<T*>(smem + 2 * max_rows);
+    const uint32_t total = unit_start[count], g = gridDim.x, b = blockIdx.x;
+    const uint32_t u0 = uint32_t(uint64_t(b) * total / g), u1 = uint32_t(uint64_t(b + 1) * total / g);
+    auto get = [&](uint32_t u, GatherDesc& dd, uint32_t& lu) {
+        const uint32_t p = find_problem(unit_start, count, u);
+        dd = descs[p];
+        lu = u - unit_start[p];
+    };
+    wide_pipeline<T, M>(u0, u1, get, tab0, tab1, max_rows, tile, nt != 0);
+}
+
 // ---------------------------------------------------------------- host side
 
 namespace {
 
 typedef void (*PlainFn)(GatherDesc, int);
-typedef void (*BatchFn)(const GatherDesc*, const uint32_t*, uint32_t, int);
-
-template <typename T, int S>
-PlainFn pick_plain_s(int variant, int U)
-{
-    if (variant == LFBP_GATHER_DIRECT) return U >= 2 ? k_direct<T, S, 2> : k_direct<T, S, 1>;
-    return U >= 2 ? k_staged<T, S, 2> : k_staged<T, S, 1>;
-}
-
-template <typename T, int S>
-BatchFn pick_batch_s(int variant, int U)
-{
-    if (variant == LFBP_GATHER_DIRECT) return U >= 2 ? k_direct_batched<T, S, 2> : k_direct_batched<T, S, 1>;
-    return U >= 2 ? k_staged_batched<T, S, 2> : k_staged_batched<T, S, 1>;
-}
+typedef void (*BatchFn)(const GatherDesc*, const uint32_t*, uint32_t, uint32_t, int);
 
 // S = 64-element segments per row loaded per step: enough to cover a row of
 // W elements in one step up to W = 1024, in batches of 16 beyond that.
@@ -289,84 +523,119 @@ int segments_for(uint32_t W)
 }
 
 template <typename T>
-PlainFn pick_plain(int variant, uint32_t W, int U)
+PlainFn pick_plain(const LaunchPlan& p, uint32_t W)
 {
+    const bool U2 = p.rows_in_flight >= 2;
+    if (p.variant == LFBP_GATHER_WIDE) {
+        const bool pers = p.persistent == 1;
+        switch (p.vec_per_thread) {
+            case 2: return pers ? k_wide_persist<T, 2> : k_wide<T, 2>;
+            case 4: return pers ? k_wide_persist<T, 4> : k_wide<T, 4>;
+            default: return pers ? k_wide_persist<T, 8> : k_wide<T, 8>;
+        }
+    }
+    const bool direct = p.variant == LFBP_GATHER_DIRECT;
     switch (segments_for(W)) {
-        case 2: return pick_plain_s<T, 2>(variant, U);
-        case 4: return pick_plain_s<T, 4>(variant, U);
-        case 8: return pick_plain_s<T, 8>(variant, U);
-        default: return pick_plain_s<T, 16>(variant, U);
+        case 2: return direct ? (U2 ? k_direct<T, 2, 2> : k_direct<T, 2, 1>) : (U2 ? k_staged<T, 2, 2> : k_staged<T, 2, 1>);
+        case 4: return direct ? (U2 ? k_direct<T, 4, 2> : k_direct<T, 4, 1>) : (U2 ? k_staged<T, 4, 2> : k_staged<T, 4, 1>);
+        case 8: return direct ? (U2 ? k_direct<T, 8, 2> : k_direct<T, 8, 1>) : (U2 ? k_staged<T, 8, 2> : k_staged<T, 8, 1>);
+        default:
+            return direct ? (U2 ? k_direct<T, 16, 2> : k_direct<T, 16, 1>) : (U2 ? k_staged<T, 16, 2> : k_staged<T, 16, 1>);
     }
 }
 
 template <typename T>
-BatchFn pick_batch(int variant, uint32_t W, int U)
+BatchFn pick_batch(const LaunchPlan& p, uint32_t W)
 {
-    switch (segments_for(W)) {
-        case 2: return pick_batch_s<T, 2>(variant, U);
-        case 4: return pick_batch_s<T, 4>(variant, U);
-        case 8: return pick_batch_s<T, 8>(variant, U);
-        default: return pick_batch_s<T, 16>(variant, U);
+    const bool U2 = p.rows_in_flight >= 2;
+    if (p.variant == LFBP_GATHER_WIDE) {
+        const bool pers = p.persistent == 1;
+        switch (p.vec_per_thread) {
+            case 2: return pers ? k_wide_batched_persist<T, 2> : k_wide_batched<T, 2>;
+            case 4: return pers ? k_wide_batched_persist<T, 4> : k_wide_batched<T, 4>;
+            default: return pers ? k_wide_batched_persist<T, 8> : k_wide_batched<T, 8>;
+        }
     }
+    const bool direct = p.variant == LFBP_GATHER_DIRECT;
+    switch (segments_for(W)) {
+        case 2:
+            return direct ? (U2 ? k_direct_batched<T, 2, 2> : k_direct_batched<T, 2, 1>)
+                          : (U2 ? k_staged_batched<T, 2, 2> : k_staged_batched<T, 2, 1>);
+        case 4:
+            return direct ? (U2 ? k_direct_batched<T, 4, 2> : k_direct_batched<T, 4, 1>)
+                          : (U2 ? k_staged_batched<T, 4, 2> : k_staged_batched<T, 4, 1>);
+        case 8:
+            return direct ? (U2 ? k_direct_batched<T, 8, 2> : k_direct_batched<T, 8, 1>)
+                          : (U2 ? k_staged_batched<T, 8, 2> : k_staged_batched<T, 8, 1>);
+        default:
+            return direct ? (U2 ? k_direct_batched<T, 16, 2> : k_direct_batched<T, 16, 1>)
+                          : (U2 ? k_staged_batched<T, 16, 2> : k_staged_batched<T, 16, 1>);
+    }
+}
+
+PlainFn pick_plain_any(const LaunchPlan& p, uint32_t W, int esize)
+{
+    return esize == 4 ? pick_plain<uint32_t>(p, W) : pick_plain<uint16_t>(p, W);
+}
+
+BatchFn pick_batch_any(const LaunchPlan& p, uint32_t W, int esize)
+{
+    return esize == 4 ? pick_batch<uint32_t>(p, W) : pick_batch<uint16_t>(p, W);
+}
+
+template <typename T>
+void all_lds_kernels(std::vector<const void*>& out)
+{
+    const void* k[] = {
+        (const void*)k_staged<T, 2, 1>,       (const void*)k_staged<T, 2, 2>,       (const void*)k_staged<T, 4, 1>,
+        (const void*)k_staged<T, 4, 2>,       (const void*)k_staged<T, 8, 1>,       (const void*)k_staged<T, 8, 2>,
+        (const void*)k_staged<T, 16, 1>,      (const void*)k_staged<T, 16, 2>,      (const void*)k_staged_batched<T, 2, 1>,
+        (const void*)k_staged_batched<T, 2, 2>,  (const void*)k_staged_batched<T, 4, 1>,
+        (const void*)k_staged_batched<T, 4, 2>,  (const void*)k_staged_batched<T, 8, 1>,
+        (const void*)k_staged_batched<T, 8, 2>,  (const void*)k_staged_batched<T, 16, 1>,
+        (const void*)k_staged_batched<T, 16, 2>, (const void*)k_wide<T, 2>,
+        (const void*)k_wide<T, 4>,            (const void*)k_wide<T, 8>,            (const void*)k_wide_persist<T, 2>,
+        (const void*)k_wide_persist<T, 4>,    (const void*)k_wide_persist<T, 8>,    (const void*)k_wide_batched<T, 2>,
+        (const void*)k_wide_batched<T, 4>,    (const void*)k_wide_batched<T, 8>,
+        (const void*)k_wide_batched_persist<T, 2>, (const void*)k_wide_batched_persist<T, 4>,
+        (const void*)k_wide_batched_persist<T, 8>,
+    };
+    out.insert(out.end(), std::begin(k), std::end(k));
 }
 
 }  // namespace
 
-// Launch one problem.  The plan is fully resolved; d.rows_per_unit/nunits set.
 hipError_t launch_gather(const GatherDesc& d, int esize, const LaunchPlan& p, hipStream_t stream)
 {
-    PlainFn fn = esize == 4 ? pick_plain<uint32_t>(p.variant, d.W, p.rows_in_flight)
-                            : pick_plain<uint16_t>(p.variant, d.W, p.rows_in_flight);
-    const size_t shmem = p.variant == LFBP_GATHER_STAGED ? size_t(p.tile_bytes) : 0;
-    hipLaunchKernelGGL(fn, dim3(p.grid), dim3(p.threads), shmem, stream, d, p.nontemporal == 1 ? 1 : 0);
+    PlainFn fn = pick_plain_any(p, d.W, esize);
+    hipLaunchKernelGGL(fn, dim3(p.grid), dim3(p.threads), size_t(p.lds_bytes), stream, d, p.nontemporal == 1 ? 1 : 0);
     return hipGetLastError();
 }
 
-// Launch a batch.  All problems share variant, threads, U and S (the largest W
-// of the batch picks S); descs and unit_start live in device memory.
 hipError_t launch_gather_batched(const GatherDesc* descs_dev, const uint32_t* unit_start_dev, uint32_t count,
-                                 uint32_t maxW, int esize, const LaunchPlan& p, hipStream_t stream)
+                                 uint32_t maxW, uint32_t max_rows, int esize, const LaunchPlan& p, hipStream_t stream)
 {
-    BatchFn fn = esize == 4 ? pick_batch<uint32_t>(p.variant, maxW, p.rows_in_flight)
-                            : pick_batch<uint16_t>(p.variant, maxW, p.rows_in_flight);
-    const size_t shmem = p.variant == LFBP_GATHER_STAGED ? size_t(p.tile_bytes) : 0;
-    hipLaunchKernelGGL(fn, dim3(p.grid), dim3(p.threads), shmem, stream, descs_dev, unit_start_dev, count,
-                       p.nontemporal == 1 ? 1 : 0);
+    BatchFn fn = pick_batch_any(p, maxW, esize);
+    hipLaunchKernelGGL(fn, dim3(p.grid), dim3(p.threads), size_t(p.lds_bytes), stream, descs_dev, unit_start_dev,
+                       count, max_rows, p.nontemporal == 1 ? 1 : 0);
     return hipGetLastError();
 }
 
-// Workgroups of the batched kernel that fit one CU at once.
-int batched_occupancy(int variant, uint32_t maxW, int esize, int U, int threads, int smem)
+// Workgroups of a kernel that fit one CU at once.
+int gather_occupancy(const LaunchPlan& p, uint32_t W, int esize, bool batched)
 {
-    BatchFn fn = esize == 4 ? pick_batch<uint32_t>(variant, maxW, U) : pick_batch<uint16_t>(variant, maxW, U);
+    const void* fn = batched ? reinterpret_cast<const void*>(pick_batch_any(p, W, esize))
+                             : reinterpret_cast<const void*>(pick_plain_any(p, W, esize));
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(fn), threads, size_t(smem)) !=
-        hipSuccess)
-        return 1;
-    return n;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, p.threads, size_t(p.lds_bytes)) != hipSuccess) return 1;
+    return n < 1 ? 1 : n;
 }
 
 hipError_t set_gather_smem_limits(int max_bytes)
 {
-    // Allow the staged kernels to use up to max_bytes of dynamic LDS.
-    const void* fns[] = {
-        (const void*)k_staged<uint32_t, 2, 1>,  (const void*)k_staged<uint32_t, 2, 2>,
-        (const void*)k_staged<uint32_t, 4, 1>,  (const void*)k_staged<uint32_t, 4, 2>,
-        (const void*)k_staged<uint32_t, 8, 1>,  (const void*)k_staged<uint32_t, 8, 2>,
-        (const void*)k_staged<uint32_t, 16, 1>, (const void*)k_staged<uint32_t, 16, 2>,
-        (const void*)k_staged<uint16_t, 2, 1>,  (const void*)k_staged<uint16_t, 2, 2>,
-        (const void*)k_staged<uint16_t, 4, 1>,  (const void*)k_staged<uint16_t, 4, 2>,
-        (const void*)k_staged<uint16_t, 8, 1>,  (const void*)k_staged<uint16_t, 8, 2>,
-        (const void*)k_staged<uint16_t, 16, 1>, (const void*)k_staged<uint16_t, 16, 2>,
-        (const void*)k_staged_batched<uint32_t, 2, 1>,  (const void*)k_staged_batched<uint32_t, 2, 2>,
-        (const void*)k_staged_batched<uint32_t, 4, 1>,  (const void*)k_staged_batched<uint32_t, 4, 2>,
-        (const void*)k_staged_batched<uint32_t, 8, 1>,  (const void*)k_staged_batched<uint32_t, 8, 2>,
-        (const void*)k_staged_batched<uint32_t, 16, 1>, (const void*)k_staged_batched<uint32_t, 16, 2>,
-        (const void*)k_staged_batched<uint16_t, 2, 1>,  (const void*)k_staged_batched<uint16_t, 2, 2>,
-        (const void*)k_staged_batched<uint16_t, 4, 1>,  (const void*)k_staged_batched<uint16_t, 4, 2>,
-        (const void*)k_staged_batched<uint16_t, 8, 1>,  (const void*)k_staged_batched<uint16_t, 8, 2>,
-        (const void*)k_staged_batched<uint16_t, 16, 1>, (const void*)k_staged_batched<uint16_t, 16, 2>,
-    };
+    std::vector<const void*> fns;
+    all_lds_kernels<uint32_t>(fns);
+    all_lds_kernels<uint16_t>(fns);
     for (const void* f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_bytes);
         if (e != hipSuccess) return e;

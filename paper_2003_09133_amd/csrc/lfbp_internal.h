@@ -59,6 +59,7 @@ LFBP_HD inline uint32_t fdiv(uint32_t n, const FastDiv& f)
 struct GatherDesc {
     const void* H;
     void* Ht;
+    uint64_t E;          // elements of H (and H')
     uint32_t ns, nt, nx, ny, nz;
     uint32_t W;          // ny*nz, elements per x-row
     uint32_t NB;         // ns*nt, number of blocks of nx x-rows
@@ -66,21 +67,35 @@ struct GatherDesc {
     uint32_t a_off;      // a(s') = (s' + a_off) mod nx
     uint32_t b_off;      // b(t') = (t' + b_off) mod ny
     FastDiv fnx, fny, fnt;
-    // work decomposition
-    uint32_t rows_per_unit;  // output x-rows per work unit
-    uint32_t nunits;         // ceil(nrows / rows_per_unit)
-    uint32_t phase_out;      // (address of Ht / element size) mod (16 / element size)
+    // work decomposition: a work unit is rows_per_unit consecutive output x-rows
+    uint32_t rows_per_unit;
+    uint32_t nunits;
+    uint32_t phase_in;   // (address of H  / element size) mod (16 / element size)
+    uint32_t phase_out;  // (address of Ht / element size) mod (16 / element size)
+    uint32_t vpr;        // WIDE: 16-byte vectors reserved per x-row
+    FastDiv fvpr;
+    uint32_t xcd_remap;  // 1: spread consecutive units over one XCD (one workgroup per unit)
     uint32_t pad;
 };
 
 // Kernel selection resolved by the host runtime.
 struct LaunchPlan {
-    int variant;        // LFBP_GATHER_DIRECT or LFBP_GATHER_STAGED
+    int variant;        // LFBP_GATHER_DIRECT, _STAGED or _WIDE
     int threads;        // workgroup size
-    int rows_in_flight; // rows per wavefront step (DIRECT) or per wave load batch (STAGED)
-    int tile_bytes;     // STAGED LDS bytes
+    int rows_in_flight; // DIRECT/STAGED: rows per wavefront step
+    int vec_per_thread; // WIDE: 16-byte loads per thread per unit
+    int lds_bytes;      // dynamic LDS per workgroup
     int nontemporal;    // 1 or 2
+    int persistent;     // 1: workgroups loop over units; 2: one workgroup per unit
     int grid;           // workgroups launched
+};
+
+// 16-byte row-table entry of the WIDE kernels: where an input x-row starts
+// (aligned down to a 16-byte vector) and by how much it rotates.
+struct RowEnt {
+    int64_t vbase;  // element index of the aligned vector holding the row's first element
+    uint32_t lead;  // row start - vbase
+    uint32_t rot;   // left rotation of the row, elements
 };
 
 }  // namespace lfbp

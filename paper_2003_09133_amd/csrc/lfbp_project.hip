@@ -88,7 +88,11 @@ static ProjShape proj_shape(const lfbp_shape& s, int64_t R, int64_t C)
     return p;
 }
 
-hipError_t project_init() { return hipSuccess; }
+hipError_t project_init(int max_lds)
+{
+    (void)max_lds;
+    return hipSuccess;
+}
 
 hipError_t launch_forward(const float* H, const lfbp_shape& s, const float* g, int64_t R, int64_t C, float* f,
                           hipStream_t stream)

@@ -2,10 +2,11 @@
 //
 // The table is a text file written by the autotuner
 // (paper_2003_09133_amd/autotune.py): one entry per line,
-//   <esize> <W> <nx> <variant> <threads> <rows_in_flight> <tile_bytes> <nontemporal> <grid>
+//   <batched 0|1> <esize> <W> <nx> <variant> <threads> <rows_in_flight> <tile_bytes>
+//   <vec_per_thread> <nontemporal> <persistent> <grid>
 // '#' starts a comment.  It is read once, from $LFBP_TUNE_TABLE if set, else
 // from lfbp_tune.txt next to liblfbp.so.  Shapes without an entry use the
-// defaults below.
+// built-in defaults below.
 #include "lfbp_tune.h"
 
 #include <dlfcn.h>
@@ -17,12 +18,14 @@
 #include <string>
 #include <vector>
 
+#include "lfbp_validate.h"
+
 namespace lfbp {
 
 namespace {
 
 struct Entry {
-    int esize, W, nx;
+    int batched, esize, W, nx;
     lfbp_gather_config cfg;
 };
 
@@ -52,15 +55,14 @@ void load_table()
         if (hash) *hash = 0;
         Entry e;
         std::memset(&e, 0, sizeof(e));
-        const int n = std::sscanf(line, "%d %d %d %d %d %d %d %d %d", &e.esize, &e.W, &e.nx, &e.cfg.variant,
-                                  &e.cfg.block_threads, &e.cfg.rows_in_flight, &e.cfg.tile_bytes,
-                                  &e.cfg.nontemporal, &e.cfg.grid);
-        if (n != 9) continue;
-        const lfbp_gather_config& c = e.cfg;
-        const bool ok = (c.variant == LFBP_GATHER_DIRECT || c.variant == LFBP_GATHER_STAGED) &&
-                        c.block_threads >= 64 && c.block_threads <= 512 && c.block_threads % 64 == 0 &&
-                        (c.rows_in_flight == 1 || c.rows_in_flight == 2) && c.tile_bytes >= 0 &&
-                        c.tile_bytes <= 65536 && (c.nontemporal == 1 || c.nontemporal == 2) && c.grid >= 0;
+        lfbp_gather_config& c = e.cfg;
+        const int n = std::sscanf(line, "%d %d %d %d %d %d %d %d %d %d %d %d", &e.batched, &e.esize, &e.W, &e.nx,
+                                  &c.variant, &c.block_threads, &c.rows_in_flight, &c.tile_bytes,
+                                  &c.vec_per_thread, &c.nontemporal, &c.persistent, &c.grid);
+        if (n != 12) continue;
+        const bool ok = c.variant >= LFBP_GATHER_DIRECT && c.variant <= LFBP_GATHER_WIDE && c.block_threads > 0 &&
+                        c.rows_in_flight > 0 && c.vec_per_thread > 0 && c.nontemporal > 0 && c.persistent > 0 &&
+                        check_config(&c) == LFBP_OK;
         if (ok) g_table.push_back(e);
     }
     std::fclose(fh);
@@ -68,18 +70,20 @@ void load_table()
 
 }  // namespace
 
-lfbp_gather_config tuned_config(const lfbp_shape& s, int esize)
+lfbp_gather_config tuned_config(const lfbp_shape& s, int esize, bool batched)
 {
     std::call_once(g_once, load_table);
     const int W = int(s.ny * s.nz), nx = int(s.nx);
     for (const Entry& e : g_table)
-        if (e.esize == esize && e.W == W && e.nx == nx) return e.cfg;
+        if (e.batched == int(batched) && e.esize == esize && e.W == W && e.nx == nx) return e.cfg;
     lfbp_gather_config c;
-    c.variant = LFBP_GATHER_STAGED;
+    c.variant = LFBP_GATHER_WIDE;
     c.block_threads = 256;
     c.rows_in_flight = 2;
-    c.tile_bytes = 32768;
+    c.tile_bytes = 16384;
+    c.vec_per_thread = 4;
     c.nontemporal = 1;
+    c.persistent = batched ? 1 : 2;
     c.grid = 0;
     return c;
 }

@@ -6,8 +6,9 @@
 namespace lfbp {
 
 // The configuration for one problem: an entry of the tuning table when one
-// matches (dtype, W = ny*nz, nx), else the built-in defaults.  Every field is
-// set (grid may be 0 = one workgroup per work unit).
-lfbp_gather_config tuned_config(const lfbp_shape& s, int esize);
+// matches (batched or plain, element size, W = ny*nz, nx), else the built-in
+// defaults.  Every field is set except grid, which may be 0 (= one workgroup
+// per unit, or every workgroup slot of the device when persistent).
+lfbp_gather_config tuned_config(const lfbp_shape& s, int esize, bool batched);
 
 }  // namespace lfbp

@@ -69,24 +69,29 @@ lfbp_status check_gather(const void* H, const void* Ht, const lfbp_shape& s, lfb
 lfbp_status check_config(const lfbp_gather_config* c)
 {
     if (!c) return LFBP_OK;
-    if (c->variant < 0 || c->variant > LFBP_GATHER_STAGED) return LFBP_EINVAL;
+    if (c->variant < 0 || c->variant > LFBP_GATHER_WIDE) return LFBP_EINVAL;
     if (c->block_threads != 0 && (c->block_threads < 64 || c->block_threads > 512 || c->block_threads % 64))
         return LFBP_EINVAL;
     if (c->rows_in_flight != 0 && c->rows_in_flight != 1 && c->rows_in_flight != 2) return LFBP_EINVAL;
     if (c->tile_bytes < 0 || c->tile_bytes > 65536) return LFBP_EINVAL;
+    if (c->vec_per_thread != 0 && c->vec_per_thread != 2 && c->vec_per_thread != 4 && c->vec_per_thread != 8)
+        return LFBP_EINVAL;
     if (c->nontemporal < 0 || c->nontemporal > 2) return LFBP_EINVAL;
+    if (c->persistent < 0 || c->persistent > 2) return LFBP_EINVAL;
     if (c->grid < 0) return LFBP_EINVAL;
     return LFBP_OK;
 }
 
-lfbp_status check_project(const float* psf, const lfbp_shape& s, const float* in2, int64_t in2_elems, int64_t R,
-                          int64_t C, const float* out, int64_t out_elems)
+lfbp_status check_project(const float* psf, const lfbp_shape& s, const float* in2, int64_t R, int64_t C,
+                          const float* out, bool forward)
 {
     if (!psf || !in2 || !out) return LFBP_EINVAL;
     if (R < 1 || C < 1) return LFBP_EINVAL;
     const lfbp_status st = check_shape(s, 4);
     if (st != LFBP_OK) return st;
     if (mul_sat(mul_sat(uint64_t(R), uint64_t(C)), uint64_t(s.nz)) >= LIM31) return LFBP_ESHAPE;
+    const int64_t image = R * C, volume = image * s.nz;
+    const int64_t in2_elems = forward ? volume : image, out_elems = forward ? image : volume;
     const uintptr_t a = reinterpret_cast<uintptr_t>(psf), b = reinterpret_cast<uintptr_t>(in2),
                     c = reinterpret_cast<uintptr_t>(out);
     if (a % 4 || b % 4 || c % 4) return LFBP_EALIGN;

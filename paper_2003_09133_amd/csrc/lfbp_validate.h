@@ -20,10 +20,10 @@ lfbp_status check_gather(const void* H, const void* Ht, const lfbp_shape& s, lfb
 // Configuration fields (0 = tuned default is always accepted).
 lfbp_status check_config(const lfbp_gather_config* cfg);
 
-// Full check of one projector call: in1 (H or Ht), in2 (g or f) read, out written.
-// in2_elems and out_elems are the element counts of the second input and the output.
-lfbp_status check_project(const float* psf, const lfbp_shape& s, const float* in2, int64_t in2_elems, int64_t R,
-                          int64_t C, const float* out, int64_t out_elems);
+// Full check of one projector call.  forward: psf = H, in2 = g [nz][R][C],
+// out = f [R][C]; else psf = H', in2 = f [R][C], out = g [nz][R][C].
+lfbp_status check_project(const float* psf, const lfbp_shape& s, const float* in2, int64_t R, int64_t C,
+                          const float* out, bool forward);
 
 // True when [a, a+na) and [b, b+nb) (bytes) overlap.
 bool ranges_overlap(const void* a, uint64_t na, const void* b, uint64_t nb);

@@ -71,8 +71,9 @@ def test_null_dtype_alias_align():
 
 def test_bad_config_fields():
     L = _abi.lib()
-    for field, val in [("variant", 3), ("block_threads", 96), ("block_threads", 1024),
-                       ("rows_in_flight", 3), ("tile_bytes", 70000), ("nontemporal", 3), ("grid", -1)]:
+    for field, val in [("variant", 4), ("block_threads", 96), ("block_threads", 1024),
+                       ("rows_in_flight", 3), ("tile_bytes", 70000), ("vec_per_thread", 3),
+                       ("vec_per_thread", 16), ("nontemporal", 3), ("persistent", 3), ("grid", -1)]:
         c = GatherConfig()
         setattr(c, field, val)
         assert L.lfbp_compute_Ht_config(P1, P2, GOOD, _abi.F32, ctypes.byref(c), None) == _abi.EINVAL, field
@@ -87,7 +88,7 @@ def test_default_config_resolves_every_field():
         assert L.lfbp_default_config(shape, dt, ctypes.byref(c)) == _abi.OK
         d = c.as_dict()
         assert all(v > 0 for v in d.values()), d
-        assert d["variant"] in (_abi.GATHER_DIRECT, _abi.GATHER_STAGED)
+        assert d["variant"] in (_abi.GATHER_DIRECT, _abi.GATHER_STAGED, _abi.GATHER_WIDE)
     c = GatherConfig()
     assert L.lfbp_default_config(Shape(4, 3, 3, 3, 3), _abi.F32, ctypes.byref(c)) == _abi.ESHAPE
     assert L.lfbp_default_config(GOOD, 9, ctypes.byref(c)) == _abi.EDTYPE

@@ -1,0 +1,105 @@
+"""Batched H' (one launch for many PSF arrays) against the CPU oracle."""
+import numpy as np
+import pytest
+import torch
+
+import lfsynth
+import oracle
+import paper_2003_09133_amd as lf
+from gpu_util import DEV, assert_same_bits, gpu_equal_bits, sample_indices, to_dev
+
+pytestmark = pytest.mark.gpu
+
+BATCH_CONFIGS = [
+    None,
+    {"variant": lf.GATHER_WIDE, "persistent": 1, "grid": 3, "vec_per_thread": 2},
+    {"variant": lf.GATHER_WIDE, "persistent": 2, "vec_per_thread": 8, "block_threads": 512},
+    {"variant": lf.GATHER_STAGED, "persistent": 1, "tile_bytes": 8192},
+    {"variant": lf.GATHER_STAGED, "persistent": 2},
+    {"variant": lf.GATHER_DIRECT, "persistent": 1, "grid": 11, "rows_in_flight": 1},
+]
+
+
+def mixed_shapes(seed, n):
+    rng = np.random.default_rng(seed)
+    odd = lambda lo, hi: int(rng.integers(lo, hi + 1)) | 1
+    return [(odd(1, 61), odd(1, 61), odd(1, 13), odd(1, 13), int(rng.integers(1, 30))) for _ in range(n)]
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float16])
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_mixed_batch_all_configs(dtype, use_graph):
+    shapes = mixed_shapes(3, 9) + [(1, 1, 1, 1, 1), (63, 63, 7, 7, 9), (3, 3, 1, 3, 700)]
+    Hs = [lfsynth.bits(s, i + 100, dtype) for i, s in enumerate(shapes)]
+    refs = [oracle.Ht_rows(H) for H in Hs]
+    dHs = [to_dev(H) for H in Hs]
+    for cfg in BATCH_CONFIGS:
+        outs = lf.compute_Ht_batched(dHs, config=cfg, use_graph=use_graph)
+        torch.cuda.synchronize()
+        for i, (o, r) in enumerate(zip(outs, refs)):
+            assert_same_bits(o.cpu().numpy(), r, f"set {i} {shapes[i]} {cfg} graph={use_graph}")
+
+
+def test_single_problem_batch_equals_plain():
+    H = to_dev(lfsynth.bits((45, 39, 9, 7, 13), 5, np.float32))
+    (o,) = lf.compute_Ht_batched([H])
+    assert gpu_equal_bits(o, lf.compute_Ht(H))
+
+
+def test_graph_replays_follow_new_data():
+    """The plan (descriptor table + graph) is reused for the same table; every
+    replay reads the current contents, with unrelated eager work and
+    synchronisations between replays."""
+    shapes = [(21, 21, 7, 7, 5), (33, 27, 11, 9, 3), (15, 15, 3, 3, 11)]
+    dHs = [torch.empty(s, dtype=torch.float32, device=DEV) for s in shapes]
+    outs = [torch.empty_like(h) for h in dHs]
+    scratch = torch.zeros(1 << 20, device=DEV)
+    for rep in range(4):
+        hs = [lfsynth.bits(s, 1000 * rep + i, np.float32) for i, s in enumerate(shapes)]
+        for d, h in zip(dHs, hs):
+            d.copy_(torch.from_numpy(h))
+        lf.compute_Ht_batched(dHs, outs)
+        scratch.add_(1.0)                                  # eager work between replays
+        torch.cuda.synchronize()
+        for o, h in zip(outs, hs):
+            assert_same_bits(o.cpu().numpy(), oracle.Ht_rows(h), f"replay {rep}")
+        lf.compute_Ht(dHs[0])                              # plain calls interleaved
+    lf.release_plans()
+    lf.compute_Ht_batched(dHs, outs)
+    torch.cuda.synchronize()
+    assert_same_bits(outs[1].cpu().numpy(), oracle.Ht_rows(hs[1]), "after release")
+
+
+def test_batch_rejects_mixed_dtypes_and_overlap():
+    a = torch.zeros((5, 5, 3, 3, 2), device=DEV)
+    b = torch.zeros((5, 5, 3, 3, 2), device=DEV, dtype=torch.float16)
+    with pytest.raises(TypeError):
+        lf.compute_Ht_batched([a, b])
+    with pytest.raises(lf.LfbpError):
+        lf.compute_Ht_batched([a, a.clone()], outs=[a.clone(), a])   # output 1 is input 0
+
+
+def test_sixteen_set_table_full_size():
+    """The 16-set batch at full size (25.9 GB in, 25.9 GB out): sampled oracle
+    check per set, equality with 16 plain launches, and reversibility."""
+    dHs, shapes = [], []
+    for w in lfsynth.BATCHED_SETS:
+        dHs.append(to_dev(lfsynth.bits(w.shape, w.seed, np.float32)))
+        shapes.append(w.shape)
+    outs = lf.compute_Ht_batched(dHs)
+    torch.cuda.synchronize()
+    for i, (w, o) in enumerate(zip(lfsynth.BATCHED_SETS, outs)):
+        H = lfsynth.bits(w.shape, w.seed, np.float32)
+        idx = sample_indices(H.size, 200_000, i)
+        got = o.view(-1)[torch.from_numpy(idx).to(DEV)].cpu().numpy()
+        assert_same_bits(got, oracle.Ht_at(H, idx), f"set {i} {w.shape}")
+        del H
+    plain = torch.empty_like(outs[0])
+    for i, (h, o) in enumerate(zip(dHs, outs)):
+        plain = torch.empty_like(h)
+        lf.compute_Ht_into(h, plain)
+        assert gpu_equal_bits(plain, o), f"set {i}: batched != plain"
+    del plain
+    back = lf.compute_Ht_batched(outs)
+    for i, (h, b) in enumerate(zip(dHs, back)):
+        assert gpu_equal_bits(h, b), f"set {i} not reversible"

@@ -21,10 +21,14 @@ CONFIGS = [
     None,
     {"variant": lf.GATHER_DIRECT, "rows_in_flight": 1},
     {"variant": lf.GATHER_DIRECT, "rows_in_flight": 2, "block_threads": 128},
+    {"variant": lf.GATHER_DIRECT, "nontemporal": 2, "persistent": 1, "grid": 5, "block_threads": 64},
     {"variant": lf.GATHER_STAGED, "tile_bytes": 4096, "rows_in_flight": 1},
     {"variant": lf.GATHER_STAGED, "tile_bytes": 65536, "block_threads": 512},
-    {"variant": lf.GATHER_STAGED, "nontemporal": 2, "grid": 3},
-    {"variant": lf.GATHER_DIRECT, "nontemporal": 2, "grid": 5, "block_threads": 64},
+    {"variant": lf.GATHER_STAGED, "nontemporal": 2, "persistent": 1, "grid": 3},
+    {"variant": lf.GATHER_WIDE, "vec_per_thread": 2, "block_threads": 64},
+    {"variant": lf.GATHER_WIDE, "vec_per_thread": 8, "block_threads": 512, "nontemporal": 2},
+    {"variant": lf.GATHER_WIDE, "vec_per_thread": 4, "persistent": 1, "grid": 7},
+    {"variant": lf.GATHER_WIDE, "vec_per_thread": 2, "persistent": 1, "block_threads": 128},
 ]
 
 
@@ -69,14 +73,15 @@ def test_shapes_all_variants(shape):
             assert_same_bits(run(H, cfg), ref, f"{shape} {np.dtype(dtype).name} {cfg}")
 
 
-def test_row_too_wide_for_a_tile_falls_back_to_direct():
-    """ny*nz*4 bytes beyond the largest LDS tile: the staged request is served
-    by the direct kernel and stays exact."""
-    shape = (3, 3, 3, 3, 6000)
+@pytest.mark.parametrize("nz", [6000, 20000])
+def test_rows_wider_than_a_tile(nz):
+    """x-rows of 72 KB and 240 KB: the requested kernel hands over to one that
+    fits (WIDE -> STAGED -> DIRECT) and the result stays exact."""
+    shape = (3, 3, 3, 3, nz)
     H = lfsynth.bits(shape, 5, np.float32)
     ref = oracle.Ht_rows(H)
-    assert_same_bits(run(H, {"variant": lf.GATHER_STAGED}), ref, "wide rows")
-    assert_same_bits(run(H), ref, "wide rows default")
+    for cfg in (None, {"variant": lf.GATHER_STAGED}, {"variant": lf.GATHER_WIDE, "persistent": 1}):
+        assert_same_bits(run(H, cfg), ref, f"wide rows {cfg}")
 
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float16])
@@ -96,7 +101,8 @@ def test_unaligned_views_and_no_writes_outside(dtype):
             canary = torch.full((E + 2 * ve + 64,), -7.0, dtype=tdt, device=DEV)
             dst = canary[32 + off_out:32 + off_out + E].view(shape)
             hin = src[off_in:off_in + E].view(shape)
-            for cfg in (None, {"variant": lf.GATHER_DIRECT}, {"variant": lf.GATHER_STAGED, "tile_bytes": 2048}):
+            for cfg in (None, {"variant": lf.GATHER_DIRECT}, {"variant": lf.GATHER_STAGED, "tile_bytes": 2048},
+                        {"variant": lf.GATHER_WIDE, "persistent": 1, "grid": 3, "vec_per_thread": 2}):
                 canary.fill_(-7.0)
                 lf.compute_Ht_into(hin, dst, config=cfg)
                 torch.cuda.synchronize()
