@@ -45,9 +45,11 @@ def parse():
 
 
 def kernel_source_sha() -> str:
+    """Digest of everything that decides which gather kernel runs and how."""
     h = hashlib.sha256()
-    for f in ("lfbp_gather.hip", "lfbp_internal.h"):
-        with open(os.path.join(ROOT, "paper_2003_09133_amd", "csrc", f), "rb") as fh:
+    for f in ("csrc/lfbp_gather.hip", "csrc/lfbp_internal.h", "csrc/lfbp_api.cpp", "csrc/lfbp_tune.cpp",
+              "lfbp_tune.txt"):
+        with open(os.path.join(ROOT, "paper_2003_09133_amd", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 

@@ -17,8 +17,7 @@
 namespace lfbp {
 
 hipError_t launch_gather(const GatherDesc& d, int esize, const LaunchPlan& p, hipStream_t stream);
-hipError_t launch_gather_batched(const GatherDesc* descs_dev, const uint32_t* unit_start_dev, uint32_t count,
-                                 uint32_t maxW, uint32_t max_rows, int esize, const LaunchPlan& p,
+hipError_t launch_gather_batched(const BatchArgs& a, uint32_t maxW, int esize, const LaunchPlan& p,
                                  hipStream_t stream);
 hipError_t set_gather_smem_limits(int max_bytes);
 int gather_occupancy(const LaunchPlan& p, uint32_t W, int esize, bool batched);
@@ -167,7 +166,7 @@ int grid_for(const lfbp_gather_config& c, LaunchPlan& p, uint32_t units, uint32_
 {
     if (c.persistent != 1) return int(units);
     int g = c.grid;
-    if (g <= 0) g = g_cus * gather_occupancy(p, W, es, batched);
+    if (g <= 0) g = g_cus * gather_occupancy(p, W, es, batched);  // a multiple of 8: one share per XCD
     return int(std::min<uint64_t>(uint64_t(g), units));
 }
 
@@ -179,9 +178,10 @@ struct BatchPlan {
     lfbp_dtype dtype = LFBP_F32;
     lfbp_gather_config key{};
     int use_graph = 1;
-    GatherDesc* descs_dev = nullptr;
+    GatherDesc* descs_dev = nullptr;      // only for batches beyond kInlineProblems
     uint32_t* unit_start_dev = nullptr;
-    uint32_t count = 0, maxW = 0, max_rows = 0;
+    uint32_t maxW = 0;
+    BatchArgs args{};
     LaunchPlan plan{};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -254,18 +254,31 @@ lfbp_status build_plan(BatchPlan& bp, const lfbp_problem* probs, int32_t count, 
     const uint32_t total = start[size_t(count)];
     LaunchPlan lp = make_plan(c, lds);
     lp.grid = grid_for(c, lp, total, maxW, es, true);
-    if (hipMalloc(reinterpret_cast<void**>(&bp.descs_dev), sizeof(GatherDesc) * size_t(count)) != hipSuccess)
-        return LFBP_ENOMEM;
-    if (hipMalloc(reinterpret_cast<void**>(&bp.unit_start_dev), sizeof(uint32_t) * (size_t(count) + 1)) != hipSuccess)
-        return LFBP_ENOMEM;
-    if (hipMemcpy(bp.descs_dev, descs.data(), sizeof(GatherDesc) * size_t(count), hipMemcpyHostToDevice) != hipSuccess)
-        return LFBP_EDEVICE;
-    if (hipMemcpy(bp.unit_start_dev, start.data(), sizeof(uint32_t) * (size_t(count) + 1), hipMemcpyHostToDevice) !=
-        hipSuccess)
-        return LFBP_EDEVICE;
-    bp.count = uint32_t(count);
+    BatchArgs& a = bp.args;
+    std::memset(&a, 0, sizeof(a));
+    a.count = uint32_t(count);
+    a.total = total;
+    a.max_rows = max_rows;
+    a.nt = c.nontemporal == 1 ? 1 : 0;
+    if (uint32_t(count) <= kInlineProblems) {
+        for (int32_t i = 0; i < count; ++i) a.d[i] = descs[size_t(i)];
+        for (int32_t i = 0; i <= count; ++i) a.start[i] = start[size_t(i)];
+    } else {
+        if (hipMalloc(reinterpret_cast<void**>(&bp.descs_dev), sizeof(GatherDesc) * size_t(count)) != hipSuccess)
+            return LFBP_ENOMEM;
+        if (hipMalloc(reinterpret_cast<void**>(&bp.unit_start_dev), sizeof(uint32_t) * (size_t(count) + 1)) !=
+            hipSuccess)
+            return LFBP_ENOMEM;
+        if (hipMemcpy(bp.descs_dev, descs.data(), sizeof(GatherDesc) * size_t(count), hipMemcpyHostToDevice) !=
+            hipSuccess)
+            return LFBP_EDEVICE;
+        if (hipMemcpy(bp.unit_start_dev, start.data(), sizeof(uint32_t) * (size_t(count) + 1),
+                      hipMemcpyHostToDevice) != hipSuccess)
+            return LFBP_EDEVICE;
+        a.table = bp.descs_dev;
+        a.table_start = bp.unit_start_dev;
+    }
     bp.maxW = maxW;
-    bp.max_rows = max_rows;
     bp.plan = lp;
     bp.dtype = dt;
     bp.use_graph = use_graph;
@@ -275,8 +288,7 @@ lfbp_status build_plan(BatchPlan& bp, const lfbp_problem* probs, int32_t count, 
         if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return LFBP_EDEVICE;
         hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            const hipError_t le =
-                launch_gather_batched(bp.descs_dev, bp.unit_start_dev, bp.count, bp.maxW, bp.max_rows, es, lp, cs);
+            const hipError_t le = launch_gather_batched(bp.args, bp.maxW, es, lp, cs);
             e = hipStreamEndCapture(cs, &bp.graph);
             if (le != hipSuccess) e = le;
         }
@@ -411,8 +423,7 @@ lfbp_status lfbp_compute_Ht_batched_config(const lfbp_problem* problems, int32_t
     if (plan->use_graph)
         e = hipGraphLaunch(plan->exec, s);
     else
-        e = launch_gather_batched(plan->descs_dev, plan->unit_start_dev, plan->count, plan->maxW, plan->max_rows,
-                                  dtype_size(dtype), plan->plan, s);
+        e = launch_gather_batched(plan->args, plan->maxW, dtype_size(dtype), plan->plan, s);
     return e == hipSuccess ? LFBP_OK : LFBP_EDEVICE;
 }
 

@@ -341,49 +341,60 @@ __device__ __forceinline__ void wide_unit(const GatherDesc& d, uint32_t unit, Ro
     lds_barrier();
 }
 
-// Persistent, software-pipelined: units [u0, u1) of one descriptor source.
-// Get(u) returns the descriptor and local unit of global unit u.
+// Persistent, software-pipelined walk over global units u_first,
+// u_first + stride, ... below total.  Get(u, desc, local) returns the
+// descriptor and the problem-local index of global unit u.
 template <typename T, int M, class Get>
-__device__ __forceinline__ void wide_pipeline(uint32_t u0, uint32_t u1, Get get, RowEnt* tab0, RowEnt* tab1,
-                                              uint32_t tab_rows, T* tile, bool nt)
+__device__ __forceinline__ void wide_pipeline(uint32_t u_first, uint32_t stride, uint32_t total, Get get,
+                                              RowEnt* tab0, RowEnt* tab1, T* tile, bool nt)
 {
     constexpr uint32_t VE = 16 / sizeof(T);
-    if (u0 >= u1) return;
-    (void)tab_rows;
+    if (u_first >= total) return;
     GatherDesc dc;
     uint32_t lc;
-    get(u0, dc, lc);
+    get(u_first, dc, lc);
     uint32_t R0 = lc * dc.rows_per_unit;
     uint32_t nr = min(dc.rows_per_unit, dc.nrows - R0);
     wide_table<T>(dc, R0, nr, tab0);
     lds_barrier();
     u32x4 v[M];
     wide_load<T, M>(dc, nr, tab0, v);
-    for (uint32_t u = u0; u < u1; ++u) {
-        RowEnt* tc = ((u - u0) & 1u) ? tab1 : tab0;
-        RowEnt* tn = ((u - u0) & 1u) ? tab0 : tab1;
+    bool flip = false;
+    for (uint32_t u = u_first; u < total; u += stride) {
+        RowEnt* tc = flip ? tab1 : tab0;
+        RowEnt* tn = flip ? tab0 : tab1;
+        flip = !flip;
         const uint64_t O0 = uint64_t(R0) * dc.W;
         const uint32_t lead = uint32_t((O0 + dc.phase_out) % VE);
         wide_scatter<T, M>(dc, nr, tc, v, tile, lead);
         GatherDesc dn;
         uint32_t ln = 0, Rn = 0, nn = 0;
-        const bool more = u + 1 < u1;
+        const bool more = uint64_t(u) + stride < total;
         if (more) {
-            get(u + 1, dn, ln);
+            get(u + stride, dn, ln);
             Rn = ln * dn.rows_per_unit;
             nn = min(dn.rows_per_unit, dn.nrows - Rn);
             wide_table<T>(dn, Rn, nn, tn);
         }
-        lds_barrier();                               // tile and next table complete
-        if (more) wide_load<T, M>(dn, nn, tn, v);    // next unit's loads in flight ...
+        lds_barrier();                                    // tile and next table complete
+        if (more) wide_load<T, M>(dn, nn, tn, v);         // next unit's loads in flight ...
         emit_tile<T>(dc, O0, nr * dc.W, lead, tile, nt);  // ... while this tile is written
-        lds_barrier();                               // tile free again
+        lds_barrier();                                    // tile free again
         if (more) {
             dc = dn;
             R0 = Rn;
             nr = nn;
         }
     }
+}
+
+// First unit of workgroup b in a persistent grid of g workgroups: at every
+// step the grid covers a window of g consecutive units, and each XCD
+// (workgroups b = x mod 8) takes a contiguous eighth of the window.
+__device__ __forceinline__ uint32_t persistent_first(uint32_t b, uint32_t g)
+{
+    if (g & 7u) return b;
+    return (b & 7u) * (g >> 3) + (b >> 3);
 }
 
 // ---------------------------------------------------------------- entries
@@ -419,92 +430,92 @@ __global__ void __launch_bounds__(512) k_wide_persist(GatherDesc d, int nt)
     RowEnt* tab0 = reinterpret_cast<RowEnt*>(smem);
     RowEnt* tab1 = tab0 + d.rows_per_unit;
     T* tile = reinterpret_cast<T*>(smem + 2 * d.rows_per_unit);
-    const uint32_t n = d.nunits, g = gridDim.x, b = blockIdx.x;
-    const uint32_t u0 = uint32_t(uint64_t(b) * n / g), u1 = uint32_t(uint64_t(b + 1) * n / g);
     auto get = [&](uint32_t u, GatherDesc& dd, uint32_t& lu) {
         dd = d;
         lu = u;
     };
-    wide_pipeline<T, M>(u0, u1, get, tab0, tab1, d.rows_per_unit, tile, nt != 0);
+    wide_pipeline<T, M>(persistent_first(blockIdx.x, gridDim.x), gridDim.x, d.nunits, get, tab0, tab1, tile,
+                        nt != 0);
 }
 
-// Batched entries: unit_start[p] = first global unit of problem p,
-// unit_start[count] = total.
-__device__ __forceinline__ uint32_t find_problem(const uint32_t* unit_start, uint32_t count, uint32_t g)
+// Problem and problem-local unit of global unit g of a batch.  Up to
+// kInlineProblems descriptors travel in the kernel arguments (found with a
+// scalar scan, no dependent memory loads); larger batches use a device table
+// searched by bisection.
+__device__ __forceinline__ void batch_unit(const BatchArgs& a, uint32_t g, GatherDesc& d, uint32_t& local)
 {
-    uint32_t lo = 0, hi = count;  // unit_start[lo] <= g < unit_start[hi]
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (unit_start[mid] <= g)
-            lo = mid;
-        else
-            hi = mid;
+    if (a.table == nullptr) {
+        uint32_t p = 0;
+#pragma unroll
+        for (uint32_t i = 1; i < kInlineProblems; ++i)
+            if (i < a.count && a.start[i] <= g) p = i;
+        d = a.d[p];
+        local = g - a.start[p];
+    } else {
+        uint32_t lo = 0, hi = a.count;  // table_start[lo] <= g < table_start[hi]
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (a.table_start[mid] <= g)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        d = a.table[lo];
+        local = g - a.table_start[lo];
     }
-    return lo;
 }
 
 template <typename T, int S, int U>
-__global__ void __launch_bounds__(512)
-    k_direct_batched(const GatherDesc* descs, const uint32_t* unit_start, uint32_t count, uint32_t max_rows, int nt)
+__global__ void __launch_bounds__(512) k_direct_batched(BatchArgs a)
 {
-    (void)max_rows;
-    const uint32_t total = unit_start[count];
-    for (uint32_t g = blockIdx.x; g < total; g += gridDim.x) {
-        const uint32_t p = find_problem(unit_start, count, g);
-        const GatherDesc d = descs[p];
-        direct_unit<T, S, U>(d, g - unit_start[p], nt != 0);
+    for (uint32_t g = blockIdx.x; g < a.total; g += gridDim.x) {
+        GatherDesc d;
+        uint32_t lu;
+        batch_unit(a, g, d, lu);
+        direct_unit<T, S, U>(d, lu, a.nt != 0);
     }
 }
 
 template <typename T, int S, int U>
-__global__ void __launch_bounds__(512)
-    k_staged_batched(const GatherDesc* descs, const uint32_t* unit_start, uint32_t count, uint32_t max_rows, int nt)
+__global__ void __launch_bounds__(512) k_staged_batched(BatchArgs a)
 {
-    (void)max_rows;
     extern __shared__ u32x4 smem[];
     T* lds = reinterpret_cast<T*>(smem);
-    const uint32_t total = unit_start[count];
-    for (uint32_t g = blockIdx.x; g < total; g += gridDim.x) {
-        const uint32_t p = find_problem(unit_start, count, g);
-        const GatherDesc d = descs[p];
-        staged_unit<T, S, U>(d, g - unit_start[p], lds, nt != 0);
+    for (uint32_t g = blockIdx.x; g < a.total; g += gridDim.x) {
+        GatherDesc d;
+        uint32_t lu;
+        batch_unit(a, g, d, lu);
+        staged_unit<T, S, U>(d, lu, lds, a.nt != 0);
     }
 }
 
-// One workgroup per unit over all problems.  max_rows = largest rows_per_unit.
+// One workgroup per unit over all problems (units of one XCD contiguous when
+// the grid covers every unit).
 template <typename T, int M>
-__global__ void __launch_bounds__(512)
-    k_wide_batched(const GatherDesc* descs, const uint32_t* unit_start, uint32_t count, uint32_t max_rows, int nt)
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(M >= 8 ? 5 : 8))) k_wide_batched(BatchArgs a)
 {
     extern __shared__ u32x4 smem[];
     RowEnt* tab = reinterpret_cast<RowEnt*>(smem);
-    T* tile = reinterpret_cast<T*>(smem + max_rows);
-    const uint32_t total = unit_start[count];
-    for (uint32_t g = blockIdx.x; g < total; g += gridDim.x) {
-        const uint32_t p = find_problem(unit_start, count, g);
-        const GatherDesc d = descs[p];
-        wide_unit<T, M>(d, g - unit_start[p], tab, tile, nt != 0);
+    T* tile = reinterpret_cast<T*>(smem + a.max_rows);
+    for (uint32_t b = blockIdx.x; b < a.total; b += gridDim.x) {
+        GatherDesc d;
+        uint32_t lu;
+        batch_unit(a, unit_of_block(b, a.total, gridDim.x == a.total), d, lu);
+        wide_unit<T, M>(d, lu, tab, tile, a.nt != 0);
     }
 }
 
-// Persistent and pipelined over all problems: workgroup b owns the contiguous
-// global units [b*total/grid, (b+1)*total/grid).
+// Persistent and pipelined over all problems.
 template <typename T, int M>
-__global__ void __launch_bounds__(512) k_wide_batched_persist(const GatherDesc* descs, const uint32_t* unit_start,
-                                                              uint32_t count, uint32_t max_rows, int nt)
+__global__ void __launch_bounds__(512) k_wide_batched_persist(BatchArgs a)
 {
     extern __shared__ u32x4 smem[];
     RowEnt* tab0 = reinterpret_cast<RowEnt*>(smem);
-    RowEnt* tab1 = tab0 + max_rows;
-    T* tile = reinterpret_cast<T*>(smem + 2 * max_rows);
-    const uint32_t total = unit_start[count], g = gridDim.x, b = blockIdx.x;
-    const uint32_t u0 = uint32_t(uint64_t(b) * total / g), u1 = uint32_t(uint64_t(b + 1) * total / g);
-    auto get = [&](uint32_t u, GatherDesc& dd, uint32_t& lu) {
-        const uint32_t p = find_problem(unit_start, count, u);
-        dd = descs[p];
-        lu = u - unit_start[p];
-    };
-    wide_pipeline<T, M>(u0, u1, get, tab0, tab1, max_rows, tile, nt != 0);
+    RowEnt* tab1 = tab0 + a.max_rows;
+    T* tile = reinterpret_cast<T*>(smem + 2 * a.max_rows);
+    auto get = [&](uint32_t u, GatherDesc& dd, uint32_t& lu) { batch_unit(a, u, dd, lu); };
+    wide_pipeline<T, M>(persistent_first(blockIdx.x, gridDim.x), gridDim.x, a.total, get, tab0, tab1, tile,
+                        a.nt != 0);
 }
 
 // ---------------------------------------------------------------- host side
@@ -512,7 +523,7 @@ __global__ void __launch_bounds__(512) k_wide_batched_persist(const GatherDesc* 
 namespace {
 
 typedef void (*PlainFn)(GatherDesc, int);
-typedef void (*BatchFn)(const GatherDesc*, const uint32_t*, uint32_t, uint32_t, int);
+typedef void (*BatchFn)(BatchArgs);
 
 // S = 64-element segments per row loaded per step: enough to cover a row of
 // W elements in one step up to W = 1024, in batches of 16 beyond that.
@@ -612,12 +623,11 @@ hipError_t launch_gather(const GatherDesc& d, int esize, const LaunchPlan& p, hi
     return hipGetLastError();
 }
 
-hipError_t launch_gather_batched(const GatherDesc* descs_dev, const uint32_t* unit_start_dev, uint32_t count,
-                                 uint32_t maxW, uint32_t max_rows, int esize, const LaunchPlan& p, hipStream_t stream)
+hipError_t launch_gather_batched(const BatchArgs& a, uint32_t maxW, int esize, const LaunchPlan& p,
+                                 hipStream_t stream)
 {
     BatchFn fn = pick_batch_any(p, maxW, esize);
-    hipLaunchKernelGGL(fn, dim3(p.grid), dim3(p.threads), size_t(p.lds_bytes), stream, descs_dev, unit_start_dev,
-                       count, max_rows, p.nontemporal == 1 ? 1 : 0);
+    hipLaunchKernelGGL(fn, dim3(p.grid), dim3(p.threads), size_t(p.lds_bytes), stream, a);
     return hipGetLastError();
 }
 

@@ -90,6 +90,22 @@ struct LaunchPlan {
     int grid;           // workgroups launched
 };
 
+// Kernel arguments of a batched launch.  Up to kInlineProblems descriptors
+// travel by value (table == nullptr); larger batches point at a device table
+// of descriptors and unit prefix sums.
+constexpr uint32_t kInlineProblems = 16;
+
+struct BatchArgs {
+    const GatherDesc* table;     // device descriptor table, or nullptr
+    const uint32_t* table_start; // device: first global unit of each problem, count+1 entries
+    uint32_t count;              // problems
+    uint32_t total;              // work units of all problems
+    uint32_t max_rows;           // largest rows_per_unit (LDS table size)
+    uint32_t nt;                 // 1: streaming stores
+    uint32_t start[kInlineProblems + 1];
+    GatherDesc d[kInlineProblems];
+};
+
 // 16-byte row-table entry of the WIDE kernels: where an input x-row starts
 // (aligned down to a 16-byte vector) and by how much it rotates.
 struct RowEnt {

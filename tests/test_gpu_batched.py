@@ -103,3 +103,17 @@ def test_sixteen_set_table_full_size():
     back = lf.compute_Ht_batched(outs)
     for i, (h, b) in enumerate(zip(dHs, back)):
         assert gpu_equal_bits(h, b), f"set {i} not reversible"
+
+
+@pytest.mark.parametrize("n", [17, 40])
+def test_batch_beyond_inline_descriptors(n):
+    """More problems than travel in the kernel arguments: the device table path."""
+    shapes = mixed_shapes(11 + n, n)
+    Hs = [lfsynth.bits(s, 7 * i + 1, np.float32) for i, s in enumerate(shapes)]
+    dHs = [to_dev(H) for H in Hs]
+    for cfg in (None, {"variant": lf.GATHER_WIDE, "persistent": 2}, {"variant": lf.GATHER_STAGED},
+                {"variant": lf.GATHER_DIRECT, "persistent": 1, "grid": 9}):
+        outs = lf.compute_Ht_batched(dHs, config=cfg)
+        torch.cuda.synchronize()
+        for i, (o, H) in enumerate(zip(outs, Hs)):
+            assert_same_bits(o.cpu().numpy(), oracle.Ht_rows(H), f"{n} problems, set {i} {cfg}")
