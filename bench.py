@@ -187,6 +187,62 @@ def bench_batched(args, torch):
     return out
 
 
+def bench_projector(args, torch):
+    """One step = forward projection f = H g plus the backprojection of f
+    through the GPU-built H' (the two products of one gradient evaluation)."""
+    import numpy as np
+    import lfsynth
+    import paper_2003_09133_amd as lf
+
+    pw = lfsynth.PROJECTOR
+    H, _ = lfsynth.make_H(pw.psf)
+    R, C = pw.image
+    dev = torch.device("cuda:0")
+    dH = torch.from_numpy(H).to(dev)
+    dHt = lf.compute_Ht(dH)
+    g = torch.from_numpy(lfsynth.uniform_f32((pw.psf.shape[4], R, C), pw.g_seed)).to(dev)
+    f = torch.empty((R, C), device=dev)
+    gb = torch.empty_like(g)
+
+    def step():
+        lf.forward(dH, g, out=f)
+        lf.backward(dHt, f, out=gb)
+
+    t_fwd, _ = time_steps(lambda: lf.forward(dH, g, out=f), args.steps, args.warmup, torch)
+    t_bwd, _ = time_steps(lambda: lf.backward(dHt, f, out=gb), args.steps, args.warmup, torch)
+    elapsed, wall = time_steps(step, args.steps, args.warmup, torch)
+    sec = elapsed / args.steps
+    ns, nt, nx, ny, nz = pw.psf.shape
+    flop_proj = 2.0 * nz * R * C * ns * nt         # multiply-adds of one projection, no edge clipping
+    tflops_fwd = flop_proj / (t_fwd / args.steps) / 1e12
+    out = {
+        "metric": "projections/s (forward + backprojection pair)", "value": round(1.0 / sec, 2),
+        "unit": "pairs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(sec * 1e3, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"projector {R}x{C} px, {pw.lenslets}x{pw.lenslets} lenslets, "
+                               f"H{list(pw.psf.shape)} f32",
+                   "forward_ms": round(t_fwd / args.steps * 1e3, 4),
+                   "backward_ms": round(t_bwd / args.steps * 1e3, 4),
+                   "flop_per_projection": flop_proj, "wall_s": round(wall, 3)},
+        "roofline": {"bound": "mfma", "achieved": round(tflops_fwd, 2), "peak": FP32_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(tflops_fwd / FP32_PEAK_TFLOPS, 4), "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        nth = cores_used()
+        rng = np.random.default_rng(0)
+        pix = rng.integers(0, [R, C], size=(400, 2))
+        t0 = time.perf_counter()
+        oracle.forward_at(H, g.cpu().numpy(), pix, nthreads=nth)
+        dt = time.perf_counter() - t0
+        per_proj = dt * (R * C) / len(pix)
+        out["cpu_baseline"] = {"value": round(1.0 / (2 * per_proj), 6), "unit": "pairs/s", "cores": nth,
+                               "kind": "oracle", "sample": f"float64 oracle forward at {len(pix)} random pixels "
+                                                           f"({dt:.2f} s), scaled to a full forward+backward pair"}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -200,7 +256,7 @@ def main():
     if args.workload == "batched":
         out = bench_batched(args, torch)
     elif args.workload == "projector":
-        raise SystemExit("projector benchmark: not built yet")
+        out = bench_projector(args, torch)
     else:
         out = bench_plain(args, torch)
     print(json.dumps(out), flush=True)

@@ -1,0 +1,137 @@
+"""Forward projection f = H g and backprojection with the GPU-built H' against
+the float64 CPU oracle (relative L2 <= 1e-5), the dense measurement matrix on
+tiny grids, the adjoint identity, finite differences and autograd."""
+import numpy as np
+import pytest
+import torch
+
+import lfsynth
+import oracle
+import paper_2003_09133_amd as lf
+from gpu_util import DEV, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def rel_l2(got, ref):
+    got, ref = np.asarray(got, np.float64), np.asarray(ref, np.float64)
+    return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+
+SMALL = [((15, 15, 3, 3, 3), 21, 21), ((15, 15, 3, 3, 3), 20, 23), ((9, 7, 3, 5, 2), 12, 10),
+         ((5, 5, 5, 5, 1), 7, 8), ((7, 9, 1, 1, 3), 11, 9), ((1, 1, 1, 1, 2), 4, 5), ((3, 3, 7, 7, 2), 14, 21),
+         ((33, 25, 11, 5, 4), 55, 40), ((45, 45, 15, 15, 5), 90, 75), ((21, 21, 3, 3, 9), 8, 7)]
+
+
+@pytest.mark.parametrize("shape,R,C", SMALL)
+def test_forward_backward_vs_oracle(shape, R, C):
+    H = lfsynth.uniform_f32(shape, 1)
+    g = lfsynth.uniform_f32((shape[4], R, C), 2)
+    f = lfsynth.uniform_f32((R, C), 3)
+    dH = to_dev(H)
+    dHt = lf.compute_Ht(dH)
+    fg = lf.forward(dH, to_dev(g))
+    bg = lf.backward(dHt, to_dev(f))
+    torch.cuda.synchronize()
+    assert rel_l2(fg.cpu().numpy(), oracle.forward(H, g)) <= TOL
+    assert rel_l2(bg.cpu().numpy(), oracle.backward(H, f)) <= TOL
+
+
+@pytest.mark.parametrize("shape,R,C", [((5, 5, 3, 3, 2), 9, 12), ((7, 9, 3, 5, 1), 8, 11),
+                                       ((3, 3, 1, 1, 2), 5, 6)])
+def test_dense_matrix_and_its_transpose(shape, R, C):
+    """Tiny grids: the GPU forward is A g and the GPU backward (through H') is
+    A^T f for the explicitly built and transposed measurement matrix."""
+    H = lfsynth.uniform_f32(shape, 4)
+    g = lfsynth.uniform_f32((shape[4], R, C), 5)
+    f = lfsynth.uniform_f32((R, C), 6)
+    A = oracle.A_dense(H, R, C).astype(np.float64)
+    At = np.ascontiguousarray(A.T)
+    dH = to_dev(H)
+    fg = lf.forward(dH, to_dev(g)).cpu().numpy().ravel()
+    bg = lf.backward(lf.compute_Ht(dH), to_dev(f)).cpu().numpy().ravel()
+    assert rel_l2(fg, A @ g.astype(np.float64).ravel()) <= TOL
+    assert rel_l2(bg, At @ f.astype(np.float64).ravel()) <= TOL
+
+
+def test_adjoint_identity_on_gpu():
+    shape, R, C = (45, 45, 15, 15, 5), 120, 105
+    dH = to_dev(lfsynth.uniform_f32(shape, 7))
+    dHt = lf.compute_Ht(dH)
+    g = to_dev(lfsynth.uniform_f32((shape[4], R, C), 8))
+    f = to_dev(lfsynth.uniform_f32((R, C), 9))
+    lhs = torch.sum(lf.forward(dH, g).double() * f.double()).item()
+    rhs = torch.sum(g.double() * lf.backward(dHt, f).double()).item()
+    assert abs(lhs - rhs) / abs(lhs) <= TOL
+
+
+def crop_workload():
+    """An 8 x 8-lenslet crop of the projector workload: the microscope PSF,
+    120 x 120 px, 21 depths."""
+    w = lfsynth.MICROSCOPE
+    H, _ = lfsynth.make_H(w)
+    R = C = 8 * w.shape[2]
+    g = lfsynth.uniform_f32((w.shape[4], R, C), lfsynth.PROJECTOR.g_seed)
+    return H, g, R, C
+
+
+def test_crop_vs_oracle_and_finite_differences():
+    H, g, R, C = crop_workload()
+    dH, dg = to_dev(H), to_dev(g)
+    dHt = lf.compute_Ht(dH)
+    f = lf.forward(dH, dg)
+    torch.cuda.synchronize()
+    assert rel_l2(f.cpu().numpy(), oracle.forward(H, g)) <= TOL
+    # gradient of L(g) = <f(g), w> by autograd, against central differences
+    w = to_dev(lfsynth.uniform_f32((R, C), 10))
+    gg = dg.clone().requires_grad_(True)
+    loss = torch.sum(lf.LFProject.apply(gg, dH, dHt) * w)
+    loss.backward()
+    grad = gg.grad.double()
+    rng = np.random.default_rng(0)
+    for k in range(3):
+        e = torch.from_numpy(rng.standard_normal(g.shape).astype(np.float32)).to(DEV)
+        eps = 1.0                          # the map is linear: differences are exact up to rounding
+        lp = torch.sum(lf.forward(dH, dg + eps * e).double() * w.double())
+        lm = torch.sum(lf.forward(dH, dg - eps * e).double() * w.double())
+        fd = ((lp - lm) / (2 * eps)).item()
+        an = torch.sum(grad * e.double()).item()
+        scale = torch.sum(torch.abs(grad) * torch.abs(e.double())).item()
+        assert abs(fd - an) <= 1e-5 * scale, (k, fd, an)
+    # the autograd gradient is the backprojection of w through H'
+    assert rel_l2(grad.cpu().numpy(), oracle.backward(H, w.cpu().numpy())) <= TOL
+
+
+def test_project_builds_Ht_when_missing():
+    H, g, R, C = crop_workload()
+    dH = to_dev(H)
+    gg = to_dev(g).requires_grad_(True)
+    f = lf.project(gg, dH)
+    f.sum().backward()
+    ref = oracle.backward(H, np.ones((R, C), np.float32))
+    assert rel_l2(gg.grad.cpu().numpy(), ref) <= TOL
+
+
+def test_projector_workload_full_size_sampled():
+    """Full projector workload: 600 x 600 px, 40 x 40 lenslets, 21 depths, the
+    microscope PSF; checked at sampled pixels and voxels (borders included)."""
+    pw = lfsynth.PROJECTOR
+    H, _ = lfsynth.make_H(pw.psf)
+    R, C = pw.image
+    g = lfsynth.uniform_f32((pw.psf.shape[4], R, C), pw.g_seed)
+    dH = to_dev(H)
+    dHt = lf.compute_Ht(dH)
+    f = lf.forward(dH, to_dev(g))
+    fb = lf.backward(dHt, f)
+    torch.cuda.synchronize()
+    fn, fbn = f.cpu().numpy(), fb.cpu().numpy()
+    rng = np.random.default_rng(3)
+    pix = np.concatenate([rng.integers(0, [R, C], size=(1500, 2)),
+                          np.array([(0, 0), (R - 1, C - 1), (0, C - 1), (R - 1, 0), (R // 2, C // 2)])])
+    assert rel_l2(fn[pix[:, 0], pix[:, 1]], oracle.forward_at(H, g, pix)) <= TOL
+    vox = np.concatenate([np.column_stack([rng.integers(0, pw.psf.shape[4], 1500),
+                                           rng.integers(0, R, 1500), rng.integers(0, C, 1500)]),
+                          np.array([(0, 0, 0), (20, R - 1, C - 1), (10, 0, C - 1)])])
+    assert rel_l2(fbn[vox[:, 0], vox[:, 1], vox[:, 2]], oracle.backward_at(H, fn, vox)) <= TOL
