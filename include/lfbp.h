@@ -155,12 +155,28 @@ LFBP_API lfbp_status lfbp_compute_Ht_batched_config(const lfbp_problem* problems
  *             P = p-s+hs, Q = q-t+ht, terms with P, Q outside the image dropped.
  *
  * H  float32 [ns][nt][nx][ny][nz];  g float32 [nz][R][C];  f float32 [R][C],
- * overwritten.  Float32 arithmetic with float32 accumulation.
+ * overwritten.  Float32 products and sums on the matrix cores, with the
+ * running sums folded into a second float32 accumulator every few hundred
+ * terms and the split partial sums added in float64; results do not depend on
+ * scheduling (no atomics).
+ * Workspace: this call takes lfbp_forward_workspace_size() bytes from the
+ * stream-ordered allocator (hipMallocAsync) and returns them on the stream;
+ * lfbp_forward_ws uses caller memory instead and allocates nothing.
  * Errors EINVAL (null, R or C < 1), ESHAPE, EALIAS (f overlapping H or g),
- * EALIGN, EDEVICE.  Allocates nothing.
+ * EALIGN, ENOMEM, EDEVICE.
  */
 LFBP_API lfbp_status lfbp_forward(const float* H, lfbp_shape shape, const float* g, int64_t R, int64_t C, float* f,
-                         void* stream);
+                                  void* stream);
+
+/* Bytes of device workspace lfbp_forward_ws needs for this shape and image. */
+LFBP_API int64_t lfbp_forward_workspace_size(lfbp_shape shape, int64_t R, int64_t C);
+
+/* lfbp_forward with a caller-provided device workspace of at least
+ * lfbp_forward_workspace_size() bytes, 256-byte aligned, not overlapping H, g
+ * or f; its contents are scratch.  Errors as lfbp_forward, plus EINVAL when
+ * the workspace is NULL, too small or misaligned.  Allocates nothing. */
+LFBP_API lfbp_status lfbp_forward_ws(const float* H, lfbp_shape shape, const float* g, int64_t R, int64_t C,
+                                     float* f, void* workspace, int64_t workspace_bytes, void* stream);
 
 /*
  * lfbp_backward -- backprojection of an image into the volume with H'
@@ -172,7 +188,9 @@ LFBP_API lfbp_status lfbp_forward(const float* H, lfbp_shape shape, const float*
  * terms with the H' index outside 0..ns-1 / 0..nt-1 dropped.  With Ht from
  * lfbp_compute_Ht(H) this is exactly the adjoint of lfbp_forward(H).
  * Ht float32 [ns][nt][nx][ny][nz]; f float32 [R][C]; g float32 [nz][R][C],
- * overwritten.  Errors as lfbp_forward.  Allocates nothing.
+ * overwritten.  Float32 on the matrix cores with the two-level accumulation
+ * of lfbp_forward; deterministic.  Errors EINVAL, ESHAPE, EALIAS, EALIGN,
+ * EDEVICE.  Allocates nothing.
  */
 LFBP_API lfbp_status lfbp_backward(const float* Ht, lfbp_shape shape, const float* f, int64_t R, int64_t C, float* g,
                           void* stream);

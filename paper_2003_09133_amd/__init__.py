@@ -21,7 +21,8 @@ from . import _abi
 from ._abi import (F16, F32, GATHER_AUTO, GATHER_DIRECT, GATHER_STAGED, GATHER_WIDE, GatherConfig,
                    LfbpError, Problem, Shape)
 
-__all__ = ["compute_Ht", "compute_Ht_into", "compute_Ht_batched", "forward", "backward", "LFProject",
+__all__ = ["compute_Ht", "compute_Ht_into", "compute_Ht_batched", "forward", "forward_workspace_size",
+           "backward", "LFProject",
            "project", "default_config", "GatherConfig", "LfbpError", "release_plans", "version",
            "GATHER_AUTO", "GATHER_DIRECT", "GATHER_STAGED", "GATHER_WIDE"]
 
@@ -126,8 +127,15 @@ def _check_f32(t: torch.Tensor, name: str, dim: int):
         raise ValueError(f"{name} must be a contiguous float32 GPU tensor")
 
 
-def forward(H: torch.Tensor, g: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
-    """Forward projection f = H g: g [nz, R, C] -> f [R, C] (float32)."""
+def forward_workspace_size(shape, R: int, C: int) -> int:
+    """Bytes of scratch device memory the forward projection needs."""
+    return int(_abi.lib().lfbp_forward_workspace_size(Shape.of(shape), int(R), int(C)))
+
+
+def forward(H: torch.Tensor, g: torch.Tensor, out: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
+            stream=None) -> torch.Tensor:
+    """Forward projection f = H g: g [nz, R, C] -> f [R, C] (float32).
+    The scratch workspace comes from torch's allocator unless given."""
     _check_f32(H, "H", 5)
     _check_f32(g, "g", 3)
     nz, R, C = g.shape
@@ -135,8 +143,14 @@ def forward(H: torch.Tensor, g: torch.Tensor, out: torch.Tensor | None = None, s
         raise ValueError("g must have nz depth planes")
     f = torch.empty((R, C), dtype=torch.float32, device=g.device) if out is None else out
     _check_f32(f, "out", 2)
-    _abi.check(_abi.lib().lfbp_forward(H.data_ptr(), Shape.of(H.shape), g.data_ptr(), R, C, f.data_ptr(),
-                                       _stream(stream)), "lfbp_forward")
+    need = forward_workspace_size(H.shape, R, C)
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=g.device)
+    if workspace.numel() * workspace.element_size() < need or not workspace.is_cuda:
+        raise ValueError(f"workspace must be a GPU tensor of at least {need} bytes")
+    _abi.check(_abi.lib().lfbp_forward_ws(H.data_ptr(), Shape.of(H.shape), g.data_ptr(), R, C, f.data_ptr(),
+                                          workspace.data_ptr(), workspace.numel() * workspace.element_size(),
+                                          _stream(stream)), "lfbp_forward")
     return f
 
 

@@ -69,6 +69,8 @@ def lib():
             "lfbp_compute_Ht_batched_config": (st, [ctypes.POINTER(Problem), i32, i32,
                                                     ctypes.POINTER(GatherConfig), i32, vp]),
             "lfbp_forward": (st, [vp, Shape, vp, i64, i64, vp, vp]),
+            "lfbp_forward_ws": (st, [vp, Shape, vp, i64, i64, vp, vp, i64, vp]),
+            "lfbp_forward_workspace_size": (i64, [Shape, i64, i64]),
             "lfbp_backward": (st, [vp, Shape, vp, i64, i64, vp, vp]),
             "lfbp_status_string": (ctypes.c_char_p, [st]),
             "lfbp_release_plans": (None, []),

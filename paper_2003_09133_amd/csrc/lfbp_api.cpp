@@ -26,6 +26,9 @@ hipError_t launch_forward(const float* H, const lfbp_shape& s, const float* g, i
 hipError_t launch_backward(const float* Ht, const lfbp_shape& s, const float* f, int64_t R, int64_t C, float* g,
                            hipStream_t stream);
 hipError_t project_init(int max_lds);
+size_t forward_workspace_bytes(const lfbp_shape& s, int64_t R, int64_t C);
+hipError_t launch_forward_ws(const float* H, const lfbp_shape& s, const float* gin, int64_t R, int64_t C, float* f,
+                             void* ws, hipStream_t stream);
 
 namespace {
 
@@ -444,8 +447,33 @@ lfbp_status lfbp_forward(const float* H, lfbp_shape shape, const float* g, int64
     const lfbp_status st = check_project(H, shape, g, R, C, f, true);
     if (st != LFBP_OK) return st;
     if (ensure_init() != hipSuccess) return LFBP_EDEVICE;
-    return launch_forward(H, shape, g, R, C, f, static_cast<hipStream_t>(stream)) == hipSuccess ? LFBP_OK
-                                                                                             : LFBP_EDEVICE;
+    const hipError_t e = launch_forward(H, shape, g, R, C, f, static_cast<hipStream_t>(stream));
+    if (e == hipErrorOutOfMemory) return LFBP_ENOMEM;
+    return e == hipSuccess ? LFBP_OK : LFBP_EDEVICE;
+}
+
+int64_t lfbp_forward_workspace_size(lfbp_shape shape, int64_t R, int64_t C)
+{
+    if (R < 1 || C < 1 || check_shape(shape, 4) != LFBP_OK) return 0;
+    if (uint64_t(R) * uint64_t(C) * uint64_t(shape.nz) >= (uint64_t(1) << 31)) return 0;
+    return int64_t(forward_workspace_bytes(shape, R, C));
+}
+
+lfbp_status lfbp_forward_ws(const float* H, lfbp_shape shape, const float* g, int64_t R, int64_t C, float* f,
+                            void* workspace, int64_t workspace_bytes, void* stream)
+{
+    lfbp_status st = check_project(H, shape, g, R, C, f, true);
+    if (st != LFBP_OK) return st;
+    const int64_t need = int64_t(forward_workspace_bytes(shape, R, C));
+    if (!workspace || workspace_bytes < need || reinterpret_cast<uintptr_t>(workspace) % 256) return LFBP_EINVAL;
+    const uint64_t img = uint64_t(R) * uint64_t(C) * 4, vol = img * uint64_t(shape.nz);
+    if (ranges_overlap(workspace, uint64_t(need), H, shape_elems(shape) * 4) ||
+        ranges_overlap(workspace, uint64_t(need), g, vol) || ranges_overlap(workspace, uint64_t(need), f, img))
+        return LFBP_EALIAS;
+    if (ensure_init() != hipSuccess) return LFBP_EDEVICE;
+    return launch_forward_ws(H, shape, g, R, C, f, workspace, static_cast<hipStream_t>(stream)) == hipSuccess
+               ? LFBP_OK
+               : LFBP_EDEVICE;
 }
 
 lfbp_status lfbp_backward(const float* Ht, lfbp_shape shape, const float* f, int64_t R, int64_t C, float* g,

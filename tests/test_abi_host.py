@@ -157,3 +157,18 @@ int main() {
     subprocess.run(["g++", "-O2", "-std=c++17", f"-I{ROOT}/include", f"-I{ROOT}/paper_2003_09133_amd/csrc",
                     str(src), "-o", str(exe)], check=True)
     assert subprocess.run([str(exe)], capture_output=True, text=True).stdout.strip() == "ok"
+
+
+def test_forward_workspace_validation_before_launch():
+    L = _abi.lib()
+    shape = Shape(165, 165, 15, 15, 21)
+    need = L.lfbp_forward_workspace_size(shape, 600, 600)
+    assert need > 21 * 600 * 600 * 4                    # depth-last copy of g plus partial sums
+    assert L.lfbp_forward_workspace_size(Shape(4, 5, 3, 3, 1), 10, 10) == 0
+    assert L.lfbp_forward_workspace_size(shape, 0, 600) == 0
+    H, g, f, ws = 0x1000000, 0x40000000, 0x80000000, 0xC0000000
+    assert L.lfbp_forward_ws(H, shape, g, 600, 600, f, None, need, None) == _abi.EINVAL
+    assert L.lfbp_forward_ws(H, shape, g, 600, 600, f, ws, need - 1, None) == _abi.EINVAL
+    assert L.lfbp_forward_ws(H, shape, g, 600, 600, f, ws + 16, need, None) == _abi.EINVAL
+    assert L.lfbp_forward_ws(H, shape, g, 600, 600, f, g + 256, need, None) == _abi.EALIAS
+    assert L.lfbp_forward_ws(H, shape, g, 600, 600, f, f - 256, need, None) == _abi.EALIAS

@@ -135,3 +135,20 @@ def test_projector_workload_full_size_sampled():
                                            rng.integers(0, R, 1500), rng.integers(0, C, 1500)]),
                           np.array([(0, 0, 0), (20, R - 1, C - 1), (10, 0, C - 1)])])
     assert rel_l2(fbn[vox[:, 0], vox[:, 1], vox[:, 2]], oracle.backward_at(H, fn, vox)) <= TOL
+
+
+def test_forward_without_workspace_uses_stream_allocator():
+    """The workspace-free entry point (scratch from hipMallocAsync) gives the
+    same bits as the workspace form."""
+    import ctypes
+    from paper_2003_09133_amd import _abi
+    shape, R, C = (45, 45, 15, 15, 5), 97, 120
+    dH = to_dev(lfsynth.uniform_f32(shape, 21))
+    g = to_dev(lfsynth.uniform_f32((shape[4], R, C), 22))
+    f1 = torch.empty((R, C), device=DEV)
+    st = _abi.lib().lfbp_forward(dH.data_ptr(), _abi.Shape.of(shape), g.data_ptr(), R, C, f1.data_ptr(),
+                                 torch.cuda.current_stream().cuda_stream)
+    assert st == 0
+    f2 = lf.forward(dH, g)
+    torch.cuda.synchronize()
+    assert torch.equal(f1, f2)
