@@ -119,9 +119,12 @@ __device__ __forceinline__ void fold(f32x16 (&acc)[2][2], f32x16 (&tot)[2][2])
 // ------------------------------------------------------------------ forward
 
 // Operand registers of one forward stage (stage = one (s', t') pair and one
-// chunk of kFwdZC depth planes).
-constexpr int kFwdAPer = (kMT * kFwdZC + kThreads - 1) / kThreads;  // A elements per thread
-constexpr int kFwdBPer = (kNT * kFwdZC + kThreads - 1) / kThreads;  // B elements per thread
+// chunk of kFwdZC depth planes).  Thread t owns B column n0 + t (all depths of
+// the chunk: one contiguous run of H) and A row m0 + (t mod 64) at depths
+// t/64, t/64 + 4, ... (contiguous runs of the depth-last copy of g), so a
+// stage's addresses are a uniform base plus per-thread constants.
+constexpr int kFwdAPer = (kFwdZC + 3) / 4;  // depths per thread in the A tile
+constexpr int kFwdBPer = kFwdZC;           // depths per thread in the B tile
 
 struct FwdArgs {
     const float* H;    // [ns][nt][nx][ny][nz]
@@ -134,67 +137,98 @@ struct FwdArgs {
     int splits;
 };
 
-__device__ __forceinline__ void fwd_load(const FwdArgs& a, int stage, int m0, int n0, float (&ra)[kFwdAPer],
-                                         float (&rb)[kFwdBPer])
+struct FwdThread {
+    int64_t hoff;  // (u*nt + v)*cell of this thread's B column; -1: padding column
+    int u, v;
+    int P0, Q0;    // nx*Lp + hs, ny*Lq + ht of this thread's A row; P0 < 0: padding row
+    int zg;        // first depth of this thread in the A tile
+};
+
+__device__ __forceinline__ FwdThread fwd_thread(const FwdArgs& a, int m0, int n0)
+{
+    const ProjGeom& g = a.g;
+    FwdThread t;
+    const int tid = threadIdx.x;
+    const int n = n0 + tid;
+    t.u = 0;
+    t.v = 0;
+    t.hoff = -1;
+    if (n < a.N) {
+        t.u = int(fdiv(uint32_t(n), g.fny));
+        t.v = n - t.u * g.ny;
+        t.hoff = (int64_t(t.u) * g.nt + t.v) * (int64_t(g.nx) * g.ny * g.nz);
+    }
+    const int m = m0 + (tid & 63);
+    t.zg = __builtin_amdgcn_readfirstlane(tid >> 6);
+    t.P0 = -1 << 30;
+    t.Q0 = 0;
+    if (m < g.M) {
+        const int Lp = m / g.Lc, Lq = m - Lp * g.Lc;
+        t.P0 = g.nx * Lp + g.hs;
+        t.Q0 = g.ny * Lq + g.ht;
+    }
+    return t;
+}
+
+// Raw operand values of a stage plus what decides which of them are real:
+// the zero mask is applied when the values are written to LDS, after the
+// stage's MFMA work, so the loads stay in flight during that work.
+struct FwdMask {
+    bool va, vb;  // this lane's A row / B column has data at this stage
+    int zn;       // depth planes present in the stage (uniform)
+};
+
+__device__ __forceinline__ FwdMask fwd_load(const FwdArgs& a, const FwdThread& th, int stage,
+                                            float (&ra)[kFwdAPer], float (&rb)[kFwdBPer])
 {
     const ProjGeom& g = a.g;
     const int st = stage / a.nzc, zc = stage - st * a.nzc;
     const int sr = int(fdiv(uint32_t(st), g.fKc)), tc = st - sr * g.Kc;
-    const int sp = sr - (g.nx - 1), tp = tc - (g.ny - 1);       // s', t'
-    const int z0 = zc * kFwdZC;
+    const int sp = sr - (g.nx - 1), tp = tc - (g.ny - 1);  // s', t'
+    const int z0 = zc * kFwdZC, zn = min(kFwdZC, g.nz - z0);
     const int x = imod(g.hs - sp, g.nx), y = imod(g.ht - tp, g.ny);
-    const int tid = threadIdx.x;
-    // A: element e -> (m = e / ZC, z = e % ZC), depth fastest (contiguous in gT)
+    // B column: H[s'+u][t'+v][x][y][z0 .. z0+zn)
+    // Loads are unconditional: lanes without data read element 0 of the array
+    // and keep zero, so no load sits behind a branch.
+    const bool vb = (th.hoff >= 0) & (unsigned(sp + th.u) < unsigned(g.ns)) & (unsigned(tp + th.v) < unsigned(g.nt));
+    const float* pb = vb ? a.H + ((int64_t(sp) * g.nt + tp) * (int64_t(g.nx) * g.ny * g.nz) + th.hoff +
+                                  (int64_t(x) * g.ny + y) * g.nz + z0)
+                         : a.H;
+#pragma unroll
+    for (int z = 0; z < kFwdBPer; ++z) rb[z] = pb[z < zn ? z : zn - 1];  // uniform clamp, no branch
+    // A row: gT[P][Q][z0 + zg + 4j]
+    const int P = th.P0 - sp, Q = th.Q0 - tp;
+    const bool va = (P >= 0) & (P < g.R) & (Q >= 0) & (Q < g.C);
+    // pa points at depth z0 of the pixel (or at gT[0] for lanes without data);
+    // the clamped depth min(zl, zn-1) lies in [0, zn), so every read stays
+    // inside the pixel's run (or inside gT[0, zn)).
+    const float* pa = va ? a.gT + ((int64_t(P) * g.C + Q) * g.nz + z0) : a.gT;
 #pragma unroll
     for (int j = 0; j < kFwdAPer; ++j) {
-        const int e = tid + j * kThreads;
-        const int ml = int(fdiv(uint32_t(e), g.fzc)), zl = e - ml * kFwdZC;
-        const int m = m0 + ml, z = z0 + zl;
-        float v = 0.0f;
-        if (ml < kMT && m < g.M && z < g.nz) {
-            const int Lp = m / g.Lc, Lq = m - Lp * g.Lc;
-            const int P = g.nx * Lp + g.hs - sp, Q = g.ny * Lq + g.ht - tp;
-            if (P >= 0 && P < g.R && Q >= 0 && Q < g.C) v = a.gT[(size_t(P) * g.C + Q) * g.nz + z];
-        }
-        ra[j] = v;
+        const int zl = th.zg + 4 * j;  // zg is the wave index: uniform
+        ra[j] = pa[zl < zn ? zl : zn - 1];
     }
-    // B: element e -> (n = e / ZC, z = e % ZC)
-    const size_t cell = size_t(g.nx) * g.ny * g.nz;
-#pragma unroll
-    for (int j = 0; j < kFwdBPer; ++j) {
-        const int e = tid + j * kThreads;
-        const int nl = int(fdiv(uint32_t(e), g.fzc)), zl = e - nl * kFwdZC;
-        const int n = n0 + nl, z = z0 + zl;
-        float v = 0.0f;
-        if (nl < kNT && n < a.N && z < g.nz) {
-            const int u = int(fdiv(uint32_t(n), g.fny)), vv = n - u * g.ny;
-            const int s = sp + u, t = tp + vv;
-            if (s >= 0 && s < g.ns && t >= 0 && t < g.nt)
-                v = a.H[(size_t(s) * g.nt + t) * cell + (size_t(x) * g.ny + y) * g.nz + z];
-        }
-        rb[j] = v;
-    }
+    FwdMask mk;
+    mk.va = va;
+    mk.vb = vb;
+    mk.zn = zn;
+    return mk;
 }
 
-__device__ __forceinline__ void fwd_store(float* As, float* Bs, const float (&ra)[kFwdAPer],
-                                          const float (&rb)[kFwdBPer], const ProjGeom& g)
+__device__ __forceinline__ void fwd_store(float* As, float* Bs, const FwdThread& th, const FwdMask& mk,
+                                          const float (&ra)[kFwdAPer], const float (&rb)[kFwdBPer])
 {
     const int tid = threadIdx.x;
 #pragma unroll
-    for (int j = 0; j < kFwdAPer; ++j) {
-        const int e = tid + j * kThreads;
-        const int ml = int(fdiv(uint32_t(e), g.fzc)), zl = e - ml * kFwdZC;
-        if (ml < kMT) As[zl * kAStride + ml] = ra[j];
-    }
+    for (int z = 0; z < kFwdBPer; ++z) Bs[z * kBStride + tid] = (mk.vb & (z < mk.zn)) ? rb[z] : 0.0f;
 #pragma unroll
-    for (int j = 0; j < kFwdBPer; ++j) {
-        const int e = tid + j * kThreads;
-        const int nl = int(fdiv(uint32_t(e), g.fzc)), zl = e - nl * kFwdZC;
-        if (nl < kNT) Bs[zl * kBStride + nl] = rb[j];
+    for (int j = 0; j < kFwdAPer; ++j) {
+        const int zl = th.zg + 4 * j;
+        if (zl < kFwdZC) As[zl * kAStride + (tid & 63)] = (mk.va & (zl < mk.zn)) ? ra[j] : 0.0f;
     }
 }
 
-__global__ void __launch_bounds__(kThreads) k_fwd_gemm(FwdArgs a)
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) k_fwd_gemm(FwdArgs a)
 {
     __shared__ float As[2][kFwdZC * kAStride];
     __shared__ float Bs[2][kFwdZC * kBStride];
@@ -205,21 +239,23 @@ __global__ void __launch_bounds__(kThreads) k_fwd_gemm(FwdArgs a)
     const bool active = n0 + wave * 64 < a.Npad;
     f32x16 acc[2][2] = {}, tot[2][2] = {};
     float ra[kFwdAPer], rb[kFwdBPer];
+    const FwdThread th = fwd_thread(a, m0, n0);
+    FwdMask mk{};
     if (s_begin < s_end) {
-        fwd_load(a, s_begin, m0, n0, ra, rb);
-        fwd_store(As[0], Bs[0], ra, rb, a.g);
+        mk = fwd_load(a, th, s_begin, ra, rb);
+        fwd_store(As[0], Bs[0], th, mk, ra, rb);
         __syncthreads();
     }
     int buf = 0, since = 0;
     for (int s = s_begin; s < s_end; ++s) {
         const bool more = s + 1 < s_end;
-        if (more) fwd_load(a, s + 1, m0, n0, ra, rb);
+        if (more) mk = fwd_load(a, th, s + 1, ra, rb);
         if (active) mma_stage(As[buf], Bs[buf], kFwdZC, wave, lane, acc);
         if (++since == kFold) {
             fold(acc, tot);
             since = 0;
         }
-        if (more) fwd_store(As[buf ^ 1], Bs[buf ^ 1], ra, rb, a.g);
+        if (more) fwd_store(As[buf ^ 1], Bs[buf ^ 1], th, mk, ra, rb);
         __syncthreads();
         buf ^= 1;
     }
@@ -272,7 +308,7 @@ __global__ void __launch_bounds__(256) k_depth_last(const float* g, int nz, int 
 
 // ------------------------------------------------------------------ backward
 
-constexpr int kBwdAPer = (kMT * kBwdKC + kThreads - 1) / kThreads;  // 4
+constexpr int kBwdAPer = (kMT * kBwdKC + kThreads - 1) / kThreads;  // 4 pairs per thread
 constexpr int kBwdBPer = kBwdKC;                                    // one column per thread, all rows
 
 struct BwdArgs {
@@ -284,61 +320,58 @@ struct BwdArgs {
     int K;             // Kr*Kc
 };
 
-__device__ __forceinline__ void bwd_load(const BwdArgs& a, int k0, int m0, int n, int cx, int cy, int z,
-                                         float (&ra)[kBwdAPer], float (&rb)[kBwdBPer])
+// Thread t owns B column n0 + t = (cx, cy, z) and, in the A tile, row
+// m0 + t/4 at the 4 consecutive pairs 4(t mod 4) .. 4(t mod 4)+3 of the stage.
+// Per-element zero masks of a backward stage, bit j (A) and bit kk (B).
+struct BwdMask {
+    uint32_t a, b;
+};
+
+__device__ __forceinline__ BwdMask bwd_load(const BwdArgs& a, int k0, int m, int P0, int Q0, int64_t hoff, int cx,
+                                            int cy, float (&ra)[kBwdAPer], float (&rb)[kBwdBPer])
 {
+    BwdMask mk{0u, 0u};
     const ProjGeom& g = a.geo;
     const int tid = threadIdx.x;
-    // A: element e -> (m = e / KC, kk = e % KC): consecutive (r, r2) are consecutive f columns
+    // A: f[P0 - r][Q0 - r2] for this thread's 4 pairs
 #pragma unroll
     for (int j = 0; j < kBwdAPer; ++j) {
-        const int e = tid + j * kThreads;
-        const int ml = e / kBwdKC, kk = e - ml * kBwdKC;
-        const int m = m0 + ml, k = k0 + kk;
-        float v = 0.0f;
-        if (m < g.M && k < a.K) {
-            const int ri = int(fdiv(uint32_t(k), g.fKc)), r2i = k - ri * g.Kc;
-            const int r = ri - (g.nx - 1), r2 = r2i - (g.ny - 1);
-            const int Lp = m / g.Lc, Lq = m - Lp * g.Lc;
-            const int p = g.nx * Lp + g.hs - r, q = g.ny * Lq + g.ht - r2;
-            if (p >= 0 && p < g.R && q >= 0 && q < g.C) v = a.f[size_t(p) * g.C + q];
-        }
-        ra[j] = v;
+        const int k = k0 + 4 * (tid & 3) + j;
+        const int ri = int(fdiv(uint32_t(k), g.fKc)), r2i = k - ri * g.Kc;
+        const int p = P0 - (ri - (g.nx - 1)), q = Q0 - (r2i - (g.ny - 1));
+        const bool ok = (m < g.M) & (k < a.K) & (p >= 0) & (p < g.R) & (q >= 0) & (q < g.C);
+        ra[j] = a.f[ok ? int64_t(p) * g.C + q : 0];
+        mk.a |= uint32_t(ok) << j;
     }
-    // B: this thread's column n = (cx, cy, z), rows k0..k0+KC-1
-    const size_t cell = size_t(g.nx) * g.ny * g.nz;
+    // B: Ht[r+cx][r2+cy][x][y][z]; (r, r2, x, y) are uniform over the workgroup
+    const int64_t cell = int64_t(g.nx) * g.ny * g.nz;
 #pragma unroll
     for (int kk = 0; kk < kBwdKC; ++kk) {
         const int k = k0 + kk;
-        float v = 0.0f;
-        if (n < a.N && k < a.K) {
-            const int ri = int(fdiv(uint32_t(k), g.fKc)), r2i = k - ri * g.Kc;
-            const int r = ri - (g.nx - 1), r2 = r2i - (g.ny - 1);
-            const int s = r + cx, t = r2 + cy;
-            if (s >= 0 && s < g.ns && t >= 0 && t < g.nt) {
-                const int x = imod(g.hs - r, g.nx), y = imod(g.ht - r2, g.ny);
-                v = a.Ht[(size_t(s) * g.nt + t) * cell + (size_t(x) * g.ny + y) * g.nz + z];
-            }
-        }
-        rb[kk] = v;
+        const int ri = int(fdiv(uint32_t(k), g.fKc)), r2i = k - ri * g.Kc;
+        const int r = ri - (g.nx - 1), r2 = r2i - (g.ny - 1);
+        const int x = imod(g.hs - r, g.nx), y = imod(g.ht - r2, g.ny);
+        const bool valid = (hoff >= 0) & (k < a.K) & (unsigned(r + cx) < unsigned(g.ns)) &
+                           (unsigned(r2 + cy) < unsigned(g.nt));
+        const int64_t base = (int64_t(r) * g.nt + r2) * cell + (int64_t(x) * g.ny + y) * g.nz;
+        rb[kk] = a.Ht[valid ? base + hoff : 0];
+        mk.b |= uint32_t(valid) << kk;
     }
+    return mk;
 }
 
-__device__ __forceinline__ void bwd_store(float* As, float* Bs, const float (&ra)[kBwdAPer],
+__device__ __forceinline__ void bwd_store(float* As, float* Bs, const BwdMask& mk, const float (&ra)[kBwdAPer],
                                           const float (&rb)[kBwdBPer])
 {
     const int tid = threadIdx.x;
 #pragma unroll
-    for (int j = 0; j < kBwdAPer; ++j) {
-        const int e = tid + j * kThreads;
-        const int ml = e / kBwdKC, kk = e - ml * kBwdKC;
-        As[kk * kAStride + ml] = ra[j];
-    }
+    for (int j = 0; j < kBwdAPer; ++j)
+        As[(4 * (tid & 3) + j) * kAStride + (tid >> 2)] = ((mk.a >> j) & 1u) ? ra[j] : 0.0f;
 #pragma unroll
-    for (int kk = 0; kk < kBwdKC; ++kk) Bs[kk * kBStride + tid] = rb[kk];
+    for (int kk = 0; kk < kBwdKC; ++kk) Bs[kk * kBStride + tid] = ((mk.b >> kk) & 1u) ? rb[kk] : 0.0f;
 }
 
-__global__ void __launch_bounds__(kThreads) k_bwd_gemm(BwdArgs a)
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) k_bwd_gemm(BwdArgs a)
 {
     __shared__ float As[2][kBwdKC * kAStride];
     __shared__ float Bs[2][kBwdKC * kBStride];
@@ -346,31 +379,40 @@ __global__ void __launch_bounds__(kThreads) k_bwd_gemm(BwdArgs a)
     const int m0 = blockIdx.x * kMT, n0 = blockIdx.y * kNT;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const bool active = n0 + wave * 64 < a.N;
-    // this thread's B column
+    // this thread's B column (cx, cy, z) and A row
     const int n = n0 + int(threadIdx.x);
-    int cx = 0, cy = 0, z = 0;
+    int cx = 0, cy = 0;
+    int64_t hoff = -1;
     if (n < a.N) {
         const int c = int(fdiv(uint32_t(n), g.fnz));
-        z = n - c * g.nz;
+        const int z = n - c * g.nz;
         cx = int(fdiv(uint32_t(c), g.fny));
         cy = c - cx * g.ny;
+        hoff = (int64_t(cx) * g.nt + cy) * (int64_t(g.nx) * g.ny * g.nz) + z;
+    }
+    const int m = m0 + int(threadIdx.x >> 2);
+    int P0 = 0, Q0 = 0;
+    if (m < g.M) {
+        const int Lp = m / g.Lc, Lq = m - Lp * g.Lc;
+        P0 = g.nx * Lp + g.hs;
+        Q0 = g.ny * Lq + g.ht;
     }
     f32x16 acc[2][2] = {}, tot[2][2] = {};
     float ra[kBwdAPer], rb[kBwdBPer];
     const int stages = (a.K + kBwdKC - 1) / kBwdKC;
-    bwd_load(a, 0, m0, n, cx, cy, z, ra, rb);
-    bwd_store(As[0], Bs[0], ra, rb);
+    BwdMask mk = bwd_load(a, 0, m, P0, Q0, hoff, cx, cy, ra, rb);
+    bwd_store(As[0], Bs[0], mk, ra, rb);
     __syncthreads();
     int buf = 0, since = 0;
     for (int s = 0; s < stages; ++s) {
         const bool more = s + 1 < stages;
-        if (more) bwd_load(a, (s + 1) * kBwdKC, m0, n, cx, cy, z, ra, rb);
+        if (more) mk = bwd_load(a, (s + 1) * kBwdKC, m, P0, Q0, hoff, cx, cy, ra, rb);
         if (active) mma_stage(As[buf], Bs[buf], kBwdKC, wave, lane, acc);
         if (++since == kFold) {
             fold(acc, tot);
             since = 0;
         }
-        if (more) bwd_store(As[buf ^ 1], Bs[buf ^ 1], ra, rb);
+        if (more) bwd_store(As[buf ^ 1], Bs[buf ^ 1], mk, ra, rb);
         __syncthreads();
         buf ^= 1;
     }
@@ -402,7 +444,7 @@ int g_cus_proj = 256;
 
 int fwd_splits(const ProjGeom& g, int mtiles, int ntiles, int stages)
 {
-    const int want = (2 * g_cus_proj + mtiles * ntiles - 1) / (mtiles * ntiles);
+    const int want = (2 * g_cus_proj) / (mtiles * ntiles);  // one round at two workgroups per CU
     return std::max(1, std::min({want, 64, std::max(1, stages / 8)}));
 }
 
