@@ -118,13 +118,21 @@ __device__ __forceinline__ void fold(f32x16 (&acc)[2][2], f32x16 (&tot)[2][2])
 
 // ------------------------------------------------------------------ forward
 
-// Operand registers of one forward stage (stage = one (s', t') pair and one
-// chunk of kFwdZC depth planes).  Thread t owns B column n0 + t (all depths of
-// the chunk: one contiguous run of H) and A row m0 + (t mod 64) at depths
-// t/64, t/64 + 4, ... (contiguous runs of the depth-last copy of g), so a
-// stage's addresses are a uniform base plus per-thread constants.
-constexpr int kFwdAPer = (kFwdZC + 3) / 4;  // depths per thread in the A tile
-constexpr int kFwdBPer = kFwdZC;           // depths per thread in the B tile
+// Operand fetch of one forward stage (stage = one (s', t') pair and one chunk
+// of up to kFwdZC depth planes).  Every B column (pixel class (u,v)) and every
+// A row (lenslet) needs one contiguous run of <= kFwdZC floats: H[s'+u][t'+v]
+// [x][y][z0..] and gT[P][Q][z0..].  Each run is read as the kFwdVPR aligned
+// 16-byte vectors that cover it (consecutive lanes take consecutive vectors of
+// a run), and the vectors are scattered into the LDS tile when it is written,
+// after the stage's MFMA work.  A 16-byte aligned vector that holds at least
+// one element of the run never leaves the run's page, so the reads need no
+// bounds branch; elements outside the run are written to LDS as zeros.
+constexpr int kFwdVPR = (kFwdZC + 3 + 3) / 4;                           // vectors per run: 7
+constexpr int kFwdBSlots = kNT * kFwdVPR / kThreads;                     // 7 per thread
+constexpr int kFwdASlots = (kMT * kFwdVPR + kThreads - 1) / kThreads;    // 2 per thread
+static_assert(kNT * kFwdVPR % kThreads == 0, "B slots must tile the workgroup");
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 struct FwdArgs {
     const float* H;    // [ns][nt][nx][ny][nz]
@@ -135,51 +143,21 @@ struct FwdArgs {
     int stages;        // Kr*Kc*nzc
     int nzc;           // depth chunks
     int splits;
+    int phaseH;        // (address of H / 4) mod 4
+    int phaseG;        // (address of gT / 4) mod 4
 };
 
-struct FwdThread {
-    int64_t hoff;  // (u*nt + v)*cell of this thread's B column; -1: padding column
-    int u, v;
-    int P0, Q0;    // nx*Lp + hs, ny*Lq + ht of this thread's A row; P0 < 0: padding row
-    int zg;        // first depth of this thread in the A tile
+// Loaded vectors of one stage and, per slot, the run's offset inside its first
+// vector (bits 0-1) and whether the run exists (bit 2).
+struct FwdRegs {
+    u32x4 b[kFwdBSlots];
+    u32x4 a[kFwdASlots];
+    uint32_t bmeta[kFwdBSlots];
+    uint32_t ameta[kFwdASlots];
+    int zn;  // depth planes present in the stage (uniform)
 };
 
-__device__ __forceinline__ FwdThread fwd_thread(const FwdArgs& a, int m0, int n0)
-{
-    const ProjGeom& g = a.g;
-    FwdThread t;
-    const int tid = threadIdx.x;
-    const int n = n0 + tid;
-    t.u = 0;
-    t.v = 0;
-    t.hoff = -1;
-    if (n < a.N) {
-        t.u = int(fdiv(uint32_t(n), g.fny));
-        t.v = n - t.u * g.ny;
-        t.hoff = (int64_t(t.u) * g.nt + t.v) * (int64_t(g.nx) * g.ny * g.nz);
-    }
-    const int m = m0 + (tid & 63);
-    t.zg = __builtin_amdgcn_readfirstlane(tid >> 6);
-    t.P0 = -1 << 30;
-    t.Q0 = 0;
-    if (m < g.M) {
-        const int Lp = m / g.Lc, Lq = m - Lp * g.Lc;
-        t.P0 = g.nx * Lp + g.hs;
-        t.Q0 = g.ny * Lq + g.ht;
-    }
-    return t;
-}
-
-// Raw operand values of a stage plus what decides which of them are real:
-// the zero mask is applied when the values are written to LDS, after the
-// stage's MFMA work, so the loads stay in flight during that work.
-struct FwdMask {
-    bool va, vb;  // this lane's A row / B column has data at this stage
-    int zn;       // depth planes present in the stage (uniform)
-};
-
-__device__ __forceinline__ FwdMask fwd_load(const FwdArgs& a, const FwdThread& th, int stage,
-                                            float (&ra)[kFwdAPer], float (&rb)[kFwdBPer])
+__device__ __forceinline__ void fwd_load(const FwdArgs& a, int m0, int n0, int stage, FwdRegs& R)
 {
     const ProjGeom& g = a.g;
     const int st = stage / a.nzc, zc = stage - st * a.nzc;
@@ -187,44 +165,77 @@ __device__ __forceinline__ FwdMask fwd_load(const FwdArgs& a, const FwdThread& t
     const int sp = sr - (g.nx - 1), tp = tc - (g.ny - 1);  // s', t'
     const int z0 = zc * kFwdZC, zn = min(kFwdZC, g.nz - z0);
     const int x = imod(g.hs - sp, g.nx), y = imod(g.ht - tp, g.ny);
-    // B column: H[s'+u][t'+v][x][y][z0 .. z0+zn)
-    // Loads are unconditional: lanes without data read element 0 of the array
-    // and keep zero, so no load sits behind a branch.
-    const bool vb = (th.hoff >= 0) & (unsigned(sp + th.u) < unsigned(g.ns)) & (unsigned(tp + th.v) < unsigned(g.nt));
-    const float* pb = vb ? a.H + ((int64_t(sp) * g.nt + tp) * (int64_t(g.nx) * g.ny * g.nz) + th.hoff +
-                                  (int64_t(x) * g.ny + y) * g.nz + z0)
-                         : a.H;
+    const int64_t cell = int64_t(g.nx) * g.ny * g.nz;
+    const int64_t sbase = (int64_t(sp) * g.nt + tp) * cell + (int64_t(x) * g.ny + y) * g.nz + z0;
+    const int tid = threadIdx.x;
+    R.zn = zn;
 #pragma unroll
-    for (int z = 0; z < kFwdBPer; ++z) rb[z] = pb[z < zn ? z : zn - 1];  // uniform clamp, no branch
-    // A row: gT[P][Q][z0 + zg + 4j]
-    const int P = th.P0 - sp, Q = th.Q0 - tp;
-    const bool va = (P >= 0) & (P < g.R) & (Q >= 0) & (Q < g.C);
-    // pa points at depth z0 of the pixel (or at gT[0] for lanes without data);
-    // the clamped depth min(zl, zn-1) lies in [0, zn), so every read stays
-    // inside the pixel's run (or inside gT[0, zn)).
-    const float* pa = va ? a.gT + ((int64_t(P) * g.C + Q) * g.nz + z0) : a.gT;
-#pragma unroll
-    for (int j = 0; j < kFwdAPer; ++j) {
-        const int zl = th.zg + 4 * j;  // zg is the wave index: uniform
-        ra[j] = pa[zl < zn ? zl : zn - 1];
+    for (int j = 0; j < kFwdBSlots; ++j) {
+        const int e = tid + j * kThreads;
+        const int nl = e / kFwdVPR, k = e - nl * kFwdVPR;
+        const int n = n0 + nl;
+        const int u = int(fdiv(uint32_t(n), g.fny)), v = n - u * g.ny;
+        const bool valid = (n < a.N) & (unsigned(sp + u) < unsigned(g.ns)) & (unsigned(tp + v) < unsigned(g.nt));
+        const int64_t rs = sbase + (int64_t(u) * g.nt + v) * cell;
+        const int lead = valid ? int((rs + a.phaseH) & 3) : 0;
+        const int64_t vb = valid ? rs - lead : -int64_t(a.phaseH);
+        const int kmax = (lead + zn - 1) >> 2;
+        const int kk = k < kmax ? k : kmax;                 // always a vector that overlaps the run
+        R.b[j] = *reinterpret_cast<const u32x4*>(a.H + vb + 4 * kk);
+        R.bmeta[j] = uint32_t(lead) | (uint32_t(valid) << 2);
     }
-    FwdMask mk;
-    mk.va = va;
-    mk.vb = vb;
-    mk.zn = zn;
-    return mk;
+#pragma unroll
+    for (int j = 0; j < kFwdASlots; ++j) {
+        const int e = tid + j * kThreads;
+        const int ml = e / kFwdVPR, k = e - ml * kFwdVPR;
+        const int m = m0 + ml;
+        const int Lp = m / g.Lc, Lq = m - Lp * g.Lc;
+        const int P = g.nx * Lp + g.hs - sp, Q = g.ny * Lq + g.ht - tp;
+        const bool valid = (ml < kMT) & (m < g.M) & (P >= 0) & (P < g.R) & (Q >= 0) & (Q < g.C);
+        const int64_t rs = (int64_t(P) * g.C + Q) * g.nz + z0;
+        const int lead = valid ? int((rs + a.phaseG) & 3) : 0;
+        const int64_t vb = valid ? rs - lead : -int64_t(a.phaseG);
+        const int kmax = (lead + zn - 1) >> 2;
+        const int kk = k < kmax ? k : kmax;
+        R.a[j] = *reinterpret_cast<const u32x4*>(a.gT + vb + 4 * kk);
+        R.ameta[j] = uint32_t(lead) | (uint32_t(valid) << 2);
+    }
 }
 
-__device__ __forceinline__ void fwd_store(float* As, float* Bs, const FwdThread& th, const FwdMask& mk,
-                                          const float (&ra)[kFwdAPer], const float (&rb)[kFwdBPer])
+// Scatter the stage's vectors into As[z][m] and Bs[z][n]: vector k of a run
+// holds depths 4k - lead .. 4k - lead + 3, so the kFwdVPR vectors of a run
+// write every depth 0..kFwdZC-1 of its row or column exactly once.
+__device__ __forceinline__ void fwd_store(float* As, float* Bs, const FwdRegs& R)
 {
     const int tid = threadIdx.x;
 #pragma unroll
-    for (int z = 0; z < kFwdBPer; ++z) Bs[z * kBStride + tid] = (mk.vb & (z < mk.zn)) ? rb[z] : 0.0f;
+    for (int j = 0; j < kFwdBSlots; ++j) {
+        const int e = tid + j * kThreads;
+        const int nl = e / kFwdVPR, k = e - nl * kFwdVPR;
+        const int lead = int(R.bmeta[j] & 3u);
+        const bool valid = (R.bmeta[j] >> 2) & 1u;
+        const float v4[4] = {__uint_as_float(R.b[j].x), __uint_as_float(R.b[j].y), __uint_as_float(R.b[j].z),
+                             __uint_as_float(R.b[j].w)};
 #pragma unroll
-    for (int j = 0; j < kFwdAPer; ++j) {
-        const int zl = th.zg + 4 * j;
-        if (zl < kFwdZC) As[zl * kAStride + (tid & 63)] = (mk.va & (zl < mk.zn)) ? ra[j] : 0.0f;
+        for (int q = 0; q < 4; ++q) {
+            const int z = 4 * k + q - lead;
+            if (z >= 0 && z < kFwdZC) Bs[z * kBStride + nl] = (valid & (z < R.zn)) ? v4[q] : 0.0f;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kFwdASlots; ++j) {
+        const int e = tid + j * kThreads;
+        const int ml = e / kFwdVPR, k = e - ml * kFwdVPR;
+        if (ml >= kMT) continue;
+        const int lead = int(R.ameta[j] & 3u);
+        const bool valid = (R.ameta[j] >> 2) & 1u;
+        const float v4[4] = {__uint_as_float(R.a[j].x), __uint_as_float(R.a[j].y), __uint_as_float(R.a[j].z),
+                             __uint_as_float(R.a[j].w)};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int z = 4 * k + q - lead;
+            if (z >= 0 && z < kFwdZC) As[z * kAStride + ml] = (valid & (z < R.zn)) ? v4[q] : 0.0f;
+        }
     }
 }
 
@@ -238,24 +249,22 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const bool active = n0 + wave * 64 < a.Npad;
     f32x16 acc[2][2] = {}, tot[2][2] = {};
-    float ra[kFwdAPer], rb[kFwdBPer];
-    const FwdThread th = fwd_thread(a, m0, n0);
-    FwdMask mk{};
+    FwdRegs regs;
     if (s_begin < s_end) {
-        mk = fwd_load(a, th, s_begin, ra, rb);
-        fwd_store(As[0], Bs[0], th, mk, ra, rb);
+        fwd_load(a, m0, n0, s_begin, regs);
+        fwd_store(As[0], Bs[0], regs);
         __syncthreads();
     }
     int buf = 0, since = 0;
     for (int s = s_begin; s < s_end; ++s) {
         const bool more = s + 1 < s_end;
-        if (more) mk = fwd_load(a, th, s + 1, ra, rb);
+        if (more) fwd_load(a, m0, n0, s + 1, regs);
         if (active) mma_stage(As[buf], Bs[buf], kFwdZC, wave, lane, acc);
         if (++since == kFold) {
             fold(acc, tot);
             since = 0;
         }
-        if (more) fwd_store(As[buf ^ 1], Bs[buf ^ 1], th, mk, ra, rb);
+        if (more) fwd_store(As[buf ^ 1], Bs[buf ^ 1], regs);
         __syncthreads();
         buf ^= 1;
     }
@@ -344,18 +353,30 @@ __device__ __forceinline__ BwdMask bwd_load(const BwdArgs& a, int k0, int m, int
         mk.a |= uint32_t(ok) << j;
     }
     // B: Ht[r+cx][r2+cy][x][y][z]; (r, r2, x, y) are uniform over the workgroup
+    // and advance by one pair per row of the stage: one division per stage,
+    // then scalar increments (r2 up by one, x and y down by one, cyclically).
     const int64_t cell = int64_t(g.nx) * g.ny * g.nz;
+    int ri = int(fdiv(uint32_t(k0), g.fKc));
+    int r2i = k0 - ri * g.Kc;
+    int x = imod(g.hs - (ri - (g.nx - 1)), g.nx);
+    int y = imod(g.ht - (r2i - (g.ny - 1)), g.ny);
+    const int y_first = imod(g.ht + g.ny - 1, g.ny);  // y at r2 = -(ny-1)
 #pragma unroll
     for (int kk = 0; kk < kBwdKC; ++kk) {
-        const int k = k0 + kk;
-        const int ri = int(fdiv(uint32_t(k), g.fKc)), r2i = k - ri * g.Kc;
         const int r = ri - (g.nx - 1), r2 = r2i - (g.ny - 1);
-        const int x = imod(g.hs - r, g.nx), y = imod(g.ht - r2, g.ny);
-        const bool valid = (hoff >= 0) & (k < a.K) & (unsigned(r + cx) < unsigned(g.ns)) &
+        const bool valid = (hoff >= 0) & (k0 + kk < a.K) & (unsigned(r + cx) < unsigned(g.ns)) &
                            (unsigned(r2 + cy) < unsigned(g.nt));
         const int64_t base = (int64_t(r) * g.nt + r2) * cell + (int64_t(x) * g.ny + y) * g.nz;
         rb[kk] = a.Ht[valid ? base + hoff : 0];
         mk.b |= uint32_t(valid) << kk;
+        if (++r2i == g.Kc) {
+            r2i = 0;
+            ++ri;
+            x = x == 0 ? g.nx - 1 : x - 1;
+            y = y_first;
+        } else {
+            y = y == 0 ? g.ny - 1 : y - 1;
+        }
     }
     return mk;
 }
@@ -492,6 +513,8 @@ hipError_t launch_forward_ws(const float* H, const lfbp_shape& s, const float* g
     const size_t gT_bytes = (size_t(g.nz) * g.R * g.C * sizeof(float) + 255) / 256 * 256;
     float* gT = static_cast<float*>(ws);
     a.gT = gT;
+    a.phaseH = int((reinterpret_cast<uintptr_t>(H) / 4) % 4);
+    a.phaseG = int((reinterpret_cast<uintptr_t>(gT) / 4) % 4);
     a.partial = reinterpret_cast<float*>(static_cast<char*>(ws) + gT_bytes);
     const int plane = g.R * g.C;
     hipLaunchKernelGGL(k_depth_last, dim3(unsigned((plane + 31) / 32), unsigned((g.nz + 31) / 32)), dim3(256), 0,

@@ -4,9 +4,11 @@ A mirror, in NumPy, of the index arithmetic of the operand loaders and result
 writes of k_fwd_gemm / k_fwd_reduce / k_bwd_gemm (paper_2003_09133_amd/csrc/
 lfbp_project.hip): for every lane and every stage of the listed shapes, every
 global address the kernels form must lie inside its array.  Keep it in step
-with the kernels' loaders.  It guards, in particular, against the depth index
-of the forward A loader going below the start of the depth-last copy of g when
-a depth chunk has fewer planes than there are wavefronts.
+with the kernels' loaders.  The forward loaders read 16-byte vectors that
+may extend past the run they serve: each must be aligned and share its 16-byte
+line with an element of its array, for every alignment of the array, and the
+scatter of the vectors into LDS must write every (depth, row/column) slot of
+the stage exactly once, from the element the GEMM formulation names.
 """
 import itertools
 
@@ -14,13 +16,21 @@ import numpy as np
 import pytest
 
 kThreads, kMT, kNT, kFwdZC, kBwdKC = 256, 64, 256, 22, 16
-kFwdAPer = (kFwdZC + 3) // 4
+kFwdVPR = (kFwdZC + 3 + 3) // 4
+kFwdBSlots = kNT * kFwdVPR // kThreads
+kFwdASlots = (kMT * kFwdVPR + kThreads - 1) // kThreads
 def geom(shape, R, C):
     ns, nt, nx, ny, nz = shape
     return dict(ns=ns, nt=nt, nx=nx, ny=ny, nz=nz, hs=(ns-1)//2, ht=(nt-1)//2, R=R, C=C,
                 Lr=-(-R//nx), Lc=-(-C//ny), M=(-(-R//nx))*(-(-C//ny)), Kr=ns+nx-1, Kc=nt+ny-1)
 def imod(a, n): return a % n
-def check_fwd(shape, R, C, cus=256, stage_sample=None):
+def vec_ok(start, size, phase):
+    """A 16-byte vector read at element `start` of an fp32 array whose first
+    element sits at word `phase` of a 16-byte line: it must be aligned and
+    share its line with at least one element of the array (so it stays on a
+    page the array occupies)."""
+    return (np.all((start + phase) % 4 == 0) and start.max() <= size - 1 and (start + 3).min() >= 0)
+def check_fwd(shape, R, C, cus=256, stage_sample=None, phases=(0, 1, 2, 3)):
     g = geom(shape, R, C); ns, nt, nx, ny, nz = shape
     E = ns*nt*nx*ny*nz; N = nx*ny
     mtiles, ntiles = -(-g['M']//kMT), -(-N//kNT)
@@ -33,24 +43,53 @@ def check_fwd(shape, R, C, cus=256, stage_sample=None):
     st_list = range(stages) if stage_sample is None else stage_sample(stages)
     for mt, nt_ in itertools.product(range(mtiles), range(ntiles)):
         m0, n0 = mt*kMT, nt_*kNT
-        n = n0 + tid; hoff = np.where(n < N, (n//ny*nt + n % ny)*cell, -1); u = np.where(n < N, n//ny, 0); v = np.where(n < N, n % ny, 0)
-        m = m0 + (tid & 63); zg = tid >> 6
-        P0 = np.where(m < g['M'], nx*(m//g['Lc']) + g['hs'], -(1 << 30)); Q0 = np.where(m < g['M'], ny*(m % g['Lc']) + g['ht'], 0)
         for stage in st_list:
             st, zc = divmod(stage, nzc); sr, tc = divmod(st, g['Kc']); sp, tp = sr-(nx-1), tc-(ny-1)
             z0 = zc*kFwdZC; zn = min(kFwdZC, nz-z0); x, y = imod(g['hs']-sp, nx), imod(g['ht']-tp, ny)
-            vb = (hoff >= 0) & ((sp+u) >= 0) & ((sp+u) < ns) & ((tp+v) >= 0) & ((tp+v) < nt)
-            pb = np.where(vb, (sp*nt+tp)*cell + hoff + (x*ny+y)*nz + z0, 0)
-            for z in range(kFwdZC):
-                idx = pb + (z if z < zn else zn-1)
-                assert idx.min() >= 0 and idx.max() < E, ("B", shape, R, C, stage, z)
-            P, Q = P0 - sp, Q0 - tp
-            va = (P >= 0) & (P < R) & (Q >= 0) & (Q < C)
-            pa = np.where(va, (P*C + Q)*nz + z0, 0)
-            for j in range(kFwdAPer):
-                zl = zg + 4*j
-                idx = pa + np.where(zl < zn, zl, zn-1)
-                assert idx.min() >= 0 and idx.max() < gT_size, ("A", shape, R, C, stage, j)
+            sbase = (sp*nt + tp)*cell + (x*ny + y)*nz + z0
+            for phase in phases:
+                # B: slot e = tid + 256 j -> column nl = e // VPR, vector k = e % VPR
+                cover = np.zeros((kNT, kFwdZC), np.int64)
+                for j in range(kFwdBSlots):
+                    e = tid + j*kThreads; nl, k = e // kFwdVPR, e % kFwdVPR; n = n0 + nl
+                    u, v = n // ny, n % ny
+                    valid = (n < N) & (sp+u >= 0) & (sp+u < ns) & (tp+v >= 0) & (tp+v < nt)
+                    rs = sbase + (u*nt + v)*cell
+                    lead = np.where(valid, (rs + phase) & 3, 0)
+                    vb = np.where(valid, rs - lead, -phase)
+                    kmax = (lead + zn - 1) >> 2
+                    kk = np.minimum(k, kmax)
+                    assert vec_ok(vb + 4*kk, E, phase), ("B", shape, R, C, stage, phase, j)
+                    # the vector holds the run's depths at the positions the store takes them from
+                    src = vb + 4*kk
+                    for q in range(4):
+                        z = 4*k + q - lead
+                        inr = (z >= 0) & (z < kFwdZC)
+                        live = inr & valid & (z < zn)
+                        assert np.all(src[live] + q == rs[live] + z[live])
+                        np.add.at(cover, (nl[inr], z[inr]), 1)
+                assert np.all(cover == 1), ("B cover", shape, stage)
+                # A: 448 slots over 2 per thread
+                cover = np.zeros((kMT, kFwdZC), np.int64)
+                for j in range(kFwdASlots):
+                    e = tid + j*kThreads; ml, k = e // kFwdVPR, e % kFwdVPR; m = m0 + ml
+                    Lp, Lq = m // g['Lc'], m % g['Lc']
+                    P, Q = nx*Lp + g['hs'] - sp, ny*Lq + g['ht'] - tp
+                    valid = (ml < kMT) & (m < g['M']) & (P >= 0) & (P < R) & (Q >= 0) & (Q < C)
+                    rs = (P*C + Q)*nz + z0
+                    lead = np.where(valid, (rs + phase) & 3, 0)
+                    vb = np.where(valid, rs - lead, -phase)
+                    kmax = (lead + zn - 1) >> 2
+                    kk = np.minimum(k, kmax)
+                    assert vec_ok(vb + 4*kk, gT_size, phase), ("A", shape, R, C, stage, phase, j)
+                    src = vb + 4*kk
+                    for q in range(4):
+                        z = 4*k + q - lead
+                        inr = (z >= 0) & (z < kFwdZC) & (ml < kMT)
+                        live = inr & valid & (z < zn)
+                        assert np.all(src[live] + q == rs[live] + z[live])
+                        np.add.at(cover, (ml[inr], z[inr]), 1)
+                assert np.all(cover == 1), ("A cover", shape, stage)
         # partial writes
         for split in [0, splits-1]:
             li, lk = tid & 31, (tid & 63) >> 5; wave = tid >> 6
@@ -119,3 +158,13 @@ def test_projector_addresses_in_bounds_full_size_edges():
     edge = lambda n: sorted(set([0, 1, 2, n // 2, n - 3, n - 2, n - 1]) & set(range(n)))
     check_fwd((165, 165, 15, 15, 21), 600, 600, stage_sample=edge)
     check_bwd((165, 165, 15, 15, 21), 600, 600, kk_sample=edge)
+
+
+def test_projector_addresses_in_bounds_gpu_test_shapes():
+    """The larger shapes the GPU tests run, at edge and randomly sampled stages."""
+    rng = np.random.default_rng(0)
+    pick = lambda n: sorted(set([0, 1, n // 2, n - 2, n - 1]) | set(rng.integers(0, n, 40).tolist()))
+    for shape, R, C in [((45, 45, 15, 15, 5), 120, 105), ((45, 45, 15, 15, 5), 97, 120),
+                        ((165, 165, 15, 15, 21), 120, 120), ((33, 25, 11, 5, 4), 55, 40)]:
+        check_fwd(shape, R, C, stage_sample=pick)
+        check_bwd(shape, R, C, kk_sample=pick)
