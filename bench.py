@@ -203,13 +203,18 @@ def bench_projector(args, torch):
     g = torch.from_numpy(lfsynth.uniform_f32((pw.psf.shape[4], R, C), pw.g_seed)).to(dev)
     f = torch.empty((R, C), device=dev)
     gb = torch.empty_like(g)
+    # scratch for the operand records, allocated once as an iterative solver would
+    wf = torch.empty(lf.forward_workspace_size(H.shape, R, C), dtype=torch.uint8, device=dev)
+    wb = torch.empty(lf.backward_workspace_size(H.shape, R, C), dtype=torch.uint8, device=dev)
+    fwd = lambda: lf.forward(dH, g, out=f, workspace=wf)
+    bwd = lambda: lf.backward(dHt, f, out=gb, workspace=wb)
 
     def step():
-        lf.forward(dH, g, out=f)
-        lf.backward(dHt, f, out=gb)
+        fwd()
+        bwd()
 
-    t_fwd, _ = time_steps(lambda: lf.forward(dH, g, out=f), args.steps, args.warmup, torch)
-    t_bwd, _ = time_steps(lambda: lf.backward(dHt, f, out=gb), args.steps, args.warmup, torch)
+    t_fwd, _ = time_steps(fwd, args.steps, args.warmup, torch)
+    t_bwd, _ = time_steps(bwd, args.steps, args.warmup, torch)
     elapsed, wall = time_steps(step, args.steps, args.warmup, torch)
     sec = elapsed / args.steps
     ns, nt, nx, ny, nz = pw.psf.shape

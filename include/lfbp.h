@@ -159,16 +159,21 @@ LFBP_API lfbp_status lfbp_compute_Ht_batched_config(const lfbp_problem* problems
  * running sums folded into a second float32 accumulator every few hundred
  * terms and the split partial sums added in float64; results do not depend on
  * scheduling (no atomics).
- * Workspace: this call takes lfbp_forward_workspace_size() bytes from the
- * stream-ordered allocator (hipMallocAsync) and returns them on the stream;
- * lfbp_forward_ws uses caller memory instead and allocates nothing.
- * Errors EINVAL (null, R or C < 1), ESHAPE, EALIAS (f overlapping H or g),
- * EALIGN, ENOMEM, EDEVICE.
+ * Workspace: the operands are first copied into the layout the matrix cores
+ * read (H as one record of 22 depth values per (patch shift, pixel class),
+ * g split by pixel phase); this call takes lfbp_forward_workspace_size()
+ * bytes for that from the stream-ordered allocator (hipMallocAsync) and
+ * returns them on the stream; lfbp_forward_ws uses caller memory instead and
+ * allocates nothing.
+ * Errors EINVAL (null, R or C < 1), ESHAPE (including shapes whose operand
+ * copies exceed the kernels' 32-bit index ranges), EALIAS (f overlapping H
+ * or g), EALIGN, ENOMEM, EDEVICE.
  */
 LFBP_API lfbp_status lfbp_forward(const float* H, lfbp_shape shape, const float* g, int64_t R, int64_t C, float* f,
                                   void* stream);
 
-/* Bytes of device workspace lfbp_forward_ws needs for this shape and image. */
+/* Bytes of device workspace lfbp_forward_ws needs for this shape and image
+ * (0 when the shape or image is invalid). */
 LFBP_API int64_t lfbp_forward_workspace_size(lfbp_shape shape, int64_t R, int64_t C);
 
 /* lfbp_forward with a caller-provided device workspace of at least
@@ -189,11 +194,25 @@ LFBP_API lfbp_status lfbp_forward_ws(const float* H, lfbp_shape shape, const flo
  * lfbp_compute_Ht(H) this is exactly the adjoint of lfbp_forward(H).
  * Ht float32 [ns][nt][nx][ny][nz]; f float32 [R][C]; g float32 [nz][R][C],
  * overwritten.  Float32 on the matrix cores with the two-level accumulation
- * of lfbp_forward; deterministic.  Errors EINVAL, ESHAPE, EALIAS, EALIGN,
- * EDEVICE.  Allocates nothing.
+ * of lfbp_forward; deterministic.  Like lfbp_forward it first copies its
+ * operands into the matrix-core layout, in lfbp_backward_workspace_size()
+ * bytes taken from the stream-ordered allocator; lfbp_backward_ws uses
+ * caller memory instead.  Errors EINVAL, ESHAPE, EALIAS, EALIGN, ENOMEM,
+ * EDEVICE.
  */
 LFBP_API lfbp_status lfbp_backward(const float* Ht, lfbp_shape shape, const float* f, int64_t R, int64_t C, float* g,
-                          void* stream);
+                                   void* stream);
+
+/* Bytes of device workspace lfbp_backward_ws needs for this shape and image
+ * (0 when the shape or image is invalid). */
+LFBP_API int64_t lfbp_backward_workspace_size(lfbp_shape shape, int64_t R, int64_t C);
+
+/* lfbp_backward with a caller-provided device workspace of at least
+ * lfbp_backward_workspace_size() bytes, 256-byte aligned, not overlapping
+ * Ht, f or g; its contents are scratch.  Errors as lfbp_backward, plus EINVAL
+ * when the workspace is NULL, too small or misaligned.  Allocates nothing. */
+LFBP_API lfbp_status lfbp_backward_ws(const float* Ht, lfbp_shape shape, const float* f, int64_t R, int64_t C,
+                                      float* g, void* workspace, int64_t workspace_bytes, void* stream);
 
 /* Static text for a status code (never NULL). */
 LFBP_API const char* lfbp_status_string(lfbp_status s);

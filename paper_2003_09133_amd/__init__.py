@@ -22,7 +22,7 @@ from ._abi import (F16, F32, GATHER_AUTO, GATHER_DIRECT, GATHER_STAGED, GATHER_W
                    LfbpError, Problem, Shape)
 
 __all__ = ["compute_Ht", "compute_Ht_into", "compute_Ht_batched", "forward", "forward_workspace_size",
-           "backward", "LFProject",
+           "backward", "backward_workspace_size", "LFProject",
            "project", "default_config", "GatherConfig", "LfbpError", "release_plans", "version",
            "GATHER_AUTO", "GATHER_DIRECT", "GATHER_STAGED", "GATHER_WIDE"]
 
@@ -143,26 +143,39 @@ def forward(H: torch.Tensor, g: torch.Tensor, out: torch.Tensor | None = None, w
         raise ValueError("g must have nz depth planes")
     f = torch.empty((R, C), dtype=torch.float32, device=g.device) if out is None else out
     _check_f32(f, "out", 2)
-    need = forward_workspace_size(H.shape, R, C)
-    if workspace is None:
-        workspace = torch.empty(need, dtype=torch.uint8, device=g.device)
-    if workspace.numel() * workspace.element_size() < need or not workspace.is_cuda:
-        raise ValueError(f"workspace must be a GPU tensor of at least {need} bytes")
+    workspace = _workspace(workspace, forward_workspace_size(H.shape, R, C), g.device)
     _abi.check(_abi.lib().lfbp_forward_ws(H.data_ptr(), Shape.of(H.shape), g.data_ptr(), R, C, f.data_ptr(),
                                           workspace.data_ptr(), workspace.numel() * workspace.element_size(),
                                           _stream(stream)), "lfbp_forward")
     return f
 
 
-def backward(Ht: torch.Tensor, f: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
-    """Backprojection g = H' f: f [R, C] -> g [nz, R, C] (float32)."""
+def backward_workspace_size(shape, R: int, C: int) -> int:
+    """Bytes of scratch device memory the backprojection needs."""
+    return int(_abi.lib().lfbp_backward_workspace_size(Shape.of(shape), int(R), int(C)))
+
+
+def _workspace(workspace, need, device):
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=device)
+    if workspace.numel() * workspace.element_size() < need or not workspace.is_cuda:
+        raise ValueError(f"workspace must be a GPU tensor of at least {need} bytes")
+    return workspace
+
+
+def backward(Ht: torch.Tensor, f: torch.Tensor, out: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
+             stream=None) -> torch.Tensor:
+    """Backprojection g = H' f: f [R, C] -> g [nz, R, C] (float32).
+    The scratch workspace comes from torch's allocator unless given."""
     _check_f32(Ht, "Ht", 5)
     _check_f32(f, "f", 2)
     R, C = f.shape
     g = torch.empty((Ht.shape[4], R, C), dtype=torch.float32, device=f.device) if out is None else out
     _check_f32(g, "out", 3)
-    _abi.check(_abi.lib().lfbp_backward(Ht.data_ptr(), Shape.of(Ht.shape), f.data_ptr(), R, C, g.data_ptr(),
-                                        _stream(stream)), "lfbp_backward")
+    workspace = _workspace(workspace, backward_workspace_size(Ht.shape, R, C), f.device)
+    _abi.check(_abi.lib().lfbp_backward_ws(Ht.data_ptr(), Shape.of(Ht.shape), f.data_ptr(), R, C, g.data_ptr(),
+                                           workspace.data_ptr(), workspace.numel() * workspace.element_size(),
+                                           _stream(stream)), "lfbp_backward")
     return g
 
 

@@ -72,6 +72,8 @@ def lib():
             "lfbp_forward_ws": (st, [vp, Shape, vp, i64, i64, vp, vp, i64, vp]),
             "lfbp_forward_workspace_size": (i64, [Shape, i64, i64]),
             "lfbp_backward": (st, [vp, Shape, vp, i64, i64, vp, vp]),
+            "lfbp_backward_ws": (st, [vp, Shape, vp, i64, i64, vp, vp, i64, vp]),
+            "lfbp_backward_workspace_size": (i64, [Shape, i64, i64]),
             "lfbp_status_string": (ctypes.c_char_p, [st]),
             "lfbp_release_plans": (None, []),
             "lfbp_version": (ctypes.c_char_p, []),

@@ -18,15 +18,39 @@
 //   A = f[nx*LP + hs - r][ny*LQ + ht - r2]
 //   B = Ht[r+cx][r2+cy][(hs - r) mod nx][(ht - r2) mod ny][z]
 //
-// Kernel.  A workgroup of 4 wavefronts owns a 64 x 256 output tile (wave w owns
-// columns 64w..64w+63 as 2 x 2 MFMA tiles of 32 x 32).  The reduction runs in
-// stages staged through double-buffered LDS: the next stage's operands are
-// loaded from global memory into registers while the matrix cores work on the
-// current one.  Accumulation is two-level: the MFMA accumulators are folded into
-// a second float32 register set every few stages, so rounding grows with the
+// Operand records.  Each product runs as one GEMM kernel over "records": the
+// reduction runs in stages of 22 indices, split into two halves of 11 (lanes
+// 0-31 of a wavefront feed the matrix cores from the first half, lanes 32-63
+// from the second, which is a fixed permutation of the reduction order), and
+// one stage of one operand row or column is a record of 24 floats: the halves
+// at offsets 0 and 12, each padded with one zero.  Before the GEMM the
+// operands are copied into records, with explicit zeros wherever the
+// formulation above has zeros:
+//   forward  B[stage][class][24] from H; A from g split by pixel phase,
+//            one block per (px, py, depth chunk) holding a record per lenslet
+//            of the phase plane, with zero lenslets around the image, so the
+//            record of lenslet (Lp,Lq) at stage (s',t',chunk) is the record at
+//            lenslet offset (floor((hs-s')/nx), floor((ht-t')/ny)) in phase
+//            plane ((hs-s') mod nx, (ht-t') mod ny);
+//   backward A[stage][lenslet][24] from f and B[stage][column][24] from H'.
+// A lane reads its half of a record as three 16-byte vectors and hands the
+// values to the matrix cores straight from registers.  The records of one
+// block (one stage of one operand, or one phase plane and depth chunk of g)
+// are stored vector-major, [vector v][record][half][4 floats], so that each
+// 16-byte load instruction of a wavefront reads 1 KB of consecutive memory.
+//
+// GEMM kernel.  A workgroup of 4 wavefronts owns a 64 x 256 output tile; wave
+// w owns columns 64w..64w+63 as 2 x 2 MFMA tiles of 32 x 32 and works on its
+// own: each lane loads the next stage's records (its two rows and two columns)
+// into registers while the matrix cores consume the current stage, so there
+// is neither LDS staging nor a workgroup barrier in the loop.  Accumulation is
+// two-level: the MFMA accumulators are folded into float32 sums held in LDS
+// (one region per wavefront) every few stages, so rounding grows with the
 // chunk length, not with the ~10^5-10^6 terms of a full sum.  The forward
-// splits K over workgroups (partials reduced in a fixed order by a second
-// kernel, so results are deterministic); the backward needs no split.
+// splits the reduction over workgroups (partials added in a fixed order, in
+// float64, by a second kernel, so results are deterministic); the backward
+// needs no split.  Workgroups that read the same operand slab are placed on
+// the same XCD (L2).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -36,24 +60,27 @@
 namespace lfbp {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kMT = 64;       // output rows (lenslet positions) per workgroup
-constexpr int kNT = 256;      // output columns per workgroup (4 waves x 64)
-constexpr int kAStride = kMT + 1;   // LDS row strides, padded against bank conflicts
-constexpr int kBStride = kNT + 1;
-constexpr int kFwdZC = 22;    // forward: depth planes per stage (even)
-constexpr int kBwdKC = 16;    // backward: (r, r2) pairs per stage
-constexpr int kFold = 16;     // stages between folds of the MFMA accumulators
+constexpr int kMT = 64;              // output rows per workgroup (shared by its 4 waves)
+constexpr int kNT = 256;             // output columns per workgroup (64 per wave)
+constexpr int kHalf = 11;            // MFMA steps per stage (two reduction indices each)
+constexpr int kStageK = 2 * kHalf;   // reduction indices per stage
+constexpr int kRec = 24;             // floats per record (halves at 0 and 12)
+constexpr int kRecVec = kRec / 4;    // 16-byte vectors per record (3 per half)
+constexpr int kFold = 16;            // stages between folds of the MFMA accumulators
+constexpr int kXcds = 8;
+constexpr int kTargetBlocks = 512;
 
 struct ProjGeom {
     int ns, nt, nx, ny, nz, hs, ht, R, C;
     int Lr, Lc;   // lenslets per image side (ceil(R/nx), ceil(C/ny))
     int M;        // Lr*Lc
     int Kr, Kc;   // ns+nx-1, nt+ny-1
-    FastDiv fKc, fny, fnz, fzc;
+    FastDiv fKc, fny, fnz, fLc;
 };
 
 ProjGeom make_geom(const lfbp_shape& s, int64_t R, int64_t C)
@@ -76,7 +103,7 @@ ProjGeom make_geom(const lfbp_shape& s, int64_t R, int64_t C)
     g.fKc = make_fastdiv(uint32_t(g.Kc));
     g.fny = make_fastdiv(uint32_t(g.ny));
     g.fnz = make_fastdiv(uint32_t(g.nz));
-    g.fzc = make_fastdiv(uint32_t(kFwdZC));
+    g.fLc = make_fastdiv(uint32_t(g.Lc));
     return g;
 }
 
@@ -86,202 +113,470 @@ __device__ __forceinline__ int imod(int a, int n)
     return r < 0 ? r + n : r;
 }
 
-// MFMA work of one stage from LDS buffers As[kc][kAStride], Bs[kc][kBStride].
-__device__ __forceinline__ void mma_stage(const float* As, const float* Bs, int kc, int wave, int lane,
-                                          f32x16 (&acc)[2][2])
+// Reduction index inside a stage of record slot q (0..23); -1 for the pads.
+__device__ __forceinline__ int slot_k(int q)
 {
-    const int li = lane & 31, lk = lane >> 5;
-    const int nb = wave * 64;
-    for (int s = 0; s < kc; s += 2) {
-        const int k = s + lk;
-        const float a0 = As[k * kAStride + li];
-        const float a1 = As[k * kAStride + 32 + li];
-        const float b0 = Bs[k * kBStride + nb + li];
-        const float b1 = Bs[k * kBStride + nb + 32 + li];
+    const int h = q >= 12 ? 1 : 0, j = q - 12 * h;
+    return j < kHalf ? kHalf * h + j : -1;
+}
+
+struct GemmArgs {
+    const float* A;   // left operand records
+    const float* B;   // right operand records [stage][Npad][kRec]
+    float* out;       // forward: partial tiles [splits][Mpad][Npad]; backward: g [nz][R][C]
+    ProjGeom g;
+    int M, N, Mpad, Npad;
+    int mtiles, ntiles;
+    int stages, splits;
+    // forward: A blocks are (px, py, depth chunk), LRp x LCp records each
+    int nzc, LRp, LCp, padP, padQ;
+    FastDiv fnzc;
+};
+
+// Geometry of the forward depth chunking and of the phase-split copy of g.
+struct FwdLayout {
+    int nzc;            // depth chunks of kStageK planes
+    int stages;         // Kr*Kc*nzc
+    int padP, padQ;     // zero lenslets before the image (rows, columns)
+    int LRp, LCp;       // padded lenslet grid
+};
+
+FwdLayout fwd_layout(const ProjGeom& g)
+{
+    FwdLayout L;
+    L.nzc = (g.nz + kStageK - 1) / kStageK;
+    L.stages = g.Kr * g.Kc * L.nzc;
+    // lenslet offsets floor((hs - s')/nx) over s' in [-(nx-1), ns-1] span
+    // [-ceil(hs/nx), floor((hs+nx-1)/nx)] = [-pad, pad]
+    L.padP = (g.hs + g.nx - 1) / g.nx;
+    L.padQ = (g.ht + g.ny - 1) / g.ny;
+    L.LRp = g.Lr + 2 * L.padP;
+    L.LCp = g.Lc + 2 * L.padQ;
+    return L;
+}
+
+// Forward stage (s', t', chunk) of stage index s: Kr*Kc*nzc stages, chunk fastest.
+struct FwdStage {
+    int sp, tp, zc, px, py, dP, dQ;
+};
+
+__device__ __forceinline__ FwdStage fwd_stage(const ProjGeom& g, const FastDiv& fnzc, int nzc, int s)
+{
+    FwdStage t;
+    const int st = int(fdiv(uint32_t(s), fnzc));
+    t.zc = s - st * nzc;
+    const int sr = int(fdiv(uint32_t(st), g.fKc)), tc = st - sr * g.Kc;
+    t.sp = sr - (g.nx - 1);
+    t.tp = tc - (g.ny - 1);
+    const int e = g.hs - t.sp, f = g.ht - t.tp;
+    t.px = imod(e, g.nx);
+    t.py = imod(f, g.ny);
+    t.dP = (e - t.px) / g.nx;   // exact: floor(e / nx)
+    t.dQ = (f - t.py) / g.ny;
+    return t;
+}
+
+// --------------------------------------------------------------- GEMM kernel
+
+struct Frag {
+    f32x4 a[2][3];   // rows 32i + (lane mod 32), this lane's half of the stage
+    f32x4 b[2][3];   // columns 32j + (lane mod 32)
+};
+
+// Record blocks are read through buffer resources: a wavefront-uniform base
+// and size in scalar registers, this lane's 32-bit byte offset in a vector
+// register, the vector plane's offset in a scalar register.  No per-load
+// address arithmetic or address registers in the vector file, and a read
+// outside the block returns zeros instead of touching other memory.
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+constexpr int kRsrcWord3 = 0x00020000;   // raw buffer, 32-bit data format
+
+__device__ __forceinline__ Rsrc make_rsrc(const char* base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(base), short(0), int(bytes), kRsrcWord3);
+}
+
+__device__ __forceinline__ f32x4 load_vec(Rsrc r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, int(voff), int(soff), 0));
+}
+
+// ra, rb: the stage's A and B record blocks; oa, ob: this lane's (record,
+// half) byte offsets; sa, sb: bytes between the vector planes of a block.
+__device__ __forceinline__ void load_frag(Rsrc ra, Rsrc rb, const uint32_t (&oa)[2], const uint32_t (&ob)[2],
+                                          uint32_t sa, uint32_t sb, Frag& f)
+{
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int v = 0; v < 3; ++v) f.a[i][v] = load_vec(ra, oa[i], v * sa);
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 3; ++v) f.b[j][v] = load_vec(rb, ob[j], v * sb);
+}
+
+__device__ __forceinline__ void mma_stage(const Frag& f, f32x16 (&acc)[2][2])
+{
+#pragma unroll
+    for (int s = 0; s < kHalf; ++s) {
+        const float a0 = f.a[0][s >> 2][s & 3], a1 = f.a[1][s >> 2][s & 3];
+        const float b0 = f.b[0][s >> 2][s & 3], b1 = f.b[1][s >> 2][s & 3];
         acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
         acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
         acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
         acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
     }
+    // The last float of each half (a zero pad) is never read by the MFMAs.  Keep
+    // the whole loaded vector live until here anyway: otherwise its register is
+    // handed out while the load that fills it is still in flight, and the
+    // reuse forces a wait for the prefetch of later stages.
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        asm volatile("" ::"v"(f.a[i][2]));
+        asm volatile("" ::"v"(f.b[i][2]));
+    }
 }
 
-__device__ __forceinline__ void fold(f32x16 (&acc)[2][2], f32x16 (&tot)[2][2])
+// T[tile][quad][lane] += accumulator registers 4*quad .. 4*quad+3; acc = 0.
+__device__ __forceinline__ void fold(f32x16 (&acc)[2][2], f32x4 (*T)[4][64], int lane)
 {
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-            tot[i][j] += acc[i][j];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                f32x4 v = T[2 * i + j][q][lane];
+                v.x += acc[i][j][4 * q];
+                v.y += acc[i][j][4 * q + 1];
+                v.z += acc[i][j][4 * q + 2];
+                v.w += acc[i][j][4 * q + 3];
+                T[2 * i + j][q][lane] = v;
+            }
             acc[i][j] = f32x16{};
         }
 }
 
-// ------------------------------------------------------------------ forward
-
-// Operand fetch of one forward stage (stage = one (s', t') pair and one chunk
-// of up to kFwdZC depth planes).  Every B column (pixel class (u,v)) and every
-// A row (lenslet) needs one contiguous run of <= kFwdZC floats: H[s'+u][t'+v]
-// [x][y][z0..] and gT[P][Q][z0..].  Each run is read as the kFwdVPR aligned
-// 16-byte vectors that cover it (consecutive lanes take consecutive vectors of
-// a run), and the vectors are scattered into the LDS tile when it is written,
-// after the stage's MFMA work.  A 16-byte aligned vector that holds at least
-// one element of the run never leaves the run's page, so the reads need no
-// bounds branch; elements outside the run are written to LDS as zeros.
-constexpr int kFwdVPR = (kFwdZC + 3 + 3) / 4;                           // vectors per run: 7
-constexpr int kFwdBSlots = kNT * kFwdVPR / kThreads;                     // 7 per thread
-constexpr int kFwdASlots = (kMT * kFwdVPR + kThreads - 1) / kThreads;    // 2 per thread
-static_assert(kNT * kFwdVPR % kThreads == 0, "B slots must tile the workgroup");
-
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-
-struct FwdArgs {
-    const float* H;    // [ns][nt][nx][ny][nz]
-    const float* gT;   // [R][C][nz]  (g with depth innermost)
-    float* partial;    // [splits][Mpad][Npad]
-    ProjGeom g;
-    int N, Npad, Mpad;
-    int stages;        // Kr*Kc*nzc
-    int nzc;           // depth chunks
-    int splits;
-    int phaseH;        // (address of H / 4) mod 4
-    int phaseG;        // (address of gT / 4) mod 4
-};
-
-// Loaded vectors of one stage and, per slot, the run's offset inside its first
-// vector (bits 0-1) and whether the run exists (bit 2).
-struct FwdRegs {
-    u32x4 b[kFwdBSlots];
-    u32x4 a[kFwdASlots];
-    uint32_t bmeta[kFwdBSlots];
-    uint32_t ameta[kFwdASlots];
-    int zn;  // depth planes present in the stage (uniform)
-};
-
-__device__ __forceinline__ void fwd_load(const FwdArgs& a, int m0, int n0, int stage, FwdRegs& R)
+// Workgroup -> (m tile, n tile, split), with consecutive logical indices (same
+// n tile / split, all m tiles) on the same XCD: dispatch deals workgroups to
+// the XCDs round-robin.
+__device__ __forceinline__ void tile_of_block(const GemmArgs& a, int& mt, int& nt, int& split)
 {
+    const int nb = a.mtiles * a.ntiles * a.splits;
+    const int b = int(blockIdx.x);
+    const int x = b % kXcds, q = nb / kXcds, r = nb % kXcds;
+    const int L = x * q + min(x, r) + b / kXcds;
+    mt = L % a.mtiles;
+    const int rest = L / a.mtiles;
+    nt = rest % a.ntiles;
+    split = rest / a.ntiles;
+}
+
+template <bool kFwd>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) k_gemm(GemmArgs a)
+{
+    __shared__ f32x4 tot[kThreads / 64][4][4][64];   // per wave: 4 tiles x 16 sums x 64 lanes
+    int mt, ntile, split;
+    tile_of_block(a, mt, ntile, split);
     const ProjGeom& g = a.g;
-    const int st = stage / a.nzc, zc = stage - st * a.nzc;
-    const int sr = int(fdiv(uint32_t(st), g.fKc)), tc = st - sr * g.Kc;
-    const int sp = sr - (g.nx - 1), tp = tc - (g.ny - 1);  // s', t'
-    const int z0 = zc * kFwdZC, zn = min(kFwdZC, g.nz - z0);
-    const int x = imod(g.hs - sp, g.nx), y = imod(g.ht - tp, g.ny);
-    const int64_t cell = int64_t(g.nx) * g.ny * g.nz;
-    const int64_t sbase = (int64_t(sp) * g.nt + tp) * cell + (int64_t(x) * g.ny + y) * g.nz + z0;
-    const int tid = threadIdx.x;
-    R.zn = zn;
-#pragma unroll
-    for (int j = 0; j < kFwdBSlots; ++j) {
-        const int e = tid + j * kThreads;
-        const int nl = e / kFwdVPR, k = e - nl * kFwdVPR;
-        const int n = n0 + nl;
-        const int u = int(fdiv(uint32_t(n), g.fny)), v = n - u * g.ny;
-        const bool valid = (n < a.N) & (unsigned(sp + u) < unsigned(g.ns)) & (unsigned(tp + v) < unsigned(g.nt));
-        const int64_t rs = sbase + (int64_t(u) * g.nt + v) * cell;
-        const int lead = valid ? int((rs + a.phaseH) & 3) : 0;
-        const int64_t vb = valid ? rs - lead : -int64_t(a.phaseH);
-        const int kmax = (lead + zn - 1) >> 2;
-        const int kk = k < kmax ? k : kmax;                 // always a vector that overlaps the run
-        R.b[j] = *reinterpret_cast<const u32x4*>(a.H + vb + 4 * kk);
-        R.bmeta[j] = uint32_t(lead) | (uint32_t(valid) << 2);
-    }
-#pragma unroll
-    for (int j = 0; j < kFwdASlots; ++j) {
-        const int e = tid + j * kThreads;
-        const int ml = e / kFwdVPR, k = e - ml * kFwdVPR;
-        const int m = m0 + ml;
-        const int Lp = m / g.Lc, Lq = m - Lp * g.Lc;
-        const int P = g.nx * Lp + g.hs - sp, Q = g.ny * Lq + g.ht - tp;
-        const bool valid = (ml < kMT) & (m < g.M) & (P >= 0) & (P < g.R) & (Q >= 0) & (Q < g.C);
-        const int64_t rs = (int64_t(P) * g.C + Q) * g.nz + z0;
-        const int lead = valid ? int((rs + a.phaseG) & 3) : 0;
-        const int64_t vb = valid ? rs - lead : -int64_t(a.phaseG);
-        const int kmax = (lead + zn - 1) >> 2;
-        const int kk = k < kmax ? k : kmax;
-        R.a[j] = *reinterpret_cast<const u32x4*>(a.gT + vb + 4 * kk);
-        R.ameta[j] = uint32_t(lead) | (uint32_t(valid) << 2);
-    }
-}
-
-// Scatter the stage's vectors into As[z][m] and Bs[z][n]: vector k of a run
-// holds depths 4k - lead .. 4k - lead + 3, so the kFwdVPR vectors of a run
-// write every depth 0..kFwdZC-1 of its row or column exactly once.
-__device__ __forceinline__ void fwd_store(float* As, float* Bs, const FwdRegs& R)
-{
-    const int tid = threadIdx.x;
-#pragma unroll
-    for (int j = 0; j < kFwdBSlots; ++j) {
-        const int e = tid + j * kThreads;
-        const int nl = e / kFwdVPR, k = e - nl * kFwdVPR;
-        const int lead = int(R.bmeta[j] & 3u);
-        const bool valid = (R.bmeta[j] >> 2) & 1u;
-        const float v4[4] = {__uint_as_float(R.b[j].x), __uint_as_float(R.b[j].y), __uint_as_float(R.b[j].z),
-                             __uint_as_float(R.b[j].w)};
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int z = 4 * k + q - lead;
-            if (z >= 0 && z < kFwdZC) Bs[z * kBStride + nl] = (valid & (z < R.zn)) ? v4[q] : 0.0f;
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < kFwdASlots; ++j) {
-        const int e = tid + j * kThreads;
-        const int ml = e / kFwdVPR, k = e - ml * kFwdVPR;
-        if (ml >= kMT) continue;
-        const int lead = int(R.ameta[j] & 3u);
-        const bool valid = (R.ameta[j] >> 2) & 1u;
-        const float v4[4] = {__uint_as_float(R.a[j].x), __uint_as_float(R.a[j].y), __uint_as_float(R.a[j].z),
-                             __uint_as_float(R.a[j].w)};
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int z = 4 * k + q - lead;
-            if (z >= 0 && z < kFwdZC) As[z * kAStride + ml] = (valid & (z < R.zn)) ? v4[q] : 0.0f;
-        }
-    }
-}
-
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) k_fwd_gemm(FwdArgs a)
-{
-    __shared__ float As[2][kFwdZC * kAStride];
-    __shared__ float Bs[2][kFwdZC * kBStride];
-    const int m0 = blockIdx.x * kMT, n0 = blockIdx.y * kNT, split = blockIdx.z;
+    const int m0 = mt * kMT, n0 = ntile * kNT;
     const int s_begin = int(int64_t(a.stages) * split / a.splits);
     const int s_end = int(int64_t(a.stages) * (split + 1) / a.splits);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const bool active = n0 + wave * 64 < a.Npad;
-    f32x16 acc[2][2] = {}, tot[2][2] = {};
-    FwdRegs regs;
-    if (s_begin < s_end) {
-        fwd_load(a, m0, n0, s_begin, regs);
-        fwd_store(As[0], Bs[0], regs);
-        __syncthreads();
+    const int wave = int(threadIdx.x) >> 6, lane = int(threadIdx.x) & 63;
+    const int li = lane & 31, lk = lane >> 5;
+    f32x4 (*T)[4][64] = tot[wave];
+
+    // Record r, half h of a block sits at 16-byte vector 2r + h of each of the
+    // block's three vector planes; lane offsets are in bytes.
+    const int64_t arows = kFwd ? int64_t(a.LRp) * a.LCp : a.Mpad;   // records per A block
+    uint32_t oa[2], ob[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int m = m0 + 32 * i + li;
+        if (kFwd) {
+            const int mc = min(m, a.M - 1);   // rows past the last lenslet compute unused values
+            const int Lp = int(fdiv(uint32_t(mc), g.fLc)), Lq = mc - Lp * g.Lc;
+            oa[i] = uint32_t(16 * (2 * (Lp * a.LCp + Lq) + lk));
+        } else {
+            oa[i] = uint32_t(16 * (2 * m + lk));
+        }
     }
-    int buf = 0, since = 0;
-    for (int s = s_begin; s < s_end; ++s) {
-        const bool more = s + 1 < s_end;
-        if (more) fwd_load(a, m0, n0, s + 1, regs);
-        if (active) mma_stage(As[buf], Bs[buf], kFwdZC, wave, lane, acc);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) ob[j] = uint32_t(16 * (2 * (n0 + 64 * wave + 32 * j + li) + lk));
+    const char* A1 = reinterpret_cast<const char*>(a.A);
+    const char* B1 = reinterpret_cast<const char*>(a.B);
+    const uint32_t ablock = uint32_t(16 * kRecVec * arows), bblock = uint32_t(16 * kRecVec * a.Npad);
+
+    auto a_rsrc = [&](int s) -> Rsrc {
+        if (!kFwd) return make_rsrc(A1 + int64_t(s) * ablock, ablock);
+        // block (phase plane, depth chunk), shifted by the stage's lenslet offset
+        const FwdStage t = fwd_stage(g, a.fnzc, a.nzc, s);
+        const uint32_t shift = uint32_t(32 * ((t.dP + a.padP) * a.LCp + t.dQ + a.padQ));
+        return make_rsrc(A1 + int64_t(t.px * g.ny + t.py) * a.nzc * ablock + int64_t(t.zc) * ablock + shift,
+                         ablock - shift);
+    };
+
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) T[t][q][lane] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    f32x16 acc[2][2] = {};
+    // Three register sets rotate, so the loads of a stage are issued two
+    // stages (~2 x 44 MFMAs per wave) before its MFMAs: enough to cover reads
+    // that miss the L2.  Every load is issued unconditionally (the stage index
+    // is clamped) so that the wait before a stage's MFMAs only covers that
+    // stage's loads, never the prefetch behind it.
+    const int s_last = max(s_begin, s_end - 1);
+    auto load = [&](int s, Frag& f) {
+        const int sc = min(s, s_last);
+        load_frag(a_rsrc(sc), make_rsrc(B1 + int64_t(sc) * bblock, bblock), oa, ob, uint32_t(32 * arows),
+                  uint32_t(32 * a.Npad), f);
+        // keep the prefetch ahead of the MFMAs that follow (compiler barrier for
+        // the optimiser, scheduling barrier for the back end)
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    Frag f0, f1, f2;
+    int since = 0;
+    auto step = [&](const Frag& f) {
+        mma_stage(f, acc);
         if (++since == kFold) {
-            fold(acc, tot);
+            fold(acc, T, lane);
             since = 0;
         }
-        if (more) fwd_store(As[buf ^ 1], Bs[buf ^ 1], regs);
-        __syncthreads();
-        buf ^= 1;
+    };
+    if (s_begin < s_end) {
+        // Whole groups of three stages in a loop with one path through it (so
+        // the wait analysis sees the same loads in flight on every entry),
+        // then the zero to two stages left, whose loads the last group issued.
+        load(s_begin, f0);
+        load(s_begin + 1, f1);
+        int s = s_begin;
+        for (const int s3 = s_begin + (s_end - s_begin) / 3 * 3; s < s3; s += 3) {
+            load(s + 2, f2);
+            step(f0);
+            load(s + 3, f0);
+            step(f1);
+            load(s + 4, f1);
+            step(f2);
+        }
+        if (s < s_end) step(f0);
+        if (s + 1 < s_end) step(f1);
     }
-    fold(acc, tot);
-    if (!active) return;
-    float* out = a.partial + size_t(split) * a.Mpad * a.Npad;
-    const int li = lane & 31, lk = lane >> 5;
+    fold(acc, T, lane);
+
+    const int nb = n0 + 64 * wave;
+    if (kFwd) {
+        float* out = a.out + size_t(split) * a.Mpad * a.Npad;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+            for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int m = m0 + 32 * i + 8 * (r >> 2) + 4 * lk + (r & 3);
-                const int n = n0 + wave * 64 + 32 * j + li;
-                out[size_t(m) * a.Npad + n] = tot[i][j][r];
-            }
+                for (int q = 0; q < 4; ++q) {
+                    const f32x4 v = T[2 * i + j][q][lane];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int m = m0 + 32 * i + 8 * q + 4 * lk + e;
+                        out[size_t(m) * a.Npad + nb + 32 * j + li] = v[e];
+                    }
+                }
+    } else {
+        const size_t plane = size_t(g.R) * g.C;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int n = nb + 32 * j + li;
+            if (n >= a.N) continue;
+            const int c = int(fdiv(uint32_t(n), g.fnz)), z = n - c * g.nz;
+            const int cx = int(fdiv(uint32_t(c), g.fny)), cy = c - cx * g.ny;
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const f32x4 v = T[2 * i + j][q][lane];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int m = m0 + 32 * i + 8 * q + 4 * lk + e;
+                        if (m >= g.M) continue;
+                        const int Lp = int(fdiv(uint32_t(m), g.fLc)), Lq = m - Lp * g.Lc;
+                        const int P = g.nx * Lp + cx, Q = g.ny * Lq + cy;
+                        if (P < g.R && Q < g.C) a.out[z * plane + size_t(P) * g.C + Q] = v[e];
+                    }
+                }
+        }
+    }
+}
+
+// ------------------------------------------------------------ operand packing
+
+struct PackArgs {
+    ProjGeom g;
+    int N, Npad, Mpad;
+    int stages;
+    int nzc, LRp, LCp, padP, padQ;
+    FastDiv fnzc, fLCp;
+};
+
+// Item i of a block of `rows` records (i < 6 rows): vector plane v, record r,
+// half h, in the block's storage order; slot0 = first slot of the 4 it holds.
+struct RecItem {
+    int r, slot0;
+};
+
+__device__ __forceinline__ RecItem rec_item(int i, int rows)
+{
+    const int v = i / (2 * rows), rem = i - v * 2 * rows;
+    RecItem it;
+    it.r = rem >> 1;
+    it.slot0 = 12 * (rem & 1) + 4 * v;
+    return it;
+}
+
+// Forward B records: record n of stage s holds, at the slot of depth z,
+// H[s'+u][t'+v][(hs-s') mod nx][(ht-t') mod ny][z] for class n = (u,v) (0
+// outside the patch).  A workgroup builds kNT records of one stage: it reads
+// each record's run of H with six neighbouring lanes into LDS, record-major,
+// then writes the block in its vector-major order, 1 KB per wavefront store.
+__global__ void __launch_bounds__(256) k_pack_fwd_b(const float* H, PackArgs p, float* Bp)
+{
+    __shared__ f32x4 rec[kNT * kRecVec];
+    const ProjGeom& g = p.g;
+    const int s = int(blockIdx.x), n0 = int(blockIdx.y) * kNT;
+    const FwdStage t = fwd_stage(g, p.fnzc, p.nzc, s);
+    const int64_t cell = int64_t(g.nx) * g.ny * g.nz;
+    const int64_t xy = (int64_t(t.px) * g.ny + t.py) * g.nz + int64_t(t.zc) * kStageK;
+#pragma unroll
+    for (int k = 0; k < kRecVec; ++k) {
+        const int i = int(threadIdx.x) + k * kThreads;   // record i / 6, vector i % 6
+        const int nl = i / kRecVec, c = i - nl * kRecVec, n = n0 + nl;
+        const int u = int(fdiv(uint32_t(n), g.fny)), v = n - u * g.ny;
+        const bool valid = n < p.N && unsigned(t.sp + u) < unsigned(g.ns) && unsigned(t.tp + v) < unsigned(g.nt);
+        const int64_t run = valid ? (int64_t(t.sp + u) * g.nt + (t.tp + v)) * cell + xy : 0;
+        f32x4 o;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int kz = slot_k(4 * c + q);
+            o[q] = (valid && kz >= 0 && t.zc * kStageK + kz < g.nz) ? H[run + kz] : 0.0f;
+        }
+        rec[i] = o;
+    }
+    __syncthreads();
+    f32x4* out = reinterpret_cast<f32x4*>(Bp) + int64_t(s) * kRecVec * p.Npad;
+#pragma unroll
+    for (int k = 0; k < kRecVec; ++k) {
+        const int j = int(threadIdx.x) + k * kThreads;   // vector plane j / 512, record, half
+        const int vp = j / (2 * kNT), rem = j - vp * 2 * kNT, nl = rem >> 1, h = rem & 1;
+        out[(int64_t(vp) * p.Npad + n0 + nl) * 2 + h] = rec[nl * kRecVec + 3 * h + vp];
+    }
+}
+
+// g with depth innermost: gT[P][Q][z] = g[z][P][Q], through an LDS tile.
+__global__ void __launch_bounds__(256) k_depth_last(const float* g, int nz, int plane, float* gT)
+{
+    __shared__ float tile[32][33];
+    const int z0 = blockIdx.y * 32, p0 = blockIdx.x * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+    for (int r = ty; r < 32; r += 8) {
+        const int z = z0 + r, pix = p0 + tx;
+        tile[r][tx] = (z < nz && pix < plane) ? g[size_t(z) * plane + pix] : 0.0f;
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int pix = p0 + r, z = z0 + tx;
+        if (pix < plane && z < nz) gT[size_t(pix) * nz + z] = tile[tx][r];
+    }
+}
+
+// Forward A records, g split by pixel phase with zero lenslets around it: the
+// block of (px, py, depth chunk zc) holds record LP*LCp + LQ with slot values
+// g[z][nx(LP-padP)+px][ny(LQ-padQ)+py] (0 outside the image).
+__global__ void __launch_bounds__(256) k_pack_fwd_a(const float* gT, PackArgs p, float* gS)
+{
+    const ProjGeom& g = p.g;
+    const int blk = int(blockIdx.x);   // (px, py, zc)
+    const int rows = p.LRp * p.LCp;
+    const int item = int(blockIdx.y) * 256 + int(threadIdx.x);
+    if (item >= rows * kRecVec) return;
+    const int pxy = int(fdiv(uint32_t(blk), p.fnzc)), zc = blk - pxy * p.nzc;
+    const int px = int(fdiv(uint32_t(pxy), g.fny)), py = pxy - px * g.ny;
+    const RecItem it = rec_item(item, rows);
+    const int LP = int(fdiv(uint32_t(it.r), p.fLCp)), LQ = it.r - LP * p.LCp;
+    const int P = g.nx * (LP - p.padP) + px, Q = g.ny * (LQ - p.padQ) + py;
+    const bool valid = unsigned(P) < unsigned(g.R) && unsigned(Q) < unsigned(g.C);
+    const int64_t run = valid ? (int64_t(P) * g.C + Q) * g.nz : 0;
+    f32x4 o;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int k = slot_k(it.slot0 + q);
+        const int z = zc * kStageK + k;
+        o[q] = (valid && k >= 0 && z < g.nz) ? gT[run + z] : 0.0f;
+    }
+    reinterpret_cast<f32x4*>(gS)[int64_t(blk) * kRecVec * rows + item] = o;
+}
+
+// Backward reduction index k (0..Kr*Kc-1) -> (r, r2).
+__device__ __forceinline__ void bwd_pair(const ProjGeom& g, int k, int& r, int& r2)
+{
+    const int ri = int(fdiv(uint32_t(k), g.fKc));
+    r = ri - (g.nx - 1);
+    r2 = k - ri * g.Kc - (g.ny - 1);
+}
+
+// Backward B records: Bp[s][n][slot] = Ht[r+cx][r2+cy][(hs-r) mod nx][(ht-r2) mod ny][z]
+// for column n = (cx,cy,z) and the pair (r,r2) of the slot (0 outside).
+__global__ void __launch_bounds__(256) k_pack_bwd_b(const float* Ht, PackArgs p, float* Bp)
+{
+    const ProjGeom& g = p.g;
+    const int s = int(blockIdx.x);
+    const int item = int(blockIdx.y) * 256 + int(threadIdx.x);
+    if (item >= p.Npad * kRecVec) return;
+    const RecItem it = rec_item(item, p.Npad);
+    const int n = it.r;
+    const int cz = int(fdiv(uint32_t(n), g.fnz)), z = n - cz * g.nz;
+    const int cx = int(fdiv(uint32_t(cz), g.fny)), cy = cz - cx * g.ny;
+    const int64_t cell = int64_t(g.nx) * g.ny * g.nz;
+    const int K = g.Kr * g.Kc;
+    f32x4 o;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int kk = slot_k(it.slot0 + q);
+        const int k = s * kStageK + kk;
+        int r = 0, r2 = 0;
+        bwd_pair(g, k, r, r2);
+        const bool valid = n < p.N && kk >= 0 && k < K && unsigned(r + cx) < unsigned(g.ns) &&
+                           unsigned(r2 + cy) < unsigned(g.nt);
+        const int x = imod(g.hs - r, g.nx), y = imod(g.ht - r2, g.ny);
+        const int64_t idx = (int64_t(r + cx) * g.nt + (r2 + cy)) * cell + (int64_t(x) * g.ny + y) * g.nz + z;
+        o[q] = valid ? Ht[idx] : 0.0f;
+    }
+    reinterpret_cast<f32x4*>(Bp)[int64_t(s) * kRecVec * p.Npad + item] = o;
+}
+
+// Backward A records: Ap[s][m][slot] = f[nx*LP + hs - r][ny*LQ + ht - r2] for
+// lenslet m = (LP,LQ) and the pair (r,r2) of the slot (0 outside the image).
+__global__ void __launch_bounds__(256) k_pack_bwd_a(const float* f, PackArgs p, float* Ap)
+{
+    const ProjGeom& g = p.g;
+    const int s = int(blockIdx.x);
+    const int item = int(blockIdx.y) * 256 + int(threadIdx.x);
+    if (item >= p.Mpad * kRecVec) return;
+    const RecItem it = rec_item(item, p.Mpad);
+    const int m = it.r;
+    const int LP = int(fdiv(uint32_t(m), g.fLc)), LQ = m - LP * g.Lc;
+    const int K = g.Kr * g.Kc;
+    f32x4 o;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int kk = slot_k(it.slot0 + q);
+        const int k = s * kStageK + kk;
+        int r = 0, r2 = 0;
+        bwd_pair(g, k, r, r2);
+        const int P = g.nx * LP + g.hs - r, Q = g.ny * LQ + g.ht - r2;
+        const bool valid = m < g.M && kk >= 0 && k < K && unsigned(P) < unsigned(g.R) && unsigned(Q) < unsigned(g.C);
+        o[q] = valid ? f[valid ? int64_t(P) * g.C + Q : 0] : 0.0f;
+    }
+    reinterpret_cast<f32x4*>(Ap)[int64_t(s) * kRecVec * p.Mpad + item] = o;
 }
 
 // f[p][q] = sum over splits of the partial tile entry of (lenslet, class).
@@ -298,236 +593,192 @@ __global__ void __launch_bounds__(256) k_fwd_reduce(const float* partial, int sp
     f[i] = float(acc);
 }
 
-// gT[P][Q][z] = g[z][P][Q] through an LDS tile.
-__global__ void __launch_bounds__(256) k_depth_last(const float* g, int nz, int plane, float* gT)
-{
-    __shared__ float tile[32][33];
-    const int z0 = blockIdx.y * 32, p0 = blockIdx.x * 32;
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
-    for (int r = ty; r < 32; r += 8) {
-        const int z = z0 + r, p = p0 + tx;
-        tile[r][tx] = (z < nz && p < plane) ? g[size_t(z) * plane + p] : 0.0f;
-    }
-    __syncthreads();
-    for (int r = ty; r < 32; r += 8) {
-        const int p = p0 + r, z = z0 + tx;
-        if (p < plane && z < nz) gT[size_t(p) * nz + z] = tile[tx][r];
-    }
-}
+// ---------------------------------------------------------------- host side
 
-// ------------------------------------------------------------------ backward
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
-constexpr int kBwdAPer = (kMT * kBwdKC + kThreads - 1) / kThreads;  // 4 pairs per thread
-constexpr int kBwdBPer = kBwdKC;                                    // one column per thread, all rows
-
-struct BwdArgs {
-    const float* Ht;   // [ns][nt][nx][ny][nz]
-    const float* f;    // [R][C]
-    float* g;          // [nz][R][C]
-    ProjGeom geo;
-    int N;             // nx*ny*nz
-    int K;             // Kr*Kc
+struct FwdPlan {
+    ProjGeom g;
+    FwdLayout L;
+    int N, Npad, Mpad, mtiles, ntiles, splits;
+    size_t gT_bytes, gS_bytes, B_bytes, part_bytes;
 };
 
-// Thread t owns B column n0 + t = (cx, cy, z) and, in the A tile, row
-// m0 + t/4 at the 4 consecutive pairs 4(t mod 4) .. 4(t mod 4)+3 of the stage.
-// Per-element zero masks of a backward stage, bit j (A) and bit kk (B).
-struct BwdMask {
-    uint32_t a, b;
+FwdPlan fwd_plan(const lfbp_shape& s, int64_t R, int64_t C)
+{
+    FwdPlan P;
+    P.g = make_geom(s, R, C);
+    P.L = fwd_layout(P.g);
+    P.N = P.g.nx * P.g.ny;
+    P.mtiles = (P.g.M + kMT - 1) / kMT;
+    P.ntiles = (P.N + kNT - 1) / kNT;
+    P.Mpad = P.mtiles * kMT;
+    P.Npad = P.ntiles * kNT;
+    // About kTargetBlocks workgroups (one round at two per CU on 256 CUs).  The
+    // split count depends on the shape only, so the workspace size and the
+    // order of the float64 reduction do not depend on the device.
+    const int want = kTargetBlocks / (P.mtiles * P.ntiles);
+    P.splits = std::max(1, std::min({want, 64, std::max(1, P.L.stages / 64)}));
+    P.gT_bytes = align256(size_t(P.g.nz) * P.g.R * P.g.C * sizeof(float));
+    P.gS_bytes = align256(size_t(P.N) * P.L.LRp * P.L.LCp * P.L.nzc * kRec * sizeof(float));
+    P.B_bytes = align256(size_t(P.L.stages) * P.Npad * kRec * sizeof(float));
+    P.part_bytes = size_t(P.splits) * P.Mpad * P.Npad * sizeof(float);
+    return P;
+}
+
+struct BwdPlan {
+    ProjGeom g;
+    int N, Npad, Mpad, mtiles, ntiles, stages;
+    size_t A_bytes, B_bytes;
 };
 
-__device__ __forceinline__ BwdMask bwd_load(const BwdArgs& a, int k0, int m, int P0, int Q0, int64_t hoff, int cx,
-                                            int cy, float (&ra)[kBwdAPer], float (&rb)[kBwdBPer])
+BwdPlan bwd_plan(const lfbp_shape& s, int64_t R, int64_t C)
 {
-    BwdMask mk{0u, 0u};
-    const ProjGeom& g = a.geo;
-    const int tid = threadIdx.x;
-    // A: f[P0 - r][Q0 - r2] for this thread's 4 pairs
-#pragma unroll
-    for (int j = 0; j < kBwdAPer; ++j) {
-        const int k = k0 + 4 * (tid & 3) + j;
-        const int ri = int(fdiv(uint32_t(k), g.fKc)), r2i = k - ri * g.Kc;
-        const int p = P0 - (ri - (g.nx - 1)), q = Q0 - (r2i - (g.ny - 1));
-        const bool ok = (m < g.M) & (k < a.K) & (p >= 0) & (p < g.R) & (q >= 0) & (q < g.C);
-        ra[j] = a.f[ok ? int64_t(p) * g.C + q : 0];
-        mk.a |= uint32_t(ok) << j;
-    }
-    // B: Ht[r+cx][r2+cy][x][y][z]; (r, r2, x, y) are uniform over the workgroup
-    // and advance by one pair per row of the stage: one division per stage,
-    // then scalar increments (r2 up by one, x and y down by one, cyclically).
-    const int64_t cell = int64_t(g.nx) * g.ny * g.nz;
-    int ri = int(fdiv(uint32_t(k0), g.fKc));
-    int r2i = k0 - ri * g.Kc;
-    int x = imod(g.hs - (ri - (g.nx - 1)), g.nx);
-    int y = imod(g.ht - (r2i - (g.ny - 1)), g.ny);
-    const int y_first = imod(g.ht + g.ny - 1, g.ny);  // y at r2 = -(ny-1)
-#pragma unroll
-    for (int kk = 0; kk < kBwdKC; ++kk) {
-        const int r = ri - (g.nx - 1), r2 = r2i - (g.ny - 1);
-        const bool valid = (hoff >= 0) & (k0 + kk < a.K) & (unsigned(r + cx) < unsigned(g.ns)) &
-                           (unsigned(r2 + cy) < unsigned(g.nt));
-        const int64_t base = (int64_t(r) * g.nt + r2) * cell + (int64_t(x) * g.ny + y) * g.nz;
-        rb[kk] = a.Ht[valid ? base + hoff : 0];
-        mk.b |= uint32_t(valid) << kk;
-        if (++r2i == g.Kc) {
-            r2i = 0;
-            ++ri;
-            x = x == 0 ? g.nx - 1 : x - 1;
-            y = y_first;
-        } else {
-            y = y == 0 ? g.ny - 1 : y - 1;
-        }
-    }
-    return mk;
+    BwdPlan P;
+    P.g = make_geom(s, R, C);
+    P.N = P.g.nx * P.g.ny * P.g.nz;
+    P.mtiles = (P.g.M + kMT - 1) / kMT;
+    P.ntiles = (P.N + kNT - 1) / kNT;
+    P.Mpad = P.mtiles * kMT;
+    P.Npad = P.ntiles * kNT;
+    P.stages = (P.g.Kr * P.g.Kc + kStageK - 1) / kStageK;
+    P.A_bytes = align256(size_t(P.stages) * P.Mpad * kRec * sizeof(float));
+    P.B_bytes = align256(size_t(P.stages) * P.Npad * kRec * sizeof(float));
+    return P;
 }
 
-__device__ __forceinline__ void bwd_store(float* As, float* Bs, const BwdMask& mk, const float (&ra)[kBwdAPer],
-                                          const float (&rb)[kBwdBPer])
+PackArgs pack_args(const ProjGeom& g, int N, int Npad, int Mpad, int stages)
 {
-    const int tid = threadIdx.x;
-#pragma unroll
-    for (int j = 0; j < kBwdAPer; ++j)
-        As[(4 * (tid & 3) + j) * kAStride + (tid >> 2)] = ((mk.a >> j) & 1u) ? ra[j] : 0.0f;
-#pragma unroll
-    for (int kk = 0; kk < kBwdKC; ++kk) Bs[kk * kBStride + tid] = ((mk.b >> kk) & 1u) ? rb[kk] : 0.0f;
+    PackArgs p{};
+    p.g = g;
+    p.N = N;
+    p.Npad = Npad;
+    p.Mpad = Mpad;
+    p.stages = stages;
+    p.nzc = 1;
+    p.LRp = 1;
+    p.LCp = 1;
+    p.fnzc = make_fastdiv(1);
+    p.fLCp = make_fastdiv(1);
+    return p;
 }
 
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) k_bwd_gemm(BwdArgs a)
-{
-    __shared__ float As[2][kBwdKC * kAStride];
-    __shared__ float Bs[2][kBwdKC * kBStride];
-    const ProjGeom& g = a.geo;
-    const int m0 = blockIdx.x * kMT, n0 = blockIdx.y * kNT;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const bool active = n0 + wave * 64 < a.N;
-    // this thread's B column (cx, cy, z) and A row
-    const int n = n0 + int(threadIdx.x);
-    int cx = 0, cy = 0;
-    int64_t hoff = -1;
-    if (n < a.N) {
-        const int c = int(fdiv(uint32_t(n), g.fnz));
-        const int z = n - c * g.nz;
-        cx = int(fdiv(uint32_t(c), g.fny));
-        cy = c - cx * g.ny;
-        hoff = (int64_t(cx) * g.nt + cy) * (int64_t(g.nx) * g.ny * g.nz) + z;
-    }
-    const int m = m0 + int(threadIdx.x >> 2);
-    int P0 = 0, Q0 = 0;
-    if (m < g.M) {
-        const int Lp = m / g.Lc, Lq = m - Lp * g.Lc;
-        P0 = g.nx * Lp + g.hs;
-        Q0 = g.ny * Lq + g.ht;
-    }
-    f32x16 acc[2][2] = {}, tot[2][2] = {};
-    float ra[kBwdAPer], rb[kBwdBPer];
-    const int stages = (a.K + kBwdKC - 1) / kBwdKC;
-    BwdMask mk = bwd_load(a, 0, m, P0, Q0, hoff, cx, cy, ra, rb);
-    bwd_store(As[0], Bs[0], mk, ra, rb);
-    __syncthreads();
-    int buf = 0, since = 0;
-    for (int s = 0; s < stages; ++s) {
-        const bool more = s + 1 < stages;
-        if (more) mk = bwd_load(a, (s + 1) * kBwdKC, m, P0, Q0, hoff, cx, cy, ra, rb);
-        if (active) mma_stage(As[buf], Bs[buf], kBwdKC, wave, lane, acc);
-        if (++since == kFold) {
-            fold(acc, tot);
-            since = 0;
-        }
-        if (more) bwd_store(As[buf ^ 1], Bs[buf ^ 1], mk, ra, rb);
-        __syncthreads();
-        buf ^= 1;
-    }
-    fold(acc, tot);
-    if (!active) return;
-    const int li = lane & 31, lk = lane >> 5;
-    const size_t plane = size_t(g.R) * g.C;
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        const int nn = n0 + wave * 64 + 32 * j + li;
-        if (nn >= a.N) continue;
-        const int c = int(fdiv(uint32_t(nn), g.fnz));
-        const int zz = nn - c * g.nz;
-        const int ccx = int(fdiv(uint32_t(c), g.fny)), ccy = c - ccx * g.ny;
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int m = m0 + 32 * i + 8 * (r >> 2) + 4 * lk + (r & 3);
-                if (m >= g.M) continue;
-                const int Lp = m / g.Lc, Lq = m - Lp * g.Lc;
-                const int P = g.nx * Lp + ccx, Q = g.ny * Lq + ccy;
-                if (P < g.R && Q < g.C) a.g[zz * plane + size_t(P) * g.C + Q] = tot[i][j][r];
-            }
-    }
-}
-
-int g_cus_proj = 256;
-
-int fwd_splits(const ProjGeom& g, int mtiles, int ntiles, int stages)
-{
-    const int want = (2 * g_cus_proj) / (mtiles * ntiles);  // one round at two workgroups per CU
-    return std::max(1, std::min({want, 64, std::max(1, stages / 8)}));
-}
+unsigned blocks_for(int64_t items) { return unsigned((items + 255) / 256); }
 
 }  // namespace
 
 hipError_t project_init(int max_lds)
 {
     (void)max_lds;
-    int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
-        g_cus_proj = cus;
     return hipSuccess;
 }
 
-// Workspace of the forward projection: g with depth innermost, then the
-// split-K partial tiles.
+// Workspace of the forward projection: g with depth innermost, the A and B
+// records, then the split partial tiles.
 size_t forward_workspace_bytes(const lfbp_shape& s, int64_t R, int64_t C)
 {
-    const ProjGeom g = make_geom(s, R, C);
-    const int N = g.nx * g.ny, Npad = (N + 63) / 64 * 64;
-    const int mtiles = (g.M + kMT - 1) / kMT, ntiles = (N + kNT - 1) / kNT;
-    const int nzc = (g.nz + kFwdZC - 1) / kFwdZC;
-    const int stages = g.Kr * g.Kc * nzc;
-    const int splits = fwd_splits(g, mtiles, ntiles, stages);
-    const size_t gT = size_t(g.nz) * g.R * g.C * sizeof(float);
-    const size_t part = size_t(splits) * size_t(mtiles * kMT) * size_t(ntiles * kNT) * sizeof(float);
-    return (gT + 255) / 256 * 256 + part;
+    const FwdPlan P = fwd_plan(s, R, C);
+    return P.gT_bytes + P.gS_bytes + P.B_bytes + P.part_bytes;
+}
+
+// Workspace of the backprojection: the A and B records.
+size_t backward_workspace_bytes(const lfbp_shape& s, int64_t R, int64_t C)
+{
+    const BwdPlan P = bwd_plan(s, R, C);
+    return P.A_bytes + P.B_bytes;
 }
 
 hipError_t launch_forward_ws(const float* H, const lfbp_shape& s, const float* gin, int64_t R, int64_t C, float* f,
                              void* ws, hipStream_t stream)
 {
-    const ProjGeom g = make_geom(s, R, C);
-    FwdArgs a;
-    a.H = H;
-    a.g = g;
-    a.N = g.nx * g.ny;
-    const int mtiles = (g.M + kMT - 1) / kMT, ntiles = (a.N + kNT - 1) / kNT;
-    a.Mpad = mtiles * kMT;
-    a.Npad = ntiles * kNT;
-    a.nzc = (g.nz + kFwdZC - 1) / kFwdZC;
-    a.stages = g.Kr * g.Kc * a.nzc;
-    a.splits = fwd_splits(g, mtiles, ntiles, a.stages);
-    const size_t gT_bytes = (size_t(g.nz) * g.R * g.C * sizeof(float) + 255) / 256 * 256;
-    float* gT = static_cast<float*>(ws);
-    a.gT = gT;
-    a.phaseH = int((reinterpret_cast<uintptr_t>(H) / 4) % 4);
-    a.phaseG = int((reinterpret_cast<uintptr_t>(gT) / 4) % 4);
-    a.partial = reinterpret_cast<float*>(static_cast<char*>(ws) + gT_bytes);
+    const FwdPlan P = fwd_plan(s, R, C);
+    const ProjGeom& g = P.g;
+    char* w = static_cast<char*>(ws);
+    float* gT = reinterpret_cast<float*>(w);
+    float* gS = reinterpret_cast<float*>(w + P.gT_bytes);
+    float* Bp = reinterpret_cast<float*>(w + P.gT_bytes + P.gS_bytes);
+    float* part = reinterpret_cast<float*>(w + P.gT_bytes + P.gS_bytes + P.B_bytes);
+
+    PackArgs p = pack_args(g, P.N, P.Npad, P.Mpad, P.L.stages);
+    p.nzc = P.L.nzc;
+    p.LRp = P.L.LRp;
+    p.LCp = P.L.LCp;
+    p.padP = P.L.padP;
+    p.padQ = P.L.padQ;
+    p.fnzc = make_fastdiv(uint32_t(P.L.nzc));
+    p.fLCp = make_fastdiv(uint32_t(P.L.LCp));
+
     const int plane = g.R * g.C;
     hipLaunchKernelGGL(k_depth_last, dim3(unsigned((plane + 31) / 32), unsigned((g.nz + 31) / 32)), dim3(256), 0,
                        stream, gin, g.nz, plane, gT);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_fwd_gemm, dim3(unsigned(mtiles), unsigned(ntiles), unsigned(a.splits)), dim3(kThreads), 0,
-                       stream, a);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_pack_fwd_a, dim3(unsigned(P.N * P.L.nzc), blocks_for(int64_t(P.L.LRp) * P.L.LCp * kRecVec)),
+                       dim3(256), 0, stream, gT, p, gS);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_pack_fwd_b, dim3(unsigned(P.L.stages), unsigned(P.ntiles)), dim3(kThreads), 0, stream, H, p,
+                       Bp);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+
+    GemmArgs a{};
+    a.A = gS;
+    a.B = Bp;
+    a.out = part;
+    a.g = g;
+    a.M = g.M;
+    a.N = P.N;
+    a.Mpad = P.Mpad;
+    a.Npad = P.Npad;
+    a.mtiles = P.mtiles;
+    a.ntiles = P.ntiles;
+    a.stages = P.L.stages;
+    a.splits = P.splits;
+    a.nzc = P.L.nzc;
+    a.LRp = P.L.LRp;
+    a.LCp = P.L.LCp;
+    a.padP = P.L.padP;
+    a.padQ = P.L.padQ;
+    a.fnzc = p.fnzc;
+    hipLaunchKernelGGL(k_gemm<true>, dim3(unsigned(P.mtiles * P.ntiles * P.splits)), dim3(kThreads), 0, stream, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     const int64_t npix = int64_t(g.R) * g.C;
-    hipLaunchKernelGGL(k_fwd_reduce, dim3(unsigned((npix + 255) / 256)), dim3(256), 0, stream, a.partial, a.splits,
-                       a.Mpad, a.Npad, g, f);
+    hipLaunchKernelGGL(k_fwd_reduce, dim3(blocks_for(npix)), dim3(256), 0, stream, part, P.splits, P.Mpad, P.Npad, g,
+                       f);
+    return hipGetLastError();
+}
+
+hipError_t launch_backward_ws(const float* Ht, const lfbp_shape& s, const float* f, int64_t R, int64_t C, float* g_out,
+                              void* ws, hipStream_t stream)
+{
+    const BwdPlan P = bwd_plan(s, R, C);
+    const ProjGeom& g = P.g;
+    char* w = static_cast<char*>(ws);
+    float* Ap = reinterpret_cast<float*>(w);
+    float* Bp = reinterpret_cast<float*>(w + P.A_bytes);
+    const PackArgs p = pack_args(g, P.N, P.Npad, P.Mpad, P.stages);
+    hipLaunchKernelGGL(k_pack_bwd_a, dim3(unsigned(P.stages), blocks_for(int64_t(P.Mpad) * kRecVec)), dim3(256), 0,
+                       stream, f, p, Ap);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_pack_bwd_b, dim3(unsigned(P.stages), blocks_for(int64_t(P.Npad) * kRecVec)), dim3(256), 0,
+                       stream, Ht, p, Bp);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    GemmArgs a{};
+    a.A = Ap;
+    a.B = Bp;
+    a.out = g_out;
+    a.g = g;
+    a.M = g.M;
+    a.N = P.N;
+    a.Mpad = P.Mpad;
+    a.Npad = P.Npad;
+    a.mtiles = P.mtiles;
+    a.ntiles = P.ntiles;
+    a.stages = P.stages;
+    a.splits = 1;
+    a.nzc = 1;
+    a.fnzc = make_fastdiv(1);
+    hipLaunchKernelGGL(k_gemm<false>, dim3(unsigned(P.mtiles * P.ntiles)), dim3(kThreads), 0, stream, a);
     return hipGetLastError();
 }
 
@@ -545,16 +796,12 @@ hipError_t launch_forward(const float* H, const lfbp_shape& s, const float* g, i
 hipError_t launch_backward(const float* Ht, const lfbp_shape& s, const float* f, int64_t R, int64_t C, float* g,
                            hipStream_t stream)
 {
-    BwdArgs a;
-    a.Ht = Ht;
-    a.f = f;
-    a.g = g;
-    a.geo = make_geom(s, R, C);
-    a.N = a.geo.nx * a.geo.ny * a.geo.nz;
-    a.K = a.geo.Kr * a.geo.Kc;
-    const int mtiles = (a.geo.M + kMT - 1) / kMT, ntiles = (a.N + kNT - 1) / kNT;
-    hipLaunchKernelGGL(k_bwd_gemm, dim3(unsigned(mtiles), unsigned(ntiles)), dim3(kThreads), 0, stream, a);
-    return hipGetLastError();
+    void* ws = nullptr;
+    hipError_t e = hipMallocAsync(&ws, backward_workspace_bytes(s, R, C), stream);
+    if (e != hipSuccess) return e;
+    e = launch_backward_ws(Ht, s, f, R, C, g, ws, stream);
+    const hipError_t e2 = hipFreeAsync(ws, stream);
+    return e != hipSuccess ? e : e2;
 }
 
 }  // namespace lfbp

@@ -82,14 +82,38 @@ lfbp_status check_config(const lfbp_gather_config* c)
     return LFBP_OK;
 }
 
-lfbp_status check_project(const float* psf, const lfbp_shape& s, const float* in2, int64_t R, int64_t C,
-                          const float* out, bool forward)
+lfbp_status check_project_shape(const lfbp_shape& s, int64_t R, int64_t C)
 {
-    if (!psf || !in2 || !out) return LFBP_EINVAL;
     if (R < 1 || C < 1) return LFBP_EINVAL;
     const lfbp_status st = check_shape(s, 4);
     if (st != LFBP_OK) return st;
     if (mul_sat(mul_sat(uint64_t(R), uint64_t(C)), uint64_t(s.nz)) >= LIM31) return LFBP_ESHAPE;
+    // Sizes of the projector's operand records (24 floats per stage of 22
+    // reduction indices): stage counts, record indices per stage and the
+    // workspace must stay inside the kernels' 32-bit grid and index ranges.
+    const uint64_t Kr = uint64_t(s.ns + s.nx - 1), Kc = uint64_t(s.nt + s.ny - 1);
+    const uint64_t pairs = mul_sat(Kr, Kc);
+    if (mul_sat(pairs, uint64_t(s.nz)) >= LIM31) return LFBP_ESHAPE;
+    // A record block (96 bytes per record) is addressed with 32-bit offsets:
+    // columns (nx*ny*nz, padded), lenslets (padded) and the lenslet grid of g
+    // with its zero border must each stay below 2^31 bytes of records.
+    const uint64_t cols = mul_sat(mul_sat(uint64_t(s.nx), uint64_t(s.ny)), uint64_t(s.nz)) + 256;
+    const uint64_t hs = uint64_t(s.ns - 1) / 2, ht = uint64_t(s.nt - 1) / 2;
+    const uint64_t Lr = uint64_t((R + s.nx - 1) / s.nx), Lc = uint64_t((C + s.ny - 1) / s.ny);
+    const uint64_t grid = mul_sat(Lr + 2 * ((hs + s.nx - 1) / s.nx), Lc + 2 * ((ht + s.ny - 1) / s.ny));
+    const uint64_t lenslets = mul_sat(Lr, Lc) + 64;
+    if (mul_sat(cols, 96) >= LIM31 || mul_sat(lenslets, 96) >= LIM31 || mul_sat(grid, 96) >= LIM31)
+        return LFBP_ESHAPE;
+    if (mul_sat(mul_sat(mul_sat(pairs, uint64_t(s.nz)), cols + lenslets + grid), 96) >= LIM62) return LFBP_ESHAPE;
+    return LFBP_OK;
+}
+
+lfbp_status check_project(const float* psf, const lfbp_shape& s, const float* in2, int64_t R, int64_t C,
+                          const float* out, bool forward)
+{
+    if (!psf || !in2 || !out) return LFBP_EINVAL;
+    const lfbp_status st = check_project_shape(s, R, C);
+    if (st != LFBP_OK) return st;
     const int64_t image = R * C, volume = image * s.nz;
     const int64_t in2_elems = forward ? volume : image, out_elems = forward ? image : volume;
     const uintptr_t a = reinterpret_cast<uintptr_t>(psf), b = reinterpret_cast<uintptr_t>(in2),

@@ -163,7 +163,7 @@ def test_forward_workspace_validation_before_launch():
     L = _abi.lib()
     shape = Shape(165, 165, 15, 15, 21)
     need = L.lfbp_forward_workspace_size(shape, 600, 600)
-    assert need > 21 * 600 * 600 * 4                    # depth-last copy of g plus partial sums
+    assert need > 179 * 179 * 256 * 24 * 4              # H as records of 22 depths per (shift, class)
     assert L.lfbp_forward_workspace_size(Shape(4, 5, 3, 3, 1), 10, 10) == 0
     assert L.lfbp_forward_workspace_size(shape, 0, 600) == 0
     H, g, f, ws = 0x1000000, 0x40000000, 0x80000000, 0xC0000000
@@ -172,3 +172,40 @@ def test_forward_workspace_validation_before_launch():
     assert L.lfbp_forward_ws(H, shape, g, 600, 600, f, ws + 16, need, None) == _abi.EINVAL
     assert L.lfbp_forward_ws(H, shape, g, 600, 600, f, g + 256, need, None) == _abi.EALIAS
     assert L.lfbp_forward_ws(H, shape, g, 600, 600, f, f - 256, need, None) == _abi.EALIAS
+
+
+def test_backward_workspace_validation_before_launch():
+    L = _abi.lib()
+    shape = Shape(165, 165, 15, 15, 21)
+    need = L.lfbp_backward_workspace_size(shape, 600, 600)
+    # A and B records: 24 floats per (stage of 22 (r, r2) pairs, lenslet or column)
+    stages = -(-(179 * 179) // 22)
+    assert need == (stages * 1600 * 24 * 4 + 255) // 256 * 256 + (stages * 4864 * 24 * 4 + 255) // 256 * 256
+    assert L.lfbp_backward_workspace_size(Shape(4, 5, 3, 3, 1), 10, 10) == 0
+    assert L.lfbp_backward_workspace_size(shape, 600, 0) == 0
+    Ht, f, g, ws = 0x1000000, 0x40000000, 0x80000000, 0x100000000
+    assert L.lfbp_backward_ws(Ht, shape, f, 600, 600, g, None, need, None) == _abi.EINVAL
+    assert L.lfbp_backward_ws(Ht, shape, f, 600, 600, g, ws, need - 1, None) == _abi.EINVAL
+    assert L.lfbp_backward_ws(Ht, shape, f, 600, 600, g, ws + 64, need, None) == _abi.EINVAL
+    assert L.lfbp_backward_ws(Ht, shape, f, 600, 600, g, f - 512, need, None) == _abi.EALIAS
+    assert L.lfbp_backward_ws(Ht, shape, f, 600, 600, g, g + 512, need, None) == _abi.EALIAS
+    assert L.lfbp_backward_ws(Ht, shape, f, 600, 600, g, Ht + 512, need, None) == _abi.EALIAS
+    assert L.lfbp_backward_ws(Ht, Shape(15, 14, 3, 3, 3), f, 30, 30, g, ws, need, None) == _abi.ESHAPE
+
+
+def test_projector_index_range_limits():
+    """Shapes whose operand records would leave the kernels' 32-bit ranges are
+    refused before anything runs: (ns+nx-1)(nt+ny-1)nz must stay below 2^31,
+    and so must the bytes of one record block (columns, lenslets, or the
+    phase-split lenslet grid of g with its zero border)."""
+    L = _abi.lib()
+    big = Shape(4001, 4001, 101, 101, 150)         # 4101^2 * 150 = 2.5e9 stage-depth products
+    assert L.lfbp_forward(P1, big, P2, 30, 30, P2 + 0x100000, None) == _abi.ESHAPE
+    assert L.lfbp_backward(P1, big, P2, 30, 30, P2 + 0x100000, None) == _abi.ESHAPE
+    assert L.lfbp_forward_workspace_size(big, 30, 30) == 0
+    assert L.lfbp_backward_workspace_size(big, 30, 30) == 0
+    ok = Shape(4001, 4001, 101, 101, 100)          # 1.7e9 < 2^31
+    assert L.lfbp_forward_workspace_size(ok, 30, 30) > 0
+    border = Shape(20001, 20001, 1, 1, 5)          # g's grid with a 10^4-lenslet zero border: 4e8 records
+    assert L.lfbp_forward_workspace_size(border, 30, 30) == 0
+    assert L.lfbp_forward_workspace_size(Shape(2001, 2001, 1, 1, 5), 30, 30) > 0

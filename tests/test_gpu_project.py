@@ -137,9 +137,9 @@ def test_projector_workload_full_size_sampled():
     assert rel_l2(fbn[vox[:, 0], vox[:, 1], vox[:, 2]], oracle.backward_at(H, fn, vox)) <= TOL
 
 
-def test_forward_without_workspace_uses_stream_allocator():
-    """The workspace-free entry point (scratch from hipMallocAsync) gives the
-    same bits as the workspace form."""
+def test_without_workspace_uses_stream_allocator():
+    """The workspace-free entry points (scratch from hipMallocAsync) give the
+    same bits as the workspace forms."""
     import ctypes
     from paper_2003_09133_amd import _abi
     shape, R, C = (45, 45, 15, 15, 5), 97, 120
@@ -152,3 +152,31 @@ def test_forward_without_workspace_uses_stream_allocator():
     f2 = lf.forward(dH, g)
     torch.cuda.synchronize()
     assert torch.equal(f1, f2)
+    dHt = lf.compute_Ht(dH)
+    g1 = torch.empty((shape[4], R, C), device=DEV)
+    st = _abi.lib().lfbp_backward(dHt.data_ptr(), _abi.Shape.of(shape), f2.data_ptr(), R, C, g1.data_ptr(),
+                                  torch.cuda.current_stream().cuda_stream)
+    assert st == 0
+    g2 = lf.backward(dHt, f2)
+    torch.cuda.synchronize()
+    assert torch.equal(g1, g2)
+
+
+def test_workspace_reuse_across_shapes():
+    """One workspace, sized for the largest call, serves calls of other shapes
+    in turn (stale records from the earlier call are overwritten or unused)."""
+    big, small = ((45, 45, 15, 15, 5), 120, 105), ((15, 15, 3, 3, 3), 21, 21)
+    wsz = max(lf.forward_workspace_size(s, R, C) for s, R, C in (big, small))
+    bsz = max(lf.backward_workspace_size(s, R, C) for s, R, C in (big, small))
+    wf = torch.empty(wsz, dtype=torch.uint8, device=DEV)
+    wb = torch.empty(bsz, dtype=torch.uint8, device=DEV)
+    for shape, R, C in (big, small, big):
+        H = lfsynth.uniform_f32(shape, 31)
+        g = lfsynth.uniform_f32((shape[4], R, C), 32)
+        f = lfsynth.uniform_f32((R, C), 33)
+        dH = to_dev(H)
+        fg = lf.forward(dH, to_dev(g), workspace=wf)
+        bg = lf.backward(lf.compute_Ht(dH), to_dev(f), workspace=wb)
+        torch.cuda.synchronize()
+        assert rel_l2(fg.cpu().numpy(), oracle.forward(H, g)) <= TOL
+        assert rel_l2(bg.cpu().numpy(), oracle.backward(H, f)) <= TOL

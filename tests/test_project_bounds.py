@@ -1,170 +1,257 @@
-"""Address bounds of the projector kernels, on the CPU.
+"""The projector kernels' index arithmetic, on the CPU.
 
-A mirror, in NumPy, of the index arithmetic of the operand loaders and result
-writes of k_fwd_gemm / k_fwd_reduce / k_bwd_gemm (paper_2003_09133_amd/csrc/
-lfbp_project.hip): for every lane and every stage of the listed shapes, every
-global address the kernels form must lie inside its array.  Keep it in step
-with the kernels' loaders.  The forward loaders read 16-byte vectors that
-may extend past the run they serve: each must be aligned and share its 16-byte
-line with an element of its array, for every alignment of the array, and the
-scatter of the vectors into LDS must write every (depth, row/column) slot of
-the stage exactly once, from the element the GEMM formulation names.
+A mirror, in NumPy, of the address and index computations of the packing
+kernels, the GEMM kernel and the reduction of paper_2003_09133_amd/csrc/
+lfbp_project.hip: it checks that every global address they form lies inside
+its array, that the workgroup -> tile map is a bijection, and, by running the
+mirrored records through a float64 matrix product, that the formulation gives
+the oracle's f = H g and g = H' f.  Keep it in step with the kernels.
 """
 import itertools
 
 import numpy as np
 import pytest
 
-kThreads, kMT, kNT, kFwdZC, kBwdKC = 256, 64, 256, 22, 16
-kFwdVPR = (kFwdZC + 3 + 3) // 4
-kFwdBSlots = kNT * kFwdVPR // kThreads
-kFwdASlots = (kMT * kFwdVPR + kThreads - 1) // kThreads
+import lfsynth
+import oracle
+
+kThreads, kMT, kNT, kHalf, kStageK, kRec, kRecVec, kXcds = 256, 64, 256, 11, 22, 24, 6, 8
+
+
+def slot_k(q):
+    h = 1 if q >= 12 else 0
+    j = q - 12 * h
+    return kHalf * h + j if j < kHalf else -1
+
+
+SLOT_K = np.array([slot_k(q) for q in range(kRec)])
+
+
 def geom(shape, R, C):
     ns, nt, nx, ny, nz = shape
-    return dict(ns=ns, nt=nt, nx=nx, ny=ny, nz=nz, hs=(ns-1)//2, ht=(nt-1)//2, R=R, C=C,
-                Lr=-(-R//nx), Lc=-(-C//ny), M=(-(-R//nx))*(-(-C//ny)), Kr=ns+nx-1, Kc=nt+ny-1)
-def imod(a, n): return a % n
-def vec_ok(start, size, phase):
-    """A 16-byte vector read at element `start` of an fp32 array whose first
-    element sits at word `phase` of a 16-byte line: it must be aligned and
-    share its line with at least one element of the array (so it stays on a
-    page the array occupies)."""
-    return (np.all((start + phase) % 4 == 0) and start.max() <= size - 1 and (start + 3).min() >= 0)
-def check_fwd(shape, R, C, cus=256, stage_sample=None, phases=(0, 1, 2, 3)):
-    g = geom(shape, R, C); ns, nt, nx, ny, nz = shape
-    E = ns*nt*nx*ny*nz; N = nx*ny
-    mtiles, ntiles = -(-g['M']//kMT), -(-N//kNT)
-    nzc = -(-nz//kFwdZC); stages = g['Kr']*g['Kc']*nzc
-    want = (2*cus)//(mtiles*ntiles); splits = max(1, min(want, 64, max(1, stages//8)))
-    Mpad, Npad = mtiles*kMT, ntiles*kNT
-    gT_size = nz*R*C; part_size = splits*Mpad*Npad
-    tid = np.arange(kThreads)
-    cell = nx*ny*nz
-    st_list = range(stages) if stage_sample is None else stage_sample(stages)
-    for mt, nt_ in itertools.product(range(mtiles), range(ntiles)):
-        m0, n0 = mt*kMT, nt_*kNT
-        for stage in st_list:
-            st, zc = divmod(stage, nzc); sr, tc = divmod(st, g['Kc']); sp, tp = sr-(nx-1), tc-(ny-1)
-            z0 = zc*kFwdZC; zn = min(kFwdZC, nz-z0); x, y = imod(g['hs']-sp, nx), imod(g['ht']-tp, ny)
-            sbase = (sp*nt + tp)*cell + (x*ny + y)*nz + z0
-            for phase in phases:
-                # B: slot e = tid + 256 j -> column nl = e // VPR, vector k = e % VPR
-                cover = np.zeros((kNT, kFwdZC), np.int64)
-                for j in range(kFwdBSlots):
-                    e = tid + j*kThreads; nl, k = e // kFwdVPR, e % kFwdVPR; n = n0 + nl
-                    u, v = n // ny, n % ny
-                    valid = (n < N) & (sp+u >= 0) & (sp+u < ns) & (tp+v >= 0) & (tp+v < nt)
-                    rs = sbase + (u*nt + v)*cell
-                    lead = np.where(valid, (rs + phase) & 3, 0)
-                    vb = np.where(valid, rs - lead, -phase)
-                    kmax = (lead + zn - 1) >> 2
-                    kk = np.minimum(k, kmax)
-                    assert vec_ok(vb + 4*kk, E, phase), ("B", shape, R, C, stage, phase, j)
-                    # the vector holds the run's depths at the positions the store takes them from
-                    src = vb + 4*kk
-                    for q in range(4):
-                        z = 4*k + q - lead
-                        inr = (z >= 0) & (z < kFwdZC)
-                        live = inr & valid & (z < zn)
-                        assert np.all(src[live] + q == rs[live] + z[live])
-                        np.add.at(cover, (nl[inr], z[inr]), 1)
-                assert np.all(cover == 1), ("B cover", shape, stage)
-                # A: 448 slots over 2 per thread
-                cover = np.zeros((kMT, kFwdZC), np.int64)
-                for j in range(kFwdASlots):
-                    e = tid + j*kThreads; ml, k = e // kFwdVPR, e % kFwdVPR; m = m0 + ml
-                    Lp, Lq = m // g['Lc'], m % g['Lc']
-                    P, Q = nx*Lp + g['hs'] - sp, ny*Lq + g['ht'] - tp
-                    valid = (ml < kMT) & (m < g['M']) & (P >= 0) & (P < R) & (Q >= 0) & (Q < C)
-                    rs = (P*C + Q)*nz + z0
-                    lead = np.where(valid, (rs + phase) & 3, 0)
-                    vb = np.where(valid, rs - lead, -phase)
-                    kmax = (lead + zn - 1) >> 2
-                    kk = np.minimum(k, kmax)
-                    assert vec_ok(vb + 4*kk, gT_size, phase), ("A", shape, R, C, stage, phase, j)
-                    src = vb + 4*kk
-                    for q in range(4):
-                        z = 4*k + q - lead
-                        inr = (z >= 0) & (z < kFwdZC) & (ml < kMT)
-                        live = inr & valid & (z < zn)
-                        assert np.all(src[live] + q == rs[live] + z[live])
-                        np.add.at(cover, (ml[inr], z[inr]), 1)
-                assert np.all(cover == 1), ("A cover", shape, stage)
-        # partial writes
-        for split in [0, splits-1]:
-            li, lk = tid & 31, (tid & 63) >> 5; wave = tid >> 6
-            for i, j, r in itertools.product(range(2), range(2), range(16)):
-                mm = m0 + 32*i + 8*(r >> 2) + 4*lk + (r & 3); nn = n0 + wave*64 + 32*j + li
-                off = (split*Mpad + mm)*Npad + nn
-                assert off.min() >= 0 and off.max() < part_size
-    # reduce reads
-    p = np.arange(R)[:, None]; q = np.arange(C)[None, :]
-    mm = (p//nx)*g['Lc'] + q//ny; nn = (p % nx)*ny + q % ny
-    assert mm.max() < Mpad and nn.max() < Npad
-    return stages, splits
-def check_bwd(shape, R, C, kk_sample=None):
-    g = geom(shape, R, C); ns, nt, nx, ny, nz = shape
-    E = ns*nt*nx*ny*nz; N = nx*ny*nz; K = g['Kr']*g['Kc']; cell = nx*ny*nz
-    mtiles, ntiles = -(-g['M']//kMT), -(-N//kNT)
-    tid = np.arange(kThreads); stages = -(-K//kBwdKC)
-    st_list = range(stages) if kk_sample is None else kk_sample(stages)
-    for mt, nt_ in itertools.product(range(mtiles), range(ntiles)):
-        m0, n0 = mt*kMT, nt_*kNT
-        n = n0 + tid; c = n//nz; cx = np.where(n < N, c//ny, 0); cy = np.where(n < N, c % ny, 0); z = n % nz
-        hoff = np.where(n < N, (cx*nt + cy)*cell + z, -1)
-        m = m0 + (tid >> 2); P0 = np.where(m < g['M'], nx*(m//g['Lc']) + g['hs'], 0); Q0 = np.where(m < g['M'], ny*(m % g['Lc']) + g['ht'], 0)
-        for s in st_list:
-            k0 = s*kBwdKC
-            for j in range(4):
-                k = k0 + 4*(tid & 3) + j
-                ri, r2i = k // g['Kc'], k % g['Kc']
-                p, q = P0 - (ri-(nx-1)), Q0 - (r2i-(ny-1))
-                ok = (m < g['M']) & (k < K) & (p >= 0) & (p < R) & (q >= 0) & (q < C)
-                idx = np.where(ok, p*C + q, 0)
-                assert idx.min() >= 0 and idx.max() < R*C
-            for kk in range(kBwdKC):
-                k = k0 + kk; ri, r2i = k // g['Kc'], k % g['Kc']; r, r2 = ri-(nx-1), r2i-(ny-1)
-                x, y = imod(g['hs']-r, nx), imod(g['ht']-r2, ny)
-                valid = (hoff >= 0) & (k < K) & (r+cx >= 0) & (r+cx < ns) & (r2+cy >= 0) & (r2+cy < nt)
-                base = (r*nt + r2)*cell + (x*ny + y)*nz
-                idx = np.where(valid, base + hoff, 0)
-                assert idx.min() >= 0 and idx.max() < E, ("Ht", shape, s, kk)
-        # output writes
-        li, lk = tid & 31, (tid & 63) >> 5; wave = tid >> 6
-        for j in range(2):
-            nn = n0 + wave*64 + 32*j + li
-            c = nn // nz; zz = nn % nz; ccx, ccy = c//ny, c % ny
-            for i, r in itertools.product(range(2), range(16)):
-                mm = m0 + 32*i + 8*(r >> 2) + 4*lk + (r & 3)
-                Pp = nx*(mm//g['Lc']) + ccx; Qq = ny*(mm % g['Lc']) + ccy
-                ok = (nn < N) & (mm < g['M']) & (Pp < R) & (Qq < C)
-                off = np.where(ok, zz*R*C + Pp*C + Qq, 0)
-                assert off.min() >= 0 and off.max() < nz*R*C
-    return stages
+    Lr, Lc = -(-R // nx), -(-C // ny)
+    return dict(ns=ns, nt=nt, nx=nx, ny=ny, nz=nz, hs=(ns - 1) // 2, ht=(nt - 1) // 2, R=R, C=C, Lr=Lr, Lc=Lc,
+                M=Lr * Lc, Kr=ns + nx - 1, Kc=nt + ny - 1)
+
+
+def tile_of_block(b, mtiles, ntiles, splits):
+    nb = mtiles * ntiles * splits
+    x, q, r = b % kXcds, nb // kXcds, nb % kXcds
+    L = x * q + min(x, r) + b // kXcds
+    return L % mtiles, (L // mtiles) % ntiles, L // (mtiles * ntiles)
+
+
+def fwd_stage(g, nzc, s):
+    st, zc = divmod(s, nzc)
+    sr, tc = divmod(st, g['Kc'])
+    sp, tp = sr - (g['nx'] - 1), tc - (g['ny'] - 1)
+    e, f = g['hs'] - sp, g['ht'] - tp
+    px, py = e % g['nx'], f % g['ny']
+    return sp, tp, zc, px, py, (e - px) // g['nx'], (f - py) // g['ny']
+
+
+def fwd_plan(g, target_blocks=512):
+    N = g['nx'] * g['ny']
+    mtiles, ntiles = -(-g['M'] // kMT), -(-N // kNT)
+    nzc = -(-g['nz'] // kStageK)
+    stages = g['Kr'] * g['Kc'] * nzc
+    want = target_blocks // (mtiles * ntiles)
+    splits = max(1, min(want, 64, max(1, stages // 64)))
+    padP, padQ = (g['hs'] + g['nx'] - 1) // g['nx'], (g['ht'] + g['ny'] - 1) // g['ny']
+    return dict(N=N, mtiles=mtiles, ntiles=ntiles, Mpad=mtiles * kMT, Npad=ntiles * kNT, nzc=nzc, stages=stages,
+                splits=splits, padP=padP, padQ=padQ, LRp=g['Lr'] + 2 * padP, LCp=g['Lc'] + 2 * padQ)
+
+
+def check_blocks(mtiles, ntiles, splits):
+    seen = {tile_of_block(b, mtiles, ntiles, splits) for b in range(mtiles * ntiles * splits)}
+    assert seen == set(itertools.product(range(mtiles), range(ntiles), range(splits)))
+
+
+def to_blocks(rec):
+    """Records [blocks][rows][24] -> the kernels' storage: per block, vector
+    plane v, record, half h, 4 floats (float index ((b*3+v)*rows+r)*8+4h+c)."""
+    nb, rows, _ = rec.shape
+    return np.ascontiguousarray(rec.reshape(nb, rows, 2, 3, 4).transpose(0, 3, 1, 2, 4)).ravel()
+
+
+def read_records(flat, base4, lane4, vstride4):
+    """What the GEMM's lanes read: 16-byte vectors at base4 + lane4 + v*vstride4
+    for the halves h = 0, 1 (lane4 without the half) -> records [n][24]."""
+    out = np.empty(lane4.shape + (kRec,))
+    for h in range(2):
+        for v in range(3):
+            idx4 = base4 + 2 * lane4 + h + v * vstride4
+            assert idx4.min() >= 0 and (idx4.max() + 1) * 4 <= flat.size
+            out[..., 12 * h + 4 * v:12 * h + 4 * v + 4] = flat[(idx4[..., None] * 4 + np.arange(4))]
+    return out
+
+
+def split_ranges(stages, splits):
+    return [(stages * k // splits, stages * (k + 1) // splits) for k in range(splits)]
+
+
+def forward_mirror(H, gvol, target_blocks=512):
+    """Records and GEMM of the forward kernel; returns f (float64)."""
+    ns, nt, nx, ny, nz = H.shape
+    _, R, C = gvol.shape
+    g = geom(H.shape, R, C)
+    p = fwd_plan(g, target_blocks)
+    cell = nx * ny * nz
+    Hf = H.astype(np.float64).ravel()
+    gT = np.ascontiguousarray(np.transpose(gvol, (1, 2, 0))).astype(np.float64).ravel()
+    # k_pack_fwd_a: gS[pxy][LP][LQ][zc][slot]
+    pxy, LP, LQ, zc, q = np.meshgrid(np.arange(nx * ny), np.arange(p['LRp']), np.arange(p['LCp']),
+                                     np.arange(p['nzc']), np.arange(kRec), indexing='ij')
+    P, Q = nx * (LP - p['padP']) + pxy // ny, ny * (LQ - p['padQ']) + pxy % ny
+    k = SLOT_K[q]
+    z = zc * kStageK + k
+    ok = (P >= 0) & (P < R) & (Q >= 0) & (Q < C) & (k >= 0) & (z < nz)
+    idx = np.where(ok, (P * C + Q) * nz + z, 0)
+    assert idx.min() >= 0 and idx.max() < gT.size
+    arows = p['LRp'] * p['LCp']
+    # blocks (px, py, zc) of LRp*LCp records
+    gS = to_blocks(np.where(ok, gT[idx], 0.0).transpose(0, 3, 1, 2, 4).reshape(nx * ny * p['nzc'], arows, kRec))
+    # k_pack_fwd_b: Bp[s][n][slot]
+    s_all = np.arange(p['stages'])
+    sp, tp, zcs, pxs, pys, dP, dQ = (np.array(v) for v in zip(*[fwd_stage(g, p['nzc'], s) for s in s_all]))
+    n = np.arange(p['Npad'])
+    u, v = n // ny, n % ny
+    S, Nn, Qs = np.meshgrid(s_all, n, np.arange(kRec), indexing='ij')
+    kk = SLOT_K[Qs]
+    zz = zcs[S] * kStageK + kk
+    su, tv = sp[S] + u[Nn], tp[S] + v[Nn]
+    okb = (Nn < p['N']) & (su >= 0) & (su < ns) & (tv >= 0) & (tv < nt) & (kk >= 0) & (zz < nz)
+    idx = np.where(okb, (su * nt + tv) * cell + (pxs[S] * ny + pys[S]) * nz + zz, 0)
+    assert idx.min() >= 0 and idx.max() < H.size
+    Bp = to_blocks(np.where(okb, Hf[idx], 0.0))          # blocks = stages, Npad records each
+    # GEMM: every workgroup's lanes and stages
+    check_blocks(p['mtiles'], p['ntiles'], p['splits'])
+    m = np.arange(p['Mpad'])
+    mc = np.minimum(m, g['M'] - 1)
+    lane_a = (mc // g['Lc']) * p['LCp'] + mc % g['Lc']             # record of the lane's lenslet
+    abase = ((pxs * ny + pys) * p['nzc'] + zcs) * kRecVec * arows + 2 * ((dP + p['padP']) * p['LCp'] + dQ + p['padQ'])
+    lane_b = np.arange(p['Npad'])
+    use = SLOT_K >= 0                                               # the MFMA steps read slots 0-10 and 12-22
+    partial = np.zeros((p['splits'], p['Mpad'], p['Npad']))
+    for sidx, (b, e) in enumerate(split_ranges(p['stages'], p['splits'])):
+        for s in range(b, e):
+            Arec = read_records(gS, abase[s], lane_a, 2 * arows)
+            Brec = read_records(Bp, s * kRecVec * p['Npad'], lane_b, 2 * p['Npad'])
+            partial[sidx] += Arec[:, use] @ Brec[:, use].T
+    # k_fwd_reduce
+    pp, qq = np.meshgrid(np.arange(R), np.arange(C), indexing='ij')
+    mm = (pp // nx) * g['Lc'] + qq // ny
+    nn = (pp % nx) * ny + qq % ny
+    assert mm.max() < p['Mpad'] and nn.max() < p['Npad']
+    return partial.sum(axis=0)[mm, nn]
+
+
+def backward_mirror(Ht, f):
+    """Records and GEMM of the backprojection kernel; returns g (float64)."""
+    ns, nt, nx, ny, nz = Ht.shape
+    R, C = f.shape
+    g = geom(Ht.shape, R, C)
+    N = nx * ny * nz
+    mtiles, ntiles = -(-g['M'] // kMT), -(-N // kNT)
+    Mpad, Npad = mtiles * kMT, ntiles * kNT
+    K = g['Kr'] * g['Kc']
+    stages = -(-K // kStageK)
+    cell = nx * ny * nz
+    Hf = Ht.astype(np.float64).ravel()
+    ff = f.astype(np.float64).ravel()
+    S, Qs = np.meshgrid(np.arange(stages), np.arange(kRec), indexing='ij')
+    kk = SLOT_K[Qs]
+    k = S * kStageK + kk
+    kc = np.where(kk >= 0, k, 0)
+    ri = kc // g['Kc']
+    r, r2 = ri - (nx - 1), kc - ri * g['Kc'] - (ny - 1)
+    kok = (kk >= 0) & (k < K)
+    # k_pack_bwd_a: Ap[s][m][slot]
+    m = np.arange(Mpad)
+    LP, LQ = m // g['Lc'], m % g['Lc']
+    P = nx * LP[None, :, None] + g['hs'] - r[:, None, :]
+    Q = ny * LQ[None, :, None] + g['ht'] - r2[:, None, :]
+    oka = (m[None, :, None] < g['M']) & kok[:, None, :] & (P >= 0) & (P < R) & (Q >= 0) & (Q < C)
+    idx = np.where(oka, P * C + Q, 0)
+    assert idx.min() >= 0 and idx.max() < R * C
+    Ap = to_blocks(np.where(oka, ff[idx], 0.0))
+    # k_pack_bwd_b: Bp[s][n][slot]
+    n = np.arange(Npad)
+    cz, z = n // nz, n % nz
+    cx, cy = cz // ny, cz % ny
+    x, y = (g['hs'] - r) % nx, (g['ht'] - r2) % ny
+    rx, ry = r[:, None, :] + cx[None, :, None], r2[:, None, :] + cy[None, :, None]
+    okb = (n[None, :, None] < N) & kok[:, None, :] & (rx >= 0) & (rx < ns) & (ry >= 0) & (ry < nt)
+    idx = (rx * nt + ry) * cell + (x[:, None, :] * ny + y[:, None, :]) * nz + z[None, :, None]
+    idx = np.where(okb, idx, 0)
+    assert idx.min() >= 0 and idx.max() < Ht.size
+    Bp = to_blocks(np.where(okb, Hf[idx], 0.0))
+    check_blocks(mtiles, ntiles, 1)
+    use = SLOT_K >= 0
+    G = np.zeros((Mpad, Npad))
+    for s in range(stages):
+        Arec = read_records(Ap, s * kRecVec * Mpad, np.arange(Mpad), 2 * Mpad)
+        Brec = read_records(Bp, s * kRecVec * Npad, np.arange(Npad), 2 * Npad)
+        G += Arec[:, use] @ Brec[:, use].T
+    # epilogue: (m, n) -> g[z][nx LP + cx][ny LQ + cy]
+    out = np.zeros((nz, R, C))
+    mm, nn = np.meshgrid(np.arange(g['M']), np.arange(N), indexing='ij')
+    Pp = nx * (mm // g['Lc']) + (nn // nz) // ny
+    Qq = ny * (mm % g['Lc']) + (nn // nz) % ny
+    ok = (Pp < R) & (Qq < C)
+    out[(nn % nz)[ok], Pp[ok], Qq[ok]] = G[:g['M'], :N][ok]
+    return out
+
 
 SHAPES = [((15, 15, 3, 3, 3), 21, 21), ((15, 15, 3, 3, 3), 20, 23), ((9, 7, 3, 5, 2), 12, 10),
           ((5, 5, 5, 5, 1), 7, 8), ((7, 9, 1, 1, 3), 11, 9), ((1, 1, 1, 1, 2), 4, 5), ((3, 3, 7, 7, 2), 14, 21),
           ((21, 21, 3, 3, 9), 8, 7), ((5, 5, 3, 3, 2), 9, 12), ((3, 3, 1, 1, 2), 5, 6),
-          ((9, 9, 3, 3, 30), 10, 10), ((5, 5, 3, 3, 45), 6, 7)]
+          ((9, 9, 3, 3, 30), 10, 10), ((5, 5, 3, 3, 45), 6, 7), ((3, 3, 3, 3, 23), 7, 5)]
 
 
 @pytest.mark.parametrize("shape,R,C", SHAPES)
-def test_projector_addresses_in_bounds(shape, R, C):
-    check_fwd(shape, R, C)
-    check_bwd(shape, R, C)
+def test_projector_mirror_bounds_and_values(shape, R, C):
+    H = lfsynth.uniform_f32(shape, 1)
+    gv = lfsynth.uniform_f32((shape[4], R, C), 2)
+    f = lfsynth.uniform_f32((R, C), 3)
+    ref = oracle.forward(H, gv)
+    assert np.allclose(forward_mirror(H, gv), ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+    ref = oracle.backward(H, f)               # from H; the kernel reads H'
+    got = backward_mirror(oracle.Ht_rows(H), f)
+    assert np.allclose(got, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
 
 
-def test_projector_addresses_in_bounds_full_size_edges():
-    edge = lambda n: sorted(set([0, 1, 2, n // 2, n - 3, n - 2, n - 1]) & set(range(n)))
-    check_fwd((165, 165, 15, 15, 21), 600, 600, stage_sample=edge)
-    check_bwd((165, 165, 15, 15, 21), 600, 600, kk_sample=edge)
+@pytest.mark.parametrize("target_blocks", [1, 16, 160, 512, 608])
+def test_forward_mirror_split_counts(target_blocks):
+    """Every split count covers the stages exactly once."""
+    shape, R, C = (9, 7, 3, 5, 2), 12, 10
+    H = lfsynth.uniform_f32(shape, 4)
+    gv = lfsynth.uniform_f32((shape[4], R, C), 5)
+    ref = oracle.forward(H, gv)
+    assert np.allclose(forward_mirror(H, gv, target_blocks=target_blocks), ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
 
 
-def test_projector_addresses_in_bounds_gpu_test_shapes():
-    """The larger shapes the GPU tests run, at edge and randomly sampled stages."""
-    rng = np.random.default_rng(0)
-    pick = lambda n: sorted(set([0, 1, n // 2, n - 2, n - 1]) | set(rng.integers(0, n, 40).tolist()))
-    for shape, R, C in [((45, 45, 15, 15, 5), 120, 105), ((45, 45, 15, 15, 5), 97, 120),
-                        ((165, 165, 15, 15, 21), 120, 120), ((33, 25, 11, 5, 4), 55, 40)]:
-        check_fwd(shape, R, C, stage_sample=pick)
-        check_bwd(shape, R, C, kk_sample=pick)
+def test_workgroup_map_is_a_bijection():
+    for mt, nt, sp in itertools.product([1, 3, 25, 26], [1, 2, 19], [1, 5, 8, 20]):
+        check_blocks(mt, nt, sp)
+
+
+@pytest.mark.parametrize("shape,R,C", [((165, 165, 15, 15, 21), 600, 600), ((165, 165, 15, 15, 21), 120, 120),
+                                       ((45, 45, 15, 15, 5), 97, 120), ((345, 345, 15, 15, 51), 330, 345)])
+def test_large_shapes_record_addresses(shape, R, C):
+    """Shapes of the GPU tests and the projector workload: the lanes' record
+    addresses at every forward stage stay inside the phase-split copy of g."""
+    g = geom(shape, R, C)
+    p = fwd_plan(g)
+    arows = p['LRp'] * p['LCp']
+    gS_vecs = shape[2] * shape[3] * p['nzc'] * arows * kRecVec
+    mc = np.minimum(np.arange(p['Mpad']), g['M'] - 1)
+    lane = 2 * ((mc // g['Lc']) * p['LCp'] + mc % g['Lc'])
+    st = np.array([fwd_stage(g, p['nzc'], s) for s in range(p['stages'])])
+    _, _, zc, px, py, dP, dQ = st.T
+    base = ((px * shape[3] + py) * p['nzc'] + zc) * kRecVec * arows + 2 * ((dP + p['padP']) * p['LCp'] + dQ + p['padQ'])
+    assert base.min() + lane.min() >= 0 and base.max() + lane.max() + 1 + 2 * 2 * arows < gS_vecs
+    # the shift never carries a lane's record out of its (px, py, zc) block
+    blk = ((px * shape[3] + py) * p['nzc'] + zc) * kRecVec * arows
+    assert np.all(base - blk + lane.max() + 1 < 2 * arows) and np.all(base - blk + lane.min() >= 0)
+    check_blocks(p['mtiles'], p['ntiles'], p['splits'])
