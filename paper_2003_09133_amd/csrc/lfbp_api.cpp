@@ -1,5 +1,6 @@
-// Host runtime and C ABI of liblfbp.so: argument checks, kernel choice and work
-// decomposition, batched plans (device descriptor tables + captured hipGraphs).
+// Host runtime and C ABI of the H -> H' calls of liblfbp.so: argument checks,
+// kernel choice and work decomposition, batched plans (device descriptor
+// tables + captured hipGraphs), device set-up.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,18 +22,6 @@ hipError_t launch_gather_batched(const BatchArgs& a, uint32_t maxW, int esize, c
                                  hipStream_t stream);
 hipError_t set_gather_smem_limits(int max_bytes);
 int gather_occupancy(const LaunchPlan& p, uint32_t W, int esize, bool batched);
-hipError_t launch_forward(const float* H, const lfbp_shape& s, const float* g, int64_t R, int64_t C, float* f,
-                          hipStream_t stream);
-hipError_t launch_backward(const float* Ht, const lfbp_shape& s, const float* f, int64_t R, int64_t C, float* g,
-                           hipStream_t stream);
-hipError_t project_init(int max_lds);
-size_t forward_workspace_bytes(const lfbp_shape& s, int64_t R, int64_t C);
-hipError_t launch_forward_ws(const float* H, const lfbp_shape& s, const float* gin, int64_t R, int64_t C, float* f,
-                             void* ws, hipStream_t stream);
-size_t backward_workspace_bytes(const lfbp_shape& s, int64_t R, int64_t C);
-hipError_t launch_backward_ws(const float* Ht, const lfbp_shape& s, const float* f, int64_t R, int64_t C, float* g,
-                              void* ws, hipStream_t stream);
-
 namespace {
 
 // ---------------------------------------------------------------- device setup
@@ -42,6 +31,9 @@ hipError_t g_init_err = hipSuccess;
 int g_max_lds = 65536;  // dynamic LDS a workgroup may use (device limit, read at init)
 int g_cus = 256;
 
+}  // namespace
+
+// Once per process: device limits, gather LDS limits.
 hipError_t ensure_init()
 {
     std::call_once(g_init_once, [] {
@@ -58,10 +50,11 @@ hipError_t ensure_init()
             g_max_lds = 65536;
             g_init_err = set_gather_smem_limits(g_max_lds);
         }
-        if (g_init_err == hipSuccess) g_init_err = project_init(g_max_lds);
     });
     return g_init_err;
 }
+
+namespace {
 
 int round16(int64_t b) { return int((b + 15) / 16 * 16); }
 
@@ -442,74 +435,6 @@ void lfbp_release_plans(void)
 {
     std::lock_guard<std::mutex> lock(g_plan_mu);
     g_plans.clear();
-}
-
-lfbp_status lfbp_forward(const float* H, lfbp_shape shape, const float* g, int64_t R, int64_t C, float* f,
-                         void* stream)
-{
-    const lfbp_status st = check_project(H, shape, g, R, C, f, true);
-    if (st != LFBP_OK) return st;
-    if (ensure_init() != hipSuccess) return LFBP_EDEVICE;
-    const hipError_t e = launch_forward(H, shape, g, R, C, f, static_cast<hipStream_t>(stream));
-    if (e == hipErrorOutOfMemory) return LFBP_ENOMEM;
-    return e == hipSuccess ? LFBP_OK : LFBP_EDEVICE;
-}
-
-int64_t lfbp_forward_workspace_size(lfbp_shape shape, int64_t R, int64_t C)
-{
-    if (check_project_shape(shape, R, C) != LFBP_OK) return 0;
-    return int64_t(forward_workspace_bytes(shape, R, C));
-}
-
-lfbp_status lfbp_forward_ws(const float* H, lfbp_shape shape, const float* g, int64_t R, int64_t C, float* f,
-                            void* workspace, int64_t workspace_bytes, void* stream)
-{
-    lfbp_status st = check_project(H, shape, g, R, C, f, true);
-    if (st != LFBP_OK) return st;
-    const int64_t need = int64_t(forward_workspace_bytes(shape, R, C));
-    if (!workspace || workspace_bytes < need || reinterpret_cast<uintptr_t>(workspace) % 256) return LFBP_EINVAL;
-    const uint64_t img = uint64_t(R) * uint64_t(C) * 4, vol = img * uint64_t(shape.nz);
-    if (ranges_overlap(workspace, uint64_t(need), H, shape_elems(shape) * 4) ||
-        ranges_overlap(workspace, uint64_t(need), g, vol) || ranges_overlap(workspace, uint64_t(need), f, img))
-        return LFBP_EALIAS;
-    if (ensure_init() != hipSuccess) return LFBP_EDEVICE;
-    return launch_forward_ws(H, shape, g, R, C, f, workspace, static_cast<hipStream_t>(stream)) == hipSuccess
-               ? LFBP_OK
-               : LFBP_EDEVICE;
-}
-
-lfbp_status lfbp_backward(const float* Ht, lfbp_shape shape, const float* f, int64_t R, int64_t C, float* g,
-                          void* stream)
-{
-    const lfbp_status st = check_project(Ht, shape, f, R, C, g, false);
-    if (st != LFBP_OK) return st;
-    if (ensure_init() != hipSuccess) return LFBP_EDEVICE;
-    const hipError_t e = launch_backward(Ht, shape, f, R, C, g, static_cast<hipStream_t>(stream));
-    if (e == hipErrorOutOfMemory) return LFBP_ENOMEM;
-    return e == hipSuccess ? LFBP_OK : LFBP_EDEVICE;
-}
-
-int64_t lfbp_backward_workspace_size(lfbp_shape shape, int64_t R, int64_t C)
-{
-    if (check_project_shape(shape, R, C) != LFBP_OK) return 0;
-    return int64_t(backward_workspace_bytes(shape, R, C));
-}
-
-lfbp_status lfbp_backward_ws(const float* Ht, lfbp_shape shape, const float* f, int64_t R, int64_t C, float* g,
-                             void* workspace, int64_t workspace_bytes, void* stream)
-{
-    lfbp_status st = check_project(Ht, shape, f, R, C, g, false);
-    if (st != LFBP_OK) return st;
-    const int64_t need = int64_t(backward_workspace_bytes(shape, R, C));
-    if (!workspace || workspace_bytes < need || reinterpret_cast<uintptr_t>(workspace) % 256) return LFBP_EINVAL;
-    const uint64_t img = uint64_t(R) * uint64_t(C) * 4, vol = img * uint64_t(shape.nz);
-    if (ranges_overlap(workspace, uint64_t(need), Ht, shape_elems(shape) * 4) ||
-        ranges_overlap(workspace, uint64_t(need), f, img) || ranges_overlap(workspace, uint64_t(need), g, vol))
-        return LFBP_EALIAS;
-    if (ensure_init() != hipSuccess) return LFBP_EDEVICE;
-    return launch_backward_ws(Ht, shape, f, R, C, g, workspace, static_cast<hipStream_t>(stream)) == hipSuccess
-               ? LFBP_OK
-               : LFBP_EDEVICE;
 }
 
 }  // extern "C"

@@ -667,12 +667,6 @@ unsigned blocks_for(int64_t items) { return unsigned((items + 255) / 256); }
 
 }  // namespace
 
-hipError_t project_init(int max_lds)
-{
-    (void)max_lds;
-    return hipSuccess;
-}
-
 // Workspace of the forward projection: g with depth innermost, the A and B
 // records, then the split partial tiles.
 size_t forward_workspace_bytes(const lfbp_shape& s, int64_t R, int64_t C)

@@ -22,7 +22,11 @@ def rel_l2(got, ref):
 
 SMALL = [((15, 15, 3, 3, 3), 21, 21), ((15, 15, 3, 3, 3), 20, 23), ((9, 7, 3, 5, 2), 12, 10),
          ((5, 5, 5, 5, 1), 7, 8), ((7, 9, 1, 1, 3), 11, 9), ((1, 1, 1, 1, 2), 4, 5), ((3, 3, 7, 7, 2), 14, 21),
-         ((33, 25, 11, 5, 4), 55, 40), ((45, 45, 15, 15, 5), 90, 75), ((21, 21, 3, 3, 9), 8, 7)]
+         ((33, 25, 11, 5, 4), 55, 40), ((45, 45, 15, 15, 5), 90, 75), ((21, 21, 3, 3, 9), 8, 7),
+         # several depth chunks of 22, a ragged last chunk, and one chunk exactly full
+         ((9, 9, 3, 3, 30), 10, 10), ((5, 5, 3, 3, 45), 6, 7), ((3, 3, 3, 3, 23), 7, 5), ((7, 5, 3, 1, 22), 9, 4),
+         # more classes than one 256-column tile (nx*ny = 289), and a backward with several column tiles
+         ((21, 21, 17, 17, 2), 40, 36), ((11, 13, 5, 7, 30), 23, 30)]
 
 
 @pytest.mark.parametrize("shape,R,C", SMALL)

@@ -206,7 +206,8 @@ def backward_mirror(Ht, f):
 SHAPES = [((15, 15, 3, 3, 3), 21, 21), ((15, 15, 3, 3, 3), 20, 23), ((9, 7, 3, 5, 2), 12, 10),
           ((5, 5, 5, 5, 1), 7, 8), ((7, 9, 1, 1, 3), 11, 9), ((1, 1, 1, 1, 2), 4, 5), ((3, 3, 7, 7, 2), 14, 21),
           ((21, 21, 3, 3, 9), 8, 7), ((5, 5, 3, 3, 2), 9, 12), ((3, 3, 1, 1, 2), 5, 6),
-          ((9, 9, 3, 3, 30), 10, 10), ((5, 5, 3, 3, 45), 6, 7), ((3, 3, 3, 3, 23), 7, 5)]
+          ((9, 9, 3, 3, 30), 10, 10), ((5, 5, 3, 3, 45), 6, 7), ((3, 3, 3, 3, 23), 7, 5), ((7, 5, 3, 1, 22), 9, 4),
+          ((21, 21, 17, 17, 2), 40, 36), ((11, 13, 5, 7, 30), 23, 30)]
 
 
 @pytest.mark.parametrize("shape,R,C", SHAPES)
