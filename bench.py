@@ -34,7 +34,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="microscope",
-                    choices=sorted(PLAIN) + ["batched", "projector"])
+                    choices=sorted(PLAIN) + ["batched", "batched-small", "projector"])
     ap.add_argument("--variant", default=None, choices=[None, "direct", "staged"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy", action="store_true",
@@ -153,23 +153,36 @@ def bench_batched(args, torch):
     import lfsynth
     import paper_2003_09133_amd as lf
 
+    small = args.workload == "batched-small"
+    sets = lfsynth.SMALL_SETS if small else lfsynth.BATCHED_SETS
     dev = torch.device("cuda:0")
     Hs, Hts = [], []
-    for w in lfsynth.BATCHED_SETS:
+    for w in sets:
         H, _ = lfsynth.make_H(w)
         Hs.append(torch.from_numpy(H).to(dev))
         Hts.append(torch.empty_like(Hs[-1]))
         del H
     bytes_step = sum(2 * h.numel() * 4 for h in Hs)
 
-    def batched():
-        lf.compute_Ht_batched(Hs, Hts)
+    # Both forms with their arguments prepared once, so that each step is C
+    # calls only: one batched call, or one plain call per set.
+    from paper_2003_09133_amd import _abi
+    batched = lf.BatchedHt(Hs, Hts)
+    L = _abi.lib()
+    plain_args = [(h.data_ptr(), o.data_ptr(), _abi.Shape.of(h.shape)) for h, o in zip(Hs, Hts)]
+    stream = torch.cuda.current_stream().cuda_stream
 
     def sequential():
-        for h, o in zip(Hs, Hts):
-            lf.compute_Ht_into(h, o)
+        for hp, op, shp in plain_args:
+            L.lfbp_compute_Ht(hp, op, shp, _abi.F32, stream)
+
+    probs = batched._probs
+
+    def batched_direct():
+        L.lfbp_compute_Ht_batched_config(probs, len(Hs), _abi.F32, None, 0, stream)
 
     t_seq, _ = time_steps(sequential, args.steps, args.warmup, torch)
+    t_dir, _ = time_steps(batched_direct, args.steps, args.warmup, torch)
     t_bat, wall = time_steps(batched, args.steps, args.warmup, torch)
     sec = t_bat / args.steps
     gbs = bytes_step / sec / 1e9
@@ -177,9 +190,11 @@ def bench_batched(args, torch):
         "metric": METRIC, "value": round(gbs, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "batched 16 PSF sets f32 (Nnum 7-19, 9-25 lenslets, nz 9-41)",
-                   "bytes_per_step": bytes_step, "sets": [list(w.shape) for w in lfsynth.BATCHED_SETS],
+        "config": {"workload": ("batched 64 small PSF sets f32 (Nnum 3-7, 3-7 lenslets, nz 4-12)" if small else
+                                "batched 16 PSF sets f32 (Nnum 7-19, 9-25 lenslets, nz 9-41)"),
+                   "bytes_per_step": bytes_step, "sets": [list(w.shape) for w in sets],
                    "sequential_ms_per_step": round(t_seq / args.steps * 1e3, 4),
+                   "batched_without_graph_ms_per_step": round(t_dir / args.steps * 1e3, 4),
                    "batched_vs_sequential_speedup": round(t_seq / t_bat, 4), "wall_s": round(wall, 3)},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None},
@@ -258,7 +273,7 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}), flush=True)
         sys.exit(1)
-    if args.workload == "batched":
+    if args.workload in ("batched", "batched-small"):
         out = bench_batched(args, torch)
     elif args.workload == "projector":
         out = bench_projector(args, torch)

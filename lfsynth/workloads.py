@@ -47,6 +47,20 @@ def batched_set(i: int) -> Workload:
 BATCHED_SETS = tuple(batched_set(i) for i in range(16))
 
 
+def small_set(i: int) -> Workload:
+    """Set i of the 64-set batch of small PSFs (a depth or lens sweep of a small
+    system, where per-launch overhead is comparable with the work): Nnum cycles
+    through 3, 5, 7; the lenslet count through 3, 5, 7; nz = 4 + (7 i mod 11)."""
+    nnum = (3, 5, 7)[i % 3]
+    lens = (3, 5, 7)[(i // 3 + i) % 3]
+    nz = 4 + (7 * i) % 11
+    patch = lens * nnum
+    return Workload(f"small{i}", (patch, patch, nnum, nnum, nz), 0.8, 0.4, (nz - 1) / 2.0, 2000 + i)
+
+
+SMALL_SETS = tuple(small_set(i) for i in range(64))
+
+
 @dataclass(frozen=True)
 class ProjectorWorkload:
     name: str

@@ -21,7 +21,7 @@ from . import _abi
 from ._abi import (F16, F32, GATHER_AUTO, GATHER_DIRECT, GATHER_STAGED, GATHER_WIDE, GatherConfig,
                    LfbpError, Problem, Shape)
 
-__all__ = ["compute_Ht", "compute_Ht_into", "compute_Ht_batched", "forward", "forward_workspace_size",
+__all__ = ["compute_Ht", "compute_Ht_into", "compute_Ht_batched", "BatchedHt", "forward", "forward_workspace_size",
            "backward", "backward_workspace_size", "LFProject",
            "project", "default_config", "GatherConfig", "LfbpError", "release_plans", "version",
            "GATHER_AUTO", "GATHER_DIRECT", "GATHER_STAGED", "GATHER_WIDE"]
@@ -110,6 +110,36 @@ def compute_Ht_batched(Hs, outs=None, config=None, use_graph: bool = True, strea
                                               1 if use_graph else 0, _stream(stream))
     _abi.check(st, "lfbp_compute_Ht_batched")
     return outs
+
+
+class BatchedHt:
+    """A batch prepared once: the tensors are checked and the problem table is
+    built here, so that each call costs one C call (for repeated H' builds of
+    the same buffers, e.g. in a loop that refreshes the PSFs in place)."""
+
+    def __init__(self, Hs, outs=None):
+        self.Hs = list(Hs)
+        if not self.Hs:
+            raise ValueError("empty batch")
+        for i, H in enumerate(self.Hs):
+            _check_psf(H, f"Hs[{i}]")
+        if len({H.dtype for H in self.Hs}) != 1:
+            raise TypeError("all PSF arrays of a batch must share one dtype")
+        self.outs = [torch.empty_like(H) for H in self.Hs] if outs is None else list(outs)
+        if len(self.outs) != len(self.Hs):
+            raise ValueError("outs must match Hs")
+        for i, (H, o) in enumerate(zip(self.Hs, self.outs)):
+            _check_psf(o, f"outs[{i}]")
+            if o.shape != H.shape or o.dtype != H.dtype:
+                raise ValueError(f"outs[{i}] must have the shape and dtype of Hs[{i}]")
+        self._probs = (Problem * len(self.Hs))(*[Problem(H.data_ptr(), o.data_ptr(), Shape.of(H.shape))
+                                                 for H, o in zip(self.Hs, self.outs)])
+        self._dtype = _DTYPES[self.Hs[0].dtype]
+
+    def __call__(self, stream=None):
+        _abi.check(_abi.lib().lfbp_compute_Ht_batched(self._probs, len(self.Hs), self._dtype, _stream(stream)),
+                   "lfbp_compute_Ht_batched")
+        return self.outs
 
 
 def default_config(shape, dtype=torch.float32) -> dict:

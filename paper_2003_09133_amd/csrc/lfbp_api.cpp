@@ -307,15 +307,29 @@ lfbp_status validate_batch(const lfbp_problem* probs, int32_t count, lfbp_dtype 
         const lfbp_status st = check_gather(probs[i].H, probs[i].Ht, probs[i].shape, dt);
         if (st != LFBP_OK) return st;
     }
-    // no output may overlap any input or any other output
+    // No output may overlap any input or any other output (inputs may overlap
+    // each other).  Sweep the byte ranges in address order: a range that starts
+    // before the furthest end seen so far of a conflicting kind overlaps it.
+    struct Range {
+        uint64_t begin, end;
+        bool out;
+    };
+    std::vector<Range> r;
+    r.reserve(2 * static_cast<size_t>(count));
     for (int32_t i = 0; i < count; ++i) {
-        const uint64_t bi = shape_elems(probs[i].shape) * uint64_t(es);
-        for (int32_t j = 0; j < count; ++j) {
-            if (i == j) continue;
-            const uint64_t bj = shape_elems(probs[j].shape) * uint64_t(es);
-            if (ranges_overlap(probs[i].Ht, bi, probs[j].H, bj)) return LFBP_EALIAS;
-            if (j > i && ranges_overlap(probs[i].Ht, bi, probs[j].Ht, bj)) return LFBP_EALIAS;
-        }
+        const uint64_t b = shape_elems(probs[i].shape) * uint64_t(es);
+        const uint64_t h = reinterpret_cast<uint64_t>(probs[i].H), o = reinterpret_cast<uint64_t>(probs[i].Ht);
+        r.push_back({h, h + b, false});
+        r.push_back({o, o + b, true});
+    }
+    std::sort(r.begin(), r.end(), [](const Range& a, const Range& b) { return a.begin < b.begin; });
+    uint64_t end_in = 0, end_out = 0;
+    for (const Range& x : r) {
+        if (x.begin < end_out || (x.out && x.begin < end_in)) return LFBP_EALIAS;
+        if (x.out)
+            end_out = std::max(end_out, x.end);
+        else
+            end_in = std::max(end_in, x.end);
     }
     return LFBP_OK;
 }

@@ -5,6 +5,7 @@ import os
 import re
 import subprocess
 
+import numpy as np
 import pytest
 
 from paper_2003_09133_amd import _abi
@@ -209,3 +210,25 @@ def test_projector_index_range_limits():
     border = Shape(20001, 20001, 1, 1, 5)          # g's grid with a 10^4-lenslet zero border: 4e8 records
     assert L.lfbp_forward_workspace_size(border, 30, 30) == 0
     assert L.lfbp_forward_workspace_size(Shape(2001, 2001, 1, 1, 5), 30, 30) > 0
+
+
+def test_batch_overlap_check_against_brute_force():
+    """The batch validator's address-ordered sweep against the pairwise
+    definition (an output may overlap no input and no other output; inputs
+    may overlap).  use_graph = 5 makes every table that passes validation
+    return EINVAL before anything could launch."""
+    L = _abi.lib()
+    rng = np.random.default_rng(7)
+    shp = Shape(3, 3, 1, 1, 4)                    # 36 floats = 144 bytes
+    nb = 144
+    for trial in range(300):
+        n = int(rng.integers(1, 9))
+        base = 0x100000000
+        hs = [base + 16 * int(v) for v in rng.integers(0, 64, n)]
+        os_ = [base + 16 * int(v) for v in rng.integers(0, 64, n)]
+        probs = (Problem * n)(*[Problem(h, o, shp) for h, o in zip(hs, os_)])
+        ov = lambda a, b: a < b + nb and b < a + nb
+        bad = any(ov(os_[i], hs[j]) for i in range(n) for j in range(n)) or \
+            any(ov(os_[i], os_[j]) for i in range(n) for j in range(i + 1, n))
+        st = L.lfbp_compute_Ht_batched_config(probs, n, _abi.F32, None, 5, None)
+        assert st == (_abi.EALIAS if bad else _abi.EINVAL), (trial, hs, os_)

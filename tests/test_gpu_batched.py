@@ -117,3 +117,24 @@ def test_batch_beyond_inline_descriptors(n):
         torch.cuda.synchronize()
         for i, (o, H) in enumerate(zip(outs, Hs)):
             assert_same_bits(o.cpu().numpy(), oracle.Ht_rows(H), f"{n} problems, set {i} {cfg}")
+
+
+def test_small_set_batch_full_compare():
+    """The 64-set batch of small PSFs (launch overhead comparable with the
+    work): every set against the oracle, whole arrays, in one graph launch."""
+    Hs = [lfsynth.make_H(w)[0] for w in lfsynth.SMALL_SETS]
+    dHs = [to_dev(H) for H in Hs]
+    outs = lf.compute_Ht_batched(dHs)
+    torch.cuda.synchronize()
+    for w, o, H in zip(lfsynth.SMALL_SETS, outs, Hs):
+        assert_same_bits(o.cpu().numpy(), oracle.Ht_rows(H), f"{w.name} {w.shape}")
+    # the prepared form, called again after the PSFs are refreshed in place
+    prepared = lf.BatchedHt(dHs)
+    for rep in range(2):
+        new = [lfsynth.bits(w.shape, 50 * rep + i, np.float32) for i, w in enumerate(lfsynth.SMALL_SETS)]
+        for d, h in zip(dHs, new):
+            d.copy_(torch.from_numpy(h))
+        got = prepared()
+        torch.cuda.synchronize()
+        for i, (o, h) in enumerate(zip(got, new)):
+            assert_same_bits(o.cpu().numpy(), oracle.Ht_rows(h), f"prepared call {rep}, set {i}")
