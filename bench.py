@@ -54,6 +54,28 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
+def projector_source_sha() -> str:
+    """Digest of the projector kernels and their launch code."""
+    h = hashlib.sha256()
+    for f in ("csrc/lfbp_project.hip", "csrc/lfbp_internal.h", "csrc/lfbp_api_project.cpp"):
+        with open(os.path.join(ROOT, "paper_2003_09133_amd", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def projector_traffic():
+    """HBM bytes of one forward GEMM launch from the committed counter summary,
+    if it was taken on the current projector source; else None."""
+    path = os.path.join(ROOT, "profiles", "projector_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("kernel_source_sha") != projector_source_sha():
+        return None
+    return t["kernels"]["k_gemm<true>"]["hbm_bytes_per_launch"]
+
+
 def traffic_from_profile(workload: str):
     """HBM bytes per launch from the committed counter summary, if it was taken
     on the current kernel source; else None."""
@@ -197,7 +219,8 @@ def bench_batched(args, torch):
                    "batched_without_graph_ms_per_step": round(t_dir / args.steps * 1e3, 4),
                    "batched_vs_sequential_speedup": round(t_seq / t_bat, 4), "wall_s": round(wall, 3)},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None},
+                     "frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "traffic": None if small else traffic_from_profile("batched")},
     }
     return out
 
@@ -246,7 +269,8 @@ def bench_projector(args, torch):
                    "backward_ms": round(t_bwd / args.steps * 1e3, 4),
                    "flop_per_projection": flop_proj, "wall_s": round(wall, 3)},
         "roofline": {"bound": "mfma", "achieved": round(tflops_fwd, 2), "peak": FP32_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(tflops_fwd / FP32_PEAK_TFLOPS, 4), "traffic": None},
+                     "unit": "TFLOP/s", "frac": round(tflops_fwd / FP32_PEAK_TFLOPS, 4),
+                     "traffic": projector_traffic()},
     }
     if not args.no_cpu_baseline:
         import oracle
