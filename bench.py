@@ -5,8 +5,9 @@
 
 Prints ONE JSON line.  A step is one pass of the hot path over its synthetic
 input, already resident in HBM: one lfbp_compute_Ht call (plain workloads), one
-lfbp_compute_Ht_batched call over the 16-set table (batched), or one forward
-plus one backward projection (projector).  K steps are timed with HIP events
+lfbp_compute_Ht_batched call over a table of PSF sets (batched, batched-small),
+one forward plus one backward projection (projector), or one Richardson-Lucy
+update (rl).  K steps are timed with HIP events
 on the stream the kernels run on, bracketed by device synchronisation.
 """
 from __future__ import annotations
@@ -34,7 +35,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="microscope",
-                    choices=sorted(PLAIN) + ["batched", "batched-small", "projector"])
+                    choices=sorted(PLAIN) + ["batched", "batched-small", "projector", "rl"])
     ap.add_argument("--variant", default=None, choices=[None, "direct", "staged"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy", action="store_true",
@@ -287,6 +288,60 @@ def bench_projector(args, torch):
     return out
 
 
+def bench_rl(args, torch):
+    """One step = one Richardson-Lucy update (Eq. 2) of a 21 x 600 x 600 volume
+    from a 600 x 600 image: forward projection ending in the quotient,
+    backprojection through H' ending in the update (lfbp_rl_step)."""
+    import numpy as np
+    import lfsynth
+    import paper_2003_09133_amd as lf
+
+    pw = lfsynth.PROJECTOR
+    H, _ = lfsynth.make_H(pw.psf)
+    R, C = pw.image
+    dev = torch.device("cuda:0")
+    dH = torch.from_numpy(H).to(dev)
+    dHt = lf.compute_Ht(dH)
+    f = torch.from_numpy(lfsynth.uniform_f32((R, C), pw.g_seed + 1) + np.float32(0.5)).to(dev)
+    g = torch.ones((pw.psf.shape[4], R, C), device=dev)
+    ws = torch.empty(lf.rl_workspace_size(H.shape, R, C), dtype=torch.uint8, device=dev)
+    norm = lf.rl_norm(dHt, R, C, workspace=ws)
+
+    def step():
+        lf.rl_step(dH, dHt, f, g, norm, out=g, workspace=ws)
+
+    elapsed, wall = time_steps(step, args.steps, args.warmup, torch)
+    sec = elapsed / args.steps
+    ns, nt, nx, ny, nz = pw.psf.shape
+    flop = 2 * 2.0 * nz * R * C * ns * nt          # one forward and one backprojection
+    tflops = flop / sec / 1e12
+    out = {
+        "metric": "Richardson-Lucy iterations/s", "value": round(1.0 / sec, 2), "unit": "iterations/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"Richardson-Lucy update, {R}x{C} px, {pw.lenslets}x{pw.lenslets} lenslets, "
+                               f"H{list(pw.psf.shape)} f32", "flop_per_step": flop, "wall_s": round(wall, 3),
+                   "finite": bool(torch.isfinite(g).all().item())},
+        "roofline": {"bound": "mfma", "achieved": round(tflops, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(tflops / FP32_PEAK_TFLOPS, 4), "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        nth = cores_used()
+        rng = np.random.default_rng(0)
+        pix = rng.integers(0, [R, C], size=(400, 2))
+        gh = g.cpu().numpy()
+        t0 = time.perf_counter()
+        oracle.forward_at(H, gh, pix, nthreads=nth)
+        dt = time.perf_counter() - t0
+        per_step = 2 * dt * (R * C) / len(pix)
+        out["cpu_baseline"] = {"value": round(1.0 / per_step, 6), "unit": "iterations/s", "cores": nth,
+                               "kind": "oracle", "sample": f"float64 oracle forward at {len(pix)} random pixels "
+                                                           f"({dt:.2f} s), scaled to a forward and a backward "
+                                                           f"projection of the whole volume"}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -301,6 +356,8 @@ def main():
         out = bench_batched(args, torch)
     elif args.workload == "projector":
         out = bench_projector(args, torch)
+    elif args.workload == "rl":
+        out = bench_rl(args, torch)
     else:
         out = bench_plain(args, torch)
     print(json.dumps(out), flush=True)

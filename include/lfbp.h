@@ -214,6 +214,44 @@ LFBP_API int64_t lfbp_backward_workspace_size(lfbp_shape shape, int64_t R, int64
 LFBP_API lfbp_status lfbp_backward_ws(const float* Ht, lfbp_shape shape, const float* f, int64_t R, int64_t C,
                                       float* g, void* workspace, int64_t workspace_bytes, void* stream);
 
+/*
+ * lfbp_rl_step -- one Richardson-Lucy update of a volume estimate (Eq. 2):
+ *
+ *   g_out = g / (H' 1) * H' ( f / (H g) ),
+ *
+ * elementwise products and quotients; H g is lfbp_forward(H, g) and H' x is
+ * lfbp_backward(Ht, x).  Where (H g)[p][q] is 0 the quotient is taken as 0;
+ * where norm = H' 1 is 0 (a voxel that reaches no pixel of the image) g_out
+ * is 0.  The quotient is formed in float64 from the float64 sum of the
+ * forward projection; the update is formed in float32 in the backprojection's
+ * epilogue, so no intermediate volume is stored.
+ * H, Ht float32 [ns][nt][nx][ny][nz] (Ht = lfbp_compute_Ht(H)); f float32
+ * [R][C] (the measured image); g, norm, g_out float32 [nz][R][C]; norm is
+ * the backprojection of an all-ones image, computed once by the caller with
+ * lfbp_backward.  g_out may be g (update in place); it must not overlap any
+ * other argument.  Workspace: lfbp_rl_workspace_size() bytes from the
+ * stream-ordered allocator; lfbp_rl_step_ws takes caller memory and
+ * allocates nothing.  Errors as lfbp_forward and lfbp_backward.
+ */
+LFBP_API lfbp_status lfbp_rl_step(const float* H, const float* Ht, lfbp_shape shape, const float* f, int64_t R,
+                                  int64_t C, const float* g, const float* norm, float* g_out, void* stream);
+
+/* Bytes of device workspace lfbp_rl_step_ws needs (0 when invalid). */
+LFBP_API int64_t lfbp_rl_workspace_size(lfbp_shape shape, int64_t R, int64_t C);
+
+/* lfbp_rl_step with a caller workspace of at least lfbp_rl_workspace_size()
+ * bytes, 256-byte aligned, overlapping no argument.  Allocates nothing. */
+LFBP_API lfbp_status lfbp_rl_step_ws(const float* H, const float* Ht, lfbp_shape shape, const float* f, int64_t R,
+                                     int64_t C, const float* g, const float* norm, float* g_out, void* workspace,
+                                     int64_t workspace_bytes, void* stream);
+
+/* norm = H' 1, the backprojection of an all-ones R x C image (the normaliser
+ * of lfbp_rl_step), with a caller workspace of lfbp_rl_workspace_size() bytes
+ * (256-byte aligned, overlapping neither Ht nor norm).  norm float32
+ * [nz][R][C].  Allocates nothing.  Errors as lfbp_backward_ws. */
+LFBP_API lfbp_status lfbp_rl_norm_ws(const float* Ht, lfbp_shape shape, int64_t R, int64_t C, float* norm,
+                                     void* workspace, int64_t workspace_bytes, void* stream);
+
 /* Static text for a status code (never NULL). */
 LFBP_API const char* lfbp_status_string(lfbp_status s);
 

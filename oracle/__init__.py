@@ -52,6 +52,8 @@ def _load():
             "oracle_forward_at": [vp, vp, vp, i64, i64, vp, i64, vp, i32],
             "oracle_backward": [vp, vp, vp, i64, i64, vp, i32],
             "oracle_backward_at": [vp, vp, vp, i64, i64, vp, i64, vp, i32],
+            "oracle_forward_d": [vp, vp, vp, i64, i64, vp, i32],
+            "oracle_backward_d": [vp, vp, vp, i64, i64, vp, i32],
         }.items():
             fn = getattr(lib, name)
             fn.argtypes = args
@@ -167,4 +169,49 @@ def backward_at(H: np.ndarray, f: np.ndarray, voxels: np.ndarray, nthreads: int 
     _check(_load().oracle_backward_at(H.ctypes.data, _dims(H).ctypes.data, f.ctypes.data, R, C,
                                       vox.ctypes.data, len(vox), out.ctypes.data, nthreads),
            "oracle_backward_at")
+    return out
+
+
+def forward64(H: np.ndarray, g: np.ndarray, nthreads: int = 0) -> np.ndarray:
+    """f = A g with a float64 volume g [nz][R][C]; float64."""
+    H, g = _f32(H), np.ascontiguousarray(g, dtype=np.float64)
+    nz, R, C = g.shape
+    assert nz == H.shape[4]
+    f = np.empty((R, C), dtype=np.float64)
+    _check(_load().oracle_forward_d(H.ctypes.data, _dims(H).ctypes.data, g.ctypes.data, R, C,
+                                    f.ctypes.data, nthreads), "oracle_forward_d")
+    return f
+
+
+def backward64(H: np.ndarray, f: np.ndarray, nthreads: int = 0) -> np.ndarray:
+    """A^T f with a float64 image f [R][C], computed from H; float64."""
+    H, f = _f32(H), np.ascontiguousarray(f, dtype=np.float64)
+    R, C = f.shape
+    g = np.empty((H.shape[4], R, C), dtype=np.float64)
+    _check(_load().oracle_backward_d(H.ctypes.data, _dims(H).ctypes.data, f.ctypes.data, R, C,
+                                     g.ctypes.data, nthreads), "oracle_backward_d")
+    return g
+
+
+def rl_norm(H: np.ndarray, R: int, C: int, nthreads: int = 0) -> np.ndarray:
+    """A^T 1: the normaliser of the Richardson-Lucy update (Eq. 2), float64."""
+    return backward64(H, np.ones((R, C)), nthreads)
+
+
+def rl_step(H: np.ndarray, f: np.ndarray, g: np.ndarray, norm: np.ndarray | None = None,
+            nthreads: int = 0) -> np.ndarray:
+    """One Richardson-Lucy update (Eq. 2) in float64, from H (never H'):
+
+        g_new = g / (A^T 1) * A^T ( f / (A g) ),
+
+    elementwise.  Readings: where (A g)[p][q] is 0 the quotient is 0; where
+    A^T 1 is 0 (a voxel seen by no pixel of the image) g_new is 0."""
+    R, C = f.shape
+    norm = rl_norm(H, R, C, nthreads) if norm is None else np.asarray(norm, dtype=np.float64)
+    fp = forward64(H, g, nthreads)
+    ratio = np.zeros_like(fp)
+    np.divide(np.asarray(f, dtype=np.float64), fp, out=ratio, where=fp > 0)
+    bp = backward64(H, ratio, nthreads)
+    out = np.zeros_like(bp)
+    np.divide(np.asarray(g, dtype=np.float64) * bp, norm, out=out, where=norm > 0)
     return out

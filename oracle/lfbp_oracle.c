@@ -316,3 +316,61 @@ int oracle_backward_at(const float* H, const int64_t* dims, const float* f, int6
         out[k] = backward_voxel(&h, H, f, R, C, vox[3 * k], vox[3 * k + 1], vox[3 * k + 2]);
     return 0;
 }
+
+/* The same two projections with a float64 volume or image (the iterates of
+ * the Richardson-Lucy oracle, Eq. 2, stay in float64). */
+static double forward_pixel_d(const oshape* h, const float* H, const double* g, int64_t R, int64_t C, int64_t p,
+                              int64_t q)
+{
+    const int64_t hs = (h->ns - 1) / 2, ht = (h->nt - 1) / 2;
+    double acc = 0.0;
+    for (int64_t z = 0; z < h->nz; ++z)
+        for (int64_t P = p - hs; P <= p + hs; ++P) {
+            if (P < 0 || P >= R) continue;
+            for (int64_t Q = q - ht; Q <= q + ht; ++Q) {
+                if (Q < 0 || Q >= C) continue;
+                const int64_t k = A_index(h, p, q, z, P, Q);
+                if (k < 0) continue;
+                acc += (double)H[k] * g[(z * R + P) * C + Q];
+            }
+        }
+    return acc;
+}
+
+static double backward_voxel_d(const oshape* h, const float* H, const double* f, int64_t R, int64_t C, int64_t z,
+                               int64_t P, int64_t Q)
+{
+    const int64_t hs = (h->ns - 1) / 2, ht = (h->nt - 1) / 2;
+    double acc = 0.0;
+    for (int64_t p = P - hs; p <= P + hs; ++p) {
+        if (p < 0 || p >= R) continue;
+        for (int64_t q = Q - ht; q <= Q + ht; ++q) {
+            if (q < 0 || q >= C) continue;
+            const int64_t k = A_index(h, p, q, z, P, Q);
+            if (k < 0) continue;
+            acc += (double)H[k] * f[p * C + q];
+        }
+    }
+    return acc;
+}
+
+int oracle_forward_d(const float* H, const int64_t* dims, const double* g, int64_t R, int64_t C, double* f,
+                     int nthreads)
+{
+    const oshape h = mkshape(dims);
+#pragma omp parallel for num_threads(nthreads_or_default(nthreads)) schedule(dynamic, 1)
+    for (int64_t p = 0; p < R; ++p)
+        for (int64_t q = 0; q < C; ++q) f[p * C + q] = forward_pixel_d(&h, H, g, R, C, p, q);
+    return 0;
+}
+
+int oracle_backward_d(const float* H, const int64_t* dims, const double* f, int64_t R, int64_t C, double* g,
+                      int nthreads)
+{
+    const oshape h = mkshape(dims);
+#pragma omp parallel for num_threads(nthreads_or_default(nthreads)) schedule(dynamic, 1) collapse(2)
+    for (int64_t z = 0; z < h.nz; ++z)
+        for (int64_t P = 0; P < R; ++P)
+            for (int64_t Q = 0; Q < C; ++Q) g[(z * R + P) * C + Q] = backward_voxel_d(&h, H, f, R, C, z, P, Q);
+    return 0;
+}

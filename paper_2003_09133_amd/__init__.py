@@ -10,6 +10,7 @@ provides device memory and streams.
     forward(H, g)              f = H g (Sec. 2.1, Eq. 1)
     backward(Ht, f)            g = H' f (Eq. 2, backprojection)
     LFProject                  torch.autograd.Function: forward by H, gradient by H'
+    rl_step(H, Ht, f, g, norm) one Richardson-Lucy update (Eq. 2); richardson_lucy(H, f, n)
 """
 from __future__ import annotations
 
@@ -22,9 +23,9 @@ from ._abi import (F16, F32, GATHER_AUTO, GATHER_DIRECT, GATHER_STAGED, GATHER_W
                    LfbpError, Problem, Shape)
 
 __all__ = ["compute_Ht", "compute_Ht_into", "compute_Ht_batched", "BatchedHt", "forward", "forward_workspace_size",
-           "backward", "backward_workspace_size", "LFProject",
-           "project", "default_config", "GatherConfig", "LfbpError", "release_plans", "version",
-           "GATHER_AUTO", "GATHER_DIRECT", "GATHER_STAGED", "GATHER_WIDE"]
+           "backward", "backward_workspace_size", "LFProject", "project", "rl_norm", "rl_step",
+           "rl_workspace_size", "richardson_lucy", "default_config", "GatherConfig", "LfbpError", "release_plans",
+           "version", "GATHER_AUTO", "GATHER_DIRECT", "GATHER_STAGED", "GATHER_WIDE"]
 
 _DTYPES = {torch.float32: F32, torch.float16: F16}
 
@@ -232,6 +233,59 @@ def project(g: torch.Tensor, H: torch.Tensor, Ht: torch.Tensor | None = None) ->
     if Ht is None:
         Ht = compute_Ht(H)
     return LFProject.apply(g, H, Ht)
+
+
+def rl_norm(Ht: torch.Tensor, R: int, C: int, workspace: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """H' 1: the backprojection of an all-ones R x C image, the normaliser of
+    the Richardson-Lucy update (Eq. 2)."""
+    _check_f32(Ht, "Ht", 5)
+    norm = torch.empty((Ht.shape[4], R, C), dtype=torch.float32, device=Ht.device)
+    workspace = _workspace(workspace, rl_workspace_size(Ht.shape, R, C), Ht.device)
+    _abi.check(_abi.lib().lfbp_rl_norm_ws(Ht.data_ptr(), Shape.of(Ht.shape), int(R), int(C), norm.data_ptr(),
+                                          workspace.data_ptr(), workspace.numel() * workspace.element_size(),
+                                          _stream(stream)), "lfbp_rl_norm_ws")
+    return norm
+
+
+def rl_workspace_size(shape, R: int, C: int) -> int:
+    """Bytes of scratch device memory one Richardson-Lucy step needs."""
+    return int(_abi.lib().lfbp_rl_workspace_size(Shape.of(shape), int(R), int(C)))
+
+
+def rl_step(H: torch.Tensor, Ht: torch.Tensor, f: torch.Tensor, g: torch.Tensor, norm: torch.Tensor,
+            out: torch.Tensor | None = None, workspace: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """One Richardson-Lucy update g / (H' 1) * H'(f / (H g)) (Eq. 2).  out may
+    be g itself (in-place update)."""
+    _check_f32(H, "H", 5)
+    _check_f32(Ht, "Ht", 5)
+    _check_f32(f, "f", 2)
+    _check_f32(g, "g", 3)
+    _check_f32(norm, "norm", 3)
+    R, C = f.shape
+    if H.shape != Ht.shape or g.shape != (H.shape[4], R, C) or norm.shape != g.shape:
+        raise ValueError("H, Ht, f, g and norm shapes do not match")
+    out = torch.empty_like(g) if out is None else out
+    _check_f32(out, "out", 3)
+    workspace = _workspace(workspace, rl_workspace_size(H.shape, R, C), g.device)
+    _abi.check(_abi.lib().lfbp_rl_step_ws(H.data_ptr(), Ht.data_ptr(), Shape.of(H.shape), f.data_ptr(), R, C,
+                                          g.data_ptr(), norm.data_ptr(), out.data_ptr(), workspace.data_ptr(),
+                                          workspace.numel() * workspace.element_size(), _stream(stream)),
+               "lfbp_rl_step")
+    return out
+
+
+def richardson_lucy(H: torch.Tensor, f: torch.Tensor, iters: int, g0: torch.Tensor | None = None,
+                    Ht: torch.Tensor | None = None) -> torch.Tensor:
+    """iters Richardson-Lucy updates of a volume from the image f, starting
+    from g0 (default: ones); H' is built on the GPU when not given."""
+    Ht = compute_Ht(H) if Ht is None else Ht
+    R, C = f.shape
+    ws = torch.empty(rl_workspace_size(H.shape, R, C), dtype=torch.uint8, device=f.device)
+    norm = rl_norm(Ht, R, C, workspace=ws)
+    g = torch.ones((H.shape[4], R, C), dtype=torch.float32, device=f.device) if g0 is None else g0.clone()
+    for _ in range(iters):
+        rl_step(H, Ht, f, g, norm, out=g, workspace=ws)
+    return g
 
 
 def release_plans():

@@ -2,6 +2,8 @@
 // handling, launches).  The kernels are in lfbp_project.hip.
 #include <hip/hip_runtime.h>
 
+#include <utility>
+
 #include "lfbp.h"
 #include "lfbp_validate.h"
 
@@ -18,6 +20,14 @@ hipError_t launch_forward_ws(const float* H, const lfbp_shape& s, const float* g
                              void* ws, hipStream_t stream);
 hipError_t launch_backward_ws(const float* Ht, const lfbp_shape& s, const float* f, int64_t R, int64_t C, float* g,
                               void* ws, hipStream_t stream);
+size_t rl_workspace_bytes(const lfbp_shape& s, int64_t R, int64_t C);
+hipError_t launch_rl_step(const float* H, const float* Ht, const lfbp_shape& s, const float* fmeas, int64_t R,
+                          int64_t C, const float* g, const float* norm, float* g_out, hipStream_t stream);
+hipError_t launch_rl_step_ws(const float* H, const float* Ht, const lfbp_shape& s, const float* fmeas, int64_t R,
+                             int64_t C, const float* g, const float* norm, float* g_out, void* ws,
+                             hipStream_t stream);
+hipError_t launch_rl_norm_ws(const float* Ht, const lfbp_shape& s, int64_t R, int64_t C, float* norm, void* ws,
+                             hipStream_t stream);
 
 }  // namespace lfbp
 
@@ -89,6 +99,61 @@ lfbp_status lfbp_backward_ws(const float* Ht, lfbp_shape shape, const float* f, 
         return LFBP_EALIAS;
     if (ensure_init() != hipSuccess) return LFBP_EDEVICE;
     return launch_backward_ws(Ht, shape, f, R, C, g, workspace, static_cast<hipStream_t>(stream)) == hipSuccess
+               ? LFBP_OK
+               : LFBP_EDEVICE;
+}
+
+lfbp_status lfbp_rl_step(const float* H, const float* Ht, lfbp_shape shape, const float* f, int64_t R, int64_t C,
+                         const float* g, const float* norm, float* g_out, void* stream)
+{
+    const lfbp_status st = check_rl(H, Ht, shape, f, R, C, g, norm, g_out);
+    if (st != LFBP_OK) return st;
+    if (ensure_init() != hipSuccess) return LFBP_EDEVICE;
+    const hipError_t e = launch_rl_step(H, Ht, shape, f, R, C, g, norm, g_out, static_cast<hipStream_t>(stream));
+    if (e == hipErrorOutOfMemory) return LFBP_ENOMEM;
+    return e == hipSuccess ? LFBP_OK : LFBP_EDEVICE;
+}
+
+int64_t lfbp_rl_workspace_size(lfbp_shape shape, int64_t R, int64_t C)
+{
+    if (check_project_shape(shape, R, C) != LFBP_OK) return 0;
+    return int64_t(rl_workspace_bytes(shape, R, C));
+}
+
+lfbp_status lfbp_rl_step_ws(const float* H, const float* Ht, lfbp_shape shape, const float* f, int64_t R, int64_t C,
+                            const float* g, const float* norm, float* g_out, void* workspace, int64_t workspace_bytes,
+                            void* stream)
+{
+    const lfbp_status st = check_rl(H, Ht, shape, f, R, C, g, norm, g_out);
+    if (st != LFBP_OK) return st;
+    const int64_t need = int64_t(rl_workspace_bytes(shape, R, C));
+    if (!workspace || workspace_bytes < need || reinterpret_cast<uintptr_t>(workspace) % 256) return LFBP_EINVAL;
+    const uint64_t img = uint64_t(R) * uint64_t(C) * 4, vol = img * uint64_t(shape.nz), psf = shape_elems(shape) * 4;
+    for (const std::pair<const void*, uint64_t>& r : {std::pair<const void*, uint64_t>(H, psf), {Ht, psf}, {f, img},
+                                                      {g, vol}, {norm, vol}, {g_out, vol}})
+        if (ranges_overlap(workspace, uint64_t(need), r.first, r.second)) return LFBP_EALIAS;
+    if (ensure_init() != hipSuccess) return LFBP_EDEVICE;
+    return launch_rl_step_ws(H, Ht, shape, f, R, C, g, norm, g_out, workspace, static_cast<hipStream_t>(stream)) ==
+                   hipSuccess
+               ? LFBP_OK
+               : LFBP_EDEVICE;
+}
+
+lfbp_status lfbp_rl_norm_ws(const float* Ht, lfbp_shape shape, int64_t R, int64_t C, float* norm, void* workspace,
+                            int64_t workspace_bytes, void* stream)
+{
+    if (!Ht || !norm) return LFBP_EINVAL;
+    const lfbp_status st = check_project_shape(shape, R, C);
+    if (st != LFBP_OK) return st;
+    if (reinterpret_cast<uintptr_t>(Ht) % 4 || reinterpret_cast<uintptr_t>(norm) % 4) return LFBP_EALIGN;
+    const uint64_t vol = uint64_t(R) * uint64_t(C) * uint64_t(shape.nz) * 4, psf = shape_elems(shape) * 4;
+    if (ranges_overlap(norm, vol, Ht, psf)) return LFBP_EALIAS;
+    const int64_t need = int64_t(rl_workspace_bytes(shape, R, C));
+    if (!workspace || workspace_bytes < need || reinterpret_cast<uintptr_t>(workspace) % 256) return LFBP_EINVAL;
+    if (ranges_overlap(workspace, uint64_t(need), Ht, psf) || ranges_overlap(workspace, uint64_t(need), norm, vol))
+        return LFBP_EALIAS;
+    if (ensure_init() != hipSuccess) return LFBP_EDEVICE;
+    return launch_rl_norm_ws(Ht, shape, R, C, norm, workspace, static_cast<hipStream_t>(stream)) == hipSuccess
                ? LFBP_OK
                : LFBP_EDEVICE;
 }

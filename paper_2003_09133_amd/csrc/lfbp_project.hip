@@ -124,6 +124,10 @@ struct GemmArgs {
     const float* A;   // left operand records
     const float* B;   // right operand records [stage][Npad][kRec]
     float* out;       // forward: partial tiles [splits][Mpad][Npad]; backward: g [nz][R][C]
+    // backward, Richardson-Lucy update (Eq. 2): when set, the result v of a
+    // voxel is written as gprev * v / norm (0 where norm is 0)
+    const float* gprev;
+    const float* norm;
     ProjGeom g;
     int M, N, Mpad, Npad;
     int mtiles, ntiles;
@@ -401,7 +405,15 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2
                         if (m >= g.M) continue;
                         const int Lp = int(fdiv(uint32_t(m), g.fLc)), Lq = m - Lp * g.Lc;
                         const int P = g.nx * Lp + cx, Q = g.ny * Lq + cy;
-                        if (P < g.R && Q < g.C) a.out[z * plane + size_t(P) * g.C + Q] = v[e];
+                        if (P < g.R && Q < g.C) {
+                            const size_t o = z * plane + size_t(P) * g.C + Q;
+                            if (a.norm) {
+                                const float nv = a.norm[o];
+                                a.out[o] = nv > 0.0f ? a.gprev[o] * v[e] / nv : 0.0f;
+                            } else {
+                                a.out[o] = v[e];
+                            }
+                        }
                     }
                 }
         }
@@ -580,8 +592,10 @@ __global__ void __launch_bounds__(256) k_pack_bwd_a(const float* f, PackArgs p, 
 }
 
 // f[p][q] = sum over splits of the partial tile entry of (lenslet, class).
+// With fmeas set (Richardson-Lucy, Eq. 2), the quotient fmeas / f is written
+// instead, 0 where f is not positive.
 __global__ void __launch_bounds__(256) k_fwd_reduce(const float* partial, int splits, int Mpad, int Npad,
-                                                     ProjGeom g, float* f)
+                                                     ProjGeom g, const float* fmeas, float* f)
 {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= int64_t(g.R) * g.C) return;
@@ -590,7 +604,10 @@ __global__ void __launch_bounds__(256) k_fwd_reduce(const float* partial, int sp
     const int n = (p % g.nx) * g.ny + q % g.ny;
     double acc = 0.0;
     for (int s = 0; s < splits; ++s) acc += double(partial[(size_t(s) * Mpad + m) * Npad + n]);
-    f[i] = float(acc);
+    if (fmeas)
+        f[i] = acc > 0.0 ? float(double(fmeas[i]) / acc) : 0.0f;
+    else
+        f[i] = float(acc);
 }
 
 // ---------------------------------------------------------------- host side
@@ -682,8 +699,10 @@ size_t backward_workspace_bytes(const lfbp_shape& s, int64_t R, int64_t C)
     return P.A_bytes + P.B_bytes;
 }
 
-hipError_t launch_forward_ws(const float* H, const lfbp_shape& s, const float* gin, int64_t R, int64_t C, float* f,
-                             void* ws, hipStream_t stream)
+namespace {
+
+hipError_t forward_impl(const float* H, const lfbp_shape& s, const float* gin, int64_t R, int64_t C,
+                        const float* fmeas, float* f, void* ws, hipStream_t stream)
 {
     const FwdPlan P = fwd_plan(s, R, C);
     const ProjGeom& g = P.g;
@@ -737,12 +756,12 @@ hipError_t launch_forward_ws(const float* H, const lfbp_shape& s, const float* g
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int64_t npix = int64_t(g.R) * g.C;
     hipLaunchKernelGGL(k_fwd_reduce, dim3(blocks_for(npix)), dim3(256), 0, stream, part, P.splits, P.Mpad, P.Npad, g,
-                       f);
+                       fmeas, f);
     return hipGetLastError();
 }
 
-hipError_t launch_backward_ws(const float* Ht, const lfbp_shape& s, const float* f, int64_t R, int64_t C, float* g_out,
-                              void* ws, hipStream_t stream)
+hipError_t backward_impl(const float* Ht, const lfbp_shape& s, const float* f, int64_t R, int64_t C,
+                         const float* gprev, const float* norm, float* g_out, void* ws, hipStream_t stream)
 {
     const BwdPlan P = bwd_plan(s, R, C);
     const ProjGeom& g = P.g;
@@ -772,8 +791,79 @@ hipError_t launch_backward_ws(const float* Ht, const lfbp_shape& s, const float*
     a.splits = 1;
     a.nzc = 1;
     a.fnzc = make_fastdiv(1);
+    a.gprev = gprev;
+    a.norm = norm;
     hipLaunchKernelGGL(k_gemm<false>, dim3(unsigned(P.mtiles * P.ntiles)), dim3(kThreads), 0, stream, a);
     return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_forward_ws(const float* H, const lfbp_shape& s, const float* gin, int64_t R, int64_t C, float* f,
+                             void* ws, hipStream_t stream)
+{
+    return forward_impl(H, s, gin, R, C, nullptr, f, ws, stream);
+}
+
+hipError_t launch_backward_ws(const float* Ht, const lfbp_shape& s, const float* f, int64_t R, int64_t C, float* g,
+                              void* ws, hipStream_t stream)
+{
+    return backward_impl(Ht, s, f, R, C, nullptr, nullptr, g, ws, stream);
+}
+
+// Workspace of one Richardson-Lucy step: the larger of the two projections'
+// workspaces (used one after the other), then the quotient image.
+size_t rl_workspace_bytes(const lfbp_shape& s, int64_t R, int64_t C)
+{
+    return align256(std::max(forward_workspace_bytes(s, R, C), backward_workspace_bytes(s, R, C))) +
+           align256(size_t(R) * size_t(C) * sizeof(float));
+}
+
+// g_out = g / (H' 1) * H'(fmeas / (H g)) (Eq. 2): the forward ends in the
+// quotient, the backprojection's epilogue applies the update.  g_out may be g.
+hipError_t launch_rl_step_ws(const float* H, const float* Ht, const lfbp_shape& s, const float* fmeas, int64_t R,
+                             int64_t C, const float* g, const float* norm, float* g_out, void* ws,
+                             hipStream_t stream)
+{
+    float* ratio = reinterpret_cast<float*>(
+        static_cast<char*>(ws) + align256(std::max(forward_workspace_bytes(s, R, C), backward_workspace_bytes(s, R, C))));
+    hipError_t e = forward_impl(H, s, g, R, C, fmeas, ratio, ws, stream);
+    if (e != hipSuccess) return e;
+    return backward_impl(Ht, s, ratio, R, C, g, norm, g_out, ws, stream);
+}
+
+namespace {
+
+__global__ void __launch_bounds__(256) k_fill(float* p, int64_t n, float v)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+}  // namespace
+
+// norm = H' 1: the backprojection of an all-ones image (the normaliser of Eq. 2).
+hipError_t launch_rl_norm_ws(const float* Ht, const lfbp_shape& s, int64_t R, int64_t C, float* norm, void* ws,
+                             hipStream_t stream)
+{
+    float* ones = reinterpret_cast<float*>(
+        static_cast<char*>(ws) + align256(std::max(forward_workspace_bytes(s, R, C), backward_workspace_bytes(s, R, C))));
+    const int64_t n = R * C;
+    hipLaunchKernelGGL(k_fill, dim3(blocks_for(n)), dim3(256), 0, stream, ones, n, 1.0f);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return backward_impl(Ht, s, ones, R, C, nullptr, nullptr, norm, ws, stream);
+}
+
+hipError_t launch_rl_step(const float* H, const float* Ht, const lfbp_shape& s, const float* fmeas, int64_t R,
+                          int64_t C, const float* g, const float* norm, float* g_out, hipStream_t stream)
+{
+    void* ws = nullptr;
+    hipError_t e = hipMallocAsync(&ws, rl_workspace_bytes(s, R, C), stream);
+    if (e != hipSuccess) return e;
+    e = launch_rl_step_ws(H, Ht, s, fmeas, R, C, g, norm, g_out, ws, stream);
+    const hipError_t e2 = hipFreeAsync(ws, stream);
+    return e != hipSuccess ? e : e2;
 }
 
 hipError_t launch_forward(const float* H, const lfbp_shape& s, const float* g, int64_t R, int64_t C, float* f,

@@ -125,4 +125,20 @@ lfbp_status check_project(const float* psf, const lfbp_shape& s, const float* in
     return LFBP_OK;
 }
 
+lfbp_status check_rl(const float* H, const float* Ht, const lfbp_shape& s, const float* f, int64_t R, int64_t C,
+                     const float* g, const float* norm, const float* g_out)
+{
+    if (!H || !Ht || !f || !g || !norm || !g_out) return LFBP_EINVAL;
+    const lfbp_status st = check_project_shape(s, R, C);
+    if (st != LFBP_OK) return st;
+    for (const float* p : {H, Ht, f, g, norm, g_out})
+        if (reinterpret_cast<uintptr_t>(p) % 4) return LFBP_EALIGN;
+    const uint64_t psf = shape_elems(s) * 4, img = uint64_t(R) * uint64_t(C) * 4, vol = img * uint64_t(s.nz);
+    if (ranges_overlap(g_out, vol, H, psf) || ranges_overlap(g_out, vol, Ht, psf) ||
+        ranges_overlap(g_out, vol, f, img) || ranges_overlap(g_out, vol, norm, vol))
+        return LFBP_EALIAS;
+    if (g_out != g && ranges_overlap(g_out, vol, g, vol)) return LFBP_EALIAS;   // in place, or apart
+    return LFBP_OK;
+}
+
 }  // namespace lfbp

@@ -29,6 +29,11 @@ lfbp_status check_project_shape(const lfbp_shape& s, int64_t R, int64_t C);
 lfbp_status check_project(const float* psf, const lfbp_shape& s, const float* in2, int64_t R, int64_t C,
                           const float* out, bool forward);
 
+// Full check of one Richardson-Lucy step: g_out may be g itself but must not
+// overlap any other argument.
+lfbp_status check_rl(const float* H, const float* Ht, const lfbp_shape& s, const float* f, int64_t R, int64_t C,
+                     const float* g, const float* norm, const float* g_out);
+
 // True when [a, a+na) and [b, b+nb) (bytes) overlap.
 bool ranges_overlap(const void* a, uint64_t na, const void* b, uint64_t nb);
 

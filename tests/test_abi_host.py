@@ -232,3 +232,33 @@ def test_batch_overlap_check_against_brute_force():
             any(ov(os_[i], os_[j]) for i in range(n) for j in range(i + 1, n))
         st = L.lfbp_compute_Ht_batched_config(probs, n, _abi.F32, None, 5, None)
         assert st == (_abi.EALIAS if bad else _abi.EINVAL), (trial, hs, os_)
+
+
+def test_rl_validation_before_launch():
+    """Every rejected Richardson-Lucy call returns before a launch; a call
+    whose only fault is its workspace shows that the in-place form (g_out == g)
+    passes the argument checks."""
+    L = _abi.lib()
+    shape = Shape(15, 15, 3, 3, 3)
+    R = C = 30
+    vol = 3 * R * C * 4
+    H, Ht, f, g, n, o = 0x1000000, 0x2000000, 0x3000000, 0x4000000, 0x5000000, 0x6000000
+    need = L.lfbp_rl_workspace_size(shape, R, C)
+    assert need >= max(L.lfbp_forward_workspace_size(shape, R, C), L.lfbp_backward_workspace_size(shape, R, C))
+    assert L.lfbp_rl_step_ws(H, Ht, shape, f, R, C, g, n, o, None, need, None) == _abi.EINVAL
+    assert L.lfbp_rl_step_ws(H, Ht, shape, f, R, C, g, n, g, None, need, None) == _abi.EINVAL   # in place: ok
+    assert L.lfbp_rl_step_ws(H, Ht, shape, f, R, C, g, n, g + 4, None, need, None) == _abi.EALIAS
+    assert L.lfbp_rl_step_ws(H, Ht, shape, f, R, C, g, n, n + vol - 4, None, need, None) == _abi.EALIAS
+    assert L.lfbp_rl_step_ws(H, Ht, shape, f, R, C, g, n, Ht + 8, None, need, None) == _abi.EALIAS
+    assert L.lfbp_rl_step_ws(H, Ht, shape, f, R, C, g, n, f, None, need, None) == _abi.EALIAS
+    assert L.lfbp_rl_step_ws(H, Ht, shape, f, R, C, g, None, o, None, need, None) == _abi.EINVAL
+    assert L.lfbp_rl_step_ws(H, Ht, shape, f, R, C, g, n, o + 2, None, need, None) == _abi.EALIGN
+    assert L.lfbp_rl_step_ws(H, Ht, Shape(15, 14, 3, 3, 3), f, R, C, g, n, o, None, need, None) == _abi.ESHAPE
+    assert L.lfbp_rl_step(H, Ht, shape, f, R, C, g, n, g + 4, None) == _abi.EALIAS
+    ws = 0x10000000
+    assert L.lfbp_rl_step_ws(H, Ht, shape, f, R, C, g, n, o, g - 256, need, None) == _abi.EALIAS
+    assert L.lfbp_rl_step_ws(H, Ht, shape, f, R, C, g, n, o, ws + 64, need, None) == _abi.EINVAL
+    assert L.lfbp_rl_step_ws(H, Ht, shape, f, R, C, g, n, o, ws, need - 1, None) == _abi.EINVAL
+    assert L.lfbp_rl_norm_ws(Ht, shape, R, C, Ht + 64, ws, need, None) == _abi.EALIAS
+    assert L.lfbp_rl_norm_ws(Ht, shape, R, C, n, None, need, None) == _abi.EINVAL
+    assert L.lfbp_rl_workspace_size(Shape(4, 5, 3, 3, 1), 10, 10) == 0
