@@ -38,6 +38,8 @@ def parse():
                     choices=sorted(PLAIN) + ["batched", "batched-small", "projector", "rl"])
     ap.add_argument("--variant", default=None, choices=[None, "direct", "staged"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--inplace", action="store_true",
+                    help="plain workloads: time lfbp_compute_Ht_inplace (H' written over H)")
     ap.add_argument("--copy", action="store_true",
                     help="time a plain device-to-device copy of the same bytes instead (reference ceiling)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -147,7 +149,13 @@ def bench_plain(args, torch):
     resolved = lf.default_config(w.shape, dH.dtype)
     if cfg:
         resolved.update(cfg)
-    step = (lambda: dHt.copy_(dH)) if args.copy else (lambda: lf.compute_Ht_into(dH, dHt, config=cfg))
+    if args.copy:
+        step = lambda: dHt.copy_(dH)
+    elif args.inplace:
+        del dHt
+        step = lambda: lf.compute_Ht_inplace(dH)     # each step undoes the previous one (involution)
+    else:
+        step = lambda: lf.compute_Ht_into(dH, dHt, config=cfg)
     elapsed, wall = time_steps(step, args.steps, args.warmup, torch)
     bytes_step = 2 * H.nbytes
     sec_step = elapsed / args.steps
@@ -158,11 +166,13 @@ def bench_plain(args, torch):
         "scaling": "weak", "vs_baseline": None, "dtype": dt, "data": "synthetic",
         "config": {"workload": f"{w.name} H{list(w.shape)} {dt}", "shape": list(w.shape),
                    "bytes_per_step": bytes_step, "zero_fraction": round(zf, 4),
-                   "kernel": "torch copy_ (reference)" if args.copy else resolved, "wall_s": round(wall, 3)},
+                   "kernel": ("torch copy_ (reference)" if args.copy else
+                              "k_inplace (H' over H)" if args.inplace else resolved), "wall_s": round(wall, 3)},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile(args.workload)},
+                     "frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "traffic": None if (args.inplace or args.copy) else traffic_from_profile(args.workload)},
     }
-    if not args.no_cpu_baseline and not args.copy:
+    if not args.no_cpu_baseline and not args.copy and not args.inplace:
         nth = cores_used()
         rate, passes, per = cpu_oracle_rate(H, nth, args.cpu_seconds)
         out["cpu_baseline"] = {"value": round(rate, 3), "unit": "GB/s", "cores": nth, "kind": "oracle",

@@ -139,6 +139,16 @@ typedef struct {
 LFBP_API lfbp_status lfbp_compute_Ht_batched(const lfbp_problem* problems, int32_t count, lfbp_dtype dtype,
                                     void* stream);
 
+/*
+ * lfbp_compute_Ht_inplace -- H' written over H (the same re-arrangement as
+ * lfbp_compute_Ht).  The map is its own inverse (Sec. 4: applying it to H'
+ * gives H back), so the array is rewritten in disjoint pairs of x-row groups
+ * with no second array; calling it twice restores H.  Requires 2*ny*nz*esize
+ * <= 65536 bytes (one x-row and its partner in LDS), else ESHAPE.  Errors
+ * EINVAL, EDTYPE, ESHAPE, EALIGN, EDEVICE.  Allocates nothing.
+ */
+LFBP_API lfbp_status lfbp_compute_Ht_inplace(void* H, lfbp_shape shape, lfbp_dtype dtype, void* stream);
+
 /* Same as lfbp_compute_Ht_batched with an explicit kernel choice shared by
  * every problem, and graph use: use_graph = 1 replays a captured graph,
  * 0 launches the kernel directly.  cfg may be NULL. */

@@ -22,7 +22,7 @@ from . import _abi
 from ._abi import (F16, F32, GATHER_AUTO, GATHER_DIRECT, GATHER_STAGED, GATHER_WIDE, GatherConfig,
                    LfbpError, Problem, Shape)
 
-__all__ = ["compute_Ht", "compute_Ht_into", "compute_Ht_batched", "BatchedHt", "forward", "forward_workspace_size",
+__all__ = ["compute_Ht", "compute_Ht_into", "compute_Ht_inplace", "compute_Ht_batched", "BatchedHt", "forward", "forward_workspace_size",
            "backward", "backward_workspace_size", "LFProject", "project", "rl_norm", "rl_step",
            "rl_workspace_size", "richardson_lucy", "default_config", "GatherConfig", "LfbpError", "release_plans",
            "version", "GATHER_AUTO", "GATHER_DIRECT", "GATHER_STAGED", "GATHER_WIDE"]
@@ -80,6 +80,15 @@ def compute_Ht(H: torch.Tensor, config=None, stream=None) -> torch.Tensor:
     """H' of H (Sec. 4): a new tensor of the same shape and dtype."""
     _check_psf(H)
     return compute_Ht_into(H, torch.empty_like(H), config, stream)
+
+
+def compute_Ht_inplace(H: torch.Tensor, stream=None) -> torch.Tensor:
+    """Overwrite H with H' (the map is its own inverse: a second call restores
+    H).  Returns H."""
+    _check_psf(H, "H")
+    _abi.check(_abi.lib().lfbp_compute_Ht_inplace(H.data_ptr(), Shape.of(H.shape), _DTYPES[H.dtype],
+                                                  _stream(stream)), "lfbp_compute_Ht_inplace")
+    return H
 
 
 def compute_Ht_batched(Hs, outs=None, config=None, use_graph: bool = True, stream=None):

@@ -21,6 +21,8 @@ hipError_t launch_gather(const GatherDesc& d, int esize, const LaunchPlan& p, hi
 hipError_t launch_gather_batched(const BatchArgs& a, uint32_t maxW, int esize, const LaunchPlan& p,
                                  hipStream_t stream);
 hipError_t set_gather_smem_limits(int max_bytes);
+hipError_t set_inplace_smem_limits(int max_bytes);
+hipError_t launch_inplace(void* H, const lfbp_shape& s, int esize, int max_lds, hipStream_t stream);
 int gather_occupancy(const LaunchPlan& p, uint32_t W, int esize, bool batched);
 namespace {
 
@@ -45,10 +47,12 @@ hipError_t ensure_init()
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
             g_cus = cus;
         g_init_err = set_gather_smem_limits(g_max_lds);
+        if (g_init_err == hipSuccess) g_init_err = set_inplace_smem_limits(g_max_lds);
         if (g_init_err != hipSuccess && g_max_lds > 65536) {
             (void)hipGetLastError();
             g_max_lds = 65536;
             g_init_err = set_gather_smem_limits(g_max_lds);
+            if (g_init_err == hipSuccess) g_init_err = set_inplace_smem_limits(g_max_lds);
         }
     });
     return g_init_err;
@@ -443,6 +447,21 @@ lfbp_status lfbp_compute_Ht_batched_config(const lfbp_problem* problems, int32_t
 lfbp_status lfbp_compute_Ht_batched(const lfbp_problem* problems, int32_t count, lfbp_dtype dtype, void* stream)
 {
     return lfbp_compute_Ht_batched_config(problems, count, dtype, nullptr, 1, stream);
+}
+
+lfbp_status lfbp_compute_Ht_inplace(void* H, lfbp_shape shape, lfbp_dtype dtype, void* stream)
+{
+    if (!H) return LFBP_EINVAL;
+    const int es = dtype_size(dtype);
+    if (es == 0) return LFBP_EDTYPE;
+    const lfbp_status st = check_shape(shape, es);
+    if (st != LFBP_OK) return st;
+    if (reinterpret_cast<uintptr_t>(H) % uintptr_t(es)) return LFBP_EALIGN;
+    // one x-row of block O and its partner row must fit the LDS together
+    if (uint64_t(shape.ny) * uint64_t(shape.nz) * uint64_t(es) * 2 > uint64_t(kInplaceMinLds)) return LFBP_ESHAPE;
+    if (ensure_init() != hipSuccess) return LFBP_EDEVICE;
+    return launch_inplace(H, shape, es, g_max_lds, static_cast<hipStream_t>(stream)) == hipSuccess ? LFBP_OK
+                                                                                               : LFBP_EDEVICE;
 }
 
 void lfbp_release_plans(void)

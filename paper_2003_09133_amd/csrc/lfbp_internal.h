@@ -95,6 +95,10 @@ struct LaunchPlan {
 // of descriptors and unit prefix sums.
 constexpr uint32_t kInlineProblems = 16;
 
+// LDS the in-place kernel can count on on every device (a pair of x-rows must
+// fit; larger budgets give larger row groups).
+constexpr int kInplaceMinLds = 65536;
+
 struct BatchArgs {
     const GatherDesc* table;     // device descriptor table, or nullptr
     const uint32_t* table_start; // device: first global unit of each problem, count+1 entries

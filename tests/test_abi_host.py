@@ -262,3 +262,13 @@ def test_rl_validation_before_launch():
     assert L.lfbp_rl_norm_ws(Ht, shape, R, C, Ht + 64, ws, need, None) == _abi.EALIAS
     assert L.lfbp_rl_norm_ws(Ht, shape, R, C, n, None, need, None) == _abi.EINVAL
     assert L.lfbp_rl_workspace_size(Shape(4, 5, 3, 3, 1), 10, 10) == 0
+
+
+def test_inplace_validation_before_launch():
+    L = _abi.lib()
+    assert L.lfbp_compute_Ht_inplace(None, GOOD, _abi.F32, None) == _abi.EINVAL
+    assert L.lfbp_compute_Ht_inplace(P1, GOOD, 7, None) == _abi.EDTYPE
+    assert L.lfbp_compute_Ht_inplace(P1, Shape(15, 14, 3, 3, 3), _abi.F32, None) == _abi.ESHAPE
+    assert L.lfbp_compute_Ht_inplace(P1 + 2, GOOD, _abi.F32, None) == _abi.EALIGN
+    # an x-row pair of 2 * 9 * 1000 * 4 bytes does not fit 64 KB of LDS
+    assert L.lfbp_compute_Ht_inplace(P1, Shape(3, 3, 3, 9, 1000), _abi.F32, None) == _abi.ESHAPE

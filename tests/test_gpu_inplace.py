@@ -1,0 +1,71 @@
+"""In-place H -> H' (lfbp_compute_Ht_inplace) against the out-of-place kernels
+and the oracle, bit for bit."""
+import numpy as np
+import pytest
+import torch
+
+import lfsynth
+import oracle
+import paper_2003_09133_amd as lf
+from gpu_util import DEV, assert_same_bits, gpu_equal_bits, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def random_shapes(seed, n):
+    rng = np.random.default_rng(seed)
+    odd = lambda lo, hi: int(rng.integers(lo, hi + 1)) | 1
+    return [(odd(1, 41), odd(1, 41), odd(1, 13), odd(1, 13), int(rng.integers(1, 24))) for _ in range(n)]
+
+
+SHAPES = [(15, 15, 3, 3, 3), (1, 1, 1, 1, 1), (1, 3, 1, 1, 2), (3, 5, 5, 3, 1), (11, 7, 1, 1, 2),
+          (21, 9, 7, 3, 4), (5, 5, 9, 1, 3), (15, 15, 15, 15, 200)] + random_shapes(5, 10)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float16])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_inplace_equals_oracle_and_involution(shape, dtype):
+    H = lfsynth.bits(shape, 17, dtype)
+    d = to_dev(H)
+    lf.compute_Ht_inplace(d)
+    torch.cuda.synchronize()
+    assert_same_bits(d.cpu().numpy(), oracle.Ht_rows(H), f"{shape} {dtype.__name__}")
+    lf.compute_Ht_inplace(d)
+    torch.cuda.synchronize()
+    assert_same_bits(d.cpu().numpy(), H, f"{shape} twice")
+
+
+def test_inplace_microscope_equals_out_of_place():
+    w = lfsynth.MICROSCOPE
+    d = to_dev(lfsynth.bits(w.shape, w.seed, np.float32))
+    ref = lf.compute_Ht(d)
+    lf.compute_Ht_inplace(d)
+    assert gpu_equal_bits(d, ref)
+
+
+def test_inplace_camera_f16_equals_out_of_place():
+    w = lfsynth.CAMERA
+    d = to_dev(lfsynth.bits(w.shape, w.seed, np.float16))
+    ref = lf.compute_Ht(d)
+    lf.compute_Ht_inplace(d)
+    assert gpu_equal_bits(d, ref)
+    del ref
+    lf.compute_Ht_inplace(d)
+    back = to_dev(lfsynth.bits(w.shape, w.seed, np.float16))
+    assert gpu_equal_bits(d, back)
+
+
+def test_inplace_on_a_view_and_stream_order():
+    """A PSF array inside a larger buffer (unaligned start) with canaries
+    around it; queued after a plain build on the same stream."""
+    shape = (9, 11, 5, 3, 7)
+    n = int(np.prod(shape))
+    H = lfsynth.bits(shape, 23, np.float32)
+    buf = torch.full((n + 7,), -1.0, device=DEV)
+    view = buf[3:3 + n].view(shape)
+    view.copy_(torch.from_numpy(H))
+    out = lf.compute_Ht(view)
+    lf.compute_Ht_inplace(view)
+    torch.cuda.synchronize()
+    assert gpu_equal_bits(out, view)                  # bit patterns (the payloads include NaNs)
+    assert torch.all(buf[:3] == -1.0) and torch.all(buf[3 + n:] == -1.0)

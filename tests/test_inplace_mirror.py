@@ -1,0 +1,82 @@
+"""The in-place H -> H' kernel's index arithmetic, on the CPU.
+
+A NumPy mirror of k_inplace (paper_2003_09133_amd/csrc/lfbp_inplace.hip) and of
+its launch arithmetic: every unit (block pair, row group) reads its rows into
+two tiles before writing, units touch disjoint rows, all addresses stay inside
+the array, and the rewritten array equals the oracle's H'.  Keep it in step
+with the kernel."""
+import numpy as np
+import pytest
+
+import lfsynth
+import oracle
+
+
+def inplace_mirror(H, tile_budget=40 * 1024, max_lds=160 * 1024, esize=4):
+    ns, nt, nx, ny, nz = H.shape
+    W, NB = ny * nz, ns * nt
+    hs, ht = (ns - 1) // 2, (nt - 1) // 2
+    a_off, b_off = (nx - hs % nx) % nx, (ny - ht % ny) % ny
+    pairs = (NB - 1) // 2
+    flat = H.reshape(-1).copy()
+    if pairs == 0:
+        return flat.reshape(H.shape), set()
+    budget = tile_budget if 2 * W * esize <= tile_budget else max_lds
+    nr0 = min(nx, budget // (2 * W * esize))
+    assert nr0 > 0
+    groups = -(-nx // nr0)
+    nr_full = -(-nx // groups)
+    assert 2 * nr_full * W * esize <= budget <= max_lds
+    touched = np.zeros(flat.size, np.int64)
+    for unit in range(pairs * groups):
+        O, grp = divmod(unit, groups)
+        Op = NB - 1 - O
+        sp, tp = divmod(O, nt)
+        a, b = (sp + a_off) % nx, (tp + b_off) % ny
+        rotA, rotB = b * nz, ((ny - b) % ny) * nz
+        x0 = grp * nr_full
+        assert x0 < nx
+        nr = min(nr_full, nx - x0)
+        i = np.arange(nr * W)
+        r, j = i // W, i % W
+        xa = x0 + r
+        xb = (xa + a) % nx
+        srcA = Op * nx * W + xb * W + j
+        srcB = O * nx * W + xa * W + j
+        for idx in (srcA, srcB):
+            assert idx.min() >= 0 and idx.max() < flat.size
+        tileA = np.empty(nr * W, flat.dtype)
+        tileB = np.empty(nr * W, flat.dtype)
+        tileA[r * W + (j - rotA) % W] = flat[srcA]
+        tileB[r * W + (j - rotB) % W] = flat[srcB]
+        # writes after all reads of the unit
+        flat[O * nx * W + xa * W + j] = tileA
+        flat[Op * nx * W + xb * W + j] = tileB
+        touched[O * nx * W + xa * W + j] += 1
+        touched[Op * nx * W + xb * W + j] += 1
+    centre = (NB - 1) // 2
+    assert np.all(touched[centre * nx * W:(centre + 1) * nx * W] == 0)
+    rest = np.delete(touched, np.arange(centre * nx * W, (centre + 1) * nx * W))
+    assert np.all(rest == 1)                        # every other element written exactly once
+    return flat.reshape(H.shape), touched
+
+
+@pytest.mark.parametrize("shape", [(15, 15, 3, 3, 3), (9, 7, 3, 5, 2), (3, 5, 5, 3, 1), (1, 1, 1, 1, 2),
+                                   (1, 3, 1, 1, 1), (11, 7, 1, 1, 2), (13, 13, 5, 5, 1), (21, 9, 7, 3, 4),
+                                   (5, 5, 9, 1, 3)])
+@pytest.mark.parametrize("tile_budget", [40 * 1024, 2 * 4 * 15, 512])
+def test_inplace_mirror_equals_oracle(shape, tile_budget):
+    """The launch's tile budget (small budgets force many row groups per block
+    pair; a row pair larger than the budget falls back to the whole LDS)."""
+    H = lfsynth.bits(shape, 3, np.float32)
+    out, _ = inplace_mirror(H, tile_budget)
+    ref = oracle.Ht_rows(H)
+    assert np.array_equal(out.view(np.uint32), ref.view(np.uint32))
+
+
+def test_inplace_mirror_is_an_involution():
+    H = lfsynth.bits((9, 11, 3, 5, 2), 4, np.float32)
+    once, _ = inplace_mirror(H, 600)
+    twice, _ = inplace_mirror(once, 600)
+    assert not np.array_equal(once.view(np.uint32), H.view(np.uint32))
+    assert np.array_equal(twice.view(np.uint32), H.view(np.uint32))
