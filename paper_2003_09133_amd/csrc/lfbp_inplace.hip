@@ -21,6 +21,8 @@ namespace lfbp {
 
 struct InplaceDesc {
     void* H;
+    uint64_t E;             // elements of H
+    uint32_t phase;         // (address of H / element size) mod (16 / element size)
     uint32_t nt, nx, ny, nz, W, NB;
     uint32_t a_off, b_off;  // (s' - hs) mod nx = (s' + a_off) mod nx; likewise t'
     uint32_t nr;            // x-rows per group
@@ -31,13 +33,81 @@ struct InplaceDesc {
 namespace {
 
 constexpr int kTileBudget = 40 * 1024;   // LDS per workgroup when a row pair allows: four workgroups per CU
+constexpr int kGroupRows = 5;            // x-rows per group
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+union Vec16 {
+    u32x4 v;
+    T e[16 / sizeof(T)];
+};
+
+// Read the L contiguous elements H[g, g+L) (whole x-rows) into a tile, each
+// row rotated left by rot: aligned 16-byte loads, element loads only for a
+// vector that sticks out of the array.  Elements of the vectors outside the
+// segment belong to other rows and are dropped.
+template <typename T>
+__device__ __forceinline__ void load_segment(const T* H, uint64_t E, uint32_t phase, uint64_t g, uint32_t L,
+                                             uint32_t W, const FastDiv& fW, uint32_t rot, T* tile)
+{
+    constexpr uint32_t VE = 16 / sizeof(T);
+    const uint64_t u0 = (g + phase) / VE, u1 = (g + L + phase + VE - 1) / VE;
+    for (uint64_t u = u0 + threadIdx.x; u < u1; u += blockDim.x) {
+        const int64_t vg = int64_t(u * VE) - int64_t(phase);   // array index of the vector's first element
+        Vec16<T> p;
+        if (vg >= 0 && uint64_t(vg) + VE <= E) {
+            p.v = *reinterpret_cast<const u32x4*>(H + vg);
+        } else {
+#pragma unroll
+            for (uint32_t q = 0; q < VE; ++q) {
+                const int64_t i = vg + q;
+                p.e[q] = (i >= 0 && uint64_t(i) < E) ? H[i] : T(0);
+            }
+        }
+#pragma unroll
+        for (uint32_t q = 0; q < VE; ++q) {
+            const int64_t e = vg + int64_t(q) - int64_t(g);
+            if (e >= 0 && e < int64_t(L)) {
+                const uint32_t r = fdiv(uint32_t(e), fW), j = uint32_t(e) - r * W;
+                tile[r * W + (j >= rot ? j - rot : j + W - rot)] = p.e[q];
+            }
+        }
+    }
+}
+
+// Write a tile (already in output order) to H[g, g+L): aligned 16-byte stores
+// where a vector lies inside the segment, element stores at its ends; nothing
+// outside the segment is written.
+template <typename T>
+__device__ __forceinline__ void store_segment(T* H, uint32_t phase, uint64_t g, uint32_t L, const T* tile)
+{
+    constexpr uint32_t VE = 16 / sizeof(T);
+    const uint64_t u0 = (g + phase) / VE, u1 = (g + L + phase + VE - 1) / VE;
+    for (uint64_t u = u0 + threadIdx.x; u < u1; u += blockDim.x) {
+        const int64_t vg = int64_t(u * VE) - int64_t(phase);
+        const int64_t e0 = vg - int64_t(g);
+        if (e0 >= 0 && e0 + VE <= L) {
+            Vec16<T> p;
+#pragma unroll
+            for (uint32_t q = 0; q < VE; ++q) p.e[q] = tile[e0 + q];
+            *reinterpret_cast<u32x4*>(H + vg) = p.v;
+        } else {
+#pragma unroll
+            for (uint32_t q = 0; q < VE; ++q) {
+                const int64_t e = e0 + q;
+                if (e >= 0 && e < int64_t(L)) H[vg + q] = tile[e];
+            }
+        }
+    }
+}
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_inplace(InplaceDesc d)
 {
     extern __shared__ unsigned char smem_raw[];
     T* tileA = reinterpret_cast<T*>(smem_raw);   // output rows of block O, in output order
-    T* tileB = tileA + size_t(d.nr) * d.W;      // output rows of block O'
+    T* tileB = tileA + size_t(d.nr) * d.W;      // output rows of block O' (partner order)
     const uint32_t unit = blockIdx.x;
     const uint32_t O = fdiv(unit, d.fgroups), grp = unit - O * d.groups;
     const uint32_t Op = d.NB - 1 - O;
@@ -50,30 +120,22 @@ __global__ void __launch_bounds__(256) k_inplace(InplaceDesc d)
     const uint32_t x0 = grp * d.nr;
     if (x0 >= d.nx) return;  // never taken: the host balances groups so that every group has rows
     const uint32_t nr = min(d.nr, d.nx - x0);
-    const uint32_t W = d.W, n = nr * W;
+    const uint32_t W = d.W;
     T* H = static_cast<T*>(d.H);
-    const uint64_t baseO = uint64_t(O) * d.nx * W, baseOp = uint64_t(Op) * d.nx * W;
-    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
-        const uint32_t r = fdiv(i, d.fW), j = i - r * W;
-        const uint32_t xa = x0 + r;
-        uint32_t xb = xa + a;
-        if (xb >= d.nx) xb -= d.nx;
-        // output row (O, xa) is input row (O', xb) rotated left by rotA;
-        // output row (O', xb) is input row (O, xa) rotated left by rotB
-        const T vA = H[baseOp + uint64_t(xb) * W + j];
-        const T vB = H[baseO + uint64_t(xa) * W + j];
-        tileA[r * W + (j >= rotA ? j - rotA : j + W - rotA)] = vA;
-        tileB[r * W + (j >= rotB ? j - rotB : j + W - rotB)] = vB;
-    }
+    // rows x0.. of block O pair with rows (x0 + a) mod nx.. of block O': one
+    // segment there, or two when the partner rows wrap past row nx-1
+    uint32_t xb0 = x0 + a;
+    if (xb0 >= d.nx) xb0 -= d.nx;
+    const uint32_t k1 = min(nr, d.nx - xb0);
+    const uint64_t gO = (uint64_t(O) * d.nx + x0) * W;
+    const uint64_t gP1 = (uint64_t(Op) * d.nx + xb0) * W, gP2 = uint64_t(Op) * d.nx * W;
+    load_segment(H, d.E, d.phase, gO, nr * W, W, d.fW, rotB, tileB);
+    load_segment(H, d.E, d.phase, gP1, k1 * W, W, d.fW, rotA, tileA);
+    if (nr > k1) load_segment(H, d.E, d.phase, gP2, (nr - k1) * W, W, d.fW, rotA, tileA + size_t(k1) * W);
     __syncthreads();  // every read of the pair precedes every write
-    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
-        const uint32_t r = fdiv(i, d.fW), j = i - r * W;
-        const uint32_t xa = x0 + r;
-        uint32_t xb = xa + a;
-        if (xb >= d.nx) xb -= d.nx;
-        H[baseO + uint64_t(xa) * W + j] = tileA[i];
-        H[baseOp + uint64_t(xb) * W + j] = tileB[i];
-    }
+    store_segment(H, d.phase, gO, nr * W, tileA);
+    store_segment(H, d.phase, gP1, k1 * W, tileB);
+    if (nr > k1) store_segment(H, d.phase, gP2, (nr - k1) * W, tileB + size_t(k1) * W);
 }
 
 }  // namespace
@@ -92,6 +154,8 @@ hipError_t launch_inplace(void* H, const lfbp_shape& s, int esize, int max_lds, 
 {
     InplaceDesc d;
     d.H = H;
+    d.E = uint64_t(s.ns) * uint64_t(s.nt) * uint64_t(s.nx) * uint64_t(s.ny) * uint64_t(s.nz);
+    d.phase = uint32_t((reinterpret_cast<uintptr_t>(H) / uint32_t(esize)) % (16 / uint32_t(esize)));
     d.nt = uint32_t(s.nt);
     d.nx = uint32_t(s.nx);
     d.ny = uint32_t(s.ny);
@@ -103,11 +167,12 @@ hipError_t launch_inplace(void* H, const lfbp_shape& s, int esize, int max_lds, 
     d.b_off = (d.ny - ht % d.ny) % d.ny;
     const uint32_t pairs = (d.NB - 1) / 2;  // the centre block stays as it is
     if (pairs == 0) return hipSuccess;
-    // rows per group: two tiles of nr rows within kTileBudget bytes (several
-    // workgroups per CU), or within the whole LDS when a row pair is larger
+    // rows per group: about kGroupRows (measured best on the microscope and
+    // camera PSFs, f32 and f16), fewer when two tiles of that many rows would
+    // exceed kTileBudget, and at least one row pair (up to the whole LDS)
     const uint64_t row_bytes = uint64_t(d.W) * uint32_t(esize);
     const uint64_t budget = 2 * row_bytes <= uint64_t(kTileBudget) ? uint64_t(kTileBudget) : uint64_t(max_lds);
-    uint32_t nr = uint32_t(std::min<uint64_t>(d.nx, budget / (2 * row_bytes)));
+    uint32_t nr = uint32_t(std::min<uint64_t>(std::min<uint64_t>(d.nx, kGroupRows), budget / (2 * row_bytes)));
     if (nr == 0) return hipErrorInvalidValue;  // one x-row pair exceeds the LDS (refused on the host first)
     d.groups = (d.nx + nr - 1) / nr;
     d.nr = (d.nx + d.groups - 1) / d.groups;  // balance the groups

@@ -12,7 +12,7 @@ import lfsynth
 import oracle
 
 
-def inplace_mirror(H, tile_budget=40 * 1024, max_lds=160 * 1024, esize=4):
+def inplace_mirror(H, tile_budget=40 * 1024, max_lds=160 * 1024, esize=4, group_rows=5):
     ns, nt, nx, ny, nz = H.shape
     W, NB = ny * nz, ns * nt
     hs, ht = (ns - 1) // 2, (nt - 1) // 2
@@ -22,12 +22,13 @@ def inplace_mirror(H, tile_budget=40 * 1024, max_lds=160 * 1024, esize=4):
     if pairs == 0:
         return flat.reshape(H.shape), set()
     budget = tile_budget if 2 * W * esize <= tile_budget else max_lds
-    nr0 = min(nx, budget // (2 * W * esize))
+    nr0 = min(nx, group_rows, budget // (2 * W * esize))
     assert nr0 > 0
     groups = -(-nx // nr0)
     nr_full = -(-nx // groups)
     assert 2 * nr_full * W * esize <= budget <= max_lds
     touched = np.zeros(flat.size, np.int64)
+    E = flat.size
     for unit in range(pairs * groups):
         O, grp = divmod(unit, groups)
         Op = NB - 1 - O
@@ -37,23 +38,24 @@ def inplace_mirror(H, tile_budget=40 * 1024, max_lds=160 * 1024, esize=4):
         x0 = grp * nr_full
         assert x0 < nx
         nr = min(nr_full, nx - x0)
-        i = np.arange(nr * W)
-        r, j = i // W, i % W
-        xa = x0 + r
-        xb = (xa + a) % nx
-        srcA = Op * nx * W + xb * W + j
-        srcB = O * nx * W + xa * W + j
-        for idx in (srcA, srcB):
-            assert idx.min() >= 0 and idx.max() < flat.size
-        tileA = np.empty(nr * W, flat.dtype)
-        tileB = np.empty(nr * W, flat.dtype)
-        tileA[r * W + (j - rotA) % W] = flat[srcA]
-        tileB[r * W + (j - rotB) % W] = flat[srcB]
-        # writes after all reads of the unit
-        flat[O * nx * W + xa * W + j] = tileA
-        flat[Op * nx * W + xb * W + j] = tileB
-        touched[O * nx * W + xa * W + j] += 1
-        touched[Op * nx * W + xb * W + j] += 1
+        xb0 = (x0 + a) % nx
+        k1 = min(nr, nx - xb0)
+        gO = (O * nx + x0) * W
+        gP1, gP2 = (Op * nx + xb0) * W, Op * nx * W
+        segs_in = [(gO, nr * W, rotB, "B", 0), (gP1, k1 * W, rotA, "A", 0)]
+        segs_out = [(gO, nr * W, "A", 0), (gP1, k1 * W, "B", 0)]
+        if nr > k1:
+            segs_in.append((gP2, (nr - k1) * W, rotA, "A", k1 * W))
+            segs_out.append((gP2, (nr - k1) * W, "B", k1 * W))
+        tiles = {"A": np.empty(nr * W, flat.dtype), "B": np.empty(nr * W, flat.dtype)}
+        for g, L, rot, t, off in segs_in:            # load_segment: whole rows, rotated into the tile
+            assert g >= 0 and g + L <= E and L % W == 0
+            e = np.arange(L)
+            r, j = e // W, e % W
+            tiles[t][off + r * W + (j - rot) % W] = flat[g + e]
+        for g, L, t, off in segs_out:                 # store_segment, after every load of the unit
+            flat[g:g + L] = tiles[t][off:off + L]
+            touched[g:g + L] += 1
     centre = (NB - 1) // 2
     assert np.all(touched[centre * nx * W:(centre + 1) * nx * W] == 0)
     rest = np.delete(touched, np.arange(centre * nx * W, (centre + 1) * nx * W))
@@ -70,6 +72,9 @@ def test_inplace_mirror_equals_oracle(shape, tile_budget):
     pair; a row pair larger than the budget falls back to the whole LDS)."""
     H = lfsynth.bits(shape, 3, np.float32)
     out, _ = inplace_mirror(H, tile_budget)
+    ref = oracle.Ht_rows(H)
+    assert np.array_equal(out.view(np.uint32), ref.view(np.uint32))
+    out, _ = inplace_mirror(H, tile_budget, group_rows=1 << 20)     # whole blocks where the budget allows
     ref = oracle.Ht_rows(H)
     assert np.array_equal(out.view(np.uint32), ref.view(np.uint32))
 
