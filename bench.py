@@ -6,8 +6,8 @@
 Prints ONE JSON line.  A step is one pass of the hot path over its synthetic
 input, already resident in HBM: one lfbp_compute_Ht call (plain workloads), one
 lfbp_compute_Ht_batched call over a table of PSF sets (batched, batched-small),
-one forward plus one backward projection (projector), or one Richardson-Lucy
-update (rl).  K steps are timed with HIP events
+one forward plus one backward projection (projector), one Richardson-Lucy
+update (rl), or one gradient with respect to H (grad-psf).  K steps are timed with HIP events
 on the stream the kernels run on, bracketed by device synchronisation.
 """
 from __future__ import annotations
@@ -35,7 +35,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="microscope",
-                    choices=sorted(PLAIN) + ["batched", "batched-small", "projector", "rl"])
+                    choices=sorted(PLAIN) + ["batched", "batched-small", "projector", "rl", "grad-psf"])
     ap.add_argument("--variant", default=None, choices=[None, "direct", "staged"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--inplace", action="store_true",
@@ -352,6 +352,50 @@ def bench_rl(args, torch):
     return out
 
 
+def bench_grad_psf(args, torch):
+    """One step = the gradient of <w, H g> with respect to H (lfbp_grad_psf)
+    on the projector grid: 600 x 600 px, 21 depths, H[165,165,15,15,21]."""
+    import numpy as np
+    import lfsynth
+    import paper_2003_09133_amd as lf
+
+    pw = lfsynth.PROJECTOR
+    shape = pw.psf.shape
+    R, C = pw.image
+    dev = torch.device("cuda:0")
+    w = torch.from_numpy(lfsynth.uniform_f32((R, C), pw.g_seed + 2) - np.float32(0.5)).to(dev)
+    g = torch.from_numpy(lfsynth.uniform_f32((shape[4], R, C), pw.g_seed)).to(dev)
+    dH = torch.empty(shape, device=dev)
+    ws = torch.empty(lf.grad_psf_workspace_size(shape, R, C), dtype=torch.uint8, device=dev)
+    step = lambda: lf.grad_psf(w, g, shape, out=dH, workspace=ws)
+    elapsed, wall = time_steps(step, args.steps, args.warmup, torch)
+    sec = elapsed / args.steps
+    ns, nt, nx, ny, nz = shape
+    flop = 2.0 * nz * R * C * ns * nt
+    tflops = flop / sec / 1e12
+    out = {
+        "metric": "PSF gradients/s", "value": round(1.0 / sec, 2), "unit": "gradients/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"d<w, H g>/dH, {R}x{C} px, {pw.lenslets}x{pw.lenslets} lenslets, H{list(shape)} f32",
+                   "flop_per_step": flop, "wall_s": round(wall, 3)},
+        "roofline": {"bound": "mfma", "achieved": round(tflops, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(tflops / FP32_PEAK_TFLOPS, 4), "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        nth = cores_used()
+        idx = np.random.default_rng(0).integers(0, int(np.prod(shape)), 20000)
+        t0 = time.perf_counter()
+        oracle.grad_psf_at(shape, w.cpu().numpy(), g.cpu().numpy(), idx, nthreads=nth)
+        dt = time.perf_counter() - t0
+        per = dt * np.prod(shape) / len(idx)
+        out["cpu_baseline"] = {"value": round(1.0 / per, 6), "unit": "gradients/s", "cores": nth, "kind": "oracle",
+                               "sample": f"float64 oracle at {len(idx)} random entries of dH ({dt:.2f} s), "
+                                         f"scaled to the whole array"}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -368,6 +412,8 @@ def main():
         out = bench_projector(args, torch)
     elif args.workload == "rl":
         out = bench_rl(args, torch)
+    elif args.workload == "grad-psf":
+        out = bench_grad_psf(args, torch)
     else:
         out = bench_plain(args, torch)
     print(json.dumps(out), flush=True)

@@ -262,6 +262,36 @@ LFBP_API lfbp_status lfbp_rl_step_ws(const float* H, const float* Ht, lfbp_shape
 LFBP_API lfbp_status lfbp_rl_norm_ws(const float* Ht, lfbp_shape shape, int64_t R, int64_t C, float* norm,
                                      void* workspace, int64_t workspace_bytes, void* stream);
 
+/*
+ * lfbp_grad_psf -- gradient of a loss with respect to the PSF array, given
+ * its gradient w = dL/df with respect to the image of f = H g (Eq. 1):
+ *
+ *   dH[s][t][x][y][z] = sum over voxels (P,Q) of class (x,y) of
+ *                       w[P+s-hs][Q+t-ht] * g[z][P][Q]
+ *
+ * (pixels outside the image dropped), the derivative of <w, H g> with respect
+ * to H (f is linear in H).  For calibrating or refining H from data (the
+ * motivation of Sec. 3.1); H' of the updated H is a new lfbp_compute_Ht.
+ * w float32 [R][C]; g float32 [nz][R][C]; dH float32 [ns][nt][nx][ny][nz],
+ * overwritten, not overlapping the inputs.  Float32 on the matrix cores, one
+ * sum per entry over the lenslets, with the two-level accumulation of
+ * lfbp_forward.  Workspace from the stream-ordered allocator
+ * (lfbp_grad_psf_workspace_size() bytes); lfbp_grad_psf_ws takes caller
+ * memory and allocates nothing.  Errors EINVAL, ESHAPE, EALIAS, EALIGN,
+ * ENOMEM, EDEVICE.
+ */
+LFBP_API lfbp_status lfbp_grad_psf(const float* w, const float* g, lfbp_shape shape, int64_t R, int64_t C, float* dH,
+                                   void* stream);
+
+/* Bytes of device workspace lfbp_grad_psf_ws needs (0 when invalid). */
+LFBP_API int64_t lfbp_grad_psf_workspace_size(lfbp_shape shape, int64_t R, int64_t C);
+
+/* lfbp_grad_psf with a caller workspace of at least
+ * lfbp_grad_psf_workspace_size() bytes, 256-byte aligned, overlapping no
+ * argument.  Allocates nothing. */
+LFBP_API lfbp_status lfbp_grad_psf_ws(const float* w, const float* g, lfbp_shape shape, int64_t R, int64_t C,
+                                      float* dH, void* workspace, int64_t workspace_bytes, void* stream);
+
 /* Static text for a status code (never NULL). */
 LFBP_API const char* lfbp_status_string(lfbp_status s);
 

@@ -54,6 +54,8 @@ def _load():
             "oracle_backward_at": [vp, vp, vp, i64, i64, vp, i64, vp, i32],
             "oracle_forward_d": [vp, vp, vp, i64, i64, vp, i32],
             "oracle_backward_d": [vp, vp, vp, i64, i64, vp, i32],
+            "oracle_grad_psf": [vp, vp, vp, i64, i64, vp, i32],
+            "oracle_grad_psf_at": [vp, vp, vp, i64, i64, vp, i64, vp, i32],
         }.items():
             fn = getattr(lib, name)
             fn.argtypes = args
@@ -214,4 +216,28 @@ def rl_step(H: np.ndarray, f: np.ndarray, g: np.ndarray, norm: np.ndarray | None
     bp = backward64(H, ratio, nthreads)
     out = np.zeros_like(bp)
     np.divide(np.asarray(g, dtype=np.float64) * bp, norm, out=out, where=norm > 0)
+    return out
+
+
+def grad_psf(shape, w: np.ndarray, g: np.ndarray, nthreads: int = 0) -> np.ndarray:
+    """d<w, A g>/dH, float64 [ns][nt][nx][ny][nz], from the definition of A."""
+    w, g = _f32(w), _f32(g)
+    R, C = w.shape
+    dims = np.array(shape, dtype=np.int64)
+    assert g.shape == (shape[4], R, C)
+    out = np.empty(tuple(shape), dtype=np.float64)
+    _check(_load().oracle_grad_psf(dims.ctypes.data, w.ctypes.data, g.ctypes.data, R, C, out.ctypes.data,
+                                   nthreads), "oracle_grad_psf")
+    return out
+
+
+def grad_psf_at(shape, w: np.ndarray, g: np.ndarray, flat_idx: np.ndarray, nthreads: int = 0) -> np.ndarray:
+    """d<w, A g>/dH at the listed flat indices of H, float64."""
+    w, g = _f32(w), _f32(g)
+    R, C = w.shape
+    dims = np.array(shape, dtype=np.int64)
+    idx = np.ascontiguousarray(flat_idx, dtype=np.int64)
+    out = np.empty(idx.size, dtype=np.float64)
+    _check(_load().oracle_grad_psf_at(dims.ctypes.data, w.ctypes.data, g.ctypes.data, R, C, idx.ctypes.data,
+                                      idx.size, out.ctypes.data, nthreads), "oracle_grad_psf_at")
     return out

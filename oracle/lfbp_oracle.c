@@ -374,3 +374,58 @@ int oracle_backward_d(const float* H, const int64_t* dims, const double* f, int6
             for (int64_t Q = 0; Q < C; ++Q) g[(z * R + P) * C + Q] = backward_voxel_d(&h, H, f, R, C, z, P, Q);
     return 0;
 }
+
+/* Gradient of <w, A g> with respect to H (the forward model is linear in H):
+ * the entry H[s][t][x][y][z] links every voxel (z,P,Q) of class (x,y) with the
+ * pixel (P+s-hs, Q+t-ht), so its derivative sums w at that pixel times g at the
+ * voxel over all voxels of the class whose pixel lies in the image.  float64. */
+static double grad_psf_entry(const oshape* h, const float* w, const float* g, int64_t R, int64_t C, int64_t s,
+                             int64_t t, int64_t x, int64_t y, int64_t z)
+{
+    const int64_t hs = (h->ns - 1) / 2, ht = (h->nt - 1) / 2;
+    double acc = 0.0;
+    for (int64_t P = x; P < R; P += h->nx) {
+        const int64_t p = P + s - hs;
+        if (p < 0 || p >= R) continue;
+        for (int64_t Q = y; Q < C; Q += h->ny) {
+            const int64_t q = Q + t - ht;
+            if (q < 0 || q >= C) continue;
+            acc += (double)w[p * C + q] * (double)g[(z * R + P) * C + Q];
+        }
+    }
+    return acc;
+}
+
+int oracle_grad_psf(const int64_t* dims, const float* w, const float* g, int64_t R, int64_t C, double* dH,
+                    int nthreads)
+{
+    const oshape h = mkshape(dims);
+    const int64_t E = h.ns * h.nt * h.nx * h.ny * h.nz;
+#pragma omp parallel for num_threads(nthreads_or_default(nthreads)) schedule(dynamic, 64)
+    for (int64_t i = 0; i < E; ++i) {
+        int64_t r = i;
+        const int64_t z = r % h.nz; r /= h.nz;
+        const int64_t y = r % h.ny; r /= h.ny;
+        const int64_t x = r % h.nx; r /= h.nx;
+        const int64_t t = r % h.nt, s = r / h.nt;
+        dH[i] = grad_psf_entry(&h, w, g, R, C, s, t, x, y, z);
+    }
+    return 0;
+}
+
+/* The same at the listed flat indices of H. */
+int oracle_grad_psf_at(const int64_t* dims, const float* w, const float* g, int64_t R, int64_t C, const int64_t* idx,
+                       int64_t n, double* out, int nthreads)
+{
+    const oshape h = mkshape(dims);
+#pragma omp parallel for num_threads(nthreads_or_default(nthreads)) schedule(dynamic, 16)
+    for (int64_t k = 0; k < n; ++k) {
+        int64_t r = idx[k];
+        const int64_t z = r % h.nz; r /= h.nz;
+        const int64_t y = r % h.ny; r /= h.ny;
+        const int64_t x = r % h.nx; r /= h.nx;
+        const int64_t t = r % h.nt, s = r / h.nt;
+        out[k] = grad_psf_entry(&h, w, g, R, C, s, t, x, y, z);
+    }
+    return 0;
+}

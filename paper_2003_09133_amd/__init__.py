@@ -23,7 +23,8 @@ from ._abi import (F16, F32, GATHER_AUTO, GATHER_DIRECT, GATHER_STAGED, GATHER_W
                    LfbpError, Problem, Shape)
 
 __all__ = ["compute_Ht", "compute_Ht_into", "compute_Ht_inplace", "compute_Ht_batched", "BatchedHt", "forward", "forward_workspace_size",
-           "backward", "backward_workspace_size", "LFProject", "project", "rl_norm", "rl_step",
+           "backward", "backward_workspace_size", "grad_psf", "grad_psf_workspace_size", "LFProject", "project",
+           "rl_norm", "rl_step",
            "rl_workspace_size", "richardson_lucy", "default_config", "GatherConfig", "LfbpError", "release_plans",
            "version", "GATHER_AUTO", "GATHER_DIRECT", "GATHER_STAGED", "GATHER_WIDE"]
 
@@ -219,22 +220,52 @@ def backward(Ht: torch.Tensor, f: torch.Tensor, out: torch.Tensor | None = None,
     return g
 
 
-class LFProject(torch.autograd.Function):
-    """f = H g with the gradient g_grad = H' f_grad.
+def grad_psf_workspace_size(shape, R: int, C: int) -> int:
+    """Bytes of scratch device memory the gradient with respect to H needs."""
+    return int(_abi.lib().lfbp_grad_psf_workspace_size(Shape.of(shape), int(R), int(C)))
 
-    The projector is linear, so its vector-Jacobian product is the adjoint,
-    which is exactly the backprojection with H' (Sec. 3).  Nothing of the
-    forward pass is saved except the H' handle; H and H' get no gradient."""
+
+def grad_psf(w: torch.Tensor, g: torch.Tensor, shape, out: torch.Tensor | None = None,
+             workspace: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """d<w, H g>/dH for an image gradient w [R, C] and a volume g [nz, R, C]:
+    a float32 array of the PSF's shape [ns, nt, nx, ny, nz]."""
+    _check_f32(w, "w", 2)
+    _check_f32(g, "g", 3)
+    R, C = w.shape
+    shape = tuple(int(v) for v in shape)
+    if len(shape) != 5 or g.shape != (shape[4], R, C):
+        raise ValueError("g must be [nz, R, C] for the PSF shape given")
+    dH = torch.empty(shape, dtype=torch.float32, device=w.device) if out is None else out
+    _check_f32(dH, "out", 5)
+    workspace = _workspace(workspace, grad_psf_workspace_size(shape, R, C), w.device)
+    _abi.check(_abi.lib().lfbp_grad_psf_ws(w.data_ptr(), g.data_ptr(), Shape.of(shape), R, C, dH.data_ptr(),
+                                           workspace.data_ptr(), workspace.numel() * workspace.element_size(),
+                                           _stream(stream)), "lfbp_grad_psf")
+    return dH
+
+
+class LFProject(torch.autograd.Function):
+    """f = H g with the gradients g_grad = H' f_grad and, when H requires it,
+    H_grad = d<f_grad, H g>/dH.
+
+    The projector is linear in g, so its vector-Jacobian product with respect
+    to g is the adjoint, which is exactly the backprojection with H' (Sec. 3);
+    it is also linear in H, so the product with respect to H needs only g.
+    Saved: H' and, only when H requires a gradient, g.  H' gets no gradient."""
 
     @staticmethod
     def forward(ctx, g, H, Ht):
-        ctx.save_for_backward(Ht)
+        ctx.psf_shape = tuple(H.shape)
+        ctx.save_for_backward(Ht, g if H.requires_grad else None)
         return forward(H, g.contiguous())
 
     @staticmethod
     def backward(ctx, grad_f):
-        (Ht,) = ctx.saved_tensors
-        return backward(Ht, grad_f.contiguous()), None, None
+        Ht, g = ctx.saved_tensors
+        grad_f = grad_f.contiguous()
+        grad_g = backward(Ht, grad_f) if ctx.needs_input_grad[0] else None
+        grad_H = grad_psf(grad_f, g.contiguous(), ctx.psf_shape) if ctx.needs_input_grad[1] else None
+        return grad_g, grad_H, None
 
 
 def project(g: torch.Tensor, H: torch.Tensor, Ht: torch.Tensor | None = None) -> torch.Tensor:

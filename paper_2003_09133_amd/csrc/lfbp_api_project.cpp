@@ -28,6 +28,11 @@ hipError_t launch_rl_step_ws(const float* H, const float* Ht, const lfbp_shape& 
                              hipStream_t stream);
 hipError_t launch_rl_norm_ws(const float* Ht, const lfbp_shape& s, int64_t R, int64_t C, float* norm, void* ws,
                              hipStream_t stream);
+size_t grad_psf_workspace_bytes(const lfbp_shape& s, int64_t R, int64_t C);
+hipError_t launch_grad_psf(const float* w, const float* gv, const lfbp_shape& s, int64_t R, int64_t C, float* dH,
+                           hipStream_t stream);
+hipError_t launch_grad_psf_ws(const float* w, const float* gv, const lfbp_shape& s, int64_t R, int64_t C, float* dH,
+                              void* ws, hipStream_t stream);
 
 }  // namespace lfbp
 
@@ -154,6 +159,40 @@ lfbp_status lfbp_rl_norm_ws(const float* Ht, lfbp_shape shape, int64_t R, int64_
         return LFBP_EALIAS;
     if (ensure_init() != hipSuccess) return LFBP_EDEVICE;
     return launch_rl_norm_ws(Ht, shape, R, C, norm, workspace, static_cast<hipStream_t>(stream)) == hipSuccess
+               ? LFBP_OK
+               : LFBP_EDEVICE;
+}
+
+lfbp_status lfbp_grad_psf(const float* w, const float* g, lfbp_shape shape, int64_t R, int64_t C, float* dH,
+                          void* stream)
+{
+    const lfbp_status st = check_grad_psf(w, g, shape, R, C, dH);
+    if (st != LFBP_OK) return st;
+    if (ensure_init() != hipSuccess) return LFBP_EDEVICE;
+    const hipError_t e = launch_grad_psf(w, g, shape, R, C, dH, static_cast<hipStream_t>(stream));
+    if (e == hipErrorOutOfMemory) return LFBP_ENOMEM;
+    return e == hipSuccess ? LFBP_OK : LFBP_EDEVICE;
+}
+
+int64_t lfbp_grad_psf_workspace_size(lfbp_shape shape, int64_t R, int64_t C)
+{
+    if (check_project_shape(shape, R, C) != LFBP_OK) return 0;
+    return int64_t(grad_psf_workspace_bytes(shape, R, C));
+}
+
+lfbp_status lfbp_grad_psf_ws(const float* w, const float* g, lfbp_shape shape, int64_t R, int64_t C, float* dH,
+                             void* workspace, int64_t workspace_bytes, void* stream)
+{
+    const lfbp_status st = check_grad_psf(w, g, shape, R, C, dH);
+    if (st != LFBP_OK) return st;
+    const int64_t need = int64_t(grad_psf_workspace_bytes(shape, R, C));
+    if (!workspace || workspace_bytes < need || reinterpret_cast<uintptr_t>(workspace) % 256) return LFBP_EINVAL;
+    const uint64_t img = uint64_t(R) * uint64_t(C) * 4, vol = img * uint64_t(shape.nz), psf = shape_elems(shape) * 4;
+    if (ranges_overlap(workspace, uint64_t(need), w, img) || ranges_overlap(workspace, uint64_t(need), g, vol) ||
+        ranges_overlap(workspace, uint64_t(need), dH, psf))
+        return LFBP_EALIAS;
+    if (ensure_init() != hipSuccess) return LFBP_EDEVICE;
+    return launch_grad_psf_ws(w, g, shape, R, C, dH, workspace, static_cast<hipStream_t>(stream)) == hipSuccess
                ? LFBP_OK
                : LFBP_EDEVICE;
 }

@@ -277,9 +277,13 @@ __device__ __forceinline__ void tile_of_block(const GemmArgs& a, int& mt, int& n
     split = rest / a.ntiles;
 }
 
-template <bool kFwd>
+// What a GEMM launch computes (operand records and epilogue).
+enum GemmMode { kModeFwd = 0, kModeBwd = 1, kModeGradH = 2 };
+
+template <int kMode>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) k_gemm(GemmArgs a)
 {
+    constexpr bool kFwd = kMode == kModeFwd;
     __shared__ f32x4 tot[kThreads / 64][4][4][64];   // per wave: 4 tiles x 16 sums x 64 lanes
     int mt, ntile, split;
     tile_of_block(a, mt, ntile, split);
@@ -386,6 +390,32 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2
                         out[size_t(m) * a.Npad + nb + 32 * j + li] = v[e];
                     }
                 }
+    } else if (kMode == kModeGradH) {
+        // row m = (r, r2) = (s + x, t + y), column n = (x, y, z): the entry of
+        // dH[s][t][x][y][z] when s, t fall inside the patch
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int n = nb + 32 * j + li;
+            if (n >= a.N) continue;
+            const int c = int(fdiv(uint32_t(n), g.fnz)), z = n - c * g.nz;
+            const int x = int(fdiv(uint32_t(c), g.fny)), y = c - x * g.ny;
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const f32x4 v = T[2 * i + j][q][lane];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int m = m0 + 32 * i + 8 * q + 4 * lk + e;
+                        if (m >= a.M) continue;
+                        const int r = int(fdiv(uint32_t(m), g.fKc)), r2 = m - r * g.Kc;
+                        const int sp = r - x, tp = r2 - y;
+                        if (unsigned(sp) < unsigned(g.ns) && unsigned(tp) < unsigned(g.nt))
+                            a.out[((int64_t(sp) * g.nt + tp) * g.nx + x) * int64_t(g.ny * g.nz) + int64_t(y) * g.nz + z] =
+                                v[e];
+                    }
+                }
+        }
     } else {
         const size_t plane = size_t(g.R) * g.C;
 #pragma unroll
@@ -591,6 +621,60 @@ __global__ void __launch_bounds__(256) k_pack_bwd_a(const float* f, PackArgs p, 
     reinterpret_cast<f32x4*>(Ap)[int64_t(s) * kRecVec * p.Mpad + item] = o;
 }
 
+// Gradient with respect to H.  With P = nx*LP + x, Q = ny*LQ + y and r = s + x,
+// r2 = t + y:  dH[s][t][x][y][z] = E[(r,r2)][(x,y,z)],
+//   E[(r,r2)][(x,y,z)] = sum over lenslets (LP,LQ) of
+//       w[nx*LP + r - hs][ny*LQ + r2 - ht] * g[z][nx*LP + x][ny*LQ + y],
+// a GEMM over the lenslets (22 per stage).  A records: row (r,r2), the image
+// gradient w at the stage's lenslets (0 outside the image); B records: column
+// (x,y,z), the volume g at the stage's lenslets.
+__global__ void __launch_bounds__(256) k_pack_gh_a(const float* w, PackArgs p, float* Ap)
+{
+    const ProjGeom& g = p.g;
+    const int s = int(blockIdx.x);
+    const int item = int(blockIdx.y) * 256 + int(threadIdx.x);
+    if (item >= p.Mpad * kRecVec) return;
+    const RecItem it = rec_item(item, p.Mpad);
+    const int m = it.r;
+    const int r = int(fdiv(uint32_t(m), g.fKc)), r2 = m - r * g.Kc;
+    const bool row = m < g.Kr * g.Kc;
+    f32x4 o;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int kk = slot_k(it.slot0 + q);
+        const int k = s * kStageK + kk;   // lenslet
+        const int LP = int(fdiv(uint32_t(k), g.fLc)), LQ = k - LP * g.Lc;
+        const int pp = g.nx * LP + r - g.hs, qq = g.ny * LQ + r2 - g.ht;
+        const bool valid = row && kk >= 0 && k < g.M && unsigned(pp) < unsigned(g.R) && unsigned(qq) < unsigned(g.C);
+        o[q] = valid ? w[int64_t(pp) * g.C + qq] : 0.0f;
+    }
+    reinterpret_cast<f32x4*>(Ap)[int64_t(s) * kRecVec * p.Mpad + item] = o;
+}
+
+__global__ void __launch_bounds__(256) k_pack_gh_b(const float* gv, PackArgs p, float* Bp)
+{
+    const ProjGeom& g = p.g;
+    const int s = int(blockIdx.x);
+    const int item = int(blockIdx.y) * 256 + int(threadIdx.x);
+    if (item >= p.Npad * kRecVec) return;
+    const RecItem it = rec_item(item, p.Npad);
+    const int n = it.r;
+    const int c = int(fdiv(uint32_t(n), g.fnz)), z = n - c * g.nz;
+    const int x = int(fdiv(uint32_t(c), g.fny)), y = c - x * g.ny;
+    const int64_t plane = int64_t(g.R) * g.C;
+    f32x4 o;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int kk = slot_k(it.slot0 + q);
+        const int k = s * kStageK + kk;
+        const int LP = int(fdiv(uint32_t(k), g.fLc)), LQ = k - LP * g.Lc;
+        const int P = g.nx * LP + x, Q = g.ny * LQ + y;
+        const bool valid = n < p.N && kk >= 0 && k < g.M && P < g.R && Q < g.C;
+        o[q] = valid ? gv[z * plane + int64_t(P) * g.C + Q] : 0.0f;
+    }
+    reinterpret_cast<f32x4*>(Bp)[int64_t(s) * kRecVec * p.Npad + item] = o;
+}
+
 // f[p][q] = sum over splits of the partial tile entry of (lenslet, class).
 // With fmeas set (Richardson-Lucy, Eq. 2), the quotient fmeas / f is written
 // instead, 0 where f is not positive.
@@ -752,7 +836,8 @@ hipError_t forward_impl(const float* H, const lfbp_shape& s, const float* gin, i
     a.padP = P.L.padP;
     a.padQ = P.L.padQ;
     a.fnzc = p.fnzc;
-    hipLaunchKernelGGL(k_gemm<true>, dim3(unsigned(P.mtiles * P.ntiles * P.splits)), dim3(kThreads), 0, stream, a);
+    hipLaunchKernelGGL(k_gemm<kModeFwd>, dim3(unsigned(P.mtiles * P.ntiles * P.splits)), dim3(kThreads), 0, stream,
+                       a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int64_t npix = int64_t(g.R) * g.C;
     hipLaunchKernelGGL(k_fwd_reduce, dim3(blocks_for(npix)), dim3(256), 0, stream, part, P.splits, P.Mpad, P.Npad, g,
@@ -793,7 +878,7 @@ hipError_t backward_impl(const float* Ht, const lfbp_shape& s, const float* f, i
     a.fnzc = make_fastdiv(1);
     a.gprev = gprev;
     a.norm = norm;
-    hipLaunchKernelGGL(k_gemm<false>, dim3(unsigned(P.mtiles * P.ntiles)), dim3(kThreads), 0, stream, a);
+    hipLaunchKernelGGL(k_gemm<kModeBwd>, dim3(unsigned(P.mtiles * P.ntiles)), dim3(kThreads), 0, stream, a);
     return hipGetLastError();
 }
 
@@ -809,6 +894,85 @@ hipError_t launch_backward_ws(const float* Ht, const lfbp_shape& s, const float*
                               void* ws, hipStream_t stream)
 {
     return backward_impl(Ht, s, f, R, C, nullptr, nullptr, g, ws, stream);
+}
+
+namespace {
+
+struct GradPlan {
+    ProjGeom g;
+    int M, N, Mpad, Npad, mtiles, ntiles, stages;
+    size_t A_bytes, B_bytes;
+};
+
+GradPlan grad_plan(const lfbp_shape& s, int64_t R, int64_t C)
+{
+    GradPlan P;
+    P.g = make_geom(s, R, C);
+    P.M = P.g.Kr * P.g.Kc;
+    P.N = P.g.nx * P.g.ny * P.g.nz;
+    P.mtiles = (P.M + kMT - 1) / kMT;
+    P.ntiles = (P.N + kNT - 1) / kNT;
+    P.Mpad = P.mtiles * kMT;
+    P.Npad = P.ntiles * kNT;
+    P.stages = (P.g.M + kStageK - 1) / kStageK;
+    P.A_bytes = align256(size_t(P.stages) * P.Mpad * kRec * sizeof(float));
+    P.B_bytes = align256(size_t(P.stages) * P.Npad * kRec * sizeof(float));
+    return P;
+}
+
+}  // namespace
+
+// Workspace of the gradient with respect to H: the A and B records.
+size_t grad_psf_workspace_bytes(const lfbp_shape& s, int64_t R, int64_t C)
+{
+    const GradPlan P = grad_plan(s, R, C);
+    return P.A_bytes + P.B_bytes;
+}
+
+// dH = d<w, H g>/dH for the image gradient w [R][C] and the volume g [nz][R][C].
+hipError_t launch_grad_psf_ws(const float* w, const float* gv, const lfbp_shape& s, int64_t R, int64_t C, float* dH,
+                              void* ws, hipStream_t stream)
+{
+    const GradPlan P = grad_plan(s, R, C);
+    char* wsp = static_cast<char*>(ws);
+    float* Ap = reinterpret_cast<float*>(wsp);
+    float* Bp = reinterpret_cast<float*>(wsp + P.A_bytes);
+    const PackArgs p = pack_args(P.g, P.N, P.Npad, P.Mpad, P.stages);
+    hipLaunchKernelGGL(k_pack_gh_a, dim3(unsigned(P.stages), blocks_for(int64_t(P.Mpad) * kRecVec)), dim3(256), 0,
+                       stream, w, p, Ap);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_pack_gh_b, dim3(unsigned(P.stages), blocks_for(int64_t(P.Npad) * kRecVec)), dim3(256), 0,
+                       stream, gv, p, Bp);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    GemmArgs a{};
+    a.A = Ap;
+    a.B = Bp;
+    a.out = dH;
+    a.g = P.g;
+    a.M = P.M;
+    a.N = P.N;
+    a.Mpad = P.Mpad;
+    a.Npad = P.Npad;
+    a.mtiles = P.mtiles;
+    a.ntiles = P.ntiles;
+    a.stages = P.stages;
+    a.splits = 1;
+    a.nzc = 1;
+    a.fnzc = make_fastdiv(1);
+    hipLaunchKernelGGL(k_gemm<kModeGradH>, dim3(unsigned(P.mtiles * P.ntiles)), dim3(kThreads), 0, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_psf(const float* w, const float* gv, const lfbp_shape& s, int64_t R, int64_t C, float* dH,
+                           hipStream_t stream)
+{
+    void* ws = nullptr;
+    hipError_t e = hipMallocAsync(&ws, grad_psf_workspace_bytes(s, R, C), stream);
+    if (e != hipSuccess) return e;
+    e = launch_grad_psf_ws(w, gv, s, R, C, dH, ws, stream);
+    const hipError_t e2 = hipFreeAsync(ws, stream);
+    return e != hipSuccess ? e : e2;
 }
 
 // Workspace of one Richardson-Lucy step: the larger of the two projections'

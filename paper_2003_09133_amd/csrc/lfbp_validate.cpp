@@ -102,7 +102,8 @@ lfbp_status check_project_shape(const lfbp_shape& s, int64_t R, int64_t C)
     const uint64_t Lr = uint64_t((R + s.nx - 1) / s.nx), Lc = uint64_t((C + s.ny - 1) / s.ny);
     const uint64_t grid = mul_sat(Lr + 2 * ((hs + s.nx - 1) / s.nx), Lc + 2 * ((ht + s.ny - 1) / s.ny));
     const uint64_t lenslets = mul_sat(Lr, Lc) + 64;
-    if (mul_sat(cols, 96) >= LIM31 || mul_sat(lenslets, 96) >= LIM31 || mul_sat(grid, 96) >= LIM31)
+    if (mul_sat(cols, 96) >= LIM31 || mul_sat(lenslets, 96) >= LIM31 || mul_sat(grid, 96) >= LIM31 ||
+        mul_sat(pairs + 64, 96) >= LIM31)
         return LFBP_ESHAPE;
     if (mul_sat(mul_sat(mul_sat(pairs, uint64_t(s.nz)), cols + lenslets + grid), 96) >= LIM62) return LFBP_ESHAPE;
     return LFBP_OK;
@@ -138,6 +139,19 @@ lfbp_status check_rl(const float* H, const float* Ht, const lfbp_shape& s, const
         ranges_overlap(g_out, vol, f, img) || ranges_overlap(g_out, vol, norm, vol))
         return LFBP_EALIAS;
     if (g_out != g && ranges_overlap(g_out, vol, g, vol)) return LFBP_EALIAS;   // in place, or apart
+    return LFBP_OK;
+}
+
+lfbp_status check_grad_psf(const float* w, const float* g, const lfbp_shape& s, int64_t R, int64_t C,
+                           const float* dH)
+{
+    if (!w || !g || !dH) return LFBP_EINVAL;
+    const lfbp_status st = check_project_shape(s, R, C);
+    if (st != LFBP_OK) return st;
+    for (const float* p : {w, g, dH})
+        if (reinterpret_cast<uintptr_t>(p) % 4) return LFBP_EALIGN;
+    const uint64_t psf = shape_elems(s) * 4, img = uint64_t(R) * uint64_t(C) * 4, vol = img * uint64_t(s.nz);
+    if (ranges_overlap(dH, psf, w, img) || ranges_overlap(dH, psf, g, vol)) return LFBP_EALIAS;
     return LFBP_OK;
 }
 

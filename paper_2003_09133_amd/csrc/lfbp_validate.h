@@ -34,6 +34,11 @@ lfbp_status check_project(const float* psf, const lfbp_shape& s, const float* in
 lfbp_status check_rl(const float* H, const float* Ht, const lfbp_shape& s, const float* f, int64_t R, int64_t C,
                      const float* g, const float* norm, const float* g_out);
 
+// Full check of one gradient-with-respect-to-H call: w [R][C], g [nz][R][C],
+// dH the shape of H, not overlapping the inputs.
+lfbp_status check_grad_psf(const float* w, const float* g, const lfbp_shape& s, int64_t R, int64_t C,
+                           const float* dH);
+
 // True when [a, a+na) and [b, b+nb) (bytes) overlap.
 bool ranges_overlap(const void* a, uint64_t na, const void* b, uint64_t nb);
 

@@ -272,3 +272,20 @@ def test_inplace_validation_before_launch():
     assert L.lfbp_compute_Ht_inplace(P1 + 2, GOOD, _abi.F32, None) == _abi.EALIGN
     # an x-row pair of 2 * 9 * 1000 * 4 bytes does not fit 64 KB of LDS
     assert L.lfbp_compute_Ht_inplace(P1, Shape(3, 3, 3, 9, 1000), _abi.F32, None) == _abi.ESHAPE
+
+
+def test_grad_psf_validation_before_launch():
+    L = _abi.lib()
+    shape, R, C = GOOD, 30, 30
+    w, g, dH = 0x1000000, 0x2000000, 0x3000000
+    need = L.lfbp_grad_psf_workspace_size(shape, R, C)
+    assert need > 0 and L.lfbp_grad_psf_workspace_size(Shape(4, 5, 3, 3, 1), R, C) == 0
+    assert L.lfbp_grad_psf_ws(w, g, shape, R, C, dH, None, need, None) == _abi.EINVAL
+    assert L.lfbp_grad_psf_ws(None, g, shape, R, C, dH, 0x10000000, need, None) == _abi.EINVAL
+    assert L.lfbp_grad_psf_ws(w, g, shape, R, C, w + 16, 0x10000000, need, None) == _abi.EALIAS
+    assert L.lfbp_grad_psf_ws(w, g, shape, R, C, g + 16, 0x10000000, need, None) == _abi.EALIAS
+    assert L.lfbp_grad_psf_ws(w, g, shape, R, C, dH + 2, 0x10000000, need, None) == _abi.EALIGN
+    assert L.lfbp_grad_psf_ws(w, g, shape, R, C, dH, dH + 256, need, None) == _abi.EALIAS
+    assert L.lfbp_grad_psf_ws(w, g, shape, R, C, dH, 0x10000000, need - 1, None) == _abi.EINVAL
+    assert L.lfbp_grad_psf(w, g, Shape(15, 14, 3, 3, 3), R, C, dH, None) == _abi.ESHAPE
+    assert L.lfbp_grad_psf(w, g, shape, R, C, g, None) == _abi.EALIAS

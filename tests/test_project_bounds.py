@@ -256,3 +256,70 @@ def test_large_shapes_record_addresses(shape, R, C):
     blk = ((px * shape[3] + py) * p['nzc'] + zc) * kRecVec * arows
     assert np.all(base - blk + lane.max() + 1 < 2 * arows) and np.all(base - blk + lane.min() >= 0)
     check_blocks(p['mtiles'], p['ntiles'], p['splits'])
+
+
+def grad_mirror(shape, w, gv):
+    """Records, GEMM and epilogue of the gradient with respect to H."""
+    ns, nt, nx, ny, nz = shape
+    R, C = w.shape
+    g = geom(shape, R, C)
+    Mg = g['Kr'] * g['Kc']
+    N = nx * ny * nz
+    mtiles, ntiles = -(-Mg // kMT), -(-N // kNT)
+    Mpad, Npad = mtiles * kMT, ntiles * kNT
+    stages = -(-g['M'] // kStageK)
+    wf, gf = w.astype(np.float64).ravel(), gv.astype(np.float64).ravel()
+    S, Qs = np.meshgrid(np.arange(stages), np.arange(kRec), indexing='ij')
+    kk = SLOT_K[Qs]
+    k = S * kStageK + kk
+    kc = np.where(kk >= 0, k, 0)
+    LP, LQ = kc // g['Lc'], kc % g['Lc']
+    kok = (kk >= 0) & (k < g['M'])
+    # k_pack_gh_a: rows m = (r, r2)
+    m = np.arange(Mpad)
+    r, r2 = m // g['Kc'], m % g['Kc']
+    pp = nx * LP[:, None, :] + r[None, :, None] - g['hs']
+    qq = ny * LQ[:, None, :] + r2[None, :, None] - g['ht']
+    oka = (m[None, :, None] < Mg) & kok[:, None, :] & (pp >= 0) & (pp < R) & (qq >= 0) & (qq < C)
+    idx = np.where(oka, pp * C + qq, 0)
+    assert idx.min() >= 0 and idx.max() < R * C
+    Ap = to_blocks(np.where(oka, wf[idx], 0.0))
+    # k_pack_gh_b: columns n = (x, y, z)
+    n = np.arange(Npad)
+    cz, z = n // nz, n % nz
+    x, y = cz // ny, cz % ny
+    P = nx * LP[:, None, :] + x[None, :, None]
+    Q = ny * LQ[:, None, :] + y[None, :, None]
+    okb = (n[None, :, None] < N) & kok[:, None, :] & (P < R) & (Q < C)
+    idx = np.where(okb, z[None, :, None] * R * C + P * C + Q, 0)
+    assert idx.min() >= 0 and idx.max() < gf.size
+    Bp = to_blocks(np.where(okb, gf[idx], 0.0))
+    check_blocks(mtiles, ntiles, 1)
+    use = SLOT_K >= 0
+    E = np.zeros((Mpad, Npad))
+    for s in range(stages):
+        Arec = read_records(Ap, s * kRecVec * Mpad, np.arange(Mpad), 2 * Mpad)
+        Brec = read_records(Bp, s * kRecVec * Npad, np.arange(Npad), 2 * Npad)
+        E += Arec[:, use] @ Brec[:, use].T
+    # epilogue: (m, n) -> dH[r - x][r2 - y][x][y][z] when inside the patch
+    dH = np.full(shape, np.nan)
+    mm, nn = np.meshgrid(np.arange(Mg), np.arange(N), indexing='ij')
+    rr, rr2 = mm // g['Kc'], mm % g['Kc']
+    xx, yy, zz = (nn // nz) // ny, (nn // nz) % ny, nn % nz
+    sp, tp = rr - xx, rr2 - yy
+    ok = (sp >= 0) & (sp < ns) & (tp >= 0) & (tp < nt)
+    flat = (((sp * nt + tp) * nx + xx) * ny + yy) * nz + zz
+    assert len(np.unique(flat[ok])) == ok.sum() == np.prod(shape)     # every entry exactly once
+    dH.reshape(-1)[flat[ok]] = E[:Mg, :N][ok]
+    return dH
+
+
+@pytest.mark.parametrize("shape,R,C", [((15, 15, 3, 3, 3), 21, 21), ((9, 7, 3, 5, 2), 12, 10), ((5, 5, 5, 5, 1), 7, 8),
+                                       ((7, 9, 1, 1, 3), 11, 9), ((21, 21, 17, 17, 2), 40, 36),
+                                       ((3, 3, 7, 7, 2), 14, 21), ((9, 9, 3, 3, 30), 10, 10)])
+def test_grad_psf_mirror(shape, R, C):
+    w = lfsynth.uniform_f32((R, C), 11)
+    gv = lfsynth.uniform_f32((shape[4], R, C), 12)
+    ref = oracle.grad_psf(shape, w, gv)
+    got = grad_mirror(shape, w, gv)
+    assert np.allclose(got, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
