@@ -76,7 +76,7 @@ def projector_traffic():
         t = json.load(fh)
     if t.get("kernel_source_sha") != projector_source_sha():
         return None
-    return t["kernels"]["k_gemm<true>"]["hbm_bytes_per_launch"]
+    return t.get("kernels", {}).get("k_gemm<0>", {}).get("hbm_bytes_per_launch")
 
 
 def traffic_from_profile(workload: str):
