@@ -9,7 +9,8 @@ provides device memory and streams.
     compute_Ht_batched([H..])  many PSF arrays in one persistent launch
     forward(H, g)              f = H g (Sec. 2.1, Eq. 1)
     backward(Ht, f)            g = H' f (Eq. 2, backprojection)
-    LFProject                  torch.autograd.Function: forward by H, gradient by H'
+    LFProject                  torch.autograd.Function: forward by H, gradients by H' (g) and grad_psf (H)
+    grad_psf(w, g, shape)      d<w, H g>/dH
     rl_step(H, Ht, f, g, norm) one Richardson-Lucy update (Eq. 2); richardson_lucy(H, f, n)
 """
 from __future__ import annotations
