@@ -7,7 +7,9 @@ Prints ONE JSON line.  A step is one pass of the hot path over its synthetic
 input, already resident in HBM: one lfbp_compute_Ht call (plain workloads), one
 lfbp_compute_Ht_batched call over a table of PSF sets (batched, batched-small),
 one forward plus one backward projection (projector), one Richardson-Lucy
-update (rl), or one gradient with respect to H (grad-psf).  K steps are timed with HIP events
+update (rl), one gradient with respect to H (grad-psf), or one
+lfbp_compute_Ht_colmajor call per size of Table 1 on column-major arrays
+(table1).  K steps are timed with HIP events
 on the stream the kernels run on, bracketed by device synchronisation.
 """
 from __future__ import annotations
@@ -35,7 +37,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="microscope",
-                    choices=sorted(PLAIN) + ["batched", "batched-small", "projector", "rl", "grad-psf"])
+                    choices=sorted(PLAIN) + ["batched", "batched-small", "projector", "rl", "grad-psf", "table1"])
     ap.add_argument("--variant", default=None, choices=[None, "direct", "staged"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--inplace", action="store_true",
@@ -396,6 +398,85 @@ def bench_grad_psf(args, torch):
     return out
 
 
+def table1_paper_seconds():
+    """Seconds of the paper's CPU implementation for the Table 1 sizes (the
+    committed fixture that transcribes Table 1)."""
+    rows = {}
+    with open(os.path.join(ROOT, "tests", "golden", "table1_shapes.txt")) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                p, nx, ny, sec = line.split()
+                rows[(int(p), int(nx), int(ny))] = float(sec)
+    return rows
+
+
+def bench_table1(args, torch):
+    """One step = H' of every Table 1 size (11 depths, float32), stored
+    column-major as in the paper's implementation, one launch each.  The
+    row-major kernel on the same arrays is timed beside it."""
+    import numpy as np
+    import lfsynth
+    import paper_2003_09133_amd as lf
+
+    from paper_2003_09133_amd import _abi
+    L = _abi.lib()
+    dev = torch.device("cuda:0")
+    paper = table1_paper_seconds()
+    rows, t_col, t_row, total_bytes = [], 0.0, 0.0, 0
+    largest = None
+    for i, key in enumerate(lfsynth.TABLE1_SHAPES):
+        w = lfsynth.table1_workload(i)
+        H, _ = lfsynth.make_H(w)
+        dH = torch.from_numpy(H).to(dev)
+        del H
+        dc = dH.permute(4, 3, 2, 1, 0).contiguous().permute(4, 3, 2, 1, 0)   # column-major storage
+        out_c = torch.empty_like(dc)
+        out_r = torch.empty_like(dH)
+        nbytes = 2 * dH.numel() * dH.element_size()
+        lf.compute_Ht_colmajor(dc, out=out_c)         # argument checks once; the steps are C calls only
+        lf.compute_Ht_into(dH, out_r)
+        shp, stream = _abi.Shape.of(dH.shape), torch.cuda.current_stream().cuda_stream
+        pc, po, pr, pq = dc.data_ptr(), out_c.data_ptr(), dH.data_ptr(), out_r.data_ptr()
+        tc, _ = time_steps(lambda: L.lfbp_compute_Ht_colmajor(pc, po, shp, _abi.F32, stream), args.steps,
+                           args.warmup, torch)
+        tr, _ = time_steps(lambda: L.lfbp_compute_Ht(pr, pq, shp, _abi.F32, stream), args.steps, args.warmup,
+                           torch)
+        del dH, dc, out_c, out_r
+        tc, tr = tc / args.steps, tr / args.steps
+        t_col += tc
+        t_row += tr
+        total_bytes += nbytes
+        rows.append({"shape": list(w.shape), "colmajor_ms": round(tc * 1e3, 4),
+                     "colmajor_GBs": round(nbytes / tc / 1e9, 1), "rowmajor_ms": round(tr * 1e3, 4),
+                     "rowmajor_GBs": round(nbytes / tr / 1e9, 1), "paper_cpu_s": paper.get(tuple(key))})
+        print(f"# {w.name}: column-major {tc * 1e3:.3f} ms, row-major {tr * 1e3:.3f} ms", file=sys.stderr,
+              flush=True)
+        if largest is None or nbytes > largest[0]:
+            largest = (nbytes, tc, list(w.shape))
+    gbs = total_bytes / t_col / 1e9
+    big_gbs = largest[0] / largest[1] / 1e9
+    out = {
+        "metric": METRIC, "value": round(gbs, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(t_col * 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "Table 1 sizes, 11 depths, f32, column-major storage, one launch per size",
+                   "bytes_per_step": total_bytes, "rowmajor_ms_per_step": round(t_row * 1e3, 4),
+                   "sizes": rows},
+        "roofline": {"bound": "hbm", "achieved": round(big_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(big_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": f"k_colmajor on {largest[2]}"},
+    }
+    if not args.no_cpu_baseline:
+        nth = cores_used()
+        w = lfsynth.table1_workload(3)
+        H, _ = lfsynth.make_H(w)
+        rate, passes, per = cpu_oracle_rate(H, nth, args.cpu_seconds)
+        out["cpu_baseline"] = {"value": round(rate, 3), "unit": "GB/s", "cores": nth, "kind": "oracle",
+                               "sample": f"{passes} full passes of the (row-major) oracle over the Table 1 "
+                                         f"size {list(w.shape)} ({per:.2f} s each)"}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -414,6 +495,8 @@ def main():
         out = bench_rl(args, torch)
     elif args.workload == "grad-psf":
         out = bench_grad_psf(args, torch)
+    elif args.workload == "table1":
+        out = bench_table1(args, torch)
     else:
         out = bench_plain(args, torch)
     print(json.dumps(out), flush=True)

@@ -149,6 +149,24 @@ LFBP_API lfbp_status lfbp_compute_Ht_batched(const lfbp_problem* problems, int32
  */
 LFBP_API lfbp_status lfbp_compute_Ht_inplace(void* H, lfbp_shape shape, lfbp_dtype dtype, void* stream);
 
+/*
+ * lfbp_compute_Ht_colmajor -- H' (the re-arrangement of lfbp_compute_Ht,
+ * Sec. 4, Eqs. 4-9) for arrays stored COLUMN-MAJOR: element (s, t, x, y, z)
+ * at ((((z*ny + y)*nx + x)*nt + t)*ns + s), s fastest -- the order of the
+ * Matlab arrays the paper's implementation works on (Sec. 5, Table 1).  The
+ * shape fields keep their meaning; Ht has the same layout.  Results are
+ * bit-identical to lfbp_compute_Ht on the transposed arrays.
+ *
+ * H, Ht     DEVICE pointers, ns*nt*nx*ny*nz elements each, aligned to the
+ *           element size, not overlapping; the caller owns both.
+ * Shape     as lfbp_compute_Ht, and nx*esize <= 65536 bytes and
+ *           nt*ny*nz*ns < 2^31, else ESHAPE.
+ * Errors    EINVAL, EDTYPE, ESHAPE, EALIGN, EALIAS (checked before launch),
+ *           EDEVICE.  Allocates nothing; asynchronous on `stream`.
+ */
+LFBP_API lfbp_status lfbp_compute_Ht_colmajor(const void* H, void* Ht, lfbp_shape shape, lfbp_dtype dtype,
+                                              void* stream);
+
 /* Same as lfbp_compute_Ht_batched with an explicit kernel choice shared by
  * every problem, and graph use: use_graph = 1 replays a captured graph,
  * 0 launches the kernel directly.  cfg may be NULL. */

@@ -14,7 +14,7 @@ import subprocess
 import numpy as np
 
 from .workloads import (BATCHED_SETS, CAMERA, MICROSCOPE, PROJECTOR, SMALL_SETS, TINY,
-                        TABLE1_SHAPES, Workload, batched_set, small_set)
+                        TABLE1_SHAPES, Workload, batched_set, small_set, table1_workload)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liblfsynth.so")
@@ -22,7 +22,7 @@ _lib = None
 
 __all__ = ["build", "gauss_f32", "bits_u32", "bits_u16", "bits", "uniform_f32",
            "small_int_f32", "word", "Workload", "TINY", "MICROSCOPE", "CAMERA",
-           "PROJECTOR", "BATCHED_SETS", "SMALL_SETS", "TABLE1_SHAPES", "batched_set", "small_set", "make_H"]
+           "PROJECTOR", "BATCHED_SETS", "SMALL_SETS", "TABLE1_SHAPES", "batched_set", "small_set", "table1_workload", "make_H"]
 
 
 def build(verbose: bool = False) -> str:

@@ -81,3 +81,10 @@ PROJECTOR = ProjectorWorkload("projector", MICROSCOPE, 40, 5)
 TABLE1_SHAPES = ((89, 11, 11), (177, 11, 11), (287, 11, 11), (507, 11, 11), (91, 15, 15),
                  (121, 15, 15), (211, 21, 21), (249, 31, 31), (311, 31, 31), (307, 51, 51),
                  (181, 95, 55))
+
+
+def table1_workload(i: int) -> Workload:
+    """Row i of Table 1 as a workload: the paper's array size with 11 depths,
+    Gaussian envelope centred on the middle depth."""
+    patch, nx, ny = TABLE1_SHAPES[i]
+    return Workload(f"table1-{patch}-{nx}x{ny}", (patch, patch, nx, ny, 11), 1.0, 0.4, 5.0, 3000 + i)

@@ -23,7 +23,7 @@ from . import _abi
 from ._abi import (F16, F32, GATHER_AUTO, GATHER_DIRECT, GATHER_STAGED, GATHER_WIDE, GatherConfig,
                    LfbpError, Problem, Shape)
 
-__all__ = ["compute_Ht", "compute_Ht_into", "compute_Ht_inplace", "compute_Ht_batched", "BatchedHt", "forward", "forward_workspace_size",
+__all__ = ["compute_Ht", "compute_Ht_into", "compute_Ht_inplace", "compute_Ht_colmajor", "compute_Ht_batched", "BatchedHt", "forward", "forward_workspace_size",
            "backward", "backward_workspace_size", "grad_psf", "grad_psf_workspace_size", "LFProject", "project",
            "rl_norm", "rl_step",
            "rl_workspace_size", "richardson_lucy", "default_config", "GatherConfig", "LfbpError", "release_plans",
@@ -91,6 +91,37 @@ def compute_Ht_inplace(H: torch.Tensor, stream=None) -> torch.Tensor:
     _abi.check(_abi.lib().lfbp_compute_Ht_inplace(H.data_ptr(), Shape.of(H.shape), _DTYPES[H.dtype],
                                                   _stream(stream)), "lfbp_compute_Ht_inplace")
     return H
+
+
+def _is_colmajor(H: torch.Tensor) -> bool:
+    """5-D tensor whose storage is dense with the FIRST index fastest."""
+    expect, st = 1, []
+    for n in H.shape:
+        st.append(expect)
+        expect *= n
+    return all(n == 1 or s == e for n, s, e in zip(H.shape, H.stride(), st))
+
+
+def compute_Ht_colmajor(H: torch.Tensor, out=None, stream=None) -> torch.Tensor:
+    """H' (Sec. 4) of a column-major H of shape [ns, nt, nx, ny, nz] (s
+    fastest in memory, the layout of Matlab arrays; e.g. the
+    permute(4, 3, 2, 1, 0) view of a contiguous [nz, ny, nx, nt, ns] tensor).
+    Returns H' in the same layout (a new tensor unless `out` is given)."""
+    if not isinstance(H, torch.Tensor) or H.dim() != 5:
+        raise ValueError("H must be a 5-D tensor [ns, nt, nx, ny, nz]")
+    if not H.is_cuda:
+        raise ValueError("H must live on a GPU")
+    if H.dtype not in _DTYPES:
+        raise TypeError(f"H must be float32 or float16, got {H.dtype}")
+    if not _is_colmajor(H):
+        raise ValueError("H must be column-major (s fastest): a permute(4, 3, 2, 1, 0) view of a contiguous tensor")
+    if out is None:
+        out = torch.empty(tuple(reversed(H.shape)), dtype=H.dtype, device=H.device).permute(4, 3, 2, 1, 0)
+    elif out.shape != H.shape or out.dtype != H.dtype or not out.is_cuda or not _is_colmajor(out):
+        raise ValueError("out must be a column-major GPU tensor of H's shape and dtype")
+    _abi.check(_abi.lib().lfbp_compute_Ht_colmajor(H.data_ptr(), out.data_ptr(), Shape.of(H.shape),
+                                                   _DTYPES[H.dtype], _stream(stream)), "lfbp_compute_Ht_colmajor")
+    return out
 
 
 def compute_Ht_batched(Hs, outs=None, config=None, use_graph: bool = True, stream=None):

@@ -65,6 +65,7 @@ def lib():
             "lfbp_compute_Ht": (st, [vp, vp, Shape, i32, vp]),
             "lfbp_compute_Ht_config": (st, [vp, vp, Shape, i32, ctypes.POINTER(GatherConfig), vp]),
             "lfbp_compute_Ht_inplace": (st, [vp, Shape, i32, vp]),
+            "lfbp_compute_Ht_colmajor": (st, [vp, vp, Shape, i32, vp]),
             "lfbp_default_config": (st, [Shape, i32, ctypes.POINTER(GatherConfig)]),
             "lfbp_compute_Ht_batched": (st, [ctypes.POINTER(Problem), i32, i32, vp]),
             "lfbp_compute_Ht_batched_config": (st, [ctypes.POINTER(Problem), i32, i32,

@@ -19,7 +19,7 @@ SO = os.path.join(HERE, "liblfbp.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["lfbp_gather.hip", "lfbp_inplace.hip", "lfbp_project.hip", "lfbp_api.cpp", "lfbp_api_project.cpp", "lfbp_tune.cpp",
+SOURCES = ["lfbp_gather.hip", "lfbp_inplace.hip", "lfbp_colmajor.hip", "lfbp_project.hip", "lfbp_api.cpp", "lfbp_api_project.cpp", "lfbp_tune.cpp",
            "lfbp_validate.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden", "-Wall", "-Wno-unused-result",

@@ -23,6 +23,8 @@ hipError_t launch_gather_batched(const BatchArgs& a, uint32_t maxW, int esize, c
 hipError_t set_gather_smem_limits(int max_bytes);
 hipError_t set_inplace_smem_limits(int max_bytes);
 hipError_t launch_inplace(void* H, const lfbp_shape& s, int esize, int max_lds, hipStream_t stream);
+hipError_t set_colmajor_smem_limits(int max_bytes);
+hipError_t launch_colmajor(const void* H, void* Ht, const lfbp_shape& s, int esize, int max_lds, hipStream_t stream);
 int gather_occupancy(const LaunchPlan& p, uint32_t W, int esize, bool batched);
 namespace {
 
@@ -35,7 +37,20 @@ int g_cus = 256;
 
 }  // namespace
 
-// Once per process: device limits, gather LDS limits.
+namespace {
+
+// Dynamic LDS limits of every kernel that may use more than the default 64 KB.
+hipError_t set_smem_limits(int max_bytes)
+{
+    hipError_t e = set_gather_smem_limits(max_bytes);
+    if (e == hipSuccess) e = set_inplace_smem_limits(max_bytes);
+    if (e == hipSuccess) e = set_colmajor_smem_limits(max_bytes);
+    return e;
+}
+
+}  // namespace
+
+// Once per process: device limits, kernels' LDS limits.
 hipError_t ensure_init()
 {
     std::call_once(g_init_once, [] {
@@ -46,13 +61,11 @@ hipError_t ensure_init()
             g_max_lds = lds;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
             g_cus = cus;
-        g_init_err = set_gather_smem_limits(g_max_lds);
-        if (g_init_err == hipSuccess) g_init_err = set_inplace_smem_limits(g_max_lds);
+        g_init_err = set_smem_limits(g_max_lds);
         if (g_init_err != hipSuccess && g_max_lds > 65536) {
             (void)hipGetLastError();
             g_max_lds = 65536;
-            g_init_err = set_gather_smem_limits(g_max_lds);
-            if (g_init_err == hipSuccess) g_init_err = set_inplace_smem_limits(g_max_lds);
+            g_init_err = set_smem_limits(g_max_lds);
         }
     });
     return g_init_err;
@@ -458,10 +471,27 @@ lfbp_status lfbp_compute_Ht_inplace(void* H, lfbp_shape shape, lfbp_dtype dtype,
     if (st != LFBP_OK) return st;
     if (reinterpret_cast<uintptr_t>(H) % uintptr_t(es)) return LFBP_EALIGN;
     // one x-row of block O and its partner row must fit the LDS together
-    if (uint64_t(shape.ny) * uint64_t(shape.nz) * uint64_t(es) * 2 > uint64_t(kInplaceMinLds)) return LFBP_ESHAPE;
+    if (uint64_t(shape.ny) * uint64_t(shape.nz) * uint64_t(es) * 2 > uint64_t(kMinLds)) return LFBP_ESHAPE;
     if (ensure_init() != hipSuccess) return LFBP_EDEVICE;
     return launch_inplace(H, shape, es, g_max_lds, static_cast<hipStream_t>(stream)) == hipSuccess ? LFBP_OK
                                                                                                : LFBP_EDEVICE;
+}
+
+lfbp_status lfbp_compute_Ht_colmajor(const void* H, void* Ht, lfbp_shape shape, lfbp_dtype dtype, void* stream)
+{
+    const lfbp_status st = check_gather(H, Ht, shape, dtype);
+    if (st != LFBP_OK) return st;
+    const int es = dtype_size(dtype);
+    // one s-position of all nx rows of an input plane must fit the LDS, and
+    // the grid (at most one workgroup per s-position of every plane) the
+    // 32-bit grid size
+    if (uint64_t(shape.nx) * uint64_t(es) > uint64_t(kMinLds)) return LFBP_ESHAPE;
+    const uint64_t planes = uint64_t(shape.nt) * uint64_t(shape.ny) * uint64_t(shape.nz);
+    if (planes * uint64_t(shape.ns) >= (uint64_t(1) << 31)) return LFBP_ESHAPE;
+    if (ensure_init() != hipSuccess) return LFBP_EDEVICE;
+    return launch_colmajor(H, Ht, shape, es, g_max_lds, static_cast<hipStream_t>(stream)) == hipSuccess
+               ? LFBP_OK
+               : LFBP_EDEVICE;
 }
 
 void lfbp_release_plans(void)
