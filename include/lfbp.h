@@ -159,8 +159,8 @@ LFBP_API lfbp_status lfbp_compute_Ht_inplace(void* H, lfbp_shape shape, lfbp_dty
  *
  * H, Ht     DEVICE pointers, ns*nt*nx*ny*nz elements each, aligned to the
  *           element size, not overlapping; the caller owns both.
- * Shape     as lfbp_compute_Ht, and nx*esize <= 65536 bytes and
- *           nt*ny*nz*ns < 2^31, else ESHAPE.
+ * Shape     as lfbp_compute_Ht, and nx <= 2048 and nt*ny*nz*ns < 2^31,
+ *           else ESHAPE.
  * Errors    EINVAL, EDTYPE, ESHAPE, EALIGN, EALIAS (checked before launch),
  *           EDEVICE.  Allocates nothing; asynchronous on `stream`.
  */

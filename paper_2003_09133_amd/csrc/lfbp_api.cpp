@@ -471,7 +471,7 @@ lfbp_status lfbp_compute_Ht_inplace(void* H, lfbp_shape shape, lfbp_dtype dtype,
     if (st != LFBP_OK) return st;
     if (reinterpret_cast<uintptr_t>(H) % uintptr_t(es)) return LFBP_EALIGN;
     // one x-row of block O and its partner row must fit the LDS together
-    if (uint64_t(shape.ny) * uint64_t(shape.nz) * uint64_t(es) * 2 > uint64_t(kMinLds)) return LFBP_ESHAPE;
+    if (uint64_t(shape.ny) * uint64_t(shape.nz) * uint64_t(es) * 2 > uint64_t(kInplaceMinLds)) return LFBP_ESHAPE;
     if (ensure_init() != hipSuccess) return LFBP_EDEVICE;
     return launch_inplace(H, shape, es, g_max_lds, static_cast<hipStream_t>(stream)) == hipSuccess ? LFBP_OK
                                                                                                : LFBP_EDEVICE;
@@ -482,10 +482,11 @@ lfbp_status lfbp_compute_Ht_colmajor(const void* H, void* Ht, lfbp_shape shape, 
     const lfbp_status st = check_gather(H, Ht, shape, dtype);
     if (st != LFBP_OK) return st;
     const int es = dtype_size(dtype);
-    // one s-position of all nx rows of an input plane must fit the LDS, and
-    // the grid (at most one workgroup per s-position of every plane) the
-    // 32-bit grid size
-    if (uint64_t(shape.nx) * uint64_t(es) > uint64_t(kMinLds)) return LFBP_ESHAPE;
+    // nx <= 2048: a 16-byte vector of each of the nx rows of an input plane
+    // and the kernel's row table fit in the 64 KB of LDS every device
+    // provides; the grid (at most one workgroup per s-position of every
+    // plane) must fit the 32-bit grid size
+    if (shape.nx > 2048) return LFBP_ESHAPE;
     const uint64_t planes = uint64_t(shape.nt) * uint64_t(shape.ny) * uint64_t(shape.nz);
     if (planes * uint64_t(shape.ns) >= (uint64_t(1) << 31)) return LFBP_ESHAPE;
     if (ensure_init() != hipSuccess) return LFBP_EDEVICE;

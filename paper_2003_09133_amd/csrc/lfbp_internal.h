@@ -95,10 +95,9 @@ struct LaunchPlan {
 // of descriptors and unit prefix sums.
 constexpr uint32_t kInlineProblems = 16;
 
-// LDS a workgroup can count on on every device: the in-place kernel needs a
-// pair of x-rows in it, the column-major kernel one s-position of nx rows
-// (larger budgets give larger tiles).
-constexpr int kMinLds = 65536;
+// LDS the in-place kernel can count on on every device (a pair of x-rows must
+// fit; larger budgets give larger row groups).
+constexpr int kInplaceMinLds = 65536;
 
 struct BatchArgs {
     const GatherDesc* table;     // device descriptor table, or nullptr

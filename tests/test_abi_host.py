@@ -299,7 +299,7 @@ def test_colmajor_validation_before_launch():
     assert L.lfbp_compute_Ht_colmajor(P1, P2, Shape(15, 14, 3, 3, 3), _abi.F32, None) == _abi.ESHAPE
     assert L.lfbp_compute_Ht_colmajor(P1 + 2, P2, GOOD, _abi.F32, None) == _abi.EALIGN
     assert L.lfbp_compute_Ht_colmajor(P1, P1 + 64, GOOD, _abi.F32, None) == _abi.EALIAS
-    # one s-position of nx = 16385 rows is 65540 bytes of LDS
-    assert L.lfbp_compute_Ht_colmajor(P1, P2, Shape(3, 3, 16385, 1, 1), _abi.F32, None) == _abi.ESHAPE
+    # cells of more than 2048 rows
+    assert L.lfbp_compute_Ht_colmajor(P1, P2, Shape(3, 3, 2049, 1, 1), _abi.F16, None) == _abi.ESHAPE
     # nt * ny * nz * ns >= 2^31: at most one workgroup per position of every plane
     assert L.lfbp_compute_Ht_colmajor(P1, 1 << 44, Shape(4097, 3, 1, 1, 174763), _abi.F16, None) == _abi.ESHAPE

@@ -45,21 +45,44 @@ def test_small_shapes(shape, dtype):
     assert_same_bits(storage(out).cpu().numpy(), ref_colmajor(H), f"colmajor {shape}")
 
 
-@pytest.mark.parametrize("shape", [(9, 3, 8193, 1, 1), (5, 1, 16383, 1, 2), (7, 3, 16385, 1, 1)])
-def test_columns_larger_than_the_tile_budget(shape):
-    """nx * 4 bytes above 32 KB: tiles take the device's whole LDS, few s
-    positions each (or one: 16383 * 4 bytes), with a ragged last chunk; the
-    last shape needs more than 64 KB and is refused only in float32."""
-    H = lfsynth.bits(shape, 12, np.float32)
-    dH = to_dev_colmajor(H)
-    if shape[2] * 4 > 65536:
-        with pytest.raises(lf.LfbpError):
-            lf.compute_Ht_colmajor(dH)
-        H = lfsynth.bits(shape, 12, np.float16)
-        dH = to_dev_colmajor(H)
-    out = lf.compute_Ht_colmajor(dH)
+@pytest.mark.parametrize("dtype", [np.float32, np.float16])
+@pytest.mark.parametrize("shape", [(35, 3, 1537, 1, 1), (13, 1, 2047, 1, 2), (301, 3, 257, 1, 2)])
+def test_columns_wider_than_the_tile_budget(shape, dtype):
+    """Cells of more than 1500 rows: four 16-byte vectors of every row
+    exceed 96 KB, so tiles take up to the device's whole LDS, a few s
+    positions each, with a ragged last chunk; and 257 rows of 301 positions,
+    which the 96 KB tile budget splits into chunks."""
+    H = lfsynth.bits(shape, 12, dtype)
+    out = lf.compute_Ht_colmajor(to_dev_colmajor(H))
     torch.cuda.synchronize()
     assert_same_bits(storage(out).cpu().numpy(), ref_colmajor(H), f"colmajor {shape}")
+
+
+def test_cells_wider_than_2048_rows_are_refused():
+    H = torch.zeros((1, 3, 2049, 1, 3), device=DEV, dtype=torch.float16).permute(4, 3, 2, 1, 0)
+    assert H.shape == (3, 1, 2049, 3, 1)
+    with pytest.raises(lf.LfbpError):
+        lf.compute_Ht_colmajor(H)
+
+
+def test_unaligned_views():
+    """Arrays whose first element is not 16-byte aligned: the vector loads
+    and stores shift, the first and last vectors take the element path."""
+    shape = (21, 9, 7, 3, 4)
+    H = lfsynth.bits(shape, 14, np.float32)
+    n = H.size
+    store = torch.from_numpy(np.ascontiguousarray(H.transpose(4, 3, 2, 1, 0)).ravel()).to(DEV)
+    for off_in, off_out in ((1, 3), (2, 0), (3, 1)):
+        big = torch.zeros(n + 8, device=DEV, dtype=torch.float32)
+        big[off_in:off_in + n] = store
+        dst = torch.full((n + 8,), 7.0, device=DEV, dtype=torch.float32)
+        src = big[off_in:off_in + n].view(tuple(reversed(shape))).permute(4, 3, 2, 1, 0)
+        out = dst[off_out:off_out + n].view(tuple(reversed(shape))).permute(4, 3, 2, 1, 0)
+        lf.compute_Ht_colmajor(src, out=out)
+        torch.cuda.synchronize()
+        d = dst.cpu().numpy()
+        assert_same_bits(d[off_out:off_out + n], ref_colmajor(H), f"offsets {off_in} {off_out}")
+        assert np.all(d[:off_out] == 7.0) and np.all(d[off_out + n:] == 7.0)
 
 
 def test_agrees_with_row_major_and_is_an_involution():
