@@ -68,6 +68,28 @@ def projector_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
+def colmajor_source_sha() -> str:
+    """Digest of the column-major kernel and its launch code."""
+    h = hashlib.sha256()
+    for f in ("csrc/lfbp_colmajor.hip", "csrc/lfbp_internal.h"):
+        with open(os.path.join(ROOT, "paper_2003_09133_amd", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def colmajor_traffic(shape):
+    """HBM bytes of one column-major launch on `shape` from the committed
+    counter summary, if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "colmajor_table1_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("kernel_source_sha") != colmajor_source_sha():
+        return None
+    return t.get("shapes", {}).get("x".join(map(str, shape)), {}).get("hbm_bytes_per_launch")
+
+
 def projector_traffic():
     """HBM bytes of one forward GEMM launch from the committed counter summary,
     if it was taken on the current projector source; else None."""
@@ -463,7 +485,7 @@ def bench_table1(args, torch):
                    "bytes_per_step": total_bytes, "rowmajor_ms_per_step": round(t_row * 1e3, 4),
                    "sizes": rows},
         "roofline": {"bound": "hbm", "achieved": round(big_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(big_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(big_gbs / HBM_PEAK_GBS, 4), "traffic": colmajor_traffic(largest[2]),
                      "kernel": f"k_colmajor on {largest[2]}"},
     }
     if not args.no_cpu_baseline:
