@@ -135,6 +135,7 @@ struct GemmArgs {
     // forward: A blocks are (px, py, depth chunk), LRp x LCp records each
     int nzc, LRp, LCp, padP, padQ;
     FastDiv fnzc;
+    int Rw;           // forward: patch rows (s') in every wavefront's window
 };
 
 // Geometry of the forward depth chunking and of the phase-split copy of g.
@@ -288,10 +289,59 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2
     int mt, ntile, split;
     tile_of_block(a, mt, ntile, split);
     const ProjGeom& g = a.g;
-    const int m0 = mt * kMT, n0 = ntile * kNT;
-    const int s_begin = int(int64_t(a.stages) * split / a.splits);
-    const int s_end = int(int64_t(a.stages) * (split + 1) / a.splits);
-    const int wave = int(threadIdx.x) >> 6, lane = int(threadIdx.x) & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6), lane = int(threadIdx.x) & 63;
+    // This wavefront's 64 x 64 output block at rows m0, columns nb: a
+    // workgroup is one 64-row tile of 256 columns, 64 per wavefront (forward:
+    // one class box per wavefront).
+    const int m0 = mt * kMT;
+    const int nb = ntile * kNT + 64 * wave;
+
+    // This wavefront's window: the stages whose B records can be nonzero in
+    // its columns, w_cnt of them, window index i -> stage stage_of(i).
+    // Forward: columns are classes (u, v) = (n / ny, n mod ny), so a
+    // wavefront's 64 columns hold a few consecutive u, and s' + u must fall
+    // inside [0, ns): a run of a.Rw patch rows (the same count for every
+    // wavefront, placed to cover its u), walked with the depth chunk fastest,
+    // then the patch row, then t'.  The wavefronts of a workgroup are then
+    // always within a few stages of one another and share the A records.
+    // Backward: the reduction pairs with r + cx inside [0, ns) for some column
+    // of the workgroup, a contiguous run of stages (columns are (cx, cy, z)
+    // with z fastest, so a workgroup spans few cx).  Other products: every
+    // stage.
+    int w_cnt = a.stages, w_base = 0, sr0 = 0;
+    if (kFwd) {
+        const int nlo = nb;
+        if (nlo >= a.N) {
+            w_cnt = 0;
+        } else {
+            const int uhi = min(nlo + 63, a.N - 1) / g.ny;
+            // s' from -uhi (shifted by nx-1), kept inside the Kr patch rows
+            sr0 = min(g.nx - 1 - uhi, g.Kr - a.Rw);
+            w_cnt = a.Rw * g.Kc * a.nzc;
+        }
+    } else if (kMode == kModeBwd) {
+        // the workgroup's columns (one window for its four wavefronts keeps
+        // them on the same stages, sharing the A records)
+        const int nlo = ntile * kNT;
+        if (nlo >= a.N) {
+            w_cnt = 0;
+        } else {
+            const int nhi = min(nlo + kNT - 1, a.N - 1);
+            const int cxlo = nlo / g.nz / g.ny, cxhi = nhi / g.nz / g.ny;
+            // r + nx - 1 from nx-1-cxhi to nx-2-cxlo+ns: reduction indices [klo, khi)
+            const int klo = (g.nx - 1 - cxhi) * g.Kc, khi = (g.nx - 1 - cxlo + g.ns) * g.Kc;
+            w_base = klo / kStageK;
+            w_cnt = (khi + kStageK - 1) / kStageK - w_base;
+        }
+    }
+    auto stage_of = [&](int i) -> int {
+        if (!kFwd) return w_base + i;
+        const int j = i / a.nzc, zc = i - j * a.nzc;
+        const int tc = j / a.Rw, ir = j - tc * a.Rw;
+        return ((sr0 + ir) * g.Kc + tc) * a.nzc + zc;
+    };
+    const int s_begin = int(int64_t(w_cnt) * split / a.splits);
+    const int s_end = int(int64_t(w_cnt) * (split + 1) / a.splits);
     const int li = lane & 31, lk = lane >> 5;
     f32x4 (*T)[4][64] = tot[wave];
 
@@ -311,7 +361,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2
         }
     }
 #pragma unroll
-    for (int j = 0; j < 2; ++j) ob[j] = uint32_t(16 * (2 * (n0 + 64 * wave + 32 * j + li) + lk));
+    for (int j = 0; j < 2; ++j) ob[j] = uint32_t(16 * (2 * (nb + 32 * j + li) + lk));
     const char* A1 = reinterpret_cast<const char*>(a.A);
     const char* B1 = reinterpret_cast<const char*>(a.B);
     const uint32_t ablock = uint32_t(16 * kRecVec * arows), bblock = uint32_t(16 * kRecVec * a.Npad);
@@ -337,7 +387,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2
     // stage's loads, never the prefetch behind it.
     const int s_last = max(s_begin, s_end - 1);
     auto load = [&](int s, Frag& f) {
-        const int sc = min(s, s_last);
+        const int sc = stage_of(min(s, s_last));
         load_frag(a_rsrc(sc), make_rsrc(B1 + int64_t(sc) * bblock, bblock), oa, ob, uint32_t(32 * arows),
                   uint32_t(32 * a.Npad), f);
         // keep the prefetch ahead of the MFMAs that follow (compiler barrier for
@@ -374,7 +424,6 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2
     }
     fold(acc, T, lane);
 
-    const int nb = n0 + 64 * wave;
     if (kFwd) {
         float* out = a.out + size_t(split) * a.Mpad * a.Npad;
 #pragma unroll
@@ -702,6 +751,7 @@ struct FwdPlan {
     ProjGeom g;
     FwdLayout L;
     int N, Npad, Mpad, mtiles, ntiles, splits;
+    int Rw;           // patch rows in a wavefront's window
     size_t gT_bytes, gS_bytes, B_bytes, part_bytes;
 };
 
@@ -711,6 +761,8 @@ FwdPlan fwd_plan(const lfbp_shape& s, int64_t R, int64_t C)
     P.g = make_geom(s, R, C);
     P.L = fwd_layout(P.g);
     P.N = P.g.nx * P.g.ny;
+    // 64 consecutive classes span at most floor(63 / ny) + 2 values of u
+    P.Rw = P.g.ns + std::min(P.g.nx, 63 / P.g.ny + 2) - 1;
     P.mtiles = (P.g.M + kMT - 1) / kMT;
     P.ntiles = (P.N + kNT - 1) / kNT;
     P.Mpad = P.mtiles * kMT;
@@ -836,6 +888,7 @@ hipError_t forward_impl(const float* H, const lfbp_shape& s, const float* gin, i
     a.padP = P.L.padP;
     a.padQ = P.L.padQ;
     a.fnzc = p.fnzc;
+    a.Rw = P.Rw;
     hipLaunchKernelGGL(k_gemm<kModeFwd>, dim3(unsigned(P.mtiles * P.ntiles * P.splits)), dim3(kThreads), 0, stream,
                        a);
     if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -1,6 +1,7 @@
 // Host-only argument checks of the C ABI (no HIP calls, no HIP headers).
 #include "lfbp_validate.h"
 
+#include <algorithm>
 #include <initializer_list>
 
 namespace lfbp {
@@ -97,7 +98,10 @@ lfbp_status check_project_shape(const lfbp_shape& s, int64_t R, int64_t C)
     // A record block (96 bytes per record) is addressed with 32-bit offsets:
     // columns (nx*ny*nz, padded), lenslets (padded) and the lenslet grid of g
     // with its zero border must each stay below 2^31 bytes of records.
-    const uint64_t cols = mul_sat(mul_sat(uint64_t(s.nx), uint64_t(s.ny)), uint64_t(s.nz)) + 256;
+    // (backward: nx*ny*nz columns; forward: nx*ny classes in boxes, at most
+    // twice that many columns)
+    const uint64_t classes = mul_sat(uint64_t(s.nx), uint64_t(s.ny));
+    const uint64_t cols = std::max(mul_sat(classes, uint64_t(s.nz)), mul_sat(classes, 2)) + 512;
     const uint64_t hs = uint64_t(s.ns - 1) / 2, ht = uint64_t(s.nt - 1) / 2;
     const uint64_t Lr = uint64_t((R + s.nx - 1) / s.nx), Lc = uint64_t((C + s.ny - 1) / s.ny);
     const uint64_t grid = mul_sat(Lr + 2 * ((hs + s.nx - 1) / s.nx), Lc + 2 * ((ht + s.ny - 1) / s.ny));

@@ -50,6 +50,38 @@ def fwd_stage(g, nzc, s):
     return sp, tp, zc, px, py, (e - px) // g['nx'], (f - py) // g['ny']
 
 
+def fwd_window(g, p, ntile, wave):
+    """The wavefront's stages (k_gemm, forward), in window order: a run of Rw
+    patch rows covering the u of its 64 columns, depth chunk fastest, then
+    the patch row, then the column."""
+    nlo = ntile * kNT + 64 * wave
+    if nlo >= p['N']:
+        return []
+    uhi = min(nlo + 63, p['N'] - 1) // g['ny']
+    sr0 = min(g['nx'] - 1 - uhi, g['Kr'] - p['Rw'])
+    assert sr0 >= 0 and sr0 + p['Rw'] <= g['Kr']
+    out = []
+    for i in range(p['Rw'] * g['Kc'] * p['nzc']):
+        j, zc = divmod(i, p['nzc'])
+        tc, ir = divmod(j, p['Rw'])
+        out.append(((sr0 + ir) * g['Kc'] + tc) * p['nzc'] + zc)
+    return out
+
+
+def bwd_window(g, N, stages, ntile):
+    """The stages of n tile ntile's wavefronts (k_gemm, backward): a contiguous run."""
+    nlo = ntile * kNT
+    if nlo >= N:
+        return []
+    nhi = min(nlo + kNT - 1, N - 1)
+    cxlo, cxhi = nlo // g['nz'] // g['ny'], nhi // g['nz'] // g['ny']
+    klo, khi = (g['nx'] - 1 - cxhi) * g['Kc'], (g['nx'] - 1 - cxlo + g['ns']) * g['Kc']
+    base = klo // kStageK
+    out = list(range(base, -(-khi // kStageK)))
+    assert out[-1] < stages
+    return out
+
+
 def fwd_plan(g, target_blocks=512):
     N = g['nx'] * g['ny']
     mtiles, ntiles = -(-g['M'] // kMT), -(-N // kNT)
@@ -58,8 +90,9 @@ def fwd_plan(g, target_blocks=512):
     want = target_blocks // (mtiles * ntiles)
     splits = max(1, min(want, 64, max(1, stages // 64)))
     padP, padQ = (g['hs'] + g['nx'] - 1) // g['nx'], (g['ht'] + g['ny'] - 1) // g['ny']
+    Rw = g['ns'] + min(g['nx'], 63 // g['ny'] + 2) - 1
     return dict(N=N, mtiles=mtiles, ntiles=ntiles, Mpad=mtiles * kMT, Npad=ntiles * kNT, nzc=nzc, stages=stages,
-                splits=splits, padP=padP, padQ=padQ, LRp=g['Lr'] + 2 * padP, LCp=g['Lc'] + 2 * padQ)
+                splits=splits, padP=padP, padQ=padQ, LRp=g['Lr'] + 2 * padP, LCp=g['Lc'] + 2 * padQ, Rw=Rw)
 
 
 def check_blocks(mtiles, ntiles, splits):
@@ -116,11 +149,12 @@ def forward_mirror(H, gvol, target_blocks=512):
     sp, tp, zcs, pxs, pys, dP, dQ = (np.array(v) for v in zip(*[fwd_stage(g, p['nzc'], s) for s in s_all]))
     n = np.arange(p['Npad'])
     u, v = n // ny, n % ny
+    colok = n < p['N']
     S, Nn, Qs = np.meshgrid(s_all, n, np.arange(kRec), indexing='ij')
     kk = SLOT_K[Qs]
     zz = zcs[S] * kStageK + kk
     su, tv = sp[S] + u[Nn], tp[S] + v[Nn]
-    okb = (Nn < p['N']) & (su >= 0) & (su < ns) & (tv >= 0) & (tv < nt) & (kk >= 0) & (zz < nz)
+    okb = colok[Nn] & (su >= 0) & (su < ns) & (tv >= 0) & (tv < nt) & (kk >= 0) & (zz < nz)
     idx = np.where(okb, (su * nt + tv) * cell + (pxs[S] * ny + pys[S]) * nz + zz, 0)
     assert idx.min() >= 0 and idx.max() < H.size
     Bp = to_blocks(np.where(okb, Hf[idx], 0.0))          # blocks = stages, Npad records each
@@ -133,11 +167,20 @@ def forward_mirror(H, gvol, target_blocks=512):
     lane_b = np.arange(p['Npad'])
     use = SLOT_K >= 0                                               # the MFMA steps read slots 0-10 and 12-22
     partial = np.zeros((p['splits'], p['Mpad'], p['Npad']))
-    for sidx, (b, e) in enumerate(split_ranges(p['stages'], p['splits'])):
-        for s in range(b, e):
-            Arec = read_records(gS, abase[s], lane_a, 2 * arows)
-            Brec = read_records(Bp, s * kRecVec * p['Npad'], lane_b, 2 * p['Npad'])
-            partial[sidx] += Arec[:, use] @ Brec[:, use].T
+    okb_s = okb.any(axis=2)                                         # [stage][column] holds a nonzero slot
+    for ntile in range(p['ntiles']):
+        for wave in range(kNT // 64):
+            cols = np.arange(ntile * kNT + 64 * wave, ntile * kNT + 64 * wave + 64)
+            win = fwd_window(g, p, ntile, wave)
+            assert len(set(win)) == len(win) and all(0 <= st < p['stages'] for st in win)
+            outside = np.ones(p['stages'], bool)
+            outside[win] = False
+            assert not okb_s[np.ix_(outside, cols)].any(), "nonzero B record outside the window"
+            for sidx, (b, e) in enumerate(split_ranges(len(win), p['splits'])):
+                for s in win[b:e]:
+                    Arec = read_records(gS, abase[s], lane_a, 2 * arows)
+                    Brec = read_records(Bp, s * kRecVec * p['Npad'], lane_b[cols], 2 * p['Npad'])
+                    partial[sidx][:, cols] += Arec[:, use] @ Brec[:, use].T
     # k_fwd_reduce
     pp, qq = np.meshgrid(np.arange(R), np.arange(C), indexing='ij')
     mm = (pp // nx) * g['Lc'] + qq // ny
@@ -189,10 +232,17 @@ def backward_mirror(Ht, f):
     check_blocks(mtiles, ntiles, 1)
     use = SLOT_K >= 0
     G = np.zeros((Mpad, Npad))
-    for s in range(stages):
-        Arec = read_records(Ap, s * kRecVec * Mpad, np.arange(Mpad), 2 * Mpad)
-        Brec = read_records(Bp, s * kRecVec * Npad, np.arange(Npad), 2 * Npad)
-        G += Arec[:, use] @ Brec[:, use].T
+    okb_s = okb.any(axis=2)
+    for ntile in range(ntiles):
+        cols = np.arange(ntile * kNT, ntile * kNT + kNT)
+        win = bwd_window(g, N, stages, ntile)
+        outside = np.ones(stages, bool)
+        outside[win] = False
+        assert not okb_s[np.ix_(outside, cols)].any(), "nonzero B record outside the window"
+        for s in win:
+            Arec = read_records(Ap, s * kRecVec * Mpad, np.arange(Mpad), 2 * Mpad)
+            Brec = read_records(Bp, s * kRecVec * Npad, cols, 2 * Npad)
+            G[:, cols] += Arec[:, use] @ Brec[:, use].T
     # epilogue: (m, n) -> g[z][nx LP + cx][ny LQ + cy]
     out = np.zeros((nz, R, C))
     mm, nn = np.meshgrid(np.arange(g['M']), np.arange(N), indexing='ij')
