@@ -54,6 +54,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 
 #include "lfbp_internal.h"
 
@@ -120,6 +121,34 @@ __device__ __forceinline__ int slot_k(int q)
     return j < kHalf ? kHalf * h + j : -1;
 }
 
+
+// Forward output columns are classes (u, v) arranged in boxes of bu x bv
+// classes, one box per wavefront (64 columns): the B records of a box are
+// zero outside a window of (ns + bu - 1) x (nt + bv - 1) patch shifts, so a
+// wavefront runs only the stages of its window.  Box b = (bi, bj), bj fastest
+// (nbv boxes along v); column 64 b + du * bv + dv is class
+// (bi * bu + du, bj * bv + dv).
+struct ClassBoxes {
+    int bu, bv, nbv, boxes;
+};
+
+__device__ __forceinline__ bool class_of_col(const ClassBoxes& c, int nx, int ny, int n, int& u, int& v)
+{
+    const int b = n >> 6, k = n & 63;
+    if (b >= c.boxes || k >= c.bu * c.bv) return false;
+    const int bi = b / c.nbv, bj = b - bi * c.nbv;
+    const int du = k / c.bv, dv = k - du * c.bv;
+    u = bi * c.bu + du;
+    v = bj * c.bv + dv;
+    return u < nx && v < ny;
+}
+
+__device__ __forceinline__ int col_of_class(const ClassBoxes& c, int u, int v)
+{
+    const int bi = u / c.bu, bj = v / c.bv;
+    return (bi * c.nbv + bj) * 64 + (u - bi * c.bu) * c.bv + (v - bj * c.bv);
+}
+
 struct GemmArgs {
     const float* A;   // left operand records
     const float* B;   // right operand records [stage][Npad][kRec]
@@ -135,7 +164,7 @@ struct GemmArgs {
     // forward: A blocks are (px, py, depth chunk), LRp x LCp records each
     int nzc, LRp, LCp, padP, padQ;
     FastDiv fnzc;
-    int Rw;           // forward: patch rows (s') in every wavefront's window
+    ClassBoxes cb;    // forward column layout
 };
 
 // Geometry of the forward depth chunking and of the phase-split copy of g.
@@ -298,26 +327,27 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2
 
     // This wavefront's window: the stages whose B records can be nonzero in
     // its columns, w_cnt of them, window index i -> stage stage_of(i).
-    // Forward: columns are classes (u, v) = (n / ny, n mod ny), so a
-    // wavefront's 64 columns hold a few consecutive u, and s' + u must fall
-    // inside [0, ns): a run of a.Rw patch rows (the same count for every
-    // wavefront, placed to cover its u), walked with the depth chunk fastest,
-    // then the patch row, then t'.  The wavefronts of a workgroup are then
-    // always within a few stages of one another and share the A records.
-    // Backward: the reduction pairs with r + cx inside [0, ns) for some column
-    // of the workgroup, a contiguous run of stages (columns are (cx, cy, z)
-    // with z fastest, so a workgroup spans few cx).  Other products: every
-    // stage.
-    int w_cnt = a.stages, w_base = 0, sr0 = 0;
+    // Forward: the box's patch shifts, s' + u inside [0, ns) and t' + v
+    // inside [0, nt) for some class (u, v) of the box, in a window of the
+    // full box size for every box (a box cut short by the cell edge pads it
+    // at the far end), walked with the depth chunk fastest, then the patch
+    // row s', then t': wavefronts whose boxes share their v then stay within
+    // a few stages of one another and share the A records.  Backward: the
+    // reduction pairs with r + cx inside [0, ns) for some column of the
+    // workgroup, a contiguous run of stages (columns are (cx, cy, z) with z
+    // fastest, so a workgroup spans few cx).  Other products: every stage.
+    int w_cnt = a.stages, w_base = 0, sr0 = 0, tc0 = 0, Rw = 1;
     if (kFwd) {
-        const int nlo = nb;
-        if (nlo >= a.N) {
+        const int b = ntile * (kNT / 64) + wave;
+        if (b >= a.cb.boxes) {
             w_cnt = 0;
         } else {
-            const int uhi = min(nlo + 63, a.N - 1) / g.ny;
-            // s' from -uhi (shifted by nx-1), kept inside the Kr patch rows
-            sr0 = min(g.nx - 1 - uhi, g.Kr - a.Rw);
-            w_cnt = a.Rw * g.Kc * a.nzc;
+            const int bi = b / a.cb.nbv, bj = b - bi * a.cb.nbv;
+            const int u1 = min(g.nx, (bi + 1) * a.cb.bu) - 1, v1 = min(g.ny, (bj + 1) * a.cb.bv) - 1;
+            sr0 = g.nx - 1 - u1;   // s' from -u1 (shifted by nx - 1)
+            tc0 = g.ny - 1 - v1;
+            Rw = g.ns + a.cb.bu - 1;
+            w_cnt = Rw * (g.nt + a.cb.bv - 1) * a.nzc;
         }
     } else if (kMode == kModeBwd) {
         // the workgroup's columns (one window for its four wavefronts keeps
@@ -337,8 +367,8 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2
     auto stage_of = [&](int i) -> int {
         if (!kFwd) return w_base + i;
         const int j = i / a.nzc, zc = i - j * a.nzc;
-        const int tc = j / a.Rw, ir = j - tc * a.Rw;
-        return ((sr0 + ir) * g.Kc + tc) * a.nzc + zc;
+        const int ic = j / Rw, ir = j - ic * Rw;
+        return ((sr0 + ir) * g.Kc + tc0 + ic) * a.nzc + zc;
     };
     const int s_begin = int(int64_t(w_cnt) * split / a.splits);
     const int s_end = int(int64_t(w_cnt) * (split + 1) / a.splits);
@@ -507,6 +537,7 @@ struct PackArgs {
     int stages;
     int nzc, LRp, LCp, padP, padQ;
     FastDiv fnzc, fLCp;
+    ClassBoxes cb;    // forward column layout
 };
 
 // Item i of a block of `rows` records (i < 6 rows): vector plane v, record r,
@@ -541,8 +572,9 @@ __global__ void __launch_bounds__(256) k_pack_fwd_b(const float* H, PackArgs p, 
     for (int k = 0; k < kRecVec; ++k) {
         const int i = int(threadIdx.x) + k * kThreads;   // record i / 6, vector i % 6
         const int nl = i / kRecVec, c = i - nl * kRecVec, n = n0 + nl;
-        const int u = int(fdiv(uint32_t(n), g.fny)), v = n - u * g.ny;
-        const bool valid = n < p.N && unsigned(t.sp + u) < unsigned(g.ns) && unsigned(t.tp + v) < unsigned(g.nt);
+        int u = 0, v = 0;
+        const bool valid = class_of_col(p.cb, g.nx, g.ny, n, u, v) && unsigned(t.sp + u) < unsigned(g.ns) &&
+                           unsigned(t.tp + v) < unsigned(g.nt);
         const int64_t run = valid ? (int64_t(t.sp + u) * g.nt + (t.tp + v)) * cell + xy : 0;
         f32x4 o;
 #pragma unroll
@@ -728,13 +760,13 @@ __global__ void __launch_bounds__(256) k_pack_gh_b(const float* gv, PackArgs p, 
 // With fmeas set (Richardson-Lucy, Eq. 2), the quotient fmeas / f is written
 // instead, 0 where f is not positive.
 __global__ void __launch_bounds__(256) k_fwd_reduce(const float* partial, int splits, int Mpad, int Npad,
-                                                     ProjGeom g, const float* fmeas, float* f)
+                                                     ProjGeom g, ClassBoxes cb, const float* fmeas, float* f)
 {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= int64_t(g.R) * g.C) return;
     const int p = int(i / g.C), q = int(i - int64_t(p) * g.C);
     const int m = (p / g.nx) * g.Lc + q / g.ny;
-    const int n = (p % g.nx) * g.ny + q % g.ny;
+    const int n = col_of_class(cb, p % g.nx, q % g.ny);
     double acc = 0.0;
     for (int s = 0; s < splits; ++s) acc += double(partial[(size_t(s) * Mpad + m) * Npad + n]);
     if (fmeas)
@@ -751,9 +783,33 @@ struct FwdPlan {
     ProjGeom g;
     FwdLayout L;
     int N, Npad, Mpad, mtiles, ntiles, splits;
-    int Rw;           // patch rows in a wavefront's window
+    ClassBoxes cb;
     size_t gT_bytes, gS_bytes, B_bytes, part_bytes;
 };
+
+// Box shape of the forward columns: at most 64 classes a box, the shape that
+// minimises the wavefronts' stages, (boxes rounded up to whole workgroups) x
+// (ns + bu - 1)(nt + bv - 1), with at most 2 x classes + 256 columns
+// (bu = min(nx, 64) always qualifies); ties go to the squarer box.
+ClassBoxes class_boxes(const ProjGeom& g)
+{
+    ClassBoxes best{};
+    int64_t best_cost = -1;
+    const int64_t classes = int64_t(g.nx) * g.ny;
+    for (int bu = 1; bu <= std::min(g.nx, 64); ++bu) {
+        const int bv = std::min(g.ny, 64 / bu);
+        const int nbu = (g.nx + bu - 1) / bu, nbv = (g.ny + bv - 1) / bv;
+        const int64_t waves = (int64_t(nbu) * nbv + kNT / 64 - 1) / (kNT / 64) * (kNT / 64);
+        if (waves * 64 > 2 * classes + 256 && bu != std::min(g.nx, 64)) continue;
+        const int64_t cost = waves * (g.ns + bu - 1) * (g.nt + bv - 1);
+        if (best_cost < 0 || cost < best_cost ||
+            (cost == best_cost && std::abs(bu - bv) < std::abs(best.bu - best.bv))) {
+            best_cost = cost;
+            best = ClassBoxes{bu, bv, nbv, nbu * nbv};
+        }
+    }
+    return best;
+}
 
 FwdPlan fwd_plan(const lfbp_shape& s, int64_t R, int64_t C)
 {
@@ -761,10 +817,9 @@ FwdPlan fwd_plan(const lfbp_shape& s, int64_t R, int64_t C)
     P.g = make_geom(s, R, C);
     P.L = fwd_layout(P.g);
     P.N = P.g.nx * P.g.ny;
-    // 64 consecutive classes span at most floor(63 / ny) + 2 values of u
-    P.Rw = P.g.ns + std::min(P.g.nx, 63 / P.g.ny + 2) - 1;
+    P.cb = class_boxes(P.g);
     P.mtiles = (P.g.M + kMT - 1) / kMT;
-    P.ntiles = (P.N + kNT - 1) / kNT;
+    P.ntiles = (P.cb.boxes * 64 + kNT - 1) / kNT;
     P.Mpad = P.mtiles * kMT;
     P.Npad = P.ntiles * kNT;
     // About kTargetBlocks workgroups (one round at two per CU on 256 CUs).  The
@@ -856,6 +911,7 @@ hipError_t forward_impl(const float* H, const lfbp_shape& s, const float* gin, i
     p.padQ = P.L.padQ;
     p.fnzc = make_fastdiv(uint32_t(P.L.nzc));
     p.fLCp = make_fastdiv(uint32_t(P.L.LCp));
+    p.cb = P.cb;
 
     const int plane = g.R * g.C;
     hipLaunchKernelGGL(k_depth_last, dim3(unsigned((plane + 31) / 32), unsigned((g.nz + 31) / 32)), dim3(256), 0,
@@ -888,13 +944,13 @@ hipError_t forward_impl(const float* H, const lfbp_shape& s, const float* gin, i
     a.padP = P.L.padP;
     a.padQ = P.L.padQ;
     a.fnzc = p.fnzc;
-    a.Rw = P.Rw;
+    a.cb = P.cb;
     hipLaunchKernelGGL(k_gemm<kModeFwd>, dim3(unsigned(P.mtiles * P.ntiles * P.splits)), dim3(kThreads), 0, stream,
                        a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int64_t npix = int64_t(g.R) * g.C;
     hipLaunchKernelGGL(k_fwd_reduce, dim3(blocks_for(npix)), dim3(256), 0, stream, part, P.splits, P.Mpad, P.Npad, g,
-                       fmeas, f);
+                       P.cb, fmeas, f);
     return hipGetLastError();
 }
 

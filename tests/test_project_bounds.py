@@ -50,21 +50,56 @@ def fwd_stage(g, nzc, s):
     return sp, tp, zc, px, py, (e - px) // g['nx'], (f - py) // g['ny']
 
 
+def class_boxes(g):
+    """Box shape of the forward columns (mirror of class_boxes)."""
+    nx, ny, ns, nt = g['nx'], g['ny'], g['ns'], g['nt']
+    best, best_cost = None, None
+    for bu in range(1, min(nx, 64) + 1):
+        bv = min(ny, 64 // bu)
+        nbu, nbv = -(-nx // bu), -(-ny // bv)
+        waves = -(-(nbu * nbv) // 4) * 4
+        if waves * 64 > 2 * nx * ny + 256 and bu != min(nx, 64):
+            continue
+        cost = waves * (ns + bu - 1) * (nt + bv - 1)
+        if best is None or cost < best_cost or (cost == best_cost and abs(bu - bv) < abs(best[0] - best[1])):
+            best, best_cost = (bu, bv, nbv, nbu * nbv), cost
+    return dict(bu=best[0], bv=best[1], nbv=best[2], boxes=best[3])
+
+
+def class_of_col(cb, nx, ny, n):
+    """Column n -> class (u, v), or None for a padding column."""
+    b, k = n >> 6, n & 63
+    if b >= cb['boxes'] or k >= cb['bu'] * cb['bv']:
+        return None
+    bi, bj = divmod(b, cb['nbv'])
+    du, dv = divmod(k, cb['bv'])
+    u, v = bi * cb['bu'] + du, bj * cb['bv'] + dv
+    return (u, v) if u < nx and v < ny else None
+
+
+def col_of_class(cb, u, v):
+    bi, bj = u // cb['bu'], v // cb['bv']
+    return (bi * cb['nbv'] + bj) * 64 + (u - bi * cb['bu']) * cb['bv'] + (v - bj * cb['bv'])
+
+
 def fwd_window(g, p, ntile, wave):
-    """The wavefront's stages (k_gemm, forward), in window order: a run of Rw
-    patch rows covering the u of its 64 columns, depth chunk fastest, then
-    the patch row, then the column."""
-    nlo = ntile * kNT + 64 * wave
-    if nlo >= p['N']:
+    """The wavefront's stages (k_gemm, forward), in window order: the box's
+    (ns + bu - 1) x (nt + bv - 1) patch shifts, depth chunk fastest, then s',
+    then t'."""
+    cb = p['cb']
+    b = ntile * (kNT // 64) + wave
+    if b >= cb['boxes']:
         return []
-    uhi = min(nlo + 63, p['N'] - 1) // g['ny']
-    sr0 = min(g['nx'] - 1 - uhi, g['Kr'] - p['Rw'])
-    assert sr0 >= 0 and sr0 + p['Rw'] <= g['Kr']
+    bi, bj = divmod(b, cb['nbv'])
+    u1, v1 = min(g['nx'], (bi + 1) * cb['bu']) - 1, min(g['ny'], (bj + 1) * cb['bv']) - 1
+    sr0, tc0 = g['nx'] - 1 - u1, g['ny'] - 1 - v1
+    Rw, Cw = g['ns'] + cb['bu'] - 1, g['nt'] + cb['bv'] - 1
+    assert sr0 >= 0 and tc0 >= 0 and sr0 + Rw <= g['Kr'] and tc0 + Cw <= g['Kc']
     out = []
-    for i in range(p['Rw'] * g['Kc'] * p['nzc']):
+    for i in range(Rw * Cw * p['nzc']):
         j, zc = divmod(i, p['nzc'])
-        tc, ir = divmod(j, p['Rw'])
-        out.append(((sr0 + ir) * g['Kc'] + tc) * p['nzc'] + zc)
+        ic, ir = divmod(j, Rw)
+        out.append(((sr0 + ir) * g['Kc'] + tc0 + ic) * p['nzc'] + zc)
     return out
 
 
@@ -84,15 +119,15 @@ def bwd_window(g, N, stages, ntile):
 
 def fwd_plan(g, target_blocks=512):
     N = g['nx'] * g['ny']
-    mtiles, ntiles = -(-g['M'] // kMT), -(-N // kNT)
+    cb = class_boxes(g)
+    mtiles, ntiles = -(-g['M'] // kMT), -(-(cb['boxes'] * 64) // kNT)
     nzc = -(-g['nz'] // kStageK)
     stages = g['Kr'] * g['Kc'] * nzc
     want = target_blocks // (mtiles * ntiles)
     splits = max(1, min(want, 64, max(1, stages // 64)))
     padP, padQ = (g['hs'] + g['nx'] - 1) // g['nx'], (g['ht'] + g['ny'] - 1) // g['ny']
-    Rw = g['ns'] + min(g['nx'], 63 // g['ny'] + 2) - 1
     return dict(N=N, mtiles=mtiles, ntiles=ntiles, Mpad=mtiles * kMT, Npad=ntiles * kNT, nzc=nzc, stages=stages,
-                splits=splits, padP=padP, padQ=padQ, LRp=g['Lr'] + 2 * padP, LCp=g['Lc'] + 2 * padQ, Rw=Rw)
+                splits=splits, padP=padP, padQ=padQ, LRp=g['Lr'] + 2 * padP, LCp=g['Lc'] + 2 * padQ, cb=cb)
 
 
 def check_blocks(mtiles, ntiles, splits):
@@ -148,8 +183,11 @@ def forward_mirror(H, gvol, target_blocks=512):
     s_all = np.arange(p['stages'])
     sp, tp, zcs, pxs, pys, dP, dQ = (np.array(v) for v in zip(*[fwd_stage(g, p['nzc'], s) for s in s_all]))
     n = np.arange(p['Npad'])
-    u, v = n // ny, n % ny
-    colok = n < p['N']
+    cls = [class_of_col(p['cb'], nx, ny, c) for c in n]
+    colok = np.array([c is not None for c in cls])
+    u = np.array([c[0] if c else 0 for c in cls])
+    v = np.array([c[1] if c else 0 for c in cls])
+    assert sorted(c for c in cls if c) == [(a, b) for a in range(nx) for b in range(ny)]   # each class once
     S, Nn, Qs = np.meshgrid(s_all, n, np.arange(kRec), indexing='ij')
     kk = SLOT_K[Qs]
     zz = zcs[S] * kStageK + kk
@@ -184,7 +222,7 @@ def forward_mirror(H, gvol, target_blocks=512):
     # k_fwd_reduce
     pp, qq = np.meshgrid(np.arange(R), np.arange(C), indexing='ij')
     mm = (pp // nx) * g['Lc'] + qq // ny
-    nn = (pp % nx) * ny + qq % ny
+    nn = np.vectorize(lambda a, b: col_of_class(p['cb'], a, b))(pp % nx, qq % ny)
     assert mm.max() < p['Mpad'] and nn.max() < p['Npad']
     return partial.sum(axis=0)[mm, nn]
 
