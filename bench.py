@@ -262,7 +262,10 @@ def bench_batched(args, torch):
 
 def bench_projector(args, torch):
     """One step = forward projection f = H g plus the backprojection of f
-    through the GPU-built H' (the two products of one gradient evaluation)."""
+    through the GPU-built H' (the two products of one gradient evaluation), on
+    a prepared operator (H and H' packed once, as for any run of projections
+    with one PSF).  The time to prepare the operator and the pair time of the
+    unprepared calls, which pack H and H' on every call, are reported beside."""
     import numpy as np
     import lfsynth
     import paper_2003_09133_amd as lf
@@ -279,8 +282,21 @@ def bench_projector(args, torch):
     # scratch for the operand records, allocated once as an iterative solver would
     wf = torch.empty(lf.forward_workspace_size(H.shape, R, C), dtype=torch.uint8, device=dev)
     wb = torch.empty(lf.backward_workspace_size(H.shape, R, C), dtype=torch.uint8, device=dev)
-    fwd = lambda: lf.forward(dH, g, out=f, workspace=wf)
-    bwd = lambda: lf.backward(dHt, f, out=gb, workspace=wb)
+    fwd_plain = lambda: lf.forward(dH, g, out=f, workspace=wf)
+    bwd_plain = lambda: lf.backward(dHt, f, out=gb, workspace=wb)
+
+    def step_plain():
+        fwd_plain()
+        bwd_plain()
+
+    t_plain, _ = time_steps(step_plain, args.steps, args.warmup, torch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    op = lf.LFOperator(dH, R, C, Ht=dHt)
+    torch.cuda.synchronize()
+    t_prep = time.perf_counter() - t0
+    fwd = lambda: op.forward(g, out=f)
+    bwd = lambda: op.backward(f, out=gb)
 
     def step():
         fwd()
@@ -302,6 +318,8 @@ def bench_projector(args, torch):
                                f"H{list(pw.psf.shape)} f32",
                    "forward_ms": round(t_fwd / args.steps * 1e3, 4),
                    "backward_ms": round(t_bwd / args.steps * 1e3, 4),
+                   "prepared_operator": True, "prepare_ms": round(t_prep * 1e3, 3),
+                   "unprepared_ms_per_step": round(t_plain / args.steps * 1e3, 4),
                    "flop_per_projection": flop_proj, "wall_s": round(wall, 3)},
         "roofline": {"bound": "mfma", "achieved": round(tflops_fwd, 2), "peak": FP32_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(tflops_fwd / FP32_PEAK_TFLOPS, 4),
@@ -325,7 +343,10 @@ def bench_projector(args, torch):
 def bench_rl(args, torch):
     """One step = one Richardson-Lucy update (Eq. 2) of a 21 x 600 x 600 volume
     from a 600 x 600 image: forward projection ending in the quotient,
-    backprojection through H' ending in the update (lfbp_rl_step)."""
+    backprojection through H' ending in the update, on an operator prepared
+    once as richardson_lucy does (lfbp_rl_step_op).  The preparation time and
+    the step time of lfbp_rl_step, which packs H and H' on every call, are
+    reported beside."""
     import numpy as np
     import lfsynth
     import paper_2003_09133_amd as lf
@@ -340,9 +361,18 @@ def bench_rl(args, torch):
     g = torch.ones((pw.psf.shape[4], R, C), device=dev)
     ws = torch.empty(lf.rl_workspace_size(H.shape, R, C), dtype=torch.uint8, device=dev)
     norm = lf.rl_norm(dHt, R, C, workspace=ws)
+    g_plain = g.clone()
+    t_plain, _ = time_steps(lambda: lf.rl_step(dH, dHt, f, g_plain, norm, out=g_plain, workspace=ws), args.steps,
+                            args.warmup, torch)
+    del g_plain, ws
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    op = lf.LFOperator(dH, R, C, Ht=dHt)
+    torch.cuda.synchronize()
+    t_prep = time.perf_counter() - t0
 
     def step():
-        lf.rl_step(dH, dHt, f, g, norm, out=g, workspace=ws)
+        op.rl_step(f, g, norm, out=g)
 
     elapsed, wall = time_steps(step, args.steps, args.warmup, torch)
     sec = elapsed / args.steps
@@ -355,6 +385,8 @@ def bench_rl(args, torch):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"Richardson-Lucy update, {R}x{C} px, {pw.lenslets}x{pw.lenslets} lenslets, "
                                f"H{list(pw.psf.shape)} f32", "flop_per_step": flop, "wall_s": round(wall, 3),
+                   "prepared_operator": True, "prepare_ms": round(t_prep * 1e3, 3),
+                   "unprepared_ms_per_step": round(t_plain / args.steps * 1e3, 4),
                    "finite": bool(torch.isfinite(g).all().item())},
         "roofline": {"bound": "mfma", "achieved": round(tflops, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(tflops / FP32_PEAK_TFLOPS, 4), "traffic": None},

@@ -310,6 +310,49 @@ LFBP_API int64_t lfbp_grad_psf_workspace_size(lfbp_shape shape, int64_t R, int64
 LFBP_API lfbp_status lfbp_grad_psf_ws(const float* w, const float* g, lfbp_shape shape, int64_t R, int64_t C,
                                       float* dH, void* workspace, int64_t workspace_bytes, void* stream);
 
+/*
+ * Prepared operators.  The forward projection and the backprojection turn H
+ * and H' into packed operand records before their matrix products (about
+ * 0.35 ms each for a 165x165x15x15x21 PSF and a 600 x 600 image).  These
+ * records depend on the PSF and the image size only, so a loop that applies
+ * one PSF to many volumes or images -- the Richardson-Lucy iteration of Eq. 2,
+ * which uses H and H' unchanged in every update -- can pack them once into a
+ * caller buffer (the "operator") and pass it to the _op calls below.  Results
+ * are bit-identical to the unprepared calls.
+ *
+ * op        DEVICE buffer of lfbp_operator_size() bytes, 256-byte aligned,
+ *           owned by the caller; valid while H and H' are unchanged.
+ * workspace DEVICE buffer of lfbp_operator_workspace_size() bytes, 256-byte
+ *           aligned, for every _op call (one per stream at a time).
+ * Errors    EINVAL (NULL or short buffers, misaligned op or workspace),
+ *           ESHAPE, EALIGN, EALIAS (op, workspace, inputs and outputs must be
+ *           disjoint, except g_out == g in lfbp_rl_step_op), EDEVICE.  None
+ *           of these calls allocates.
+ */
+LFBP_API int64_t lfbp_operator_size(lfbp_shape shape, int64_t R, int64_t C);
+LFBP_API int64_t lfbp_operator_workspace_size(lfbp_shape shape, int64_t R, int64_t C);
+
+/* Pack H (forward) and H' (backward) into op. */
+LFBP_API lfbp_status lfbp_operator_prepare(const float* H, const float* Ht, lfbp_shape shape, int64_t R, int64_t C,
+                                           void* op, int64_t op_bytes, void* stream);
+
+/* lfbp_forward on a prepared operator: f [R][C] = H g, g [nz][R][C]. */
+LFBP_API lfbp_status lfbp_forward_op(const void* op, int64_t op_bytes, lfbp_shape shape, const float* g, int64_t R,
+                                     int64_t C, float* f, void* workspace, int64_t workspace_bytes, void* stream);
+
+/* lfbp_backward on a prepared operator: g [nz][R][C] = H' f, f [R][C]. */
+LFBP_API lfbp_status lfbp_backward_op(const void* op, int64_t op_bytes, lfbp_shape shape, const float* f, int64_t R,
+                                      int64_t C, float* g, void* workspace, int64_t workspace_bytes, void* stream);
+
+/* lfbp_rl_step on a prepared operator (Eq. 2); g_out may be g. */
+LFBP_API lfbp_status lfbp_rl_step_op(const void* op, int64_t op_bytes, lfbp_shape shape, const float* f, int64_t R,
+                                     int64_t C, const float* g, const float* norm, float* g_out, void* workspace,
+                                     int64_t workspace_bytes, void* stream);
+
+/* The Richardson-Lucy normaliser H'1 [nz][R][C] on a prepared operator. */
+LFBP_API lfbp_status lfbp_rl_norm_op(const void* op, int64_t op_bytes, lfbp_shape shape, int64_t R, int64_t C,
+                                     float* norm, void* workspace, int64_t workspace_bytes, void* stream);
+
 /* Static text for a status code (never NULL). */
 LFBP_API const char* lfbp_status_string(lfbp_status s);
 

@@ -26,7 +26,7 @@ from ._abi import (F16, F32, GATHER_AUTO, GATHER_DIRECT, GATHER_STAGED, GATHER_W
 __all__ = ["compute_Ht", "compute_Ht_into", "compute_Ht_inplace", "compute_Ht_colmajor", "compute_Ht_batched", "BatchedHt", "forward", "forward_workspace_size",
            "backward", "backward_workspace_size", "grad_psf", "grad_psf_workspace_size", "LFProject", "project",
            "rl_norm", "rl_step",
-           "rl_workspace_size", "richardson_lucy", "default_config", "GatherConfig", "LfbpError", "release_plans",
+           "rl_workspace_size", "richardson_lucy", "LFOperator", "default_config", "GatherConfig", "LfbpError", "release_plans",
            "version", "GATHER_AUTO", "GATHER_DIRECT", "GATHER_STAGED", "GATHER_WIDE"]
 
 _DTYPES = {torch.float32: F32, torch.float16: F16}
@@ -346,17 +346,99 @@ def rl_step(H: torch.Tensor, Ht: torch.Tensor, f: torch.Tensor, g: torch.Tensor,
     return out
 
 
+class LFOperator:
+    """H and H' packed once for R x C images (a prepared operator): forward
+    projections, backprojections and Richardson-Lucy updates on it skip the
+    per-call packing of the PSF and give bit-identical results.  The packed
+    records are copies: H and H' may be freed or changed afterwards (a changed
+    PSF needs a new operator).  One workspace serves every call, so calls on
+    one operator must not run concurrently on different streams."""
+
+    def __init__(self, H: torch.Tensor, R: int, C: int, Ht: torch.Tensor | None = None, stream=None):
+        _check_f32(H, "H", 5)
+        Ht = compute_Ht(H, stream=stream) if Ht is None else Ht
+        _check_f32(Ht, "Ht", 5)
+        if Ht.shape != H.shape:
+            raise ValueError("Ht must have the shape of H")
+        L = _abi.lib()
+        self.shape, self.R, self.C = tuple(H.shape), int(R), int(C)
+        self._s = Shape.of(self.shape)
+        nbytes = int(L.lfbp_operator_size(self._s, self.R, self.C))
+        wbytes = int(L.lfbp_operator_workspace_size(self._s, self.R, self.C))
+        if nbytes <= 0 or wbytes <= 0:
+            raise ValueError(f"shape {self.shape} with a {R} x {C} image is outside the projector's limits")
+        self.records = torch.empty(nbytes, dtype=torch.uint8, device=H.device)
+        self.workspace = torch.empty(wbytes, dtype=torch.uint8, device=H.device)
+        _abi.check(L.lfbp_operator_prepare(H.data_ptr(), Ht.data_ptr(), self._s, self.R, self.C,
+                                           self.records.data_ptr(), nbytes, _stream(stream)),
+                   "lfbp_operator_prepare")
+
+    def _op(self):
+        return self.records.data_ptr(), self.records.numel()
+
+    def _ws(self):
+        return self.workspace.data_ptr(), self.workspace.numel()
+
+    def _vol(self, name, t):
+        _check_f32(t, name, 3)
+        if tuple(t.shape) != (self.shape[4], self.R, self.C):
+            raise ValueError(f"{name} must be [nz, R, C] = {(self.shape[4], self.R, self.C)}")
+
+    def _img(self, name, t):
+        _check_f32(t, name, 2)
+        if tuple(t.shape) != (self.R, self.C):
+            raise ValueError(f"{name} must be [R, C] = {(self.R, self.C)}")
+
+    def forward(self, g: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """f = H g (Eq. 1)."""
+        self._vol("g", g)
+        out = torch.empty((self.R, self.C), dtype=torch.float32, device=g.device) if out is None else out
+        self._img("out", out)
+        _abi.check(_abi.lib().lfbp_forward_op(*self._op(), self._s, g.data_ptr(), self.R, self.C, out.data_ptr(),
+                                              *self._ws(), _stream(stream)), "lfbp_forward_op")
+        return out
+
+    def backward(self, f: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """g = H' f (the bracketed operator of Eq. 2)."""
+        self._img("f", f)
+        out = torch.empty((self.shape[4], self.R, self.C), dtype=torch.float32, device=f.device) if out is None else out
+        self._vol("out", out)
+        _abi.check(_abi.lib().lfbp_backward_op(*self._op(), self._s, f.data_ptr(), self.R, self.C, out.data_ptr(),
+                                               *self._ws(), _stream(stream)), "lfbp_backward_op")
+        return out
+
+    def rl_norm(self, stream=None) -> torch.Tensor:
+        """H' 1, the normaliser of the Richardson-Lucy update."""
+        norm = torch.empty((self.shape[4], self.R, self.C), dtype=torch.float32, device=self.records.device)
+        _abi.check(_abi.lib().lfbp_rl_norm_op(*self._op(), self._s, self.R, self.C, norm.data_ptr(), *self._ws(),
+                                              _stream(stream)), "lfbp_rl_norm_op")
+        return norm
+
+    def rl_step(self, f: torch.Tensor, g: torch.Tensor, norm: torch.Tensor, out: torch.Tensor | None = None,
+                stream=None) -> torch.Tensor:
+        """One Richardson-Lucy update (Eq. 2); out may be g itself."""
+        self._img("f", f)
+        self._vol("g", g)
+        self._vol("norm", norm)
+        out = torch.empty_like(g) if out is None else out
+        self._vol("out", out)
+        _abi.check(_abi.lib().lfbp_rl_step_op(*self._op(), self._s, f.data_ptr(), self.R, self.C, g.data_ptr(),
+                                              norm.data_ptr(), out.data_ptr(), *self._ws(), _stream(stream)),
+                   "lfbp_rl_step_op")
+        return out
+
+
 def richardson_lucy(H: torch.Tensor, f: torch.Tensor, iters: int, g0: torch.Tensor | None = None,
                     Ht: torch.Tensor | None = None) -> torch.Tensor:
     """iters Richardson-Lucy updates of a volume from the image f, starting
-    from g0 (default: ones); H' is built on the GPU when not given."""
-    Ht = compute_Ht(H) if Ht is None else Ht
+    from g0 (default: ones); H' is built on the GPU when not given.  H and H'
+    are packed once (LFOperator) for all the updates."""
     R, C = f.shape
-    ws = torch.empty(rl_workspace_size(H.shape, R, C), dtype=torch.uint8, device=f.device)
-    norm = rl_norm(Ht, R, C, workspace=ws)
+    op = LFOperator(H, R, C, Ht=Ht)
+    norm = op.rl_norm()
     g = torch.ones((H.shape[4], R, C), dtype=torch.float32, device=f.device) if g0 is None else g0.clone()
     for _ in range(iters):
-        rl_step(H, Ht, f, g, norm, out=g, workspace=ws)
+        op.rl_step(f, g, norm, out=g)
     return g
 
 

@@ -82,6 +82,13 @@ def lib():
             "lfbp_rl_norm_ws": (st, [vp, Shape, i64, i64, vp, vp, i64, vp]),
             "lfbp_grad_psf": (st, [vp, vp, Shape, i64, i64, vp, vp]),
             "lfbp_grad_psf_ws": (st, [vp, vp, Shape, i64, i64, vp, vp, i64, vp]),
+            "lfbp_operator_size": (i64, [Shape, i64, i64]),
+            "lfbp_operator_workspace_size": (i64, [Shape, i64, i64]),
+            "lfbp_operator_prepare": (st, [vp, vp, Shape, i64, i64, vp, i64, vp]),
+            "lfbp_forward_op": (st, [vp, i64, Shape, vp, i64, i64, vp, vp, i64, vp]),
+            "lfbp_backward_op": (st, [vp, i64, Shape, vp, i64, i64, vp, vp, i64, vp]),
+            "lfbp_rl_step_op": (st, [vp, i64, Shape, vp, i64, i64, vp, vp, vp, vp, i64, vp]),
+            "lfbp_rl_norm_op": (st, [vp, i64, Shape, i64, i64, vp, vp, i64, vp]),
             "lfbp_grad_psf_workspace_size": (i64, [Shape, i64, i64]),
             "lfbp_status_string": (ctypes.c_char_p, [st]),
             "lfbp_release_plans": (None, []),

@@ -892,8 +892,11 @@ size_t backward_workspace_bytes(const lfbp_shape& s, int64_t R, int64_t C)
 
 namespace {
 
+// Bpre: the B records of H already packed (a prepared operator), or null to
+// pack them into the workspace.  Workspace: g with depth innermost, the A
+// records, the B records unless prepared, the split partial tiles.
 hipError_t forward_impl(const float* H, const lfbp_shape& s, const float* gin, int64_t R, int64_t C,
-                        const float* fmeas, float* f, void* ws, hipStream_t stream)
+                        const float* fmeas, float* f, void* ws, const float* Bpre, hipStream_t stream)
 {
     const FwdPlan P = fwd_plan(s, R, C);
     const ProjGeom& g = P.g;
@@ -901,7 +904,7 @@ hipError_t forward_impl(const float* H, const lfbp_shape& s, const float* gin, i
     float* gT = reinterpret_cast<float*>(w);
     float* gS = reinterpret_cast<float*>(w + P.gT_bytes);
     float* Bp = reinterpret_cast<float*>(w + P.gT_bytes + P.gS_bytes);
-    float* part = reinterpret_cast<float*>(w + P.gT_bytes + P.gS_bytes + P.B_bytes);
+    float* part = reinterpret_cast<float*>(w + P.gT_bytes + P.gS_bytes + (Bpre ? 0 : P.B_bytes));
 
     PackArgs p = pack_args(g, P.N, P.Npad, P.Mpad, P.L.stages);
     p.nzc = P.L.nzc;
@@ -921,9 +924,13 @@ hipError_t forward_impl(const float* H, const lfbp_shape& s, const float* gin, i
     hipLaunchKernelGGL(k_pack_fwd_a, dim3(unsigned(P.N * P.L.nzc), blocks_for(int64_t(P.L.LRp) * P.L.LCp * kRecVec)),
                        dim3(256), 0, stream, gT, p, gS);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_pack_fwd_b, dim3(unsigned(P.L.stages), unsigned(P.ntiles)), dim3(kThreads), 0, stream, H, p,
-                       Bp);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (Bpre) {
+        Bp = const_cast<float*>(Bpre);
+    } else {
+        hipLaunchKernelGGL(k_pack_fwd_b, dim3(unsigned(P.L.stages), unsigned(P.ntiles)), dim3(kThreads), 0, stream, H,
+                           p, Bp);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
 
     GemmArgs a{};
     a.A = gS;
@@ -954,22 +961,27 @@ hipError_t forward_impl(const float* H, const lfbp_shape& s, const float* gin, i
     return hipGetLastError();
 }
 
+// Bpre: the B records of H' already packed, or null.  Workspace: the A
+// records, then the B records unless prepared.
 hipError_t backward_impl(const float* Ht, const lfbp_shape& s, const float* f, int64_t R, int64_t C,
-                         const float* gprev, const float* norm, float* g_out, void* ws, hipStream_t stream)
+                         const float* gprev, const float* norm, float* g_out, void* ws, const float* Bpre,
+                         hipStream_t stream)
 {
     const BwdPlan P = bwd_plan(s, R, C);
     const ProjGeom& g = P.g;
     char* w = static_cast<char*>(ws);
     float* Ap = reinterpret_cast<float*>(w);
-    float* Bp = reinterpret_cast<float*>(w + P.A_bytes);
+    float* Bp = Bpre ? const_cast<float*>(Bpre) : reinterpret_cast<float*>(w + P.A_bytes);
     const PackArgs p = pack_args(g, P.N, P.Npad, P.Mpad, P.stages);
     hipLaunchKernelGGL(k_pack_bwd_a, dim3(unsigned(P.stages), blocks_for(int64_t(P.Mpad) * kRecVec)), dim3(256), 0,
                        stream, f, p, Ap);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_pack_bwd_b, dim3(unsigned(P.stages), blocks_for(int64_t(P.Npad) * kRecVec)), dim3(256), 0,
-                       stream, Ht, p, Bp);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (!Bpre) {
+        hipLaunchKernelGGL(k_pack_bwd_b, dim3(unsigned(P.stages), blocks_for(int64_t(P.Npad) * kRecVec)), dim3(256),
+                           0, stream, Ht, p, Bp);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     GemmArgs a{};
     a.A = Ap;
     a.B = Bp;
@@ -996,13 +1008,13 @@ hipError_t backward_impl(const float* Ht, const lfbp_shape& s, const float* f, i
 hipError_t launch_forward_ws(const float* H, const lfbp_shape& s, const float* gin, int64_t R, int64_t C, float* f,
                              void* ws, hipStream_t stream)
 {
-    return forward_impl(H, s, gin, R, C, nullptr, f, ws, stream);
+    return forward_impl(H, s, gin, R, C, nullptr, f, ws, nullptr, stream);
 }
 
 hipError_t launch_backward_ws(const float* Ht, const lfbp_shape& s, const float* f, int64_t R, int64_t C, float* g,
                               void* ws, hipStream_t stream)
 {
-    return backward_impl(Ht, s, f, R, C, nullptr, nullptr, g, ws, stream);
+    return backward_impl(Ht, s, f, R, C, nullptr, nullptr, g, ws, nullptr, stream);
 }
 
 namespace {
@@ -1100,9 +1112,9 @@ hipError_t launch_rl_step_ws(const float* H, const float* Ht, const lfbp_shape& 
 {
     float* ratio = reinterpret_cast<float*>(
         static_cast<char*>(ws) + align256(std::max(forward_workspace_bytes(s, R, C), backward_workspace_bytes(s, R, C))));
-    hipError_t e = forward_impl(H, s, g, R, C, fmeas, ratio, ws, stream);
+    hipError_t e = forward_impl(H, s, g, R, C, fmeas, ratio, ws, nullptr, stream);
     if (e != hipSuccess) return e;
-    return backward_impl(Ht, s, ratio, R, C, g, norm, g_out, ws, stream);
+    return backward_impl(Ht, s, ratio, R, C, g, norm, g_out, ws, nullptr, stream);
 }
 
 namespace {
@@ -1125,7 +1137,7 @@ hipError_t launch_rl_norm_ws(const float* Ht, const lfbp_shape& s, int64_t R, in
     hipLaunchKernelGGL(k_fill, dim3(blocks_for(n)), dim3(256), 0, stream, ones, n, 1.0f);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return backward_impl(Ht, s, ones, R, C, nullptr, nullptr, norm, ws, stream);
+    return backward_impl(Ht, s, ones, R, C, nullptr, nullptr, norm, ws, nullptr, stream);
 }
 
 hipError_t launch_rl_step(const float* H, const float* Ht, const lfbp_shape& s, const float* fmeas, int64_t R,
@@ -1159,6 +1171,102 @@ hipError_t launch_backward(const float* Ht, const lfbp_shape& s, const float* f,
     e = launch_backward_ws(Ht, s, f, R, C, g, ws, stream);
     const hipError_t e2 = hipFreeAsync(ws, stream);
     return e != hipSuccess ? e : e2;
+}
+
+// ------------------------------------------------------- prepared operators
+
+// A prepared operator holds the B records of H (forward) and of H'
+// (backward), which depend on the PSF only, so that a loop over volumes and
+// images with one PSF (Richardson-Lucy, Eq. 2) packs them once.
+size_t operator_bytes(const lfbp_shape& s, int64_t R, int64_t C)
+{
+    return align256(fwd_plan(s, R, C).B_bytes) + align256(bwd_plan(s, R, C).B_bytes);
+}
+
+// Workspace of every call on a prepared operator (forward, backward, one
+// Richardson-Lucy update or its normaliser): the per-call records and, after
+// them, one image.
+size_t operator_workspace_bytes(const lfbp_shape& s, int64_t R, int64_t C)
+{
+    const FwdPlan F = fwd_plan(s, R, C);
+    const BwdPlan Bw = bwd_plan(s, R, C);
+    return align256(std::max(F.gT_bytes + F.gS_bytes + F.part_bytes, Bw.A_bytes)) +
+           align256(size_t(R) * size_t(C) * sizeof(float));
+}
+
+namespace {
+
+const float* op_fwd_b(const void* op) { return static_cast<const float*>(op); }
+
+const float* op_bwd_b(const void* op, const lfbp_shape& s, int64_t R, int64_t C)
+{
+    return reinterpret_cast<const float*>(static_cast<const char*>(op) + align256(fwd_plan(s, R, C).B_bytes));
+}
+
+float* op_image(void* ws, const lfbp_shape& s, int64_t R, int64_t C)
+{
+    const FwdPlan F = fwd_plan(s, R, C);
+    const BwdPlan Bw = bwd_plan(s, R, C);
+    return reinterpret_cast<float*>(static_cast<char*>(ws) +
+                                    align256(std::max(F.gT_bytes + F.gS_bytes + F.part_bytes, Bw.A_bytes)));
+}
+
+}  // namespace
+
+hipError_t launch_operator_prepare(const float* H, const float* Ht, const lfbp_shape& s, int64_t R, int64_t C,
+                                   void* op, hipStream_t stream)
+{
+    const FwdPlan F = fwd_plan(s, R, C);
+    PackArgs p = pack_args(F.g, F.N, F.Npad, F.Mpad, F.L.stages);
+    p.nzc = F.L.nzc;
+    p.LRp = F.L.LRp;
+    p.LCp = F.L.LCp;
+    p.padP = F.L.padP;
+    p.padQ = F.L.padQ;
+    p.fnzc = make_fastdiv(uint32_t(F.L.nzc));
+    p.fLCp = make_fastdiv(uint32_t(F.L.LCp));
+    p.cb = F.cb;
+    hipLaunchKernelGGL(k_pack_fwd_b, dim3(unsigned(F.L.stages), unsigned(F.ntiles)), dim3(kThreads), 0, stream, H, p,
+                       const_cast<float*>(op_fwd_b(op)));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const BwdPlan Bw = bwd_plan(s, R, C);
+    const PackArgs pb = pack_args(Bw.g, Bw.N, Bw.Npad, Bw.Mpad, Bw.stages);
+    hipLaunchKernelGGL(k_pack_bwd_b, dim3(unsigned(Bw.stages), blocks_for(int64_t(Bw.Npad) * kRecVec)), dim3(256), 0,
+                       stream, Ht, pb, const_cast<float*>(op_bwd_b(op, s, R, C)));
+    return hipGetLastError();
+}
+
+hipError_t launch_forward_op(const void* op, const lfbp_shape& s, const float* g, int64_t R, int64_t C, float* f,
+                             void* ws, hipStream_t stream)
+{
+    return forward_impl(nullptr, s, g, R, C, nullptr, f, ws, op_fwd_b(op), stream);
+}
+
+hipError_t launch_backward_op(const void* op, const lfbp_shape& s, const float* f, int64_t R, int64_t C, float* g,
+                              void* ws, hipStream_t stream)
+{
+    return backward_impl(nullptr, s, f, R, C, nullptr, nullptr, g, ws, op_bwd_b(op, s, R, C), stream);
+}
+
+hipError_t launch_rl_step_op(const void* op, const lfbp_shape& s, const float* fmeas, int64_t R, int64_t C,
+                             const float* g, const float* norm, float* g_out, void* ws, hipStream_t stream)
+{
+    float* ratio = op_image(ws, s, R, C);
+    hipError_t e = forward_impl(nullptr, s, g, R, C, fmeas, ratio, ws, op_fwd_b(op), stream);
+    if (e != hipSuccess) return e;
+    return backward_impl(nullptr, s, ratio, R, C, g, norm, g_out, ws, op_bwd_b(op, s, R, C), stream);
+}
+
+hipError_t launch_rl_norm_op(const void* op, const lfbp_shape& s, int64_t R, int64_t C, float* norm, void* ws,
+                             hipStream_t stream)
+{
+    float* ones = op_image(ws, s, R, C);
+    const int64_t n = R * C;
+    hipLaunchKernelGGL(k_fill, dim3(blocks_for(n)), dim3(256), 0, stream, ones, n, 1.0f);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return backward_impl(nullptr, s, ones, R, C, nullptr, nullptr, norm, ws, op_bwd_b(op, s, R, C), stream);
 }
 
 }  // namespace lfbp

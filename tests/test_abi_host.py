@@ -303,3 +303,39 @@ def test_colmajor_validation_before_launch():
     assert L.lfbp_compute_Ht_colmajor(P1, P2, Shape(3, 3, 2049, 1, 1), _abi.F16, None) == _abi.ESHAPE
     # nt * ny * nz * ns >= 2^31: at most one workgroup per position of every plane
     assert L.lfbp_compute_Ht_colmajor(P1, 1 << 44, Shape(4097, 3, 1, 1, 174763), _abi.F16, None) == _abi.ESHAPE
+
+
+def test_operator_validation_before_launch():
+    L = _abi.lib()
+    shape, R, C = GOOD, 30, 30
+    opb = L.lfbp_operator_size(shape, R, C)
+    wsb = L.lfbp_operator_workspace_size(shape, R, C)
+    assert opb > 0 and wsb > 0
+    assert L.lfbp_operator_size(Shape(4, 5, 3, 3, 1), R, C) == 0
+    assert L.lfbp_operator_workspace_size(shape, 0, C) == 0
+    # the operator holds both packed PSFs: more than either unprepared call's records
+    H, Ht, op, ws, g, f, n = 0x1000000, 0x2000000, 0x10000000, 0x20000000, 0x3000000, 0x4000000, 0x5000000
+    assert L.lfbp_operator_prepare(None, Ht, shape, R, C, op, opb, None) == _abi.EINVAL
+    assert L.lfbp_operator_prepare(H, Ht, shape, R, C, op, opb - 1, None) == _abi.EINVAL
+    assert L.lfbp_operator_prepare(H, Ht, shape, R, C, op + 16, opb, None) == _abi.EINVAL
+    assert L.lfbp_operator_prepare(H + 2, Ht, shape, R, C, op, opb, None) == _abi.EALIGN
+    assert L.lfbp_operator_prepare(H, Ht, shape, R, C, H - 256, opb, None) == _abi.EALIAS
+    assert L.lfbp_operator_prepare(H, Ht, Shape(15, 14, 3, 3, 3), R, C, op, opb, None) == _abi.ESHAPE
+    # calls on the operator
+    assert L.lfbp_forward_op(op, opb, shape, g, R, C, f, ws, wsb - 1, None) == _abi.EINVAL
+    assert L.lfbp_forward_op(op, opb, shape, g, R, C, f, None, wsb, None) == _abi.EINVAL
+    assert L.lfbp_forward_op(None, opb, shape, g, R, C, f, ws, wsb, None) == _abi.EINVAL
+    assert L.lfbp_forward_op(op, opb, shape, None, R, C, f, ws, wsb, None) == _abi.EINVAL
+    assert L.lfbp_forward_op(op, opb, shape, g + 2, R, C, f, ws, wsb, None) == _abi.EALIGN
+    assert L.lfbp_forward_op(op, opb, shape, g, R, C, g + 64, ws, wsb, None) == _abi.EALIAS     # f inside g
+    assert L.lfbp_forward_op(op, opb, shape, g, R, C, op + 64, ws, wsb, None) == _abi.EALIAS    # f inside op
+    assert L.lfbp_forward_op(op, opb, shape, g, R, C, f, op + 256, wsb, None) == _abi.EALIAS   # ws inside op
+    assert L.lfbp_forward_op(op, opb, shape, g, R, C, f, g - 256, wsb, None) == _abi.EALIAS    # ws over g
+    assert L.lfbp_backward_op(op, opb, shape, f, R, C, f + 64, ws, wsb, None) == _abi.EALIAS   # g over f
+    assert L.lfbp_backward_op(op, opb, Shape(15, 15, 3, 3, 3), f, 0, C, g, ws, wsb, None) == _abi.EINVAL
+    # Richardson-Lucy: g_out may be g, must not overlap anything else
+    assert L.lfbp_rl_step_op(op, opb, shape, f, R, C, g, n, n + 64, ws, wsb, None) == _abi.EALIAS
+    assert L.lfbp_rl_step_op(op, opb, shape, f, R, C, g, n, g + 64, ws, wsb, None) == _abi.EALIAS
+    assert L.lfbp_rl_step_op(op, opb, shape, f, R, C, g, n, g, g - 256, wsb, None) == _abi.EALIAS
+    assert L.lfbp_rl_norm_op(op, opb, shape, R, C, ws + 256, ws, wsb, None) == _abi.EALIAS
+    assert L.lfbp_rl_norm_op(op, opb, shape, R, C, None, ws, wsb, None) == _abi.EINVAL
