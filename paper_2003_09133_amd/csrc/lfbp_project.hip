@@ -335,7 +335,8 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2
     // a few stages of one another and share the A records.  Backward: the
     // reduction pairs with r + cx inside [0, ns) for some column of the
     // workgroup, a contiguous run of stages (columns are (cx, cy, z) with z
-    // fastest, so a workgroup spans few cx).  Other products: every stage.
+    // fastest, so a workgroup spans few cx).  Gradient with respect to H:
+    // every stage, or none for a tile none of whose entries is kept.
     int w_cnt = a.stages, w_base = 0, sr0 = 0, tc0 = 0, Rw = 1;
     if (kFwd) {
         const int b = ntile * (kNT / 64) + wave;
@@ -363,6 +364,15 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2
             w_base = klo / kStageK;
             w_cnt = (khi + kStageK - 1) / kStageK - w_base;
         }
+    }
+    if (kMode == kModeGradH) {
+        // rows (r, r2) of this tile and columns (x, y, z) of the workgroup: an
+        // entry is kept only when 0 <= r - x < ns, so a tile with no such pair
+        // has nothing to compute
+        const int rlo = m0 / g.Kc, rhi = min(m0 + kMT - 1, a.M - 1) / g.Kc;
+        const int nlo = ntile * kNT, nhi = min(nlo + kNT - 1, a.N - 1);
+        const int xlo = nlo / g.nz / g.ny, xhi = nhi / g.nz / g.ny;
+        if (m0 >= a.M || rhi < xlo || rlo - xhi > g.ns - 1) w_cnt = 0;
     }
     auto stage_of = [&](int i) -> int {
         if (!kFwd) return w_base + i;

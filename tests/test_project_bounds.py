@@ -389,6 +389,16 @@ def grad_mirror(shape, w, gv):
         Arec = read_records(Ap, s * kRecVec * Mpad, np.arange(Mpad), 2 * Mpad)
         Brec = read_records(Bp, s * kRecVec * Npad, np.arange(Npad), 2 * Npad)
         E += Arec[:, use] @ Brec[:, use].T
+    # k_gemm skips a tile (64 rows, the workgroup's 256 columns) with no pair
+    # 0 <= r - x < ns: its entries stay zero and none of them is kept below
+    for mt in range(mtiles):
+        for nt_ in range(ntiles):
+            m0, nlo = mt * kMT, nt_ * kNT
+            rlo, rhi = m0 // g['Kc'], min(m0 + kMT - 1, Mg - 1) // g['Kc']
+            nhi = min(nlo + kNT - 1, N - 1)
+            xlo, xhi = nlo // nz // ny, nhi // nz // ny
+            if m0 >= Mg or rhi < xlo or rlo - xhi > ns - 1:
+                E[m0:m0 + kMT, nlo:nlo + kNT] = 0.0
     # epilogue: (m, n) -> dH[r - x][r2 - y][x][y][z] when inside the patch
     dH = np.full(shape, np.nan)
     mm, nn = np.meshgrid(np.arange(Mg), np.arange(N), indexing='ij')
