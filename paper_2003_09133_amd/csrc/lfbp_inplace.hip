@@ -44,27 +44,18 @@ union Vec16 {
 };
 
 // Read the L contiguous elements H[g, g+L) (whole x-rows) into a tile, each
-// row rotated left by rot: aligned 16-byte loads, element loads only for a
-// vector that sticks out of the array.  Elements of the vectors outside the
-// segment belong to other rows and are dropped.
-template <typename T>
+// row rotated left by rot: aligned 16-byte loads, kBatch of them issued by
+// each thread before any is used; element loads only for a vector that
+// sticks out of the array (a segment at either end of H).  Elements of the
+// vectors outside the segment belong to other rows and are dropped.
+template <int kBatch, typename T>
 __device__ __forceinline__ void load_segment(const T* H, uint64_t E, uint32_t phase, uint64_t g, uint32_t L,
                                              uint32_t W, const FastDiv& fW, uint32_t rot, T* tile)
 {
     constexpr uint32_t VE = 16 / sizeof(T);
     const uint64_t u0 = (g + phase) / VE, u1 = (g + L + phase + VE - 1) / VE;
-    for (uint64_t u = u0 + threadIdx.x; u < u1; u += blockDim.x) {
-        const int64_t vg = int64_t(u * VE) - int64_t(phase);   // array index of the vector's first element
-        Vec16<T> p;
-        if (vg >= 0 && uint64_t(vg) + VE <= E) {
-            p.v = *reinterpret_cast<const u32x4*>(H + vg);
-        } else {
-#pragma unroll
-            for (uint32_t q = 0; q < VE; ++q) {
-                const int64_t i = vg + q;
-                p.e[q] = (i >= 0 && uint64_t(i) < E) ? H[i] : T(0);
-            }
-        }
+    const uint32_t nvec = uint32_t(u1 - u0);
+    auto put = [&](const Vec16<T>& p, int64_t vg) {
 #pragma unroll
         for (uint32_t q = 0; q < VE; ++q) {
             const int64_t e = vg + int64_t(q) - int64_t(g);
@@ -73,6 +64,38 @@ __device__ __forceinline__ void load_segment(const T* H, uint64_t E, uint32_t ph
                 tile[r * W + (j >= rot ? j - rot : j + W - rot)] = p.e[q];
             }
         }
+    };
+    if (u0 * VE >= phase && u1 * VE - phase <= E) {
+        // every vector lies inside H; lanes past the end reload the first
+        for (uint32_t i0 = threadIdx.x; i0 < nvec; i0 += kBatch * blockDim.x) {
+            Vec16<T> p[kBatch];
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                const uint32_t i = i0 + k * blockDim.x;
+                const int64_t vg = int64_t((u0 + (i < nvec ? i : 0)) * VE) - int64_t(phase);
+                p[k].v = *reinterpret_cast<const u32x4*>(H + vg);
+            }
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                const uint32_t i = i0 + k * blockDim.x;
+                if (i < nvec) put(p[k], int64_t((u0 + i) * VE) - int64_t(phase));
+            }
+        }
+        return;
+    }
+    for (uint32_t i = threadIdx.x; i < nvec; i += blockDim.x) {
+        const int64_t vg = int64_t((u0 + i) * VE) - int64_t(phase);   // array index of the vector's first element
+        Vec16<T> p;
+        if (vg >= 0 && uint64_t(vg) + VE <= E) {
+            p.v = *reinterpret_cast<const u32x4*>(H + vg);
+        } else {
+#pragma unroll
+            for (uint32_t q = 0; q < VE; ++q) {
+                const int64_t j = vg + q;
+                p.e[q] = (j >= 0 && uint64_t(j) < E) ? H[j] : T(0);
+            }
+        }
+        put(p, vg);
     }
 }
 
@@ -102,7 +125,7 @@ __device__ __forceinline__ void store_segment(T* H, uint32_t phase, uint64_t g, 
     }
 }
 
-template <typename T>
+template <typename T, int kBatch>
 __global__ void __launch_bounds__(256) k_inplace(InplaceDesc d)
 {
     extern __shared__ unsigned char smem_raw[];
@@ -129,9 +152,9 @@ __global__ void __launch_bounds__(256) k_inplace(InplaceDesc d)
     const uint32_t k1 = min(nr, d.nx - xb0);
     const uint64_t gO = (uint64_t(O) * d.nx + x0) * W;
     const uint64_t gP1 = (uint64_t(Op) * d.nx + xb0) * W, gP2 = uint64_t(Op) * d.nx * W;
-    load_segment(H, d.E, d.phase, gO, nr * W, W, d.fW, rotB, tileB);
-    load_segment(H, d.E, d.phase, gP1, k1 * W, W, d.fW, rotA, tileA);
-    if (nr > k1) load_segment(H, d.E, d.phase, gP2, (nr - k1) * W, W, d.fW, rotA, tileA + size_t(k1) * W);
+    load_segment<kBatch>(H, d.E, d.phase, gO, nr * W, W, d.fW, rotB, tileB);
+    load_segment<kBatch>(H, d.E, d.phase, gP1, k1 * W, W, d.fW, rotA, tileA);
+    if (nr > k1) load_segment<kBatch>(H, d.E, d.phase, gP2, (nr - k1) * W, W, d.fW, rotA, tileA + size_t(k1) * W);
     __syncthreads();  // every read of the pair precedes every write
     store_segment(H, d.phase, gO, nr * W, tileA);
     store_segment(H, d.phase, gP1, k1 * W, tileB);
@@ -142,11 +165,15 @@ __global__ void __launch_bounds__(256) k_inplace(InplaceDesc d)
 
 hipError_t set_inplace_smem_limits(int max_bytes)
 {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_inplace<uint32_t>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, max_bytes);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_inplace<uint16_t>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, max_bytes);
+    const void* kernels[] = {reinterpret_cast<const void*>(&k_inplace<uint32_t, 1>),
+                             reinterpret_cast<const void*>(&k_inplace<uint32_t, 4>),
+                             reinterpret_cast<const void*>(&k_inplace<uint16_t, 1>),
+                             reinterpret_cast<const void*>(&k_inplace<uint16_t, 4>)};
+    for (const void* k : kernels) {
+        const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, max_bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 // H <- H' in place; max_lds: dynamic LDS one workgroup may use.
@@ -184,10 +211,21 @@ hipError_t launch_inplace(void* H, const lfbp_shape& s, int esize, int max_lds, 
     const size_t lds = 2 * size_t(d.nr) * row_bytes;
     const uint64_t units = uint64_t(pairs) * d.groups;
     if (units >= (uint64_t(1) << 31)) return hipErrorInvalidValue;
-    if (esize == 4)
-        hipLaunchKernelGGL(k_inplace<uint32_t>, dim3(unsigned(units)), dim3(256), lds, stream, d);
-    else
-        hipLaunchKernelGGL(k_inplace<uint16_t>, dim3(unsigned(units)), dim3(256), lds, stream, d);
+    // loads in flight per thread: four for rows under 2 KB, one for longer
+    // rows (measured best on the microscope, camera and camera-f16 PSFs)
+    const bool batch = row_bytes < 2048;
+    const dim3 grid = dim3(static_cast<unsigned>(units)), block = dim3(256);
+    if (esize == 4) {
+        if (batch)
+            hipLaunchKernelGGL((k_inplace<uint32_t, 4>), grid, block, lds, stream, d);
+        else
+            hipLaunchKernelGGL((k_inplace<uint32_t, 1>), grid, block, lds, stream, d);
+    } else {
+        if (batch)
+            hipLaunchKernelGGL((k_inplace<uint16_t, 4>), grid, block, lds, stream, d);
+        else
+            hipLaunchKernelGGL((k_inplace<uint16_t, 1>), grid, block, lds, stream, d);
+    }
     return hipGetLastError();
 }
 
