@@ -34,11 +34,11 @@ struct ColDesc {
     uint32_t VR;             // 16-byte vectors per tile row, P / width
     uint32_t units;          // workgroups: nt * ny * nz * chunks
     uint32_t xstride;        // ns * nt: distance between x-rows
-    uint32_t dq_load, dr_load;   // workgroup size = dq_load * VR + dr_load
+    uint32_t dq_load, dr_load;   // kThreads = dq_load * VR + dr_load
     uint32_t dq_off;         // dq_load * xstride
     // per chunk kind [full chunk, last chunk]:
     uint32_t NF[2];          // whole output vectors every row holds
-    uint32_t dq_st[2], dr_st[2];   // workgroup size = dq_st * max(NF, 1) + dr_st
+    uint32_t dq_st[2], dr_st[2];   // kThreads = dq_st * max(NF, 1) + dr_st
     uint32_t du_st[2];       // (dr_st * width) mod nx
     uint32_t dnf_st[2];      // (NF * width) mod nx
     FastDiv fnt, fny, fnx, fchunks, fVR;
@@ -56,9 +56,7 @@ union Vec16 {
     T e[16 / sizeof(T)];
 };
 
-constexpr uint32_t kThreadsSmall = 256;    // workgroup size for tiles under kBigTile bytes
-constexpr uint32_t kThreadsBig = 1024;     // and for larger tiles (measured best on the Table 1 sizes)
-constexpr size_t kBigTile = 48 * 1024;
+constexpr uint32_t kThreads = 256;
 constexpr int kLoadBatch = 4;   // 16-byte loads each thread keeps in flight
 constexpr bool kXcdOrder = true;
 constexpr uint32_t kColXcds = 8;   // XCDs of the device
@@ -125,13 +123,13 @@ __device__ __forceinline__ UnitGeom unit_geom(const ColDesc& d, uint32_t unit)
 
 // Read a unit's tile for a unit at either end of H: vectors that stick out
 // of the array are read element by element.
-template <typename T, uint32_t NT>
+template <typename T>
 __device__ __forceinline__ void load_tile_edge(const ColDesc& d, const UnitGeom& g, T* tile)
 {
     constexpr uint32_t VE = 16 / sizeof(T);
     const T* H = static_cast<const T*>(d.H);
     const uint32_t xsm = d.xstride % VE;
-    for (uint32_t j = threadIdx.x; j < d.nx * d.VR; j += NT) {
+    for (uint32_t j = threadIdx.x; j < d.nx * d.VR; j += kThreads) {
         const uint32_t x = fdiv(j, d.fVR), v = j - x * d.VR;
         const uint32_t m = (g.cin + x * xsm) & (VE - 1);
         if (v * VE >= m + g.Sn) continue;
@@ -150,12 +148,12 @@ __device__ __forceinline__ void load_tile_edge(const ColDesc& d, const UnitGeom&
     }
 }
 
-// Issue the loads of kN of this thread's tile vectors, j = j0 + k * NT
+// Issue the loads of kN of this thread's tile vectors, j = j0 + k * kThreads
 // for k < kN, starting from (row x, vector v, x * xstride) = (x, v, xoff) of
 // j0 and stepping without divisions; slot[k] is the vector's tile index or
 // ~0 for none (such lanes read the aligned vector at the start of the first
 // piece again).  For units with g.safe.
-template <typename T, uint32_t NT, int kN>
+template <typename T, int kN>
 __device__ __forceinline__ void issue_loads(const ColDesc& d, const UnitGeom& g, uint32_t j0, uint32_t& x,
                                             uint32_t& v, uint32_t& xoff, u32x4 (&p)[kN], uint32_t (&slot)[kN])
 {
@@ -166,7 +164,7 @@ __device__ __forceinline__ void issue_loads(const ColDesc& d, const UnitGeom& g,
 #pragma unroll
     for (int k = 0; k < kN; ++k) {
         const uint32_t m = (g.cin + x * xsm) & (VE - 1);
-        const bool live = j0 + k * NT < total && v * VE < m + g.Sn;
+        const bool live = j0 + k * kThreads < total && v * VE < m + g.Sn;
         off[k] = live ? xoff + VE - m + v * VE : VE - g.cin;
         slot[k] = live ? x * d.P + v * VE : ~0u;
         v += d.dr_load;
@@ -196,11 +194,11 @@ __device__ __forceinline__ void commit_loads(T* tile, const u32x4 (&p)[kN], cons
 // x = (x' + a(s0 + kk)) mod nx at tile index R(x) - kk, and for the VE
 // elements kk = k0 + q of one output vector, with x_q = x_0 + q (unreduced),
 // that is rt[x_0 + q] + x_0 - k0.
-template <uint32_t VE, uint32_t NT>
+template <uint32_t VE>
 __device__ __forceinline__ void build_row_table(const ColDesc& d, const UnitGeom& g, int32_t* rt)
 {
     const uint32_t xsm = d.xstride % VE;
-    for (uint32_t i = threadIdx.x; i < d.nx + VE - 1; i += NT) {
+    for (uint32_t i = threadIdx.x; i < d.nx + VE - 1; i += kThreads) {
         const uint32_t x = i - fdiv(i, d.fnx) * d.nx;
         rt[i] = int32_t(x * d.P + ((g.cin + x * xsm) & (VE - 1)) + g.Sn - 1) - int32_t(i);
     }
@@ -211,7 +209,7 @@ __device__ __forceinline__ void build_row_table(const ColDesc& d, const UnitGeom
 // vectors start at kk = kA, the first kk whose address is aligned, and the
 // L = Sn - NF * VE elements outside them (kk < kA, kk >= kA + NF * VE) are
 // written one by one.
-template <typename T, uint32_t NT>
+template <typename T>
 __device__ __forceinline__ void store_tile(const ColDesc& d, const UnitGeom& g, const T* tile, const int32_t* rt)
 {
     constexpr uint32_t VE = 16 / sizeof(T);
@@ -220,7 +218,7 @@ __device__ __forceinline__ void store_tile(const ColDesc& d, const UnitGeom& g, 
     T* Ob = static_cast<T*>(d.Ht) + (g.out0 + g.s0);
     const uint32_t nvec = d.nx * NF;
     if (threadIdx.x < nvec) {
-        // this thread's vectors j = threadIdx.x + i * NT, as (row x',
+        // this thread's vectors j = threadIdx.x + i * kThreads, as (row x',
         // vector f), and u = (s0 + a_off + f * VE) mod nx, stepped without
         // divisions
         uint32_t xp = fdiv(threadIdx.x, d.fNF[g.last]), f = threadIdx.x - xp * NF;
@@ -229,7 +227,7 @@ __device__ __forceinline__ void store_tile(const ColDesc& d, const UnitGeom& g, 
         u -= fdiv(u, d.fnx) * d.nx;
         const uint32_t dq = d.dq_st[g.last], dr = d.dr_st[g.last], du = d.du_st[g.last], dnf = d.dnf_st[g.last];
         const uint32_t dq_off = dq * d.xstride;
-        for (uint32_t j = threadIdx.x; j < nvec; j += NT) {
+        for (uint32_t j = threadIdx.x; j < nvec; j += kThreads) {
             const uint32_t mo = (g.cout + xp * xsm) & (VE - 1);
             const uint32_t kA = (VE - mo) & (VE - 1);
             const uint32_t k0 = kA + f * VE;
@@ -261,7 +259,7 @@ __device__ __forceinline__ void store_tile(const ColDesc& d, const UnitGeom& g, 
         }
     }
     const uint32_t L = g.Sn - NF * VE;
-    for (uint32_t j = threadIdx.x; j < d.nx * L; j += NT) {
+    for (uint32_t j = threadIdx.x; j < d.nx * L; j += kThreads) {
         const uint32_t xp = fdiv(j, d.fL[g.last]), i = j - xp * L;
         const uint32_t mo = (g.cout + xp * xsm) & (VE - 1);
         const uint32_t kA = (VE - mo) & (VE - 1);
@@ -278,8 +276,8 @@ __device__ __forceinline__ void store_tile(const ColDesc& d, const UnitGeom& g, 
 // so that every aligned 16-byte vector of H that overlaps the piece lands on
 // an aligned 16-byte slot of the tile (elements of it outside the piece land
 // in the row's slack and are never read).  Serves every tile size.
-template <typename T, uint32_t NT>
-__global__ void __launch_bounds__(NT) k_colmajor(ColDesc d)
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_colmajor(ColDesc d)
 {
     constexpr uint32_t VE = 16 / sizeof(T);
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
@@ -289,18 +287,18 @@ __global__ void __launch_bounds__(NT) k_colmajor(ColDesc d)
     if (g.safe) {
         uint32_t x = fdiv(threadIdx.x, d.fVR), v = threadIdx.x - x * d.VR;
         uint32_t xoff = x * d.xstride;
-        for (uint32_t j0 = threadIdx.x; j0 < d.nx * d.VR; j0 += kLoadBatch * NT) {
+        for (uint32_t j0 = threadIdx.x; j0 < d.nx * d.VR; j0 += kLoadBatch * kThreads) {
             u32x4 p[kLoadBatch];
             uint32_t slot[kLoadBatch];
-            issue_loads<T, NT, kLoadBatch>(d, g, j0, x, v, xoff, p, slot);
+            issue_loads<T, kLoadBatch>(d, g, j0, x, v, xoff, p, slot);
             commit_loads<T, kLoadBatch>(tile, p, slot);
         }
     } else {
-        load_tile_edge<T, NT>(d, g, tile);
+        load_tile_edge(d, g, tile);
     }
-    build_row_table<VE, NT>(d, g, rt);
+    build_row_table<VE>(d, g, rt);
     lds_barrier();
-    store_tile<T, NT>(d, g, tile, rt);
+    store_tile(d, g, tile, rt);
 }
 
 constexpr int kColTileBudget = 96 * 1024;   // LDS per workgroup when the plane allows
@@ -315,10 +313,8 @@ inline uint64_t row_table_bytes(uint32_t nx, uint32_t VE)
 
 hipError_t set_colmajor_smem_limits(int max_bytes)
 {
-    const void* kernels[] = {reinterpret_cast<const void*>(&k_colmajor<uint32_t, kThreadsSmall>),
-                             reinterpret_cast<const void*>(&k_colmajor<uint16_t, kThreadsSmall>),
-                             reinterpret_cast<const void*>(&k_colmajor<uint32_t, kThreadsBig>),
-                             reinterpret_cast<const void*>(&k_colmajor<uint16_t, kThreadsBig>)};
+    const void* kernels[] = {reinterpret_cast<const void*>(&k_colmajor<uint32_t>),
+                             reinterpret_cast<const void*>(&k_colmajor<uint16_t>)};
     for (const void* k : kernels) {
         const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, max_bytes);
         if (e != hipSuccess) return e;
@@ -367,11 +363,8 @@ hipError_t launch_colmajor(const void* H, void* Ht, const lfbp_shape& s, int esi
     d.fchunks = make_fastdiv(d.chunks);
     d.fVR = make_fastdiv(d.VR);
     d.xstride = d.ns * d.nt;
-    const size_t lds = size_t(d.nx) * d.P * uint32_t(esize) + row_table_bytes(d.nx, VE);
-    if (lds > size_t(max_lds)) return hipErrorInvalidValue;
-    const uint32_t NT = lds >= kBigTile ? kThreadsBig : kThreadsSmall;
-    d.dq_load = NT / d.VR;
-    d.dr_load = NT % d.VR;
+    d.dq_load = kThreads / d.VR;
+    d.dr_load = kThreads % d.VR;
     d.dq_off = d.dq_load * d.xstride;
     // whole output vectors per row: at least floor((Sn - VE + 1) / VE) in
     // every row, whatever its alignment
@@ -380,8 +373,8 @@ hipError_t launch_colmajor(const void* H, void* Ht, const lfbp_shape& s, int esi
         const uint32_t Sn = i == 0 ? d.S : Sl;
         d.NF[i] = Sn >= VE - 1 ? (Sn - (VE - 1)) / VE : 0;
         const uint32_t nf1 = std::max(d.NF[i], 1u);
-        d.dq_st[i] = NT / nf1;
-        d.dr_st[i] = NT % nf1;
+        d.dq_st[i] = kThreads / nf1;
+        d.dr_st[i] = kThreads % nf1;
         d.du_st[i] = uint32_t((uint64_t(d.dr_st[i]) * VE) % d.nx);
         d.dnf_st[i] = uint32_t((uint64_t(d.NF[i]) * VE) % d.nx);
         d.fNF[i] = make_fastdiv(nf1);
@@ -390,17 +383,12 @@ hipError_t launch_colmajor(const void* H, void* Ht, const lfbp_shape& s, int esi
     const uint64_t units = uint64_t(d.nt) * d.ny * d.nz * d.chunks;
     if (units >= (uint64_t(1) << 31)) return hipErrorInvalidValue;
     d.units = uint32_t(units);
-    const dim3 grid = dim3(static_cast<unsigned>(units)), block = dim3(NT);
-    if (NT == kThreadsBig) {
-        if (esize == 4)
-            hipLaunchKernelGGL((k_colmajor<uint32_t, kThreadsBig>), grid, block, lds, stream, d);
-        else
-            hipLaunchKernelGGL((k_colmajor<uint16_t, kThreadsBig>), grid, block, lds, stream, d);
+    const size_t lds = size_t(d.nx) * d.P * uint32_t(esize) + row_table_bytes(d.nx, VE);
+    if (lds > size_t(max_lds)) return hipErrorInvalidValue;
+    if (esize == 4) {
+        hipLaunchKernelGGL(k_colmajor<uint32_t>, dim3(unsigned(units)), dim3(kThreads), lds, stream, d);
     } else {
-        if (esize == 4)
-            hipLaunchKernelGGL((k_colmajor<uint32_t, kThreadsSmall>), grid, block, lds, stream, d);
-        else
-            hipLaunchKernelGGL((k_colmajor<uint16_t, kThreadsSmall>), grid, block, lds, stream, d);
+        hipLaunchKernelGGL(k_colmajor<uint16_t>, dim3(unsigned(units)), dim3(kThreads), lds, stream, d);
     }
     return hipGetLastError();
 }

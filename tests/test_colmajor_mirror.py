@@ -38,18 +38,15 @@ def launch_params(shape, esize, max_lds=160 * 1024, tile_budget=96 * 1024):
     return VE, S, chunks, P
 
 
-def threads_for(nx, P, esize, VE):
-    """Workgroup size: 1024 for tiles (with the row table) of 48 KB or more."""
-    return 1024 if nx * P * esize + row_table_bytes(nx, VE) >= 48 * 1024 else 256
+THREADS = 256
 
 
-def colmajor_mirror(Hc, shape, phase_in=0, phase_out=0, threads=None, **kw):
+def colmajor_mirror(Hc, shape, phase_in=0, phase_out=0, **kw):
     """Hc: flat column-major H.  phase_*: misalignment (in elements) of the
     arrays' first element against 16 bytes, as the kernel sees it."""
     ns, nt, nx, ny, nz = shape
     esize = Hc.dtype.itemsize
     VE, S, chunks, P = launch_params(shape, esize, **kw)
-    THREADS = threads or threads_for(nx, P, esize, VE)
     VR = P // VE
     E = Hc.size
     hs, ht = (ns - 1) // 2, (nt - 1) // 2
@@ -192,9 +189,8 @@ def test_colmajor_mirror_equals_oracle(shape, dtype, budget):
     kw = {} if budget else {"tile_budget": 1, "max_lds": shape[2] * 16 * 2 + row_table_bytes(shape[2], 16 // H.itemsize)}
     ref = to_colmajor(oracle.Ht_rows(H))
     for ph in ((0, 0), (1, 3), (3, 2)):
-        for threads in (None, 256, 1024):      # the launch's choice, and both sizes
-            got = colmajor_mirror(to_colmajor(H), shape, *ph, threads=threads, **kw)
-            assert np.array_equal(got.view(np.uint8), ref.view(np.uint8)), (ph, threads)
+        got = colmajor_mirror(to_colmajor(H), shape, *ph, **kw)
+        assert np.array_equal(got.view(np.uint8), ref.view(np.uint8)), ph
 
 
 def test_wide_cells_take_the_whole_lds():
