@@ -68,6 +68,28 @@ def projector_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
+def inplace_source_sha() -> str:
+    """Digest of the in-place kernel and its launch code."""
+    h = hashlib.sha256()
+    for f in ("csrc/lfbp_inplace.hip", "csrc/lfbp_internal.h"):
+        with open(os.path.join(ROOT, "paper_2003_09133_amd", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def inplace_traffic(workload: str):
+    """HBM bytes of one in-place launch from the committed counter summary, if
+    it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"inplace_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("kernel_source_sha") != inplace_source_sha():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
 def colmajor_source_sha() -> str:
     """Digest of the column-major kernel and its launch code."""
     h = hashlib.sha256()
@@ -194,7 +216,8 @@ def bench_plain(args, torch):
                               "k_inplace (H' over H)" if args.inplace else resolved), "wall_s": round(wall, 3)},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs / HBM_PEAK_GBS, 4),
-                     "traffic": None if (args.inplace or args.copy) else traffic_from_profile(args.workload)},
+                     "traffic": (None if args.copy else inplace_traffic(args.workload) if args.inplace
+                                 else traffic_from_profile(args.workload))},
     }
     if not args.no_cpu_baseline and not args.copy and not args.inplace:
         nth = cores_used()
