@@ -8,7 +8,7 @@ import torch
 import lfsynth
 import oracle
 import paper_2003_09133_amd as lf
-from gpu_util import DEV, to_dev
+from gpu_util import DEV, gpu_equal_bits, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -139,6 +139,10 @@ def test_projector_workload_full_size_sampled():
                                            rng.integers(0, R, 1500), rng.integers(0, C, 1500)]),
                           np.array([(0, 0, 0), (20, R - 1, C - 1), (10, 0, C - 1)])])
     assert rel_l2(fbn[vox[:, 0], vox[:, 1], vox[:, 2]], oracle.backward_at(H, fn, vox)) <= TOL
+    # the prepared operator the benchmark times gives the same bits
+    op = lf.LFOperator(dH, R, C, Ht=dHt)
+    assert gpu_equal_bits(op.forward(to_dev(g)), f)
+    assert gpu_equal_bits(op.backward(f), fb)
 
 
 def test_without_workspace_uses_stream_allocator():
