@@ -72,7 +72,7 @@ constexpr int kHalf = 11;            // MFMA steps per stage (two reduction indi
 constexpr int kStageK = 2 * kHalf;   // reduction indices per stage
 constexpr int kRec = 24;             // floats per record (halves at 0 and 12)
 constexpr int kRecVec = kRec / 4;    // 16-byte vectors per record (3 per half)
-constexpr int kFold = 16;            // stages between folds of the MFMA accumulators
+constexpr int kFold = 32;            // stages between folds of the MFMA accumulators
 constexpr int kXcds = 8;
 constexpr int kTargetBlocks = 512;
 
