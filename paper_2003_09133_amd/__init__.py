@@ -407,6 +407,12 @@ class LFOperator:
                                                *self._ws(), _stream(stream)), "lfbp_backward_op")
         return out
 
+    def project(self, g: torch.Tensor) -> torch.Tensor:
+        """Differentiable f = H g on the operator: the gradient with respect
+        to g is the backprojection of the output gradient (H is fixed here;
+        use project() for a gradient with respect to H)."""
+        return _LFOpProject.apply(g, self)
+
     def rl_norm(self, stream=None) -> torch.Tensor:
         """H' 1, the normaliser of the Richardson-Lucy update."""
         norm = torch.empty((self.shape[4], self.R, self.C), dtype=torch.float32, device=self.records.device)
@@ -426,6 +432,19 @@ class LFOperator:
                                               norm.data_ptr(), out.data_ptr(), *self._ws(), _stream(stream)),
                    "lfbp_rl_step_op")
         return out
+
+
+class _LFOpProject(torch.autograd.Function):
+    """f = H g on a prepared operator, with g_grad = H' f_grad."""
+
+    @staticmethod
+    def forward(ctx, g, op):
+        ctx.op = op
+        return op.forward(g.contiguous())
+
+    @staticmethod
+    def backward(ctx, grad_f):
+        return ctx.op.backward(grad_f.contiguous()), None
 
 
 def richardson_lucy(H: torch.Tensor, f: torch.Tensor, iters: int, g0: torch.Tensor | None = None,

@@ -75,3 +75,18 @@ def test_operator_rejects_mismatched_tensors():
         op.forward(torch.zeros((shape[4], R, C + 1), device=DEV))
     with pytest.raises(ValueError):
         op.backward(torch.zeros((R + 1, C), device=DEV))
+
+
+def test_operator_projection_is_differentiable():
+    """LFOperator.project: the gradient with respect to g is the
+    backprojection of the output gradient, bit for bit."""
+    shape, R, C = (15, 15, 3, 3, 3), 21, 21
+    dH = to_dev(lfsynth.uniform_f32(shape, 66))
+    dHt = lf.compute_Ht(dH)
+    op = lf.LFOperator(dH, R, C, Ht=dHt)
+    g = to_dev(lfsynth.uniform_f32((shape[4], R, C), 67)).requires_grad_(True)
+    w = to_dev(lfsynth.uniform_f32((R, C), 68))
+    f = op.project(g)
+    assert gpu_equal_bits(f.detach(), lf.forward(dH, g.detach()))
+    (f * w).sum().backward()
+    assert gpu_equal_bits(g.grad, lf.backward(dHt, w))
