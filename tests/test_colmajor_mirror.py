@@ -211,19 +211,3 @@ def test_xcd_order_is_a_permutation(units):
     x, q, r = bid % 8, units // 8, units % 8
     unit = x * q + np.minimum(x, r) + bid // 8
     assert np.array_equal(np.sort(unit), bid)
-
-
-@pytest.mark.parametrize("units,grid", [(1, 8), (7, 8), (9, 8), (100, 16), (10769, 1024), (344542, 1024),
-                                        (20, 64)])
-def test_persistent_walk_covers_every_unit_once(units, grid):
-    """k_colmajor_pipe: workgroup b serves XCD b mod 8; the XCD's workgroups
-    walk its contiguous run of units with stride grid / 8."""
-    seen = np.zeros(units, np.int64)
-    q, r = units // 8, units % 8
-    per = grid // 8
-    for b in range(grid):
-        xcd, lid = b % 8, b // 8
-        beg = xcd * q + min(xcd, r)
-        end = beg + q + (1 if xcd < r else 0)
-        seen[np.arange(beg + lid, end, per)] += 1
-    assert np.all(seen == 1)
