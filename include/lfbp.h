@@ -128,10 +128,14 @@ typedef struct {
  *
  * problems  HOST array of `count` descriptors (copied; may be freed on return).
  * Ownership The library keeps a plan per distinct problem table (device
- *           descriptor table plus a captured hipGraph of the launch), reused
- *           when the same table is submitted again; lfbp_release_plans()
- *           frees all plans.  A plan is created on first use (hipMalloc,
- *           stream capture), so the first call with a new table allocates.
+ *           descriptor table and launch parameters), reused when the same
+ *           table is submitted again; lfbp_release_plans() frees all plans.
+ *           A plan is created on first use (hipMalloc), so the first call
+ *           with a new table allocates; later calls launch the persistent
+ *           kernel directly and allocate nothing (the launch may itself be
+ *           captured into a caller's graph).  lfbp_compute_Ht_batched_config
+ *           with use_graph = 1 keeps the launch in a captured hipGraph
+ *           instead and replays it.
  * Errors    EINVAL (problems NULL, count <= 0, or any pointer NULL), ESHAPE,
  *           EDTYPE, EALIGN, EALIAS (any input overlapping any output) -- all
  *           checked before anything is launched; ENOMEM, EDEVICE.
@@ -168,8 +172,9 @@ LFBP_API lfbp_status lfbp_compute_Ht_colmajor(const void* H, void* Ht, lfbp_shap
                                               void* stream);
 
 /* Same as lfbp_compute_Ht_batched with an explicit kernel choice shared by
- * every problem, and graph use: use_graph = 1 replays a captured graph,
- * 0 launches the kernel directly.  cfg may be NULL. */
+ * every problem, and graph use: use_graph = 1 captures the launch into a
+ * hipGraph when the plan is made and replays it on every call, 0 launches the
+ * kernel directly (what lfbp_compute_Ht_batched does).  cfg may be NULL. */
 LFBP_API lfbp_status lfbp_compute_Ht_batched_config(const lfbp_problem* problems, int32_t count, lfbp_dtype dtype,
                                            const lfbp_gather_config* cfg, int32_t use_graph, void* stream);
 

@@ -124,9 +124,10 @@ def compute_Ht_colmajor(H: torch.Tensor, out=None, stream=None) -> torch.Tensor:
     return out
 
 
-def compute_Ht_batched(Hs, outs=None, config=None, use_graph: bool = True, stream=None):
+def compute_Ht_batched(Hs, outs=None, config=None, use_graph: bool = False, stream=None):
     """H' of every tensor in Hs with one persistent kernel launch (replayed
-    from a captured hipGraph when use_graph).  All tensors share one dtype."""
+    from a hipGraph captured with the plan when use_graph).  All tensors share
+    one dtype."""
     Hs = list(Hs)
     if not Hs:
         raise ValueError("empty batch")
@@ -145,7 +146,7 @@ def compute_Ht_batched(Hs, outs=None, config=None, use_graph: bool = True, strea
                                   for H, o in zip(Hs, outs)])
     cfg = _config(config)
     L = _abi.lib()
-    if cfg is None and use_graph:
+    if cfg is None and not use_graph:
         st = L.lfbp_compute_Ht_batched(probs, len(Hs), _DTYPES[Hs[0].dtype], _stream(stream))
     else:
         st = L.lfbp_compute_Ht_batched_config(probs, len(Hs), _DTYPES[Hs[0].dtype],
@@ -158,9 +159,10 @@ def compute_Ht_batched(Hs, outs=None, config=None, use_graph: bool = True, strea
 class BatchedHt:
     """A batch prepared once: the tensors are checked and the problem table is
     built here, so that each call costs one C call (for repeated H' builds of
-    the same buffers, e.g. in a loop that refreshes the PSFs in place)."""
+    the same buffers, e.g. in a loop that refreshes the PSFs in place).
+    use_graph: replay the launch from a hipGraph captured with the plan."""
 
-    def __init__(self, Hs, outs=None):
+    def __init__(self, Hs, outs=None, use_graph: bool = False):
         self.Hs = list(Hs)
         if not self.Hs:
             raise ValueError("empty batch")
@@ -178,9 +180,11 @@ class BatchedHt:
         self._probs = (Problem * len(self.Hs))(*[Problem(H.data_ptr(), o.data_ptr(), Shape.of(H.shape))
                                                  for H, o in zip(self.Hs, self.outs)])
         self._dtype = _DTYPES[self.Hs[0].dtype]
+        self._graph = 1 if use_graph else 0
 
     def __call__(self, stream=None):
-        _abi.check(_abi.lib().lfbp_compute_Ht_batched(self._probs, len(self.Hs), self._dtype, _stream(stream)),
+        _abi.check(_abi.lib().lfbp_compute_Ht_batched_config(self._probs, len(self.Hs), self._dtype, None,
+                                                             self._graph, _stream(stream)),
                    "lfbp_compute_Ht_batched")
         return self.outs
 

@@ -459,7 +459,9 @@ lfbp_status lfbp_compute_Ht_batched_config(const lfbp_problem* problems, int32_t
 
 lfbp_status lfbp_compute_Ht_batched(const lfbp_problem* problems, int32_t count, lfbp_dtype dtype, void* stream)
 {
-    return lfbp_compute_Ht_batched_config(problems, count, dtype, nullptr, 1, stream);
+    // a direct launch: replaying the plan's one-kernel graph costs more host
+    // time per call than launching the kernel (measured on small tables)
+    return lfbp_compute_Ht_batched_config(problems, count, dtype, nullptr, 0, stream);
 }
 
 lfbp_status lfbp_compute_Ht_inplace(void* H, lfbp_shape shape, lfbp_dtype dtype, void* stream)

@@ -58,16 +58,55 @@ def test_graph_replays_follow_new_data():
         hs = [lfsynth.bits(s, 1000 * rep + i, np.float32) for i, s in enumerate(shapes)]
         for d, h in zip(dHs, hs):
             d.copy_(torch.from_numpy(h))
-        lf.compute_Ht_batched(dHs, outs)
+        lf.compute_Ht_batched(dHs, outs, use_graph=True)
         scratch.add_(1.0)                                  # eager work between replays
         torch.cuda.synchronize()
         for o, h in zip(outs, hs):
             assert_same_bits(o.cpu().numpy(), oracle.Ht_rows(h), f"replay {rep}")
         lf.compute_Ht(dHs[0])                              # plain calls interleaved
     lf.release_plans()
-    lf.compute_Ht_batched(dHs, outs)
+    lf.compute_Ht_batched(dHs, outs, use_graph=True)
     torch.cuda.synchronize()
     assert_same_bits(outs[1].cpu().numpy(), oracle.Ht_rows(hs[1]), "after release")
+
+
+def test_plain_and_batched_calls_replay_in_a_caller_graph():
+    """Plain calls and a batched call without its own graph, captured by the
+    caller into one torch CUDA graph: the calls allocate nothing and record
+    no memset, so every replay, with eager overwrites of the inputs and
+    outputs and synchronisations between replays, gives the oracle's H'."""
+    from paper_2003_09133_amd import _abi
+    shapes = [(21, 21, 7, 7, 5), (33, 27, 11, 9, 3), (15, 15, 3, 3, 11), (45, 39, 9, 7, 13)]
+    dHs = [torch.empty(s, dtype=torch.float32, device=DEV) for s in shapes]
+    plain_out = [torch.empty_like(h) for h in dHs]
+    batch_out = [torch.empty_like(h) for h in dHs]
+    L = _abi.lib()
+    probs = (_abi.Problem * len(shapes))(*[_abi.Problem(h.data_ptr(), o.data_ptr(), _abi.Shape.of(h.shape))
+                                           for h, o in zip(dHs, batch_out)])
+
+    def calls(stream):
+        for h, o in zip(dHs, plain_out):
+            assert L.lfbp_compute_Ht(h.data_ptr(), o.data_ptr(), _abi.Shape.of(h.shape), _abi.F32, stream) == 0
+        assert L.lfbp_compute_Ht_batched_config(probs, len(shapes), _abi.F32, None, 0, stream) == 0
+
+    calls(torch.cuda.current_stream().cuda_stream)       # builds the batched plan before the capture
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        calls(torch.cuda.current_stream().cuda_stream)
+    for rep in range(3):
+        hs = [lfsynth.bits(s, 500 * rep + i, np.float32) for i, s in enumerate(shapes)]
+        for d, h in zip(dHs, hs):
+            d.copy_(torch.from_numpy(h))
+        for o in plain_out + batch_out:
+            o.fill_(float("nan"))
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for i, h in enumerate(hs):
+            ref = oracle.Ht_rows(h)
+            assert_same_bits(plain_out[i].cpu().numpy(), ref, f"replay {rep} plain set {i}")
+            assert_same_bits(batch_out[i].cpu().numpy(), ref, f"replay {rep} batched set {i}")
 
 
 def test_batch_rejects_mixed_dtypes_and_overlap():
@@ -121,16 +160,16 @@ def test_batch_beyond_inline_descriptors(n):
 
 def test_small_set_batch_full_compare():
     """The 64-set batch of small PSFs (launch overhead comparable with the
-    work): every set against the oracle, whole arrays, in one graph launch."""
+    work): every set against the oracle, whole arrays, in one launch."""
     Hs = [lfsynth.make_H(w)[0] for w in lfsynth.SMALL_SETS]
     dHs = [to_dev(H) for H in Hs]
     outs = lf.compute_Ht_batched(dHs)
     torch.cuda.synchronize()
     for w, o, H in zip(lfsynth.SMALL_SETS, outs, Hs):
         assert_same_bits(o.cpu().numpy(), oracle.Ht_rows(H), f"{w.name} {w.shape}")
-    # the prepared form, called again after the PSFs are refreshed in place
-    prepared = lf.BatchedHt(dHs)
-    for rep in range(2):
+    # the prepared form (direct launch, then graph replay), called again after
+    # the PSFs are refreshed in place
+    for rep, prepared in enumerate((lf.BatchedHt(dHs), lf.BatchedHt(dHs, use_graph=True))):
         new = [lfsynth.bits(w.shape, 50 * rep + i, np.float32) for i, w in enumerate(lfsynth.SMALL_SETS)]
         for d, h in zip(dHs, new):
             d.copy_(torch.from_numpy(h))
