@@ -133,7 +133,8 @@ typedef struct {
  *           A plan is created on first use (hipMalloc), so the first call
  *           with a new table allocates; later calls launch the persistent
  *           kernel directly and allocate nothing (the launch may itself be
- *           captured into a caller's graph).  lfbp_compute_Ht_batched_config
+ *           captured into a caller's graph, which then depends on the plan:
+ *           see lfbp_release_plans).  lfbp_compute_Ht_batched_config
  *           with use_graph = 1 keeps the launch in a captured hipGraph
  *           instead and replays it.
  * Errors    EINVAL (problems NULL, count <= 0, or any pointer NULL), ESHAPE,
@@ -362,7 +363,10 @@ LFBP_API lfbp_status lfbp_rl_norm_op(const void* op, int64_t op_bytes, lfbp_shap
 LFBP_API const char* lfbp_status_string(lfbp_status s);
 
 /* Frees every batched plan (device descriptor tables and graph executables).
- * The caller must make sure no launched batch is still running. */
+ * The caller must make sure no launched batch is still running, and must not
+ * replay afterwards a graph of its own that captured a batched call of more
+ * than 16 problems: such a launch reads the plan's device table (up to 16
+ * descriptors travel in the kernel arguments and need no table). */
 LFBP_API void lfbp_release_plans(void);
 
 /* Library version string, e.g. "lfbp 0.1 gfx950". */

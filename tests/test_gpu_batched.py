@@ -109,6 +109,42 @@ def test_plain_and_batched_calls_replay_in_a_caller_graph():
             assert_same_bits(batch_out[i].cpu().numpy(), ref, f"replay {rep} batched set {i}")
 
 
+def test_concurrent_batched_calls_from_threads():
+    """Four host threads submit their own tables at the same time, each on a
+    stream of its own, alternating direct launches and graph replays; the
+    plan cache is shared under a lock, and every result is the oracle's (one
+    table of 20 problems takes the device descriptor table)."""
+    import threading
+    counts = (5, 12, 20, 3)
+    Hs = [[lfsynth.bits(s, 100 * k + i, np.float32) for i, s in enumerate(mixed_shapes(40 + k, n))]
+          for k, n in enumerate(counts)]
+    dHs = [[to_dev(h) for h in hs] for hs in Hs]
+    outs = [[torch.empty_like(h) for h in hs] for hs in dHs]
+    torch.cuda.synchronize()
+    errors = []
+
+    def work(k):
+        try:
+            stream = torch.cuda.Stream()
+            with torch.cuda.stream(stream):
+                for it in range(6):
+                    lf.compute_Ht_batched(dHs[k], outs[k], use_graph=bool(it % 2))
+            stream.synchronize()
+        except Exception as e:          # reported below, on the main thread
+            errors.append((k, e))
+
+    threads = [threading.Thread(target=work, args=(k,)) for k in range(len(counts))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors
+    torch.cuda.synchronize()
+    for k, (hs, os_) in enumerate(zip(Hs, outs)):
+        for i, (h, o) in enumerate(zip(hs, os_)):
+            assert_same_bits(o.cpu().numpy(), oracle.Ht_rows(h), f"thread {k} set {i}")
+
+
 def test_batch_rejects_mixed_dtypes_and_overlap():
     a = torch.zeros((5, 5, 3, 3, 2), device=DEV)
     b = torch.zeros((5, 5, 3, 3, 2), device=DEV, dtype=torch.float16)
