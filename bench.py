@@ -125,6 +125,20 @@ def projector_traffic():
     return t.get("kernels", {}).get("k_gemm<0>", {}).get("hbm_bytes_per_launch")
 
 
+def step_traffic(workload: str):
+    """HBM bytes of one step (every kernel of one update or gradient) from the
+    committed counter summary of a projector-family workload, if it was taken
+    on the current projector source; else None."""
+    path = os.path.join(ROOT, "profiles", f"{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("kernel_source_sha") != projector_source_sha():
+        return None
+    return t.get("hbm_bytes_per_step")
+
+
 def traffic_from_profile(workload: str):
     """HBM bytes per launch from the committed counter summary, if it was taken
     on the current kernel source; else None."""
@@ -421,7 +435,7 @@ def bench_rl(args, torch):
                    "unprepared_ms_per_step": round(t_plain / args.steps * 1e3, 4),
                    "finite": bool(torch.isfinite(g).all().item())},
         "roofline": {"bound": "mfma", "achieved": round(tflops, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(tflops / FP32_PEAK_TFLOPS, 4), "traffic": None},
+                     "frac": round(tflops / FP32_PEAK_TFLOPS, 4), "traffic": step_traffic("rl")},
     }
     if not args.no_cpu_baseline:
         import oracle
@@ -468,7 +482,7 @@ def bench_grad_psf(args, torch):
         "config": {"workload": f"d<w, H g>/dH, {R}x{C} px, {pw.lenslets}x{pw.lenslets} lenslets, H{list(shape)} f32",
                    "flop_per_step": flop, "wall_s": round(wall, 3)},
         "roofline": {"bound": "mfma", "achieved": round(tflops, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(tflops / FP32_PEAK_TFLOPS, 4), "traffic": None},
+                     "frac": round(tflops / FP32_PEAK_TFLOPS, 4), "traffic": step_traffic("grad-psf")},
     }
     if not args.no_cpu_baseline:
         import oracle

@@ -31,7 +31,9 @@ def test_profile_readers_return_none_or_bytes():
     """Traffic figures come from the committed counter summaries only when
     their recorded source digest matches the current sources."""
     for v in (bench.traffic_from_profile("microscope"), bench.projector_traffic(),
-              bench.colmajor_traffic([307, 307, 51, 51, 11])):
+              bench.colmajor_traffic([307, 307, 51, 51, 11]), bench.step_traffic("rl"),
+              bench.step_traffic("grad-psf")):
         assert v is None or (isinstance(v, int) and v > 0)
     assert bench.traffic_from_profile("no-such-workload") is None
+    assert bench.step_traffic("no-such-workload") is None
     assert bench.colmajor_traffic([3, 3, 3, 3, 3]) is None
