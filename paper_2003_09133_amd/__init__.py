@@ -6,12 +6,15 @@ include/lfbp.h; all computation runs in the library's HIP kernels.  PyTorch
 provides device memory and streams.
 
     compute_Ht(H)              H' from H by pure re-arrangement (Sec. 4)
-    compute_Ht_batched([H..])  many PSF arrays in one persistent launch
+    compute_Ht_batched([H..])  many PSF arrays in one persistent launch (BatchedHt: prepared once)
+    compute_Ht_inplace(H)      H' written over H (the map is its own inverse)
+    compute_Ht_colmajor(H)     H' of a column-major (Matlab order) H
     forward(H, g)              f = H g (Sec. 2.1, Eq. 1)
     backward(Ht, f)            g = H' f (Eq. 2, backprojection)
-    LFProject                  torch.autograd.Function: forward by H, gradients by H' (g) and grad_psf (H)
+    LFProject, project         torch.autograd.Function: forward by H, gradients by H' (g) and grad_psf (H)
     grad_psf(w, g, shape)      d<w, H g>/dH
     rl_step(H, Ht, f, g, norm) one Richardson-Lucy update (Eq. 2); richardson_lucy(H, f, n)
+    LFOperator(H, R, C)        H and H' packed once for many projections or updates
 """
 from __future__ import annotations
 
@@ -23,10 +26,10 @@ from . import _abi
 from ._abi import (F16, F32, GATHER_AUTO, GATHER_DIRECT, GATHER_STAGED, GATHER_WIDE, GatherConfig,
                    LfbpError, Problem, Shape)
 
-__all__ = ["compute_Ht", "compute_Ht_into", "compute_Ht_inplace", "compute_Ht_colmajor", "compute_Ht_batched", "BatchedHt", "forward", "forward_workspace_size",
-           "backward", "backward_workspace_size", "grad_psf", "grad_psf_workspace_size", "LFProject", "project",
-           "rl_norm", "rl_step",
-           "rl_workspace_size", "richardson_lucy", "LFOperator", "default_config", "GatherConfig", "LfbpError", "release_plans",
+__all__ = ["compute_Ht", "compute_Ht_into", "compute_Ht_inplace", "compute_Ht_colmajor", "compute_Ht_batched",
+           "BatchedHt", "forward", "forward_workspace_size", "backward", "backward_workspace_size", "grad_psf",
+           "grad_psf_workspace_size", "LFProject", "project", "rl_norm", "rl_step", "rl_workspace_size",
+           "richardson_lucy", "LFOperator", "default_config", "GatherConfig", "LfbpError", "release_plans",
            "version", "GATHER_AUTO", "GATHER_DIRECT", "GATHER_STAGED", "GATHER_WIDE"]
 
 _DTYPES = {torch.float32: F32, torch.float16: F16}
