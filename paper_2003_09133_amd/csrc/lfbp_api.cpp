@@ -177,10 +177,18 @@ LaunchPlan make_plan(const lfbp_gather_config& c, int lds)
     return p;
 }
 
+// Largest grid whose work-items (grid x threads) fit the 32-bit dispatch size,
+// a multiple of 8 (one share per XCD).  The kernels stride over their units,
+// so a grid this size still covers every unit.
+uint64_t max_grid(int threads)
+{
+    return ((uint64_t(1) << 32) - 1) / uint64_t(std::max(threads, 64)) / 8 * 8;
+}
+
 // Grid of a launch over `units` work units.
 int grid_for(const lfbp_gather_config& c, LaunchPlan& p, uint32_t units, uint32_t W, int es, bool batched)
 {
-    if (c.persistent != 1) return int(units);
+    if (c.persistent != 1) return int(std::min<uint64_t>(units, max_grid(p.threads)));
     int g = c.grid;
     if (g <= 0) g = g_cus * gather_occupancy(p, W, es, batched);  // a multiple of 8: one share per XCD
     return int(std::min<uint64_t>(uint64_t(g), units));
@@ -388,7 +396,7 @@ lfbp_status lfbp_default_config(lfbp_shape shape, lfbp_dtype dtype, lfbp_gather_
     decompose(uint32_t(shape.ny * shape.nz), es, c, rows, lds);
     if (c.grid == 0) {
         const GatherDesc d = make_desc(nullptr, nullptr, shape, es, rows);
-        c.grid = c.persistent == 1 ? g_cus : int(d.nunits);
+        c.grid = c.persistent == 1 ? g_cus : int(std::min<uint64_t>(d.nunits, max_grid(c.block_threads)));
     }
     *cfg = c;
     return LFBP_OK;

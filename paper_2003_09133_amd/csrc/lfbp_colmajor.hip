@@ -67,7 +67,7 @@ constexpr uint32_t kColXcds = 8;   // XCDs of the device
 // one L2.
 __device__ __forceinline__ uint32_t unit_of_block(uint32_t units)
 {
-    const uint32_t bid = blockIdx.x;
+    const uint32_t bid = blockIdx.x + blockIdx.y * gridDim.x;   // dispatch order; < units
     if (!kXcdOrder) return bid;
     const uint32_t x = bid % kColXcds, q = units / kColXcds, r = units % kColXcds;
     return x * q + min(x, r) + bid / kColXcds;
@@ -283,6 +283,7 @@ __global__ void __launch_bounds__(kThreads) k_colmajor(ColDesc d)
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     T* tile = reinterpret_cast<T*>(smem_raw);
     int32_t* rt = reinterpret_cast<int32_t*>(tile + d.nx * d.P);
+    if (blockIdx.x + blockIdx.y * gridDim.x >= d.units) return;   // the last row of a two-dimensional grid
     const UnitGeom g = unit_geom<VE>(d, unit_of_block(d.units));
     if (g.safe) {
         uint32_t x = fdiv(threadIdx.x, d.fVR), v = threadIdx.x - x * d.VR;
@@ -385,10 +386,14 @@ hipError_t launch_colmajor(const void* H, void* Ht, const lfbp_shape& s, int esi
     d.units = uint32_t(units);
     const size_t lds = size_t(d.nx) * d.P * uint32_t(esize) + row_table_bytes(d.nx, VE);
     if (lds > size_t(max_lds)) return hipErrorInvalidValue;
+    // one workgroup per unit; beyond 2^24 units (work-items past 32 bits) the
+    // grid takes a second dimension of 2^16-wide rows
+    const dim3 grid = units < (uint64_t(1) << 24) ? dim3(unsigned(units))
+                                                  : dim3(1u << 16, unsigned((units + 0xFFFF) >> 16));
     if (esize == 4) {
-        hipLaunchKernelGGL(k_colmajor<uint32_t>, dim3(unsigned(units)), dim3(kThreads), lds, stream, d);
+        hipLaunchKernelGGL(k_colmajor<uint32_t>, grid, dim3(kThreads), lds, stream, d);
     } else {
-        hipLaunchKernelGGL(k_colmajor<uint16_t>, dim3(unsigned(units)), dim3(kThreads), lds, stream, d);
+        hipLaunchKernelGGL(k_colmajor<uint16_t>, grid, dim3(kThreads), lds, stream, d);
     }
     return hipGetLastError();
 }

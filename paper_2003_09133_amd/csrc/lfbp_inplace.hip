@@ -27,6 +27,7 @@ struct InplaceDesc {
     uint32_t a_off, b_off;  // (s' - hs) mod nx = (s' + a_off) mod nx; likewise t'
     uint32_t nr;            // x-rows per group
     uint32_t groups;        // groups per block pair, ceil(nx / nr)
+    uint32_t units;         // workgroups: pairs * groups
     FastDiv fnx, fny, fnt, fW, fgroups;
 };
 
@@ -131,7 +132,8 @@ __global__ void __launch_bounds__(256) k_inplace(InplaceDesc d)
     extern __shared__ unsigned char smem_raw[];
     T* tileA = reinterpret_cast<T*>(smem_raw);   // output rows of block O, in output order
     T* tileB = tileA + size_t(d.nr) * d.W;      // output rows of block O' (partner order)
-    const uint32_t unit = blockIdx.x;
+    const uint32_t unit = blockIdx.x + blockIdx.y * gridDim.x;   // dispatch order
+    if (unit >= d.units) return;                                  // the last row of a two-dimensional grid
     const uint32_t O = fdiv(unit, d.fgroups), grp = unit - O * d.groups;
     const uint32_t Op = d.NB - 1 - O;
     const uint32_t sp = fdiv(O, d.fnt), tp = O - sp * d.nt;
@@ -211,10 +213,15 @@ hipError_t launch_inplace(void* H, const lfbp_shape& s, int esize, int max_lds, 
     const size_t lds = 2 * size_t(d.nr) * row_bytes;
     const uint64_t units = uint64_t(pairs) * d.groups;
     if (units >= (uint64_t(1) << 31)) return hipErrorInvalidValue;
+    d.units = uint32_t(units);
     // loads in flight per thread: four for rows under 2 KB, one for longer
     // rows (measured best on the microscope, camera and camera-f16 PSFs)
     const bool batch = row_bytes < 2048;
-    const dim3 grid = dim3(static_cast<unsigned>(units)), block = dim3(256);
+    // one workgroup per unit; beyond 2^24 units (work-items past 32 bits) the
+    // grid takes a second dimension of 2^16-wide rows
+    const dim3 grid = units < (uint64_t(1) << 24) ? dim3(static_cast<unsigned>(units))
+                                                  : dim3(1u << 16, static_cast<unsigned>((units + 0xFFFF) >> 16));
+    const dim3 block = dim3(256);
     if (esize == 4) {
         if (batch)
             hipLaunchKernelGGL((k_inplace<uint32_t, 4>), grid, block, lds, stream, d);

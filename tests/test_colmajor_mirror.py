@@ -211,3 +211,23 @@ def test_xcd_order_is_a_permutation(units):
     x, q, r = bid % 8, units // 8, units % 8
     unit = x * q + np.minimum(x, r) + bid // 8
     assert np.array_equal(np.sort(unit), bid)
+
+
+@pytest.mark.parametrize("units", [1, 8, 2**24 - 1, 2**24, 2**24 + 5, 21_000_000, 2**31 - 1])
+def test_launch_grid_covers_every_unit(units):
+    """launch_colmajor and launch_inplace: one workgroup per unit, on a second
+    grid dimension of 2^16-wide rows past 2^24 units, so that the work-items
+    of each dimension (256 threads per workgroup) fit 32 bits; workgroups of
+    the last row past the last unit return at once, and the others, in
+    dispatch order b = x + y * 2^16, map one to one onto the units."""
+    if units < 2**24:
+        gx, gy = units, 1
+    else:
+        gx, gy = 1 << 16, (units + 0xFFFF) >> 16
+    assert gx * 256 < 2**32 and gy <= 32768
+    assert gx * gy >= units > gx * (gy - 1)
+    b = np.arange(min(units, 4096))                      # a prefix: the map is the same formula throughout
+    x, q, r = b % 8, units // 8, units % 8
+    unit = x * q + np.minimum(x, r) + b // 8
+    assert unit.max() < units and np.unique(unit).size == b.size
+
