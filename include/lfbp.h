@@ -200,8 +200,11 @@ LFBP_API lfbp_status lfbp_compute_Ht_batched_config(const lfbp_problem* problems
  * returns them on the stream; lfbp_forward_ws uses caller memory instead and
  * allocates nothing.
  * Errors EINVAL (null, R or C < 1), ESHAPE (including shapes whose operand
- * copies exceed the kernels' 32-bit index ranges), EALIAS (f overlapping H
- * or g), EALIGN, ENOMEM, EDEVICE.
+ * copies exceed the kernels' 32-bit index ranges, and shapes one of whose
+ * launches would need 2^24 or more workgroups along a grid dimension: the
+ * forward's (ns+nx-1)(nt+ny-1)ceil(nz/22) record stages, R*C/32, or its GEMM
+ * tiles; the backward's and the gradient's GEMM tiles), EALIAS (f
+ * overlapping H or g), EALIGN, ENOMEM, EDEVICE.
  */
 LFBP_API lfbp_status lfbp_forward(const float* H, lfbp_shape shape, const float* g, int64_t R, int64_t C, float* f,
                                   void* stream);

@@ -61,7 +61,7 @@ lfbp_status check_op_call(const void* op, int64_t op_bytes, const lfbp_shape& s,
                           const void* ws, int64_t ws_bytes, std::initializer_list<Range> ins,
                           std::initializer_list<Range> outs)
 {
-    const lfbp_status st = check_project_shape(s, R, C);
+    const lfbp_status st = check_project_shape(s, R, C, kProjFwd | kProjBwd);
     if (st != LFBP_OK) return st;
     const int64_t op_need = int64_t(operator_bytes(s, R, C));
     if (!op || op_bytes < op_need || reinterpret_cast<uintptr_t>(op) % 256) return LFBP_EINVAL;
@@ -111,7 +111,7 @@ lfbp_status lfbp_forward(const float* H, lfbp_shape shape, const float* g, int64
 
 int64_t lfbp_forward_workspace_size(lfbp_shape shape, int64_t R, int64_t C)
 {
-    if (check_project_shape(shape, R, C) != LFBP_OK) return 0;
+    if (check_project_shape(shape, R, C, kProjFwd) != LFBP_OK) return 0;
     return int64_t(forward_workspace_bytes(shape, R, C));
 }
 
@@ -145,7 +145,7 @@ lfbp_status lfbp_backward(const float* Ht, lfbp_shape shape, const float* f, int
 
 int64_t lfbp_backward_workspace_size(lfbp_shape shape, int64_t R, int64_t C)
 {
-    if (check_project_shape(shape, R, C) != LFBP_OK) return 0;
+    if (check_project_shape(shape, R, C, kProjBwd) != LFBP_OK) return 0;
     return int64_t(backward_workspace_bytes(shape, R, C));
 }
 
@@ -179,7 +179,7 @@ lfbp_status lfbp_rl_step(const float* H, const float* Ht, lfbp_shape shape, cons
 
 int64_t lfbp_rl_workspace_size(lfbp_shape shape, int64_t R, int64_t C)
 {
-    if (check_project_shape(shape, R, C) != LFBP_OK) return 0;
+    if (check_project_shape(shape, R, C, kProjFwd | kProjBwd) != LFBP_OK) return 0;
     return int64_t(rl_workspace_bytes(shape, R, C));
 }
 
@@ -206,7 +206,7 @@ lfbp_status lfbp_rl_norm_ws(const float* Ht, lfbp_shape shape, int64_t R, int64_
                             int64_t workspace_bytes, void* stream)
 {
     if (!Ht || !norm) return LFBP_EINVAL;
-    const lfbp_status st = check_project_shape(shape, R, C);
+    const lfbp_status st = check_project_shape(shape, R, C, kProjBwd);
     if (st != LFBP_OK) return st;
     if (reinterpret_cast<uintptr_t>(Ht) % 4 || reinterpret_cast<uintptr_t>(norm) % 4) return LFBP_EALIGN;
     const uint64_t vol = uint64_t(R) * uint64_t(C) * uint64_t(shape.nz) * 4, psf = shape_elems(shape) * 4;
@@ -234,7 +234,7 @@ lfbp_status lfbp_grad_psf(const float* w, const float* g, lfbp_shape shape, int6
 
 int64_t lfbp_grad_psf_workspace_size(lfbp_shape shape, int64_t R, int64_t C)
 {
-    if (check_project_shape(shape, R, C) != LFBP_OK) return 0;
+    if (check_project_shape(shape, R, C, kProjGrad) != LFBP_OK) return 0;
     return int64_t(grad_psf_workspace_bytes(shape, R, C));
 }
 
@@ -257,13 +257,13 @@ lfbp_status lfbp_grad_psf_ws(const float* w, const float* g, lfbp_shape shape, i
 
 int64_t lfbp_operator_size(lfbp_shape shape, int64_t R, int64_t C)
 {
-    if (check_project_shape(shape, R, C) != LFBP_OK) return 0;
+    if (check_project_shape(shape, R, C, kProjFwd | kProjBwd) != LFBP_OK) return 0;
     return int64_t(operator_bytes(shape, R, C));
 }
 
 int64_t lfbp_operator_workspace_size(lfbp_shape shape, int64_t R, int64_t C)
 {
-    if (check_project_shape(shape, R, C) != LFBP_OK) return 0;
+    if (check_project_shape(shape, R, C, kProjFwd | kProjBwd) != LFBP_OK) return 0;
     return int64_t(operator_workspace_bytes(shape, R, C));
 }
 
@@ -271,7 +271,7 @@ lfbp_status lfbp_operator_prepare(const float* H, const float* Ht, lfbp_shape sh
                                   int64_t op_bytes, void* stream)
 {
     if (!H || !Ht) return LFBP_EINVAL;
-    const lfbp_status st = check_project_shape(shape, R, C);
+    const lfbp_status st = check_project_shape(shape, R, C, kProjFwd | kProjBwd);
     if (st != LFBP_OK) return st;
     const int64_t need = int64_t(operator_bytes(shape, R, C));
     if (!op || op_bytes < need || reinterpret_cast<uintptr_t>(op) % 256) return LFBP_EINVAL;

@@ -83,7 +83,7 @@ lfbp_status check_config(const lfbp_gather_config* c)
     return LFBP_OK;
 }
 
-lfbp_status check_project_shape(const lfbp_shape& s, int64_t R, int64_t C)
+lfbp_status check_project_shape(const lfbp_shape& s, int64_t R, int64_t C, unsigned ops)
 {
     if (R < 1 || C < 1) return LFBP_EINVAL;
     const lfbp_status st = check_shape(s, 4);
@@ -110,6 +110,25 @@ lfbp_status check_project_shape(const lfbp_shape& s, int64_t R, int64_t C)
         mul_sat(pairs + 64, 96) >= LIM31)
         return LFBP_ESHAPE;
     if (mul_sat(mul_sat(mul_sat(pairs, uint64_t(s.nz)), cols + lenslets + grid), 96) >= LIM62) return LFBP_ESHAPE;
+    // Every launch must count its work-items (256 per workgroup) in 32 bits
+    // along each grid dimension: fewer than 2^24 workgroups along x.  The
+    // largest x extents: forward, the B-record stages (Kr*Kc*ceil(nz/22)),
+    // the g-record grid (classes times depth chunks), the depth transpose of
+    // g (R*C/32) and the GEMM (row tiles of 64 lenslets times column tiles of
+    // 256 class-box columns; the split count keeps it at most max(tiles,
+    // 512)); backward, the GEMM over lenslets and nx*ny*nz columns; gradient,
+    // the GEMM over Kr*Kc rows and nx*ny*nz columns.  Stage counts of 22
+    // pairs or lenslets stay below 2^24 by the record limits above.
+    const uint64_t lim24 = uint64_t(1) << 24;
+    const uint64_t nzc = (uint64_t(s.nz) + 21) / 22;
+    const uint64_t fwd_cols = mul_sat(classes, 2) + 256, bwd_cols = mul_sat(classes, uint64_t(s.nz));
+    auto tiles = [](uint64_t m, uint64_t n) { return mul_sat((m + 63) / 64, (n + 255) / 256); };
+    if ((ops & kProjFwd) &&
+        (mul_sat(pairs, nzc) >= lim24 || mul_sat(classes, nzc) >= lim24 ||
+         (mul_sat(uint64_t(R), uint64_t(C)) + 31) / 32 >= lim24 || tiles(mul_sat(Lr, Lc), fwd_cols) >= lim24))
+        return LFBP_ESHAPE;
+    if ((ops & kProjBwd) && tiles(mul_sat(Lr, Lc), bwd_cols) >= lim24) return LFBP_ESHAPE;
+    if ((ops & kProjGrad) && tiles(pairs, bwd_cols) >= lim24) return LFBP_ESHAPE;
     return LFBP_OK;
 }
 
@@ -117,7 +136,7 @@ lfbp_status check_project(const float* psf, const lfbp_shape& s, const float* in
                           const float* out, bool forward)
 {
     if (!psf || !in2 || !out) return LFBP_EINVAL;
-    const lfbp_status st = check_project_shape(s, R, C);
+    const lfbp_status st = check_project_shape(s, R, C, forward ? kProjFwd : kProjBwd);
     if (st != LFBP_OK) return st;
     const int64_t image = R * C, volume = image * s.nz;
     const int64_t in2_elems = forward ? volume : image, out_elems = forward ? image : volume;
@@ -134,7 +153,7 @@ lfbp_status check_rl(const float* H, const float* Ht, const lfbp_shape& s, const
                      const float* g, const float* norm, const float* g_out)
 {
     if (!H || !Ht || !f || !g || !norm || !g_out) return LFBP_EINVAL;
-    const lfbp_status st = check_project_shape(s, R, C);
+    const lfbp_status st = check_project_shape(s, R, C, kProjFwd | kProjBwd);
     if (st != LFBP_OK) return st;
     for (const float* p : {H, Ht, f, g, norm, g_out})
         if (reinterpret_cast<uintptr_t>(p) % 4) return LFBP_EALIGN;
@@ -150,7 +169,7 @@ lfbp_status check_grad_psf(const float* w, const float* g, const lfbp_shape& s, 
                            const float* dH)
 {
     if (!w || !g || !dH) return LFBP_EINVAL;
-    const lfbp_status st = check_project_shape(s, R, C);
+    const lfbp_status st = check_project_shape(s, R, C, kProjGrad);
     if (st != LFBP_OK) return st;
     for (const float* p : {w, g, dH})
         if (reinterpret_cast<uintptr_t>(p) % 4) return LFBP_EALIGN;

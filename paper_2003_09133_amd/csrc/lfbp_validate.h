@@ -20,9 +20,13 @@ lfbp_status check_gather(const void* H, const void* Ht, const lfbp_shape& s, lfb
 // Configuration fields (0 = tuned default is always accepted).
 lfbp_status check_config(const lfbp_gather_config* cfg);
 
+// Which projector products a call runs (their launches have different sizes).
+enum ProjOps : unsigned { kProjFwd = 1, kProjBwd = 2, kProjGrad = 4 };
+
 // Shape and image size of a projection (no pointers): EINVAL for R or C < 1,
-// ESHAPE for shapes outside the kernels' index ranges.
-lfbp_status check_project_shape(const lfbp_shape& s, int64_t R, int64_t C);
+// ESHAPE for shapes outside the kernels' index ranges or, for the products
+// in `ops`, the launch sizes.
+lfbp_status check_project_shape(const lfbp_shape& s, int64_t R, int64_t C, unsigned ops);
 
 // Full check of one projector call.  forward: psf = H, in2 = g [nz][R][C],
 // out = f [R][C]; else psf = H', in2 = f [R][C], out = g [nz][R][C].

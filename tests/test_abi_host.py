@@ -206,10 +206,32 @@ def test_projector_index_range_limits():
     assert L.lfbp_forward_workspace_size(big, 30, 30) == 0
     assert L.lfbp_backward_workspace_size(big, 30, 30) == 0
     ok = Shape(4001, 4001, 101, 101, 100)          # 1.7e9 < 2^31
-    assert L.lfbp_forward_workspace_size(ok, 30, 30) > 0
+    assert L.lfbp_backward_workspace_size(ok, 30, 30) > 0
+    assert L.lfbp_forward_workspace_size(ok, 30, 30) == 0    # 84 M forward stages: a launch-size limit
     border = Shape(20001, 20001, 1, 1, 5)          # g's grid with a 10^4-lenslet zero border: 4e8 records
     assert L.lfbp_forward_workspace_size(border, 30, 30) == 0
     assert L.lfbp_forward_workspace_size(Shape(2001, 2001, 1, 1, 5), 30, 30) > 0
+
+
+def test_projector_launch_size_limits():
+    """Each product is refused when one of its launches would pass 2^24
+    workgroups of 256 work-items along a grid dimension (the 32-bit dispatch
+    size), and accepted just below: forward B-record stages Kr*Kc*ceil(nz/22),
+    the depth transpose of g (R*C/32), the gradient's GEMM tiles."""
+    L = _abi.lib()
+    fw, bw, gr = L.lfbp_forward_workspace_size, L.lfbp_backward_workspace_size, L.lfbp_grad_psf_workspace_size
+    assert fw(Shape(4097, 4097, 1, 1, 1), 8, 8) == 0              # 4097^2 stages >= 2^24
+    assert fw(Shape(4095, 4095, 1, 1, 1), 8, 8) > 0               # 4095^2 < 2^24
+    assert bw(Shape(4097, 4097, 1, 1, 1), 8, 8) > 0 and gr(Shape(4097, 4097, 1, 1, 1), 8, 8) > 0
+    assert fw(Shape(15, 15, 15, 15, 1), 23171, 23171) == 0        # R*C/32 >= 2^24
+    assert fw(Shape(15, 15, 15, 15, 1), 23169, 23169) > 0
+    assert bw(Shape(15, 15, 15, 15, 1), 23171, 23171) > 0
+    assert gr(Shape(4001, 4001, 31, 31, 60), 30, 30) == 0         # 254 k x 226 GEMM tiles
+    assert bw(Shape(4001, 4001, 31, 31, 60), 30, 30) > 0
+    assert gr(Shape(2001, 2001, 21, 21, 60), 30, 30) > 0          # 64 k x 104
+    big = Shape(4097, 4097, 1, 1, 1)
+    assert L.lfbp_forward(P1, big, P2, 8, 8, P2 + 0x100000, None) == _abi.ESHAPE
+    assert L.lfbp_operator_size(big, 8, 8) == 0 and L.lfbp_rl_workspace_size(big, 8, 8) == 0
 
 
 def test_batch_overlap_check_against_brute_force():
