@@ -1,7 +1,7 @@
 // Runs the host-side argument checks of the C ABI (lfbp_validate.cpp) under
 // AddressSanitizer and UndefinedBehaviorSanitizer (built by
 // tests/test_sanitizers.py with g++) on ordinary, degenerate and extreme
-// shapes: no check overflows or reads out of bounds, and a few verdicts are
+// shapes: no check overflows or reads out of bounds, and a few outcomes are
 // pinned.  Exit status 0 on success.
 #include <cstdint>
 #include <cstdio>
@@ -33,7 +33,7 @@ int64_t pick_dim()
 
 int expect(bool ok, const char* what)
 {
-    if (!ok) std::fprintf(stderr, "unexpected verdict: %s\n", what);
+    if (!ok) std::fprintf(stderr, "unexpected outcome: %s\n", what);
     return ok ? 0 : 1;
 }
 
