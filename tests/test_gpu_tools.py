@@ -1,0 +1,55 @@
+"""The autotuner and the benchmark as a user runs them, on the GPU, each in a
+process of its own: the autotuner writes a tuning table whose entry the
+library then uses, and bench.py prints one JSON line with every field of its
+contract."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+pytestmark = pytest.mark.gpu
+
+
+def run(args, env=None, timeout=240):
+    r = subprocess.run([sys.executable, *args], cwd=ROOT, capture_output=True, text=True, timeout=timeout,
+                       env=dict(os.environ, **(env or {})))
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-2000:]
+    return r.stdout
+
+
+def test_autotuner_writes_a_table_the_library_uses(tmp_path):
+    table = tmp_path / "tune.txt"
+    out = run(["-m", "paper_2003_09133_amd.autotune", "--workloads", "microscope", "--reps", "1",
+               "--out", str(table)])
+    report = json.loads([l for l in out.splitlines() if l.startswith("{")][-1])
+    assert report["workload"] == "microscope" and report["best_gbs"] > 0
+    rows = [l.split() for l in table.read_text().splitlines() if l.strip() and not l.startswith("#")]
+    assert len(rows) == 1 and len(rows[0]) == 12
+    key, cfg = [int(v) for v in rows[0][:4]], [int(v) for v in rows[0][4:]]
+    assert key == [0, 4, 15 * 21, 15]                        # plain, float32, W = ny*nz, nx
+    probe = ("import json, sys; sys.path.insert(0, %r); import torch, paper_2003_09133_amd as lf; "
+             "print(json.dumps(lf.default_config((165, 165, 15, 15, 21), torch.float32)))" % ROOT)
+    used = json.loads(run(["-c", probe], env={"LFBP_TUNE_TABLE": str(table)}).strip().splitlines()[-1])
+    fields = ("variant", "block_threads", "rows_in_flight", "tile_bytes", "vec_per_thread", "nontemporal",
+              "persistent")
+    assert [used[f] for f in fields] == cfg[:7]
+
+
+def test_bench_line_carries_every_field():
+    out = run(["bench.py", "--workload", "tiny", "--steps", "3", "--warmup", "1", "--cpu-seconds", "1"])
+    lines = [l for l in out.splitlines() if l.startswith("{")]
+    assert len(lines) == 1
+    d = json.loads(lines[0])
+    for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better", "scaling",
+              "vs_baseline", "dtype", "data", "config", "roofline", "cpu_baseline"):
+        assert k in d, k
+    assert d["n_gpus"] == 1 and d["steps"] == 3 and d["warmup"] == 1 and d["value"] > 0
+    assert d["config"]["workload"]
+    r = d["roofline"]
+    assert r["bound"] == "hbm" and r["peak"] == 8000.0 and r["unit"] == "GB/s"
+    assert abs(r["frac"] - r["achieved"] / r["peak"]) < 1e-3
+    c = d["cpu_baseline"]
+    assert c["kind"] == "oracle" and c["cores"] >= 1 and c["value"] > 0 and c["sample"]
