@@ -43,7 +43,8 @@ typedef enum {
     LFBP_EALIAS = -4,  /* input and output ranges overlap (in-place is not supported) */
     LFBP_EDEVICE = -5, /* a HIP call failed (launch error, no device) */
     LFBP_ENOMEM = -6,  /* the library could not allocate its own device or host memory */
-    LFBP_EALIGN = -7   /* a pointer is not aligned to its element size */
+    LFBP_EALIGN = -7,  /* a pointer is not aligned to its element size */
+    LFBP_ECAPTURE = -8 /* the call would have to allocate, and its stream is being captured into a graph */
 } lfbp_status;
 
 typedef enum { LFBP_F32 = 0, LFBP_F16 = 1 } lfbp_dtype;
@@ -121,22 +122,30 @@ typedef struct {
 
 /*
  * lfbp_compute_Ht_batched -- H' for `count` independent PSF arrays (for
- * example a depth sweep, or several lens/MLA configurations) in ONE persistent
- * kernel launch (Sec. 3.1: PSF updates inside iterative reconstruction need
- * H' recomputed often).  Each problem obeys the rules of lfbp_compute_Ht; all
- * share `dtype`.  Results are bit-identical to count separate calls.
+ * example a depth sweep, or several lens/MLA configurations) in ONE kernel
+ * launch (Sec. 3.1: PSF updates inside iterative reconstruction need H'
+ * recomputed often).  Each problem obeys the rules of lfbp_compute_Ht; all
+ * share `dtype`.  Results are bit-identical to count separate calls.  Each
+ * problem is cut into work units of its own size (the tuned size of its shape
+ * class) and every XCD of the GPU takes an even share of every problem,
+ * largest problems first.
  *
  * problems  HOST array of `count` descriptors (copied; may be freed on return).
- * Ownership The library keeps a plan per distinct problem table (device
- *           descriptor table and launch parameters), reused when the same
- *           table is submitted again; lfbp_release_plans() frees all plans.
- *           A plan is created on first use (hipMalloc), so the first call
- *           with a new table allocates; later calls launch the persistent
- *           kernel directly and allocate nothing (the launch may itself be
- *           captured into a caller's graph, which then depends on the plan:
- *           see lfbp_release_plans).  lfbp_compute_Ht_batched_config
- *           with use_graph = 1 keeps the launch in a captured hipGraph
- *           instead and replays it.
+ * Ownership The library keeps a plan per distinct problem table (pointers and
+ *           shapes): launch parameters and, for more than 16 problems, a
+ *           device descriptor table.  A call with a new table makes its plan
+ *           (one hipMalloc when a device table is needed; the table is written
+ *           by small kernels on `stream`, so nothing blocks); a call with a
+ *           known table launches at once.  At most 32 plans are kept, least
+ *           recently used dropped first; a dropped plan's device memory is
+ *           freed only after every launch of it has finished.  A plan used by
+ *           a call made under stream capture is kept until
+ *           lfbp_release_plans(), because the caller's graph reads it.  A new
+ *           plan that needs device memory (more than 16 problems, or
+ *           use_graph = 1) cannot be made while `stream` is being captured:
+ *           such a call returns ECAPTURE before any HIP call, and the capture
+ *           stays valid (submit the table once outside the capture).
+ *           lfbp_plan_count() reports the plans held.
  * Errors    EINVAL (problems NULL, count <= 0, or any pointer NULL), ESHAPE,
  *           EDTYPE, EALIGN, EALIAS (any input overlapping any output) -- all
  *           checked before anything is launched; ENOMEM, EDEVICE.
@@ -365,12 +374,15 @@ LFBP_API lfbp_status lfbp_rl_norm_op(const void* op, int64_t op_bytes, lfbp_shap
 /* Static text for a status code (never NULL). */
 LFBP_API const char* lfbp_status_string(lfbp_status s);
 
-/* Frees every batched plan (device descriptor tables and graph executables).
- * The caller must make sure no launched batch is still running, and must not
- * replay afterwards a graph of its own that captured a batched call of more
- * than 16 problems: such a launch reads the plan's device table (up to 16
- * descriptors travel in the kernel arguments and need no table). */
+/* Frees every batched plan (device descriptor tables and graph executables),
+ * after waiting for the launches of each that are still running.  The caller
+ * must not replay afterwards a graph of its own that captured a batched call
+ * of more than 16 problems: such a launch reads the plan's device table (up to
+ * 16 descriptors travel in the kernel arguments and need no table). */
 LFBP_API void lfbp_release_plans(void);
+
+/* Batched plans currently held (kept, and dropped but not yet freed). */
+LFBP_API int32_t lfbp_plan_count(void);
 
 /* Library version string, e.g. "lfbp 0.1 gfx950". */
 LFBP_API const char* lfbp_version(void);

@@ -29,7 +29,7 @@ from ._abi import (F16, F32, GATHER_AUTO, GATHER_DIRECT, GATHER_STAGED, GATHER_W
 __all__ = ["compute_Ht", "compute_Ht_into", "compute_Ht_inplace", "compute_Ht_colmajor", "compute_Ht_batched",
            "BatchedHt", "forward", "forward_workspace_size", "backward", "backward_workspace_size", "grad_psf",
            "grad_psf_workspace_size", "LFProject", "project", "rl_norm", "rl_step", "rl_workspace_size",
-           "richardson_lucy", "LFOperator", "default_config", "GatherConfig", "LfbpError", "release_plans",
+           "richardson_lucy", "LFOperator", "default_config", "GatherConfig", "LfbpError", "release_plans", "plan_count",
            "version", "GATHER_AUTO", "GATHER_DIRECT", "GATHER_STAGED", "GATHER_WIDE"]
 
 _DTYPES = {torch.float32: F32, torch.float16: F16}
@@ -466,6 +466,11 @@ def richardson_lucy(H: torch.Tensor, f: torch.Tensor, iters: int, g0: torch.Tens
     for _ in range(iters):
         op.rl_step(f, g, norm, out=g)
     return g
+
+
+def plan_count() -> int:
+    """Batched plans the library currently holds (kept, or dropped and not yet freed)."""
+    return int(_abi.lib().lfbp_plan_count())
 
 
 def release_plans():

@@ -11,12 +11,13 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("LFBP_LIB", os.path.join(HERE, "liblfbp.so"))
 
-OK, EINVAL, ESHAPE, EDTYPE, EALIAS, EDEVICE, ENOMEM, EALIGN = 0, -1, -2, -3, -4, -5, -6, -7
+OK, EINVAL, ESHAPE, EDTYPE, EALIAS, EDEVICE, ENOMEM, EALIGN, ECAPTURE = 0, -1, -2, -3, -4, -5, -6, -7, -8
 F32, F16 = 0, 1
 GATHER_AUTO, GATHER_DIRECT, GATHER_STAGED, GATHER_WIDE = 0, 1, 2, 3
 
 STATUS_NAMES = {OK: "LFBP_OK", EINVAL: "LFBP_EINVAL", ESHAPE: "LFBP_ESHAPE", EDTYPE: "LFBP_EDTYPE",
-                EALIAS: "LFBP_EALIAS", EDEVICE: "LFBP_EDEVICE", ENOMEM: "LFBP_ENOMEM", EALIGN: "LFBP_EALIGN"}
+                EALIAS: "LFBP_EALIAS", EDEVICE: "LFBP_EDEVICE", ENOMEM: "LFBP_ENOMEM", EALIGN: "LFBP_EALIGN",
+                ECAPTURE: "LFBP_ECAPTURE"}
 
 
 class Shape(ctypes.Structure):
@@ -92,6 +93,7 @@ def lib():
             "lfbp_grad_psf_workspace_size": (i64, [Shape, i64, i64]),
             "lfbp_status_string": (ctypes.c_char_p, [st]),
             "lfbp_release_plans": (None, []),
+            "lfbp_plan_count": (ctypes.c_int32, []),
             "lfbp_version": (ctypes.c_char_p, []),
         }
         for name, (res, args) in sig.items():

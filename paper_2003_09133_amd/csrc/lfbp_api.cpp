@@ -20,6 +20,7 @@ namespace lfbp {
 hipError_t launch_gather(const GatherDesc& d, int esize, const LaunchPlan& p, hipStream_t stream);
 hipError_t launch_gather_batched(const BatchArgs& a, uint32_t maxW, int esize, const LaunchPlan& p,
                                  hipStream_t stream);
+hipError_t put_words(uint32_t* dst, const uint32_t* src, size_t n, hipStream_t stream);
 hipError_t set_gather_smem_limits(int max_bytes);
 hipError_t set_inplace_smem_limits(int max_bytes);
 hipError_t launch_inplace(void* H, const lfbp_shape& s, int esize, int max_lds, hipStream_t stream);
@@ -196,31 +197,219 @@ int grid_for(const lfbp_gather_config& c, LaunchPlan& p, uint32_t units, uint32_
 
 // ---------------------------------------------------------------- batched plans
 
+// Rows per unit of a WIDE unit of about `vecs` 16-byte loads over rows of W
+// elements, within the LDS (ntab row tables); 0 if not even one row fits.
+uint32_t wide_rows(uint32_t W, int es, int64_t vecs, int ntab)
+{
+    const int64_t ve = 16 / es;
+    const int64_t vpr = (int64_t(W) + 2 * ve - 2) / ve;
+    int64_t r = std::max<int64_t>(1, vecs / vpr);
+    auto need = [&](int64_t rr) { return int64_t(ntab) * rr * 16 + round16((rr * W + 2 * ve) * es); };
+    while (r > 0 && need(r) > g_max_lds) --r;
+    return uint32_t(r);
+}
+
+// Everything a batched launch needs, computed on the host from the problem
+// table (no HIP call): descriptors sorted largest first, each with its own
+// work-unit size; the per-XCD walks; the kernel choice and grid.
+struct BatchLayout {
+    std::vector<GatherDesc> descs;
+    std::vector<uint32_t> xstart;  // [kXcds][count+1]
+    BatchArgs args{};              // everything but the table pointers
+    LaunchPlan plan{};
+    uint32_t maxW = 0;
+};
+
+lfbp_status layout_batch(const lfbp_problem* probs, int32_t count, int es, const lfbp_gather_config* user,
+                         BatchLayout& L)
+{
+    std::vector<int32_t> order(static_cast<size_t>(count));
+    for (int32_t i = 0; i < count; ++i) order[size_t(i)] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t i, int32_t j) {
+        return shape_elems(probs[i].shape) > shape_elems(probs[j].shape);
+    });
+    // One kernel for the whole batch: the tuned batched choice for the largest
+    // problem.  Every problem must fit the chosen variant; the first one that
+    // does not moves the whole batch down (WIDE -> STAGED -> DIRECT).
+    lfbp_gather_config c = resolve_config(probs[order[0]].shape, es, user, true);
+    uint32_t maxW = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        const uint32_t W = uint32_t(probs[i].shape.ny * probs[i].shape.nz);
+        maxW = std::max(maxW, W);
+        uint32_t r;
+        int l;
+        decompose(W, es, c, r, l);
+    }
+    // Work-unit size per problem.  WIDE: a unit holds as many 16-byte loads as
+    // the tuned plain kernel for that problem's shape class uses per unit (at
+    // most the batched kernel's vec_per_thread per thread), unless the caller
+    // fixed the vector count; others: as the common configuration gives.
+    const int ntab = c.persistent == 1 ? 2 : 1;
+    const int64_t cap = int64_t(c.block_threads) * c.vec_per_thread;
+    const bool own_units = c.variant == LFBP_GATHER_WIDE && !(user && user->vec_per_thread);
+    std::vector<uint32_t> rows(static_cast<size_t>(count));
+    int lds = 0;
+    uint32_t max_rows = 0;
+    for (int32_t k = 0; k < count; ++k) {
+        const lfbp_shape& sh = probs[order[size_t(k)]].shape;
+        const uint32_t W = uint32_t(sh.ny * sh.nz);
+        uint32_t r = 0;
+        int l = 0;
+        if (c.variant == LFBP_GATHER_WIDE) {
+            int64_t vecs = cap;
+            if (own_units) {
+                const lfbp_gather_config pc = tuned_config(sh, es, false);
+                if (pc.variant == LFBP_GATHER_WIDE)
+                    vecs = std::min<int64_t>(cap, int64_t(pc.block_threads) * pc.vec_per_thread);
+            }
+            r = wide_rows(W, es, vecs, ntab);
+            if (r == 0) return LFBP_ESHAPE;
+            const int64_t ve = 16 / es;
+            l = round16((int64_t(r) * W + 2 * ve) * es);  // tile only; tables added below
+        } else {
+            lfbp_gather_config ci = c;
+            decompose(W, es, ci, r, l);
+        }
+        rows[size_t(k)] = r;
+        max_rows = std::max(max_rows, r);
+        lds = std::max(lds, l);
+    }
+    if (c.variant == LFBP_GATHER_WIDE) lds += ntab * int(max_rows) * 16;
+    if (lds > g_max_lds) return LFBP_ESHAPE;
+    L.descs.resize(static_cast<size_t>(count));
+    for (int32_t k = 0; k < count; ++k) {
+        const lfbp_problem& pb = probs[order[size_t(k)]];
+        L.descs[size_t(k)] = make_desc(pb.H, pb.Ht, pb.shape, es, rows[size_t(k)]);
+    }
+    BatchArgs& a = L.args;
+    std::memset(&a, 0, sizeof(a));
+    L.xstart.assign(size_t(kXcds) * (size_t(count) + 1), 0);
+    uint64_t slots = 0;
+    for (uint32_t x = 0; x < kXcds; ++x) {
+        uint64_t cum = 0;
+        for (int32_t k = 0; k < count; ++k) {
+            L.xstart[x * (size_t(count) + 1) + size_t(k)] = uint32_t(cum);
+            cum += xcd_share(L.descs[size_t(k)].nunits, x);
+            if (cum >= (uint64_t(1) << 28)) return LFBP_ESHAPE;  // kXcds * slots < 2^31
+        }
+        L.xstart[x * (size_t(count) + 1) + size_t(count)] = uint32_t(cum);
+        a.xtotal[x] = uint32_t(cum);
+        slots = std::max(slots, cum);
+    }
+    a.count = uint32_t(count);
+    a.slots = uint32_t(slots);
+    a.max_rows = max_rows;
+    a.nt = c.nontemporal == 1 ? 1 : 0;
+    if (uint32_t(count) <= kInlineProblems)
+        for (int32_t k = 0; k < count; ++k) a.d[k] = L.descs[size_t(k)];
+    LaunchPlan lp = make_plan(c, lds);
+    const uint64_t nslots = uint64_t(kXcds) * slots;
+    if (c.persistent != 1) {
+        lp.grid = int(std::min<uint64_t>(nslots, max_grid(lp.threads)));
+    } else {
+        // a multiple of kXcds, so that every workgroup stays on one XCD's walk
+        uint64_t g = c.grid > 0 ? uint64_t(c.grid) : uint64_t(g_cus) * gather_occupancy(lp, maxW, es, true);
+        g = std::max<uint64_t>(kXcds, g / kXcds * kXcds);
+        lp.grid = int(std::min<uint64_t>(g, nslots));
+    }
+    L.plan = lp;
+    L.maxW = maxW;
+    return LFBP_OK;
+}
+
+// Upload a layout's descriptor table and per-XCD walks into `table` (device
+// memory of table_bytes(count) bytes) on `stream`, and point the launch
+// arguments at it.
+size_t table_bytes(int32_t count)
+{
+    return sizeof(GatherDesc) * size_t(count) + sizeof(uint32_t) * size_t(kXcds) * (size_t(count) + 1);
+}
+
+hipError_t upload_table(BatchLayout& L, void* table, hipStream_t stream)
+{
+    const size_t dbytes = sizeof(GatherDesc) * L.descs.size();
+    static_assert(sizeof(GatherDesc) % sizeof(uint32_t) == 0, "descriptor is whole words");
+    uint32_t* words = static_cast<uint32_t*>(table);
+    hipError_t e = put_words(words, reinterpret_cast<const uint32_t*>(L.descs.data()), dbytes / 4, stream);
+    if (e == hipSuccess) e = put_words(words + dbytes / 4, L.xstart.data(), L.xstart.size(), stream);
+    L.args.table = static_cast<const GatherDesc*>(table);
+    L.args.table_xstart = words + dbytes / 4;
+    return e;
+}
+
+// hipEventQuery without leaving "not ready" behind as the thread's last error
+// (the launch checks read hipGetLastError).
+bool event_done(hipEvent_t e)
+{
+    const hipError_t r = hipEventQuery(e);
+    if (r == hipErrorNotReady) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return true;
+}
+
+bool capturing(hipStream_t s)
+{
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(s, &st) == hipSuccess && st != hipStreamCaptureStatusNone;
+}
+
+// A cached batched plan.  Plans are keyed on the exact problem table (pointers
+// and shapes), the configuration and graph use, and are immutable once made,
+// so one plan may be launched from several streams and threads at once.
 struct BatchPlan {
     int device = -1;
     std::vector<lfbp_problem> probs;
     lfbp_dtype dtype = LFBP_F32;
     lfbp_gather_config key{};
-    int use_graph = 1;
-    GatherDesc* descs_dev = nullptr;      // only for batches beyond kInlineProblems
-    uint32_t* unit_start_dev = nullptr;
-    uint32_t maxW = 0;
-    BatchArgs args{};
-    LaunchPlan plan{};
+    int use_graph = 0;
+    BatchLayout layout;
+    void* table = nullptr;             // device table, batches beyond kInlineProblems
+    hipStream_t upload_stream = nullptr;
+    hipEvent_t ready = nullptr;        // table written (recorded on upload_stream)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    std::vector<std::pair<hipStream_t, hipEvent_t>> uses;  // last launch on each stream
+    bool pinned = false;               // used by a captured call: kept until lfbp_release_plans
+    uint64_t tick = 0;
+
+    bool holds_device() const { return table != nullptr || exec != nullptr; }
+
+    // Every launch (and the upload) of this plan has finished.
+    bool idle() const
+    {
+        if (ready && !event_done(ready)) return false;
+        for (const auto& u : uses)
+            if (!event_done(u.second)) return false;
+        return true;
+    }
+
+    void wait_idle() const
+    {
+        if (ready) (void)hipEventSynchronize(ready);
+        for (const auto& u : uses) (void)hipEventSynchronize(u.second);
+    }
 
     ~BatchPlan()
     {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
-        if (descs_dev) (void)hipFree(descs_dev);
-        if (unit_start_dev) (void)hipFree(unit_start_dev);
+        for (auto& u : uses) (void)hipEventDestroy(u.second);
+        if (ready) (void)hipEventDestroy(ready);
+        if (table) (void)hipFree(table);
     }
 };
 
+// At most kMaxPlans plans are kept; the least recently used one is dropped
+// first.  A dropped plan that holds device memory or a graph is retired and
+// freed once every launch of it has finished (checked without blocking on
+// later calls).  Plans used by a captured call are never dropped.
+constexpr size_t kMaxPlans = 32;
 std::mutex g_plan_mu;
 std::vector<std::unique_ptr<BatchPlan>> g_plans;
+std::vector<std::unique_ptr<BatchPlan>> g_retired;
+uint64_t g_tick = 0;
 
 bool same_table(const BatchPlan& p, int dev, const lfbp_problem* probs, int32_t count, lfbp_dtype dt,
                 const lfbp_gather_config& key, int use_graph)
@@ -230,89 +419,58 @@ bool same_table(const BatchPlan& p, int dev, const lfbp_problem* probs, int32_t 
     return std::memcmp(p.probs.data(), probs, sizeof(lfbp_problem) * size_t(count)) == 0;
 }
 
+void reap_retired()
+{
+    for (size_t i = 0; i < g_retired.size();) {
+        if (g_retired[i]->idle()) {
+            g_retired[i] = std::move(g_retired.back());
+            g_retired.pop_back();
+        } else {
+            ++i;
+        }
+    }
+}
+
+void evict_plans()
+{
+    while (g_plans.size() > kMaxPlans) {
+        size_t victim = g_plans.size();
+        for (size_t i = 0; i < g_plans.size(); ++i)
+            if (!g_plans[i]->pinned && (victim == g_plans.size() || g_plans[i]->tick < g_plans[victim]->tick))
+                victim = i;
+        if (victim == g_plans.size()) return;  // every plan pinned
+        std::unique_ptr<BatchPlan> p = std::move(g_plans[victim]);
+        g_plans.erase(g_plans.begin() + std::ptrdiff_t(victim));
+        if (p->holds_device() && !p->idle()) g_retired.push_back(std::move(p));
+    }
+}
+
 lfbp_status build_plan(BatchPlan& bp, const lfbp_problem* probs, int32_t count, lfbp_dtype dt,
-                       const lfbp_gather_config* user, int use_graph)
+                       const lfbp_gather_config* user, int use_graph, hipStream_t stream)
 {
     const int es = dtype_size(dt);
-    // One kernel configuration for the whole batch: the tuned choice of the
-    // largest problem; each problem's work unit is then sized for it.
-    int big = 0;
-    for (int32_t i = 1; i < count; ++i)
-        if (shape_elems(probs[i].shape) > shape_elems(probs[big].shape)) big = i;
-    lfbp_gather_config c = resolve_config(probs[big].shape, es, user, true);
-    // Every problem must fit the chosen variant; the first one that does not
-    // moves the whole batch down (WIDE -> STAGED -> DIRECT).
-    uint32_t maxW = 0;
-    for (int32_t i = 0; i < count; ++i) {
-        const uint32_t W = uint32_t(probs[i].shape.ny * probs[i].shape.nz);
-        maxW = std::max(maxW, W);
-        uint32_t r;
-        int l;
-        decompose(W, es, c, r, l);
-    }
-    std::vector<uint32_t> rows(static_cast<size_t>(count));
-    int lds = 0;
-    uint32_t max_rows = 0;
-    for (int32_t i = 0; i < count; ++i) {
-        const uint32_t W = uint32_t(probs[i].shape.ny * probs[i].shape.nz);
-        lfbp_gather_config ci = c;
-        int l = 0;
-        decompose(W, es, ci, rows[size_t(i)], l);
-        max_rows = std::max(max_rows, rows[size_t(i)]);
-        if (c.variant == LFBP_GATHER_WIDE) {
-            const int64_t ve = 16 / es;
-            l = round16((int64_t(rows[size_t(i)]) * W + 2 * ve) * es);  // tile only; tables added below
-        }
-        lds = std::max(lds, l);
-    }
-    if (c.variant == LFBP_GATHER_WIDE) lds += (c.persistent == 1 ? 2 : 1) * int(max_rows) * 16;
-    if (lds > g_max_lds) return LFBP_ESHAPE;
-    std::vector<GatherDesc> descs(static_cast<size_t>(count));
-    std::vector<uint32_t> start(static_cast<size_t>(count) + 1, 0);
-    for (int32_t i = 0; i < count; ++i) {
-        descs[size_t(i)] = make_desc(probs[i].H, probs[i].Ht, probs[i].shape, es, rows[size_t(i)]);
-        const uint64_t next = uint64_t(start[size_t(i)]) + descs[size_t(i)].nunits;
-        if (next >= (uint64_t(1) << 31)) return LFBP_ESHAPE;
-        start[size_t(i) + 1] = uint32_t(next);
-    }
-    const uint32_t total = start[size_t(count)];
-    LaunchPlan lp = make_plan(c, lds);
-    lp.grid = grid_for(c, lp, total, maxW, es, true);
-    BatchArgs& a = bp.args;
-    std::memset(&a, 0, sizeof(a));
-    a.count = uint32_t(count);
-    a.total = total;
-    a.max_rows = max_rows;
-    a.nt = c.nontemporal == 1 ? 1 : 0;
-    if (uint32_t(count) <= kInlineProblems) {
-        for (int32_t i = 0; i < count; ++i) a.d[i] = descs[size_t(i)];
-        for (int32_t i = 0; i <= count; ++i) a.start[i] = start[size_t(i)];
-    } else {
-        if (hipMalloc(reinterpret_cast<void**>(&bp.descs_dev), sizeof(GatherDesc) * size_t(count)) != hipSuccess)
-            return LFBP_ENOMEM;
-        if (hipMalloc(reinterpret_cast<void**>(&bp.unit_start_dev), sizeof(uint32_t) * (size_t(count) + 1)) !=
-            hipSuccess)
-            return LFBP_ENOMEM;
-        if (hipMemcpy(bp.descs_dev, descs.data(), sizeof(GatherDesc) * size_t(count), hipMemcpyHostToDevice) !=
-            hipSuccess)
-            return LFBP_EDEVICE;
-        if (hipMemcpy(bp.unit_start_dev, start.data(), sizeof(uint32_t) * (size_t(count) + 1),
-                      hipMemcpyHostToDevice) != hipSuccess)
-            return LFBP_EDEVICE;
-        a.table = bp.descs_dev;
-        a.table_start = bp.unit_start_dev;
-    }
-    bp.maxW = maxW;
-    bp.plan = lp;
+    const lfbp_status st = layout_batch(probs, count, es, user, bp.layout);
+    if (st != LFBP_OK) return st;
     bp.dtype = dt;
     bp.use_graph = use_graph;
     bp.probs.assign(probs, probs + count);
+    if (uint32_t(count) > kInlineProblems) {
+        if (hipMalloc(&bp.table, table_bytes(count)) != hipSuccess) {
+            (void)hipGetLastError();
+            bp.table = nullptr;
+            return LFBP_ENOMEM;
+        }
+        if (upload_table(bp.layout, bp.table, stream) != hipSuccess) return LFBP_EDEVICE;
+        if (hipEventCreateWithFlags(&bp.ready, hipEventDisableTiming) != hipSuccess) return LFBP_EDEVICE;
+        if (hipEventRecord(bp.ready, stream) != hipSuccess) return LFBP_EDEVICE;
+        bp.upload_stream = stream;
+    }
     if (use_graph) {
         hipStream_t cs = nullptr;
         if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return LFBP_EDEVICE;
         hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            const hipError_t le = launch_gather_batched(bp.args, bp.maxW, es, lp, cs);
+            const hipError_t le = launch_gather_batched(bp.layout.args, bp.layout.maxW, es, bp.layout.plan, cs);
             e = hipStreamEndCapture(cs, &bp.graph);
             if (le != hipSuccess) e = le;
         }
@@ -321,6 +479,30 @@ lfbp_status build_plan(BatchPlan& bp, const lfbp_problem* probs, int32_t count, 
         if (e != hipSuccess) return LFBP_EDEVICE;
     }
     return LFBP_OK;
+}
+
+// Record that `plan` was launched on stream s (not under capture).
+lfbp_status note_use(BatchPlan& plan, hipStream_t s)
+{
+    if (!plan.holds_device()) return LFBP_OK;
+    hipEvent_t ev = nullptr;
+    for (auto& u : plan.uses)
+        if (u.first == s) ev = u.second;
+    if (!ev) {
+        // forget finished launches on other streams before adding one
+        for (size_t i = 0; i < plan.uses.size();) {
+            if (event_done(plan.uses[i].second)) {
+                (void)hipEventDestroy(plan.uses[i].second);
+                plan.uses[i] = plan.uses.back();
+                plan.uses.pop_back();
+            } else {
+                ++i;
+            }
+        }
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return LFBP_EDEVICE;
+        plan.uses.emplace_back(s, ev);
+    }
+    return hipEventRecord(ev, s) == hipSuccess ? LFBP_OK : LFBP_EDEVICE;
 }
 
 lfbp_status validate_batch(const lfbp_problem* probs, int32_t count, lfbp_dtype dt)
@@ -377,6 +559,7 @@ const char* lfbp_status_string(lfbp_status s)
         case LFBP_EDEVICE: return "HIP device error";
         case LFBP_ENOMEM: return "out of memory";
         case LFBP_EALIGN: return "pointer not aligned to its element size";
+        case LFBP_ECAPTURE: return "the call would allocate while its stream is being captured";
         default: return "unknown status";
     }
 }
@@ -390,14 +573,17 @@ lfbp_status lfbp_default_config(lfbp_shape shape, lfbp_dtype dtype, lfbp_gather_
     if (es == 0) return LFBP_EDTYPE;
     const lfbp_status st = check_shape(shape, es);
     if (st != LFBP_OK) return st;
+    // the device's LDS size decides the work decomposition, as in a launch
+    // (with no device, the 64 KB every device provides)
+    (void)ensure_init();
     lfbp_gather_config c = resolve_config(shape, es, nullptr, false);
     uint32_t rows = 0;
     int lds = 0;
-    decompose(uint32_t(shape.ny * shape.nz), es, c, rows, lds);
-    if (c.grid == 0) {
-        const GatherDesc d = make_desc(nullptr, nullptr, shape, es, rows);
-        c.grid = c.persistent == 1 ? g_cus : int(std::min<uint64_t>(d.nunits, max_grid(c.block_threads)));
-    }
+    const uint32_t W = uint32_t(shape.ny * shape.nz);
+    decompose(W, es, c, rows, lds);
+    const GatherDesc d = make_desc(nullptr, nullptr, shape, es, rows);
+    LaunchPlan p = make_plan(c, lds);
+    c.grid = grid_for(c, p, d.nunits, W, es, false);
     *cfg = c;
     return LFBP_OK;
 }
@@ -438,9 +624,12 @@ lfbp_status lfbp_compute_Ht_batched_config(const lfbp_problem* problems, int32_t
     if (ensure_init() != hipSuccess) return LFBP_EDEVICE;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return LFBP_EDEVICE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const bool in_capture = capturing(s);
     lfbp_gather_config key{};
     if (cfg) key = *cfg;
     std::lock_guard<std::mutex> lock(g_plan_mu);
+    reap_retired();
     BatchPlan* plan = nullptr;
     for (auto& p : g_plans)
         if (same_table(*p, dev, problems, count, dtype, key, use_graph)) {
@@ -448,21 +637,35 @@ lfbp_status lfbp_compute_Ht_batched_config(const lfbp_problem* problems, int32_t
             break;
         }
     if (!plan) {
+        // a plan with device memory cannot be made inside a capture (the
+        // allocation would end the caller's capture)
+        if (in_capture && (uint32_t(count) > kInlineProblems || use_graph)) return LFBP_ECAPTURE;
         auto bp = std::make_unique<BatchPlan>();
         bp->device = dev;
         bp->key = key;
-        st = build_plan(*bp, problems, count, dtype, cfg, use_graph);
+        st = build_plan(*bp, problems, count, dtype, cfg, use_graph, s);
         if (st != LFBP_OK) return st;
         g_plans.push_back(std::move(bp));
         plan = g_plans.back().get();
+    } else if (plan->ready && plan->upload_stream != s && !event_done(plan->ready)) {
+        // the table is still being written on the stream of the plan's first
+        // call: order this launch after it
+        const hipError_t e = in_capture ? hipEventSynchronize(plan->ready) : hipStreamWaitEvent(s, plan->ready, 0);
+        if (e != hipSuccess) return LFBP_EDEVICE;
     }
-    hipStream_t s = static_cast<hipStream_t>(stream);
+    plan->tick = ++g_tick;
     hipError_t e;
     if (plan->use_graph)
         e = hipGraphLaunch(plan->exec, s);
     else
-        e = launch_gather_batched(plan->args, plan->maxW, dtype_size(dtype), plan->plan, s);
-    return e == hipSuccess ? LFBP_OK : LFBP_EDEVICE;
+        e = launch_gather_batched(plan->layout.args, plan->layout.maxW, dtype_size(dtype), plan->layout.plan, s);
+    if (e != hipSuccess) return LFBP_EDEVICE;
+    if (in_capture)
+        plan->pinned = true;
+    else if (note_use(*plan, s) != LFBP_OK)
+        return LFBP_EDEVICE;
+    evict_plans();
+    return LFBP_OK;
 }
 
 lfbp_status lfbp_compute_Ht_batched(const lfbp_problem* problems, int32_t count, lfbp_dtype dtype, void* stream)
@@ -508,7 +711,17 @@ lfbp_status lfbp_compute_Ht_colmajor(const void* H, void* Ht, lfbp_shape shape, 
 void lfbp_release_plans(void)
 {
     std::lock_guard<std::mutex> lock(g_plan_mu);
+    for (auto& p : g_plans) p->wait_idle();
+    for (auto& p : g_retired) p->wait_idle();
     g_plans.clear();
+    g_retired.clear();
+}
+
+int32_t lfbp_plan_count(void)
+{
+    std::lock_guard<std::mutex> lock(g_plan_mu);
+    reap_retired();
+    return int32_t(g_plans.size() + g_retired.size());
 }
 
 }  // extern "C"

@@ -32,6 +32,8 @@
 // problems).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstring>
 #include <iterator>
 #include <vector>
 
@@ -342,8 +344,9 @@ __device__ __forceinline__ void wide_unit(const GatherDesc& d, uint32_t unit, Ro
 }
 
 // Persistent, software-pipelined walk over global units u_first,
-// u_first + stride, ... below total.  Get(u, desc, local) returns the
-// descriptor and the problem-local index of global unit u.
+// u_first + stride, ... below total.  get(u, desc, local) returns whether unit
+// u exists, and then its descriptor and problem-local index; a unit that does
+// not exist (a hole of a batched walk) is run with no rows: no load, no store.
 template <typename T, int M, class Get>
 __device__ __forceinline__ void wide_pipeline(uint32_t u_first, uint32_t stride, uint32_t total, Get get,
                                               RowEnt* tab0, RowEnt* tab1, T* tile, bool nt)
@@ -352,9 +355,9 @@ __device__ __forceinline__ void wide_pipeline(uint32_t u_first, uint32_t stride,
     if (u_first >= total) return;
     GatherDesc dc;
     uint32_t lc;
-    get(u_first, dc, lc);
-    uint32_t R0 = lc * dc.rows_per_unit;
-    uint32_t nr = min(dc.rows_per_unit, dc.nrows - R0);
+    const bool ok = get(u_first, dc, lc);
+    uint32_t R0 = ok ? lc * dc.rows_per_unit : 0;
+    uint32_t nr = ok ? min(dc.rows_per_unit, dc.nrows - R0) : 0;
     wide_table<T>(dc, R0, nr, tab0);
     lds_barrier();
     u32x4 v[M];
@@ -371,9 +374,10 @@ __device__ __forceinline__ void wide_pipeline(uint32_t u_first, uint32_t stride,
         uint32_t ln = 0, Rn = 0, nn = 0;
         const bool more = uint64_t(u) + stride < total;
         if (more) {
-            get(u + stride, dn, ln);
-            Rn = ln * dn.rows_per_unit;
-            nn = min(dn.rows_per_unit, dn.nrows - Rn);
+            if (get(u + stride, dn, ln)) {
+                Rn = ln * dn.rows_per_unit;
+                nn = min(dn.rows_per_unit, dn.nrows - Rn);
+            }
             wide_table<T>(dn, Rn, nn, tn);
         }
         lds_barrier();                                    // tile and next table complete
@@ -433,46 +437,68 @@ __global__ void __launch_bounds__(512) k_wide_persist(GatherDesc d, int nt)
     auto get = [&](uint32_t u, GatherDesc& dd, uint32_t& lu) {
         dd = d;
         lu = u;
+        return true;
     };
     wide_pipeline<T, M>(persistent_first(blockIdx.x, gridDim.x), gridDim.x, d.nunits, get, tab0, tab1, tile,
                         nt != 0);
 }
 
-// Problem and problem-local unit of global unit g of a batch.  Up to
-// kInlineProblems descriptors travel in the kernel arguments (found with a
-// scalar scan, no dependent memory loads); larger batches use a device table
-// searched by bisection.
-__device__ __forceinline__ void batch_unit(const BatchArgs& a, uint32_t g, GatherDesc& d, uint32_t& local)
+// Problem and problem-local unit of slot b of a batched launch: slot b is
+// unit l = b / kXcds of the walk of XCD x = b mod kXcds (the XCD that
+// workgroup b runs on), which takes an even share of every problem in turn.
+// Up to kInlineProblems descriptors travel in the kernel arguments (found with
+// a scalar scan, no dependent memory loads); larger batches use a device table
+// whose per-XCD prefix sums are searched by bisection.  Returns false for the
+// slots past the end of the XCD's walk (d is then a valid descriptor of the
+// batch and local 0, so that callers may run it with no rows).
+__device__ __forceinline__ bool batch_slot(const BatchArgs& a, uint32_t b, GatherDesc& d, uint32_t& local)
 {
+    const uint32_t x = b & (kXcds - 1), l = b / kXcds;
+    if (l >= a.xtotal[x]) {
+        d = a.table == nullptr ? a.d[0] : a.table[0];
+        local = 0;
+        return false;
+    }
     if (a.table == nullptr) {
-        uint32_t p = 0;
+        uint32_t p = 0, base = 0;
+        bool found = false;
 #pragma unroll
-        for (uint32_t i = 1; i < kInlineProblems; ++i)
-            if (i < a.count && a.start[i] <= g) p = i;
+        for (uint32_t i = 0; i < kInlineProblems; ++i) {
+            if (!found && i < a.count) {
+                const uint32_t c = xcd_share(a.d[i].nunits, x);
+                if (l < base + c) {
+                    p = i;
+                    found = true;
+                } else {
+                    base += c;
+                }
+            }
+        }
         d = a.d[p];
-        local = g - a.start[p];
+        local = xcd_first(d.nunits, x) + (l - base);
     } else {
-        uint32_t lo = 0, hi = a.count;  // table_start[lo] <= g < table_start[hi]
+        const uint32_t* xs = a.table_xstart + size_t(x) * (a.count + 1);
+        uint32_t lo = 0, hi = a.count;  // xs[lo] <= l < xs[hi]
         while (hi - lo > 1) {
             const uint32_t mid = (lo + hi) >> 1;
-            if (a.table_start[mid] <= g)
+            if (xs[mid] <= l)
                 lo = mid;
             else
                 hi = mid;
         }
         d = a.table[lo];
-        local = g - a.table_start[lo];
+        local = xcd_first(d.nunits, x) + (l - xs[lo]);
     }
+    return true;
 }
 
 template <typename T, int S, int U>
 __global__ void __launch_bounds__(512) k_direct_batched(BatchArgs a)
 {
-    for (uint32_t g = blockIdx.x; g < a.total; g += gridDim.x) {
+    for (uint32_t b = blockIdx.x; b < kXcds * a.slots; b += gridDim.x) {
         GatherDesc d;
         uint32_t lu;
-        batch_unit(a, g, d, lu);
-        direct_unit<T, S, U>(d, lu, a.nt != 0);
+        if (batch_slot(a, b, d, lu)) direct_unit<T, S, U>(d, lu, a.nt != 0);
     }
 }
 
@@ -481,31 +507,29 @@ __global__ void __launch_bounds__(512) k_staged_batched(BatchArgs a)
 {
     extern __shared__ u32x4 smem[];
     T* lds = reinterpret_cast<T*>(smem);
-    for (uint32_t g = blockIdx.x; g < a.total; g += gridDim.x) {
+    for (uint32_t b = blockIdx.x; b < kXcds * a.slots; b += gridDim.x) {
         GatherDesc d;
         uint32_t lu;
-        batch_unit(a, g, d, lu);
-        staged_unit<T, S, U>(d, lu, lds, a.nt != 0);
+        if (batch_slot(a, b, d, lu)) staged_unit<T, S, U>(d, lu, lds, a.nt != 0);
     }
 }
 
-// One workgroup per unit over all problems (units of one XCD contiguous when
-// the grid covers every unit).
+// One workgroup per unit over all problems.
 template <typename T, int M>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(M >= 8 ? 5 : 8))) k_wide_batched(BatchArgs a)
+__global__ void __launch_bounds__(512) k_wide_batched(BatchArgs a)
 {
     extern __shared__ u32x4 smem[];
     RowEnt* tab = reinterpret_cast<RowEnt*>(smem);
     T* tile = reinterpret_cast<T*>(smem + a.max_rows);
-    for (uint32_t b = blockIdx.x; b < a.total; b += gridDim.x) {
+    for (uint32_t b = blockIdx.x; b < kXcds * a.slots; b += gridDim.x) {
         GatherDesc d;
         uint32_t lu;
-        batch_unit(a, unit_of_block(b, a.total, gridDim.x == a.total), d, lu);
-        wide_unit<T, M>(d, lu, tab, tile, a.nt != 0);
+        if (batch_slot(a, b, d, lu)) wide_unit<T, M>(d, lu, tab, tile, a.nt != 0);
     }
 }
 
-// Persistent and pipelined over all problems.
+// Persistent and pipelined over all problems (the grid is a multiple of
+// kXcds, so each workgroup stays on one XCD's walk).
 template <typename T, int M>
 __global__ void __launch_bounds__(512) k_wide_batched_persist(BatchArgs a)
 {
@@ -513,9 +537,14 @@ __global__ void __launch_bounds__(512) k_wide_batched_persist(BatchArgs a)
     RowEnt* tab0 = reinterpret_cast<RowEnt*>(smem);
     RowEnt* tab1 = tab0 + a.max_rows;
     T* tile = reinterpret_cast<T*>(smem + 2 * a.max_rows);
-    auto get = [&](uint32_t u, GatherDesc& dd, uint32_t& lu) { batch_unit(a, u, dd, lu); };
-    wide_pipeline<T, M>(persistent_first(blockIdx.x, gridDim.x), gridDim.x, a.total, get, tab0, tab1, tile,
-                        a.nt != 0);
+    auto get = [&](uint32_t u, GatherDesc& dd, uint32_t& lu) { return batch_slot(a, u, dd, lu); };
+    wide_pipeline<T, M>(blockIdx.x, gridDim.x, kXcds * a.slots, get, tab0, tab1, tile, a.nt != 0);
+}
+
+// Device-side copy of up to kPutWords words carried in the kernel arguments.
+__global__ void __launch_bounds__(256) k_put_words(WordChunk c)
+{
+    for (uint32_t i = threadIdx.x; i < c.n; i += blockDim.x) c.dst[i] = c.w[i];
 }
 
 // ---------------------------------------------------------------- host side
@@ -621,6 +650,24 @@ hipError_t launch_gather(const GatherDesc& d, int esize, const LaunchPlan& p, hi
     PlainFn fn = pick_plain_any(p, d.W, esize);
     hipLaunchKernelGGL(fn, dim3(p.grid), dim3(p.threads), size_t(p.lds_bytes), stream, d, p.nontemporal == 1 ? 1 : 0);
     return hipGetLastError();
+}
+
+// Write n words from host memory to device memory dst, ordered on stream:
+// the words travel in the arguments of small copy kernels, so src may be
+// reused as soon as this returns and the writes may be captured into a graph.
+hipError_t put_words(uint32_t* dst, const uint32_t* src, size_t n, hipStream_t stream)
+{
+    for (size_t i = 0; i < n; i += kPutWords) {
+        WordChunk c;
+        c.dst = dst + i;
+        c.n = uint32_t(std::min<size_t>(kPutWords, n - i));
+        c.pad = 0;
+        std::memcpy(c.w, src + i, sizeof(uint32_t) * c.n);
+        hipLaunchKernelGGL(k_put_words, dim3(1), dim3(256), 0, stream, c);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_gather_batched(const BatchArgs& a, uint32_t maxW, int esize, const LaunchPlan& p,

@@ -92,22 +92,48 @@ struct LaunchPlan {
 
 // Kernel arguments of a batched launch.  Up to kInlineProblems descriptors
 // travel by value (table == nullptr); larger batches point at a device table
-// of descriptors and unit prefix sums.
+// of descriptors and per-XCD slot prefix sums.
 constexpr uint32_t kInlineProblems = 16;
+
+// Workgroups of a launch are dealt to the XCDs round-robin (workgroup b runs
+// on XCD b mod kXcds).  A batched launch gives every XCD an even share of
+// every problem: XCD x owns, of problem p's n units, the contiguous run
+//   [x*(n/8) + min(x, n%8), ... + n/8 + (x < n%8)),
+// and walks its runs problem after problem (problems sorted largest first).
+// Slot (x, l) is the l-th unit of XCD x's walk.
+constexpr uint32_t kXcds = 8;
+
+LFBP_HD inline uint32_t xcd_share(uint32_t n, uint32_t x) { return n / kXcds + (x < n % kXcds ? 1u : 0u); }
+LFBP_HD inline uint32_t xcd_first(uint32_t n, uint32_t x)
+{
+    return x * (n / kXcds) + (x < n % kXcds ? x : n % kXcds);
+}
 
 // LDS the in-place kernel can count on on every device (a pair of x-rows must
 // fit; larger budgets give larger row groups).
 constexpr int kInplaceMinLds = 65536;
 
 struct BatchArgs {
-    const GatherDesc* table;     // device descriptor table, or nullptr
-    const uint32_t* table_start; // device: first global unit of each problem, count+1 entries
-    uint32_t count;              // problems
-    uint32_t total;              // work units of all problems
-    uint32_t max_rows;           // largest rows_per_unit (LDS table size)
-    uint32_t nt;                 // 1: streaming stores
-    uint32_t start[kInlineProblems + 1];
+    const GatherDesc* table;      // device descriptor table, or nullptr
+    const uint32_t* table_xstart; // device [kXcds][count+1]: first slot of each problem in each XCD's walk
+    uint32_t count;               // problems
+    uint32_t slots;               // longest XCD walk; slots b < kXcds*slots cover every unit
+    uint32_t max_rows;            // largest rows_per_unit (LDS table size)
+    uint32_t nt;                  // 1: streaming stores
+    uint32_t xtotal[kXcds];       // units in each XCD's walk
     GatherDesc d[kInlineProblems];
+};
+
+// Words written into device memory by one launch of the table-writer kernel
+// (descriptor tables travel to the device as kernel arguments, so uploading
+// them is stream-ordered and needs no host buffer to outlive the call).
+constexpr uint32_t kPutWords = 512;
+
+struct WordChunk {
+    uint32_t* dst;
+    uint32_t n;
+    uint32_t pad;
+    uint32_t w[kPutWords];
 };
 
 // 16-byte row-table entry of the WIDE kernels: where an input x-row starts

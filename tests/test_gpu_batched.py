@@ -213,3 +213,98 @@ def test_small_set_batch_full_compare():
         torch.cuda.synchronize()
         for i, (o, h) in enumerate(zip(got, new)):
             assert_same_bits(o.cpu().numpy(), oracle.Ht_rows(h), f"prepared call {rep}, set {i}")
+
+
+def test_plan_cache_stays_bounded():
+    """100 batched calls, each with fresh output tensors (a new pointer table,
+    so a new plan each time; 17 problems, so each plan holds a device
+    descriptor table): the number of plans the library holds stays at its
+    bound, device memory stays flat once the cache is full, and every result
+    is still the oracle's."""
+    lf.release_plans()
+    shapes = mixed_shapes(77, 17)
+    Hs = [lfsynth.bits(s, 3 * i + 2, np.float32) for i, s in enumerate(shapes)]
+    refs = [oracle.Ht_rows(H) for H in Hs]
+    dHs = [to_dev(H) for H in Hs]
+    all_outs = [[torch.empty_like(h) for h in dHs] for _ in range(100)]   # distinct pointers every call
+    torch.cuda.synchronize()
+    free_at = {}
+    for k, outs in enumerate(all_outs):
+        lf.compute_Ht_batched(dHs, outs)
+        if k in (40, 99):
+            torch.cuda.synchronize()
+            free_at[k] = torch.cuda.mem_get_info()[0]
+    torch.cuda.synchronize()
+    lf.compute_Ht_batched(dHs, all_outs[-1])          # a known table: reaps finished retired plans
+    assert lf.plan_count() <= 32, lf.plan_count()
+    assert free_at[99] >= free_at[40] - (64 << 20), (free_at[40] - free_at[99]) / 2 ** 20
+    for k in (0, 57, 99):
+        for i, (o, r) in enumerate(zip(all_outs[k], refs)):
+            assert_same_bits(o.cpu().numpy(), r, f"call {k} set {i}")
+    lf.release_plans()
+    assert lf.plan_count() == 0
+
+
+def test_new_table_used_from_a_second_stream_at_once():
+    """A plan made by a call on one stream (its device table written by
+    kernels on that stream) and used at once, with no synchronisation, by a
+    call on another stream: the second launch waits for the table."""
+    lf.release_plans()
+    shapes = mixed_shapes(91, 24)
+    Hs = [lfsynth.bits(s, 11 * i + 5, np.float32) for i, s in enumerate(shapes)]
+    dHs = [to_dev(H) for H in Hs]
+    outs_a = [torch.empty_like(h) for h in dHs]
+    outs_b = [torch.empty_like(h) for h in dHs]
+    torch.cuda.synchronize()
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    busy = torch.empty(1 << 26, device=DEV)
+    with torch.cuda.stream(sa):
+        busy.normal_()                                  # keeps stream a busy before the table is written
+        lf.compute_Ht_batched(dHs, outs_a)
+    with torch.cuda.stream(sb):
+        lf.compute_Ht_batched(dHs, outs_a)              # same table, same plan, other stream
+        lf.compute_Ht_batched(dHs, outs_b)
+    torch.cuda.synchronize()
+    for i, H in enumerate(Hs):
+        ref = oracle.Ht_rows(H)
+        assert_same_bits(outs_a[i].cpu().numpy(), ref, f"set {i}")
+        assert_same_bits(outs_b[i].cpu().numpy(), ref, f"set {i}, second table")
+    lf.release_plans()
+
+
+def test_table_of_many_problems_first_made_under_capture():
+    """A 20-problem table submitted first inside a caller's stream capture
+    needs a device table, which cannot be allocated there: the call returns
+    ECAPTURE before any HIP call and the capture stays valid.  Submitted once
+    outside, the same table is then captured, and every replay gives the
+    oracle's H'."""
+    from paper_2003_09133_amd import _abi
+    lf.release_plans()
+    shapes = mixed_shapes(5, 20)
+    dHs = [torch.empty(s, dtype=torch.float32, device=DEV) for s in shapes]
+    outs = [torch.empty_like(h) for h in dHs]
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        with pytest.raises(lf.LfbpError) as err:
+            lf.compute_Ht_batched(dHs, outs)
+    assert err.value.status == _abi.ECAPTURE
+    assert lf.plan_count() == 0
+    lf.compute_Ht_batched(dHs, outs)                    # makes the plan
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        lf.compute_Ht_batched(dHs, outs)
+    for rep in range(3):
+        hs = [lfsynth.bits(s, 70 * rep + i, np.float32) for i, s in enumerate(shapes)]
+        for d, h in zip(dHs, hs):
+            d.copy_(torch.from_numpy(h))
+        for o in outs:
+            o.fill_(float("nan"))
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for i, (o, h) in enumerate(zip(outs, hs)):
+            assert_same_bits(o.cpu().numpy(), oracle.Ht_rows(h), f"replay {rep} set {i}")
+    del graph
+    lf.release_plans()
