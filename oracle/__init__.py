@@ -26,7 +26,7 @@ def build(verbose: bool = False) -> str:
     """Compile the oracle with gcc (-O2, OpenMP)."""
     global _lib
     cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
-           os.path.join(_HERE, "lfbp_oracle.c"), "-o", _SO + ".tmp"]
+           os.path.join(_HERE, "lfbp_oracle.c"), os.path.join(_HERE, "lfbp_paper.c"), "-o", _SO + ".tmp"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
@@ -56,6 +56,7 @@ def _load():
             "oracle_backward_d": [vp, vp, vp, i64, i64, vp, i32],
             "oracle_grad_psf": [vp, vp, vp, i64, i64, vp, i32],
             "oracle_grad_psf_at": [vp, vp, vp, i64, i64, vp, i64, vp, i32],
+            "paper_Ht": [vp, i32, vp, vp, i32, vp],
         }.items():
             fn = getattr(lib, name)
             fn.argtypes = args
@@ -123,6 +124,21 @@ def Ht_at(H: np.ndarray, flat_idx: np.ndarray, nthreads: int = 0) -> np.ndarray:
     _check(_load().oracle_Ht_at(H.ctypes.data, H.dtype.itemsize, _dims(H).ctypes.data,
                                 idx.ctypes.data, idx.size, out.ctypes.data, nthreads), "oracle_Ht_at")
     return out
+
+
+def paper_Ht(H: np.ndarray, nthreads: int = 0, out: np.ndarray | None = None):
+    """H' by the paper's own method (Sec. 4: Eq. 3 with the relations of
+    Eqs. 4-9, looped as in Fig. 10), for timing "the paper's method on this
+    host".  Entries the relations do not reach keep the value they had in
+    ``out`` (zeros when ``out`` is None).  Returns ``(Ht, depth_columns_written)``."""
+    H = _payload(H)
+    if out is None:
+        out = np.zeros_like(H)
+    assert out.shape == H.shape and out.dtype == H.dtype and out.flags.c_contiguous
+    cols = ctypes.c_int64(0)
+    _check(_load().paper_Ht(H.ctypes.data, H.dtype.itemsize, _dims(H).ctypes.data, out.ctypes.data, nthreads,
+                            ctypes.byref(cols)), "paper_Ht")
+    return out, cols.value
 
 
 def _f32(a):

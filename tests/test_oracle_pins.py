@@ -303,3 +303,35 @@ def test_forward_at_and_backward_at_match_full():
     assert np.array_equal(oracle.forward_at(H, g, pix), full_f[pix[:, 0], pix[:, 1]])
     vox = np.array([(0, 0, 0), (1, R - 1, C - 1), (1, 4, 9)])
     assert np.array_equal(oracle.backward_at(H, f, vox), full_b[vox[:, 0], vox[:, 1], vox[:, 2]])
+
+
+# ---------------------------------------------------------------- the paper's method in C
+
+PAPER_SHAPES = [(5, 5, 3, 3, 2), (15, 15, 3, 3, 3), (7, 9, 3, 5, 2), (9, 11, 5, 3, 4), (3, 5, 5, 3, 1),
+                (11, 7, 1, 1, 2), (13, 13, 5, 5, 1), (21, 17, 7, 5, 3)]
+
+
+@pytest.mark.parametrize("shape", PAPER_SHAPES)
+def test_paper_method_in_c_equals_the_per_axis_relations(shape):
+    """oracle.paper_Ht (C, timed by the benchmark as the paper's method) writes
+    exactly the entries the per-axis transcription of Eqs. 4-9 writes, with the
+    same values, and leaves the others untouched."""
+    H = lfsynth.bits(shape, 31, np.float32)
+    ref, written, _ = paper_eqs.literal_Ht(H)
+    canary = np.full(H.shape, np.float32(-7.25))
+    got, cols = oracle.paper_Ht(H, out=canary.copy())
+    mask = np.broadcast_to(written[..., None], H.shape)
+    assert np.array_equal(got.view(np.uint32)[mask], ref.view(np.uint32)[mask])
+    assert (got[~mask] == np.float32(-7.25)).all()
+    assert cols == int(written.sum())
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float16])
+def test_paper_method_in_c_equals_the_oracle_with_zero_borders(dtype):
+    """On the generator's PSFs (zero on the patch border bands) the paper's
+    method gives the whole of the oracle's H', for 1 and several threads."""
+    H, _ = lfsynth.make_H(lfsynth.TINY, dtype)
+    ref = oracle.Ht_rows(H)
+    for nth in (1, 3):
+        got, _ = oracle.paper_Ht(H, nthreads=nth)
+        assert got.tobytes() == ref.tobytes()
