@@ -1,9 +1,17 @@
 #!/usr/bin/env python3
 """Benchmark of the H' build (and its batched and projector forms) on one GPU.
 
-    python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline] [--no-extras]
 
-Prints ONE JSON line.  A step is one pass of the hot path over its synthetic
+Prints ONE JSON line.  The default workload is the camera PSF
+H[345,345,15,15,51] in float32, the largest single-GPU configuration; its line
+also carries, measured in the same run, the camera PSF in float16 storage, the
+microscope PSF, and the 16-set batched table against 16 per-set launches
+(minimum and median step times of both), and, from the oracle leg, a bit-exact
+comparison of every timed output with the CPU oracle (whole arrays for the
+float32 PSFs, samples for the others).
+
+A step is one pass of the hot path over its synthetic
 input, already resident in HBM: one lfbp_compute_Ht call (plain workloads), one
 lfbp_compute_Ht_batched call over a table of PSF sets (batched, batched-small),
 one forward plus one backward projection (projector), one Richardson-Lucy
@@ -36,10 +44,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="microscope",
+    ap.add_argument("--workload", default="camera",
                     choices=sorted(PLAIN) + ["batched", "batched-small", "projector", "rl", "grad-psf", "table1"])
     ap.add_argument("--variant", default=None, choices=[None, "direct", "staged"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="camera workload: skip the camera-f16, microscope and batched figures")
     ap.add_argument("--inplace", action="store_true",
                     help="plain workloads: time lfbp_compute_Ht_inplace (H' written over H)")
     ap.add_argument("--copy", action="store_true",
@@ -160,23 +170,42 @@ def cores_used() -> int:
 
 
 def time_steps(fn, steps, warmup, torch):
+    """Total seconds of `steps` back-to-back calls of fn on the current stream
+    (HIP events), and the wall time around them."""
+    total, wall, _ = time_each(fn, steps, warmup, torch)
+    return total, wall
+
+
+def time_each(fn, steps, warmup, torch):
+    """`steps` back-to-back calls of fn with a HIP event recorded on the
+    current stream between consecutive calls: (total seconds, wall seconds,
+    per-step seconds)."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     t0 = time.perf_counter()
-    start.record(stream)
-    for _ in range(steps):
+    ev[0].record(stream)
+    for i in range(steps):
         fn()
-    stop.record(stream)
+        ev[i + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return start.elapsed_time(stop) / 1000.0, wall
+    per = [ev[i].elapsed_time(ev[i + 1]) / 1000.0 for i in range(steps)]
+    return ev[0].elapsed_time(ev[steps]) / 1000.0, wall, per
+
+
+def spread_ms(per):
+    """min / median / mean of per-step seconds, in ms."""
+    import statistics
+    return {"min": round(min(per) * 1e3, 4), "median": round(statistics.median(per) * 1e3, 4),
+            "mean": round(sum(per) / len(per) * 1e3, 4)}
 
 
 def cpu_oracle_rate(H, nthreads, budget_s):
-    """Oracle H' on the host: GB/s of (read + write) on whole passes over H."""
+    """Oracle H' on the host: GB/s of (read + write) on whole passes over H.
+    Returns (GB/s, passes, seconds per pass, the oracle's H')."""
     import numpy as np
     import oracle
     out = np.empty_like(H)
@@ -188,7 +217,110 @@ def cpu_oracle_rate(H, nthreads, budget_s):
     for _ in range(reps):
         oracle.Ht_rows(H, nthreads=nthreads, out=out)
     dt = (time.perf_counter() - t0) / reps
-    return 2.0 * H.nbytes / dt / 1e9, reps + 1, dt
+    return 2.0 * H.nbytes / dt / 1e9, reps + 1, dt, out
+
+
+def paper_method_rates(H, nthreads):
+    """The paper's own method (oracle.paper_Ht: Eqs. 4-9 looped as in Fig. 10)
+    on the host, one pass on one core and one on `nthreads`: GB/s of (read +
+    write) of H's bytes."""
+    import numpy as np
+    import oracle
+    out = np.zeros_like(H)
+    rates = {}
+    for n in (1, nthreads):
+        t0 = time.perf_counter()
+        oracle.paper_Ht(H, nthreads=n, out=out)
+        rates[n] = 2.0 * H.nbytes / (time.perf_counter() - t0) / 1e9
+    return rates
+
+
+def _bits(a):
+    import numpy as np
+    return a.view(np.uint32 if a.dtype.itemsize == 4 else np.uint16)
+
+
+def oracle_parity(checks, nthreads, full_ref=None):
+    """Bit-exact comparison of the timed GPU outputs with the oracle.  Each
+    check is (name, H, idx, got): idx None means `got` is the whole H' (compared
+    with the oracle's whole H', or with `full_ref[name]` when the timing passes
+    already produced it), else `got` holds H' at the flat indices idx."""
+    import numpy as np
+    import oracle
+    res = {}
+    for name, H, idx, got in checks:
+        if idx is None:
+            ref = (full_ref or {}).get(name)
+            if ref is None:
+                ref = oracle.Ht_rows(H, nthreads=nthreads)
+            bad = int(np.count_nonzero(_bits(ref).ravel() != _bits(got).ravel()))
+            res[name] = {"compared": f"all {got.size} elements", "mismatches": bad}
+        else:
+            ref = oracle.Ht_at(H, idx, nthreads=nthreads)
+            bad = int(np.count_nonzero(_bits(ref) != _bits(got)))
+            res[name] = {"compared": f"{idx.size} sampled elements", "mismatches": bad}
+    return res
+
+
+def gather_run(torch, lf, H, steps, warmup, config=None):
+    """Upload H, then time `steps` lfbp_compute_Ht calls into one output.
+    Returns (total s, wall s, per-step s, output tensor on the GPU)."""
+    dH = torch.from_numpy(H).to(torch.device("cuda:0"))
+    dHt = torch.empty_like(dH)
+    total, wall, per = time_each(lambda: lf.compute_Ht_into(dH, dHt, config=config), steps, warmup, torch)
+    del dH
+    return total, wall, per, dHt
+
+
+def gpu_sample(torch, t, idx):
+    """Elements of GPU tensor t at flat indices idx, copied to the host."""
+    return t.view(-1)[torch.from_numpy(idx).to(t.device)].cpu().numpy()
+
+
+def batched_vs_sequential(args, torch, lf, lfsynth, sets, rng):
+    """The batched call against one plain call per set, timed step by step on
+    the same tensors.  Returns (figures, checks for the oracle leg)."""
+    import numpy as np
+    from paper_2003_09133_amd import _abi
+
+    dev = torch.device("cuda:0")
+    Hs_host, Hs, Hts = [], [], []
+    for w in sets:
+        H, _ = lfsynth.make_H(w)
+        Hs_host.append(H)
+        Hs.append(torch.from_numpy(H).to(dev))
+        Hts.append(torch.empty_like(Hs[-1]))
+    nbytes = sum(2 * h.numel() * h.element_size() for h in Hs)
+    batched = lf.BatchedHt(Hs, Hts)
+    L = _abi.lib()
+    plain_args = [(h.data_ptr(), o.data_ptr(), _abi.Shape.of(h.shape)) for h, o in zip(Hs, Hts)]
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def sequential():
+        for hp, op, shp in plain_args:
+            L.lfbp_compute_Ht(hp, op, shp, _abi.F32, stream)
+
+    # two alternating rounds of each form, so that slow drifts of the clock or
+    # the memory state fall on both
+    per_seq, per_bat = [], []
+    for _ in range(2):
+        per_seq += time_each(sequential, args.steps, args.warmup, torch)[2]
+        per_bat += time_each(batched, args.steps, args.warmup, torch)[2]
+    checks = []
+    for i, (H, o) in enumerate(zip(Hs_host, Hts)):          # outputs of the last (batched) call
+        idx = rng.integers(0, H.size, 200_000)
+        checks.append((f"batched set {i} {list(H.shape)}", H, idx, gpu_sample(torch, o, idx)))
+    del Hs, Hts, batched
+    s_seq, s_bat = spread_ms(per_seq), spread_ms(per_bat)
+    figures = {
+        "sets": len(sets), "bytes_per_step": nbytes, "steps_per_form": len(per_bat),
+        "batched_ms": s_bat, "sequential_ms": s_seq,
+        "batched_GBs_median": round(nbytes / (s_bat["median"] * 1e-3) / 1e9, 1),
+        "speedup_median": round(s_seq["median"] / s_bat["median"], 4),
+        "speedup_min": round(s_seq["min"] / s_bat["min"], 4),
+        "speedup_mean": round(s_seq["mean"] / s_bat["mean"], 4),
+    }
+    return figures, checks
 
 
 def bench_plain(args, torch):
@@ -201,22 +333,26 @@ def bench_plain(args, torch):
     npdt = np.float32 if dt == "f32" else np.float16
     H, zf = lfsynth.make_H(w, npdt)
     dev = torch.device("cuda:0")
-    dH = torch.from_numpy(H).to(dev)
-    dHt = torch.empty_like(dH)
     cfg = None
     if args.variant:
         cfg = {"variant": lf.GATHER_DIRECT if args.variant == "direct" else lf.GATHER_STAGED}
-    resolved = lf.default_config(w.shape, dH.dtype)
+    resolved = lf.default_config(w.shape, torch.float32 if dt == "f32" else torch.float16)
     if cfg:
         resolved.update(cfg)
-    if args.copy:
-        step = lambda: dHt.copy_(dH)
-    elif args.inplace:
-        del dHt
-        step = lambda: lf.compute_Ht_inplace(dH)     # each step undoes the previous one (involution)
+    got = None
+    if args.copy or args.inplace:
+        dH = torch.from_numpy(H).to(dev)
+        if args.copy:
+            dHt = torch.empty_like(dH)
+            step = lambda: dHt.copy_(dH)
+        else:
+            step = lambda: lf.compute_Ht_inplace(dH)     # each step undoes the previous one (involution)
+        elapsed, wall, per = time_each(step, args.steps, args.warmup, torch)
     else:
-        step = lambda: lf.compute_Ht_into(dH, dHt, config=cfg)
-    elapsed, wall = time_steps(step, args.steps, args.warmup, torch)
+        elapsed, wall, per, dHt = gather_run(torch, lf, H, args.steps, args.warmup, cfg)
+        got = dHt.cpu().numpy()
+        del dHt
+    torch.cuda.empty_cache()
     bytes_step = 2 * H.nbytes
     sec_step = elapsed / args.steps
     gbs = bytes_step / sec_step / 1e9
@@ -225,7 +361,7 @@ def bench_plain(args, torch):
         "warmup": args.warmup, "ms_per_step": round(sec_step * 1e3, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": dt, "data": "synthetic",
         "config": {"workload": f"{w.name} H{list(w.shape)} {dt}", "shape": list(w.shape),
-                   "bytes_per_step": bytes_step, "zero_fraction": round(zf, 4),
+                   "bytes_per_step": bytes_step, "zero_fraction": round(zf, 4), "step_ms": spread_ms(per),
                    "kernel": ("torch copy_ (reference)" if args.copy else
                               "k_inplace (H' over H)" if args.inplace else resolved), "wall_s": round(wall, 3)},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -233,12 +369,48 @@ def bench_plain(args, torch):
                      "traffic": (None if args.copy else inplace_traffic(args.workload) if args.inplace
                                  else traffic_from_profile(args.workload))},
     }
+    checks = [] if got is None else [(out["config"]["workload"], H, None, got)]
+    if args.workload == "camera" and not (args.copy or args.inplace or args.no_extras):
+        rng = np.random.default_rng(2003)
+        also = {}
+        # the same PSF in float16 storage
+        H16 = H.astype(np.float16)
+        t16, _, per16, d16 = gather_run(torch, lf, H16, args.steps, args.warmup)
+        idx = rng.integers(0, H16.size, 2_000_000)
+        checks.append((f"{w.name} H{list(w.shape)} f16", H16, idx, gpu_sample(torch, d16, idx)))
+        del d16
+        torch.cuda.empty_cache()
+        g16 = 2 * H16.nbytes / (t16 / args.steps) / 1e9
+        also["camera-f16"] = {"GBs": round(g16, 1), "frac": round(g16 / HBM_PEAK_GBS, 4), "step_ms": spread_ms(per16),
+                              "traffic": traffic_from_profile("camera-f16")}
+        # the microscope PSF (1 GB per step: partly held by the 256 MB MALL between steps)
+        mw = lfsynth.MICROSCOPE
+        Hm, _ = lfsynth.make_H(mw)
+        tm, _, perm, dm = gather_run(torch, lf, Hm, args.steps, args.warmup)
+        checks.append((f"{mw.name} H{list(mw.shape)} f32", Hm, None, dm.cpu().numpy()))
+        del dm
+        torch.cuda.empty_cache()
+        gm = 2 * Hm.nbytes / (tm / args.steps) / 1e9
+        also["microscope"] = {"GBs": round(gm, 1), "frac": round(gm / HBM_PEAK_GBS, 4), "step_ms": spread_ms(perm),
+                              "traffic": traffic_from_profile("microscope")}
+        # 16 PSF sets: one batched launch against 16 per-set launches
+        also["batched-16"], bchecks = batched_vs_sequential(args, torch, lf, lfsynth, lfsynth.BATCHED_SETS, rng)
+        checks += bchecks
+        torch.cuda.empty_cache()
+        out["config"]["also"] = also
     if not args.no_cpu_baseline and not args.copy and not args.inplace:
         nth = cores_used()
-        rate, passes, per = cpu_oracle_rate(H, nth, args.cpu_seconds)
+        rate, passes, per_pass, ref = cpu_oracle_rate(H, nth, args.cpu_seconds)
         out["cpu_baseline"] = {"value": round(rate, 3), "unit": "GB/s", "cores": nth, "kind": "oracle",
                                "sample": f"{passes} full passes of the oracle over the same H "
-                                         f"({per:.2f} s each)"}
+                                         f"({per_pass:.2f} s each)"}
+        if args.workload == "camera":
+            pm = paper_method_rates(H, nth)
+            out["cpu_baseline"]["paper_method"] = {
+                "GBs_1_core": round(pm[1], 3), f"GBs_{nth}_cores": round(pm[nth], 3),
+                "sample": "one pass of the paper's method (Eqs. 4-9 looped as in Fig. 10, C) over the same H "
+                          "on each core count"}
+        out["config"]["bit_exact_vs_oracle"] = oracle_parity(checks, nth, {out["config"]["workload"]: ref})
     return out
 
 
@@ -570,7 +742,7 @@ def bench_table1(args, torch):
         nth = cores_used()
         w = lfsynth.table1_workload(3)
         H, _ = lfsynth.make_H(w)
-        rate, passes, per = cpu_oracle_rate(H, nth, args.cpu_seconds)
+        rate, passes, per, _ = cpu_oracle_rate(H, nth, args.cpu_seconds)
         out["cpu_baseline"] = {"value": round(rate, 3), "unit": "GB/s", "cores": nth, "kind": "oracle",
                                "sample": f"{passes} full passes of the (row-major) oracle over the Table 1 "
                                          f"size {list(w.shape)} ({per:.2f} s each)"}
