@@ -300,8 +300,11 @@ lfbp_status layout_batch(const lfbp_problem* probs, int32_t count, int es, const
     a.slots = uint32_t(slots);
     a.max_rows = max_rows;
     a.nt = c.nontemporal == 1 ? 1 : 0;
-    if (uint32_t(count) <= kInlineProblems)
+    if (uint32_t(count) <= kInlineProblems) {
         for (int32_t k = 0; k < count; ++k) a.d[k] = L.descs[size_t(k)];
+        for (uint32_t x = 0; x < kXcds; ++x)
+            for (int32_t k = 0; k <= count; ++k) a.xstart[x][k] = L.xstart[x * (size_t(count) + 1) + size_t(k)];
+    }
     LaunchPlan lp = make_plan(c, lds);
     const uint64_t nslots = uint64_t(kXcds) * slots;
     if (c.persistent != 1) {

@@ -49,8 +49,28 @@ union Pack16 {
     T e[16 / sizeof(T)];
 };
 
+// Pointers into global memory.  The arrays are always addressed through
+// these: a batched launch reads its descriptors with a runtime index, and a
+// pointer loaded that way would otherwise be treated as generic, i.e. flat
+// loads and stores, which also count against the LDS wait counter and so
+// make every LDS wait wait for the outstanding stores too.
 template <typename T>
-__device__ __forceinline__ void put(T* p, T v, bool nt)
+using gptr = __attribute__((address_space(1))) T*;
+
+template <typename T>
+__device__ __forceinline__ gptr<const T> in_ptr(const GatherDesc& d)
+{
+    return (gptr<const T>)(d.H);
+}
+
+template <typename T>
+__device__ __forceinline__ gptr<T> out_ptr(const GatherDesc& d)
+{
+    return (gptr<T>)(d.Ht);
+}
+
+template <typename T>
+__device__ __forceinline__ void put(gptr<T> p, T v, bool nt)
 {
     if (nt)
         __builtin_nontemporal_store(v, p);
@@ -58,12 +78,14 @@ __device__ __forceinline__ void put(T* p, T v, bool nt)
         *p = v;
 }
 
-__device__ __forceinline__ void put16(void* p, u32x4 v, bool nt)
+template <typename T>
+__device__ __forceinline__ void put16(gptr<T> p, u32x4 v, bool nt)
 {
+    gptr<u32x4> q = (gptr<u32x4>)p;
     if (nt)
-        __builtin_nontemporal_store(v, static_cast<u32x4*>(p));
+        __builtin_nontemporal_store(v, q);
     else
-        *static_cast<u32x4*>(p) = v;
+        *q = v;
 }
 
 // Workgroup barrier ordering LDS accesses only: outstanding global loads and
@@ -110,14 +132,14 @@ __device__ __forceinline__ void emit_tile(const GatherDesc& d, uint64_t O0, uint
                                           bool nt)
 {
     constexpr uint32_t VE = 16 / sizeof(T);
-    T* out = static_cast<T*>(d.Ht);
+    const gptr<T> out = out_ptr<T>(d);
     const uint64_t g0 = O0 + d.phase_out;
     const uint64_t u0 = g0 / VE, u1 = (g0 + L + VE - 1) / VE;
     for (uint64_t u = u0 + threadIdx.x; u < u1; u += blockDim.x) {
         const uint32_t li = uint32_t((u - u0) * VE);     // LDS index of the vector
         const int64_t rel = int64_t(li) - int64_t(lead);  // position in the unit
         if (rel >= 0 && rel + VE <= L) {
-            put16(out + (O0 + rel), *reinterpret_cast<const u32x4*>(tile + li), nt);
+            put16<T>(out + (O0 + rel), *reinterpret_cast<const u32x4*>(tile + li), nt);
         } else {
 #pragma unroll
             for (uint32_t e = 0; e < VE; ++e) {
@@ -135,8 +157,8 @@ __device__ __forceinline__ void emit_tile(const GatherDesc& d, uint64_t O0, uint
 template <typename T, int S, int U>
 __device__ __forceinline__ void direct_rows(const GatherDesc& d, uint32_t R0, uint32_t lane, bool nt)
 {
-    const T* src[U];
-    T* dst[U];
+    gptr<const T> src[U];
+    gptr<T> dst[U];
     uint32_t rot[U];
     bool live[U];
 #pragma unroll
@@ -146,8 +168,8 @@ __device__ __forceinline__ void direct_rows(const GatherDesc& d, uint32_t R0, ui
         const uint32_t Rc = live[u] ? R : R0;
         uint64_t so;
         row_source(d, Rc, so, rot[u]);
-        src[u] = static_cast<const T*>(d.H) + so;
-        dst[u] = static_cast<T*>(d.Ht) + uint64_t(Rc) * d.W;
+        src[u] = in_ptr<T>(d) + so;
+        dst[u] = out_ptr<T>(d) + uint64_t(Rc) * d.W;
     }
     const uint32_t W = d.W;
     for (uint32_t base = 0; base < W; base += 64 * S) {
@@ -205,7 +227,7 @@ __device__ __forceinline__ void staged_unit(const GatherDesc& d, uint32_t unit, 
     const uint64_t O0 = uint64_t(R0) * W;
     const uint32_t lead = uint32_t((O0 + d.phase_out) % VE);
     for (uint32_t r0 = wave * U; r0 < nr; r0 += nw * U) {
-        const T* src[U];
+        gptr<const T> src[U];
         uint32_t rot[U];
         bool live[U];
 #pragma unroll
@@ -213,7 +235,7 @@ __device__ __forceinline__ void staged_unit(const GatherDesc& d, uint32_t unit, 
             live[u] = r0 + u < nr;
             uint64_t so;
             row_source(d, R0 + (live[u] ? r0 + u : r0), so, rot[u]);
-            src[u] = static_cast<const T*>(d.H) + so;
+            src[u] = in_ptr<T>(d) + so;
         }
         for (uint32_t base = 0; base < W; base += 64 * S) {
             T v[U][S];
@@ -268,7 +290,7 @@ __device__ __forceinline__ void wide_load(const GatherDesc& d, uint32_t nr, cons
 {
     constexpr uint32_t VE = 16 / sizeof(T);
     const uint32_t nvec = nr * d.vpr;
-    const T* H = static_cast<const T*>(d.H);
+    const gptr<const T> H = in_ptr<T>(d);
 #pragma unroll
     for (int m = 0; m < M; ++m) {
         const uint32_t idx = threadIdx.x + uint32_t(m) * blockDim.x;
@@ -279,7 +301,7 @@ __device__ __forceinline__ void wide_load(const GatherDesc& d, uint32_t nr, cons
             if (k * VE < e.lead + d.W) {  // the vector holds part of the row
                 const int64_t g = e.vbase + int64_t(k * VE);
                 if (g >= 0 && uint64_t(g) + VE <= d.E) {
-                    v[m] = *reinterpret_cast<const u32x4*>(H + g);
+                    v[m] = *(gptr<const u32x4>)(H + g);
                 } else {  // a vector sticking out of the array (its first or last)
                     Pack16<T> p;
 #pragma unroll
@@ -443,41 +465,46 @@ __global__ void __launch_bounds__(512) k_wide_persist(GatherDesc d, int nt)
                         nt != 0);
 }
 
+// A descriptor read from a device table (word by word, through a global
+// pointer).
+__device__ __forceinline__ GatherDesc load_desc(gptr<const GatherDesc> p)
+{
+    static_assert(sizeof(GatherDesc) % 4 == 0, "descriptor is whole words");
+    GatherDesc d;
+    const gptr<const uint32_t> w = (gptr<const uint32_t>)p;
+    uint32_t* o = reinterpret_cast<uint32_t*>(&d);
+#pragma unroll
+    for (uint32_t i = 0; i < sizeof(GatherDesc) / 4; ++i) o[i] = w[i];
+    return d;
+}
+
 // Problem and problem-local unit of slot b of a batched launch: slot b is
 // unit l = b / kXcds of the walk of XCD x = b mod kXcds (the XCD that
 // workgroup b runs on), which takes an even share of every problem in turn.
-// Up to kInlineProblems descriptors travel in the kernel arguments (found with
-// a scalar scan, no dependent memory loads); larger batches use a device table
-// whose per-XCD prefix sums are searched by bisection.  Returns false for the
+// The first slot of each problem in each XCD's walk is a prefix table: up to
+// kInlineProblems problems it travels in the kernel arguments with the
+// descriptors (a branch-free scalar count over one row of it), larger
+// batches use a device table searched by bisection.  Returns false for the
 // slots past the end of the XCD's walk (d is then a valid descriptor of the
 // batch and local 0, so that callers may run it with no rows).
 __device__ __forceinline__ bool batch_slot(const BatchArgs& a, uint32_t b, GatherDesc& d, uint32_t& local)
 {
     const uint32_t x = b & (kXcds - 1), l = b / kXcds;
+    const gptr<const GatherDesc> table = (gptr<const GatherDesc>)a.table;
     if (l >= a.xtotal[x]) {
-        d = a.table == nullptr ? a.d[0] : a.table[0];
+        d = a.table == nullptr ? a.d[0] : load_desc(table);
         local = 0;
         return false;
     }
     if (a.table == nullptr) {
-        uint32_t p = 0, base = 0;
-        bool found = false;
+        const uint32_t* xs = a.xstart[x];
+        uint32_t p = 0;
 #pragma unroll
-        for (uint32_t i = 0; i < kInlineProblems; ++i) {
-            if (!found && i < a.count) {
-                const uint32_t c = xcd_share(a.d[i].nunits, x);
-                if (l < base + c) {
-                    p = i;
-                    found = true;
-                } else {
-                    base += c;
-                }
-            }
-        }
+        for (uint32_t i = 1; i < kInlineProblems; ++i) p += (i < a.count && xs[i] <= l) ? 1u : 0u;
         d = a.d[p];
-        local = xcd_first(d.nunits, x) + (l - base);
+        local = xcd_first(d.nunits, x) + (l - xs[p]);
     } else {
-        const uint32_t* xs = a.table_xstart + size_t(x) * (a.count + 1);
+        const gptr<const uint32_t> xs = (gptr<const uint32_t>)a.table_xstart + size_t(x) * (a.count + 1);
         uint32_t lo = 0, hi = a.count;  // xs[lo] <= l < xs[hi]
         while (hi - lo > 1) {
             const uint32_t mid = (lo + hi) >> 1;
@@ -486,7 +513,7 @@ __device__ __forceinline__ bool batch_slot(const BatchArgs& a, uint32_t b, Gathe
             else
                 hi = mid;
         }
-        d = a.table[lo];
+        d = load_desc(table + lo);
         local = xcd_first(d.nunits, x) + (l - xs[lo]);
     }
     return true;
@@ -516,7 +543,7 @@ __global__ void __launch_bounds__(512) k_staged_batched(BatchArgs a)
 
 // One workgroup per unit over all problems.
 template <typename T, int M>
-__global__ void __launch_bounds__(512) k_wide_batched(BatchArgs a)
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(M >= 8 ? 5 : 8))) k_wide_batched(BatchArgs a)
 {
     extern __shared__ u32x4 smem[];
     RowEnt* tab = reinterpret_cast<RowEnt*>(smem);
@@ -537,14 +564,21 @@ __global__ void __launch_bounds__(512) k_wide_batched_persist(BatchArgs a)
     RowEnt* tab0 = reinterpret_cast<RowEnt*>(smem);
     RowEnt* tab1 = tab0 + a.max_rows;
     T* tile = reinterpret_cast<T*>(smem + 2 * a.max_rows);
-    auto get = [&](uint32_t u, GatherDesc& dd, uint32_t& lu) { return batch_slot(a, u, dd, lu); };
+    // The arguments are read in place from the kernel-argument segment (the
+    // only argument, at offset 0): a reference to the by-value parameter
+    // kept across the pipelined loop would make the compiler copy all of it
+    // into per-lane scratch memory.
+    const BatchArgs& ka = *reinterpret_cast<const BatchArgs*>(
+        reinterpret_cast<uintptr_t>(__builtin_amdgcn_kernarg_segment_ptr()));
+    auto get = [&](uint32_t u, GatherDesc& dd, uint32_t& lu) { return batch_slot(ka, u, dd, lu); };
     wide_pipeline<T, M>(blockIdx.x, gridDim.x, kXcds * a.slots, get, tab0, tab1, tile, a.nt != 0);
 }
 
 // Device-side copy of up to kPutWords words carried in the kernel arguments.
 __global__ void __launch_bounds__(256) k_put_words(WordChunk c)
 {
-    for (uint32_t i = threadIdx.x; i < c.n; i += blockDim.x) c.dst[i] = c.w[i];
+    const gptr<uint32_t> dst = (gptr<uint32_t>)c.dst;
+    for (uint32_t i = threadIdx.x; i < c.n; i += blockDim.x) dst[i] = c.w[i];
 }
 
 // ---------------------------------------------------------------- host side

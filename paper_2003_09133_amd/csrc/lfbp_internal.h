@@ -122,6 +122,7 @@ struct BatchArgs {
     uint32_t nt;                  // 1: streaming stores
     uint32_t xtotal[kXcds];       // units in each XCD's walk
     GatherDesc d[kInlineProblems];
+    uint32_t xstart[kXcds][kInlineProblems + 1];  // inline batches: first slot of each problem per XCD
 };
 
 // Words written into device memory by one launch of the table-writer kernel
