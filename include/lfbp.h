@@ -102,6 +102,13 @@ typedef struct {
     int32_t persistent;     /* 1: `grid` workgroups loop over the work units (WIDE overlaps the loads of
                                the next unit with the stores of the current one); 2: one workgroup per unit */
     int32_t grid;           /* persistent grid size; 0 = every workgroup slot of the device */
+    int32_t waves_per_eu;   /* occupancy cap: at most this many wavefronts per SIMD (1..8; 8 = no cap),
+                               enforced by reserving LDS per workgroup */
+    int32_t schedule;       /* order in which work units meet the XCDs.  Plain WIDE launches: 1 = each XCD
+                               takes one contiguous range of units, 2 = units in launch order (consecutive
+                               units on different XCDs).  Batched: 1 = every XCD takes an even contiguous
+                               share of every problem, largest problems first; 2 = the units of all
+                               problems in launch order, largest problems first */
 } lfbp_gather_config;
 
 /* lfbp_compute_Ht with an explicit kernel choice (used by the autotuner and by

@@ -37,7 +37,8 @@ class GatherConfig(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("block_threads", ctypes.c_int32),
                 ("rows_in_flight", ctypes.c_int32), ("tile_bytes", ctypes.c_int32),
                 ("vec_per_thread", ctypes.c_int32), ("nontemporal", ctypes.c_int32),
-                ("persistent", ctypes.c_int32), ("grid", ctypes.c_int32)]
+                ("persistent", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("waves_per_eu", ctypes.c_int32), ("schedule", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

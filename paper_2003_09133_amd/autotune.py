@@ -2,14 +2,27 @@
 and writes the winners to the tuning table that liblfbp.so reads at start-up
 (paper_2003_09133_amd/lfbp_tune.txt, or $LFBP_TUNE_TABLE).
 
-    python -m paper_2003_09133_amd.autotune [--workloads microscope,camera,camera-f16,batched]
+    python -m paper_2003_09133_amd.autotune [--classes f32:7,...,f16:10] [--no-batched]
                                             [--out PATH] [--reps N]
+    python -m paper_2003_09133_amd.autotune --time-shapes "ns,nt,nx,ny,nz[:f16];..."
 
-A table entry is keyed by (batched, element size, W = ny*nz, nx); shapes with
-the same key share the kernel's work decomposition, so one timing serves all
-of them.  Inputs are random payloads (the kernels' cost does not depend on the
-values).  Only the library's C ABI is called; the choice a run makes is
-printed as one JSON line per workload.
+A table entry is keyed by (batched, element size, row class), the row class
+of a shape being floor(log2(ny*nz*esize)): the kernels cut H into units of
+whole x-rows, so the size of a row decides the work decomposition and with it
+the best configuration; a shape with no entry of its own class takes the
+nearest class's entry.  Each class is tuned on four representative PSF
+shapes (table CLASS_SHAPES), scored by the geometric mean of their rates, in
+two stages: kernel variant, workgroup size, loads per thread and store kind
+first, then occupancy cap (waves per SIMD) and the order in which units meet
+the XCDs for the best of those.  The winner's output is compared bit for bit
+with the output of the built-in default before it is written; a class whose
+best candidate does not beat the built-in default by MIN_GAIN keeps the
+default.  The batched entry is tuned on the 16-set table, in a
+child process that reads the freshly written plain entries (a batch cuts each
+problem into units of its plain class's size).  Inputs are random payloads
+(the kernels' cost does not depend on the values).  Only the library's C ABI
+is called.  --time-shapes prints, for each shape, the configuration the
+library picks and its rate (GB/s), as one JSON line.
 """
 from __future__ import annotations
 
@@ -18,23 +31,60 @@ import itertools
 import json
 import os
 import statistics
+import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_TABLE = os.path.join(HERE, "lfbp_tune.txt")
 FIELDS = ("variant", "block_threads", "rows_in_flight", "tile_bytes", "vec_per_thread", "nontemporal",
-          "persistent", "grid")
+          "persistent", "grid", "waves_per_eu", "schedule")
+
+# Representative PSF shapes (ns, nt, nx, ny, nz) of each (element size, row
+# class): odd cells and patches of an odd number of whole lenslets, 0.2 to
+# 5.5 GB per array, different cell sizes and depth counts.  A configuration is
+# scored by the geometric mean of its rates over the class's shapes, so that
+# the entry serves the whole class rather than one shape.
+CLASS_SHAPES = {
+    (4, 7): [(497, 497, 7, 7, 7), (405, 405, 9, 9, 6), (693, 693, 11, 11, 5), (385, 385, 7, 7, 9)],
+    (4, 8): [(405, 405, 9, 9, 11), (735, 735, 7, 7, 12), (253, 253, 11, 11, 9), (165, 165, 15, 15, 8)],
+    (4, 9): [(275, 275, 11, 11, 20), (525, 525, 15, 15, 10), (245, 245, 7, 7, 30), (165, 165, 15, 15, 15)],
+    (4, 10): [(165, 165, 15, 15, 21), (171, 171, 19, 19, 25), (297, 297, 11, 11, 30), (135, 135, 15, 15, 30)],
+    (4, 11): [(345, 345, 15, 15, 51), (225, 225, 15, 15, 45), (209, 209, 11, 11, 60), (135, 135, 15, 15, 40)],
+    (4, 12): [(171, 171, 19, 19, 80), (135, 135, 15, 15, 100), (99, 99, 11, 11, 120), (75, 75, 15, 15, 90)],
+    (4, 13): [(105, 105, 15, 15, 200), (57, 57, 19, 19, 150), (77, 77, 11, 11, 300), (45, 45, 15, 15, 250)],
+    (4, 14): [(45, 45, 15, 15, 300), (57, 57, 19, 19, 300), (31, 31, 31, 31, 200), (75, 75, 15, 15, 400)],
+    (2, 9): [(165, 165, 15, 15, 21), (171, 171, 19, 19, 25), (297, 297, 11, 11, 30), (135, 135, 15, 15, 30)],
+    (2, 10): [(345, 345, 15, 15, 51), (225, 225, 15, 15, 45), (209, 209, 11, 11, 60), (135, 135, 15, 15, 40)],
+}
+# A tuned entry must beat the built-in default by this factor (geometric mean
+# over the class's shapes); otherwise the class keeps the default.
+MIN_GAIN = 1.005
 
 
-def candidates(batched: bool):
+def row_class(shape, esize: int) -> int:
+    b = shape[3] * shape[4] * esize
+    return b.bit_length() - 1
+
+
+def stage1(batched: bool):
     out = []
     for thr, vec, nt in itertools.product((128, 256, 512), (2, 4, 8), (1, 2)):
         out.append({"variant": 3, "block_threads": thr, "vec_per_thread": vec, "nontemporal": nt, "persistent": 2})
     for thr, vec in itertools.product((256, 512), (2, 4)):
-        out.append({"variant": 3, "block_threads": thr, "vec_per_thread": vec, "nontemporal": 1, "persistent": 1})
-    for thr, rows, tile in itertools.product((256, 512), (1, 2), (8192, 16384, 32768)):
-        out.append({"variant": 2, "block_threads": thr, "rows_in_flight": rows, "tile_bytes": tile,
-                    "nontemporal": 1, "persistent": 2})
+        out.append({"variant": 3, "block_threads": thr, "vec_per_thread": vec, "nontemporal": 2, "persistent": 1})
+    if not batched:
+        for thr, rows, tile in itertools.product((256, 512), (1, 2), (8192, 16384, 32768)):
+            out.append({"variant": 2, "block_threads": thr, "rows_in_flight": rows, "tile_bytes": tile,
+                        "nontemporal": 1, "persistent": 2})
+    return out
+
+
+def stage2(best: dict):
+    out = []
+    for waves, sched in itertools.product((8, 6, 5, 4), (1, 2)):
+        c = dict(best)
+        c.update({"waves_per_eu": waves, "schedule": sched})
+        out.append(c)
     return out
 
 
@@ -68,16 +118,16 @@ def read_table(path):
         with open(path) as fh:
             for line in fh:
                 line = line.split("#", 1)[0].split()
-                if len(line) == 12:
-                    entries[tuple(int(v) for v in line[:4])] = [int(v) for v in line[4:]]
+                if len(line) == 13:
+                    entries[tuple(int(v) for v in line[:3])] = [int(v) for v in line[3:]]
     return entries
 
 
 def write_table(path, entries, notes):
     with open(path + ".tmp", "w") as fh:
         fh.write("# Tuning table of liblfbp.so, written by paper_2003_09133_amd/autotune.py.\n")
-        fh.write("# batched esize W nx | variant threads rows_in_flight tile_bytes vec_per_thread "
-                 "nontemporal persistent grid\n")
+        fh.write("# batched esize row_class | variant threads rows_in_flight tile_bytes vec_per_thread "
+                 "nontemporal persistent grid waves_per_eu schedule\n")
         for n in notes:
             fh.write(f"# {n}\n")
         for key in sorted(entries):
@@ -85,73 +135,162 @@ def write_table(path, entries, notes):
     os.replace(path + ".tmp", path)
 
 
-def tune_plain(lf, torch, lfsynth, name, reps):
-    wname, dt = {"microscope": ("MICROSCOPE", torch.float32), "camera": ("CAMERA", torch.float32),
-                 "camera-f16": ("CAMERA", torch.float16)}[name]
-    w = getattr(lfsynth, wname)
-    H = torch.empty(w.shape, dtype=dt, device="cuda")
-    H.view(torch.int32 if dt == torch.float32 else torch.int16).random_(0, 1 << 15)
-    Ht = torch.empty_like(H)
-    nbytes = 2 * H.numel() * H.element_size()
-    results = []
-    for cfg in candidates(False):
-        t = _time(lambda: lf.compute_Ht_into(H, Ht, config=cfg), torch, reps)
-        results.append((nbytes / t / 1e9, cfg))
+def random_psf(torch, shape, dtype):
+    H = torch.empty(shape, dtype=dtype, device="cuda")
+    H.view(torch.int32 if dtype == torch.float32 else torch.int16).random_(0, 1 << 15)
+    return H
+
+
+def same_bits(torch, a, b) -> bool:
+    it = torch.int32 if a.element_size() == 4 else torch.int16
+    return bool(torch.equal(a.view(it), b.view(it)))
+
+
+def geomean(v):
+    p = 1.0
+    for x in v:
+        p *= x
+    return p ** (1.0 / len(v))
+
+
+def sweep(runs, torch, reps, inner, batched):
+    """Two-stage sweep over (run(cfg), bytes) pairs, scored by the geometric
+    mean of the rates; returns (best score in GB/s, best config, ranked
+    results as (score, config, per-run GB/s))."""
+    def score(cfg):
+        rates = [nb / _time(lambda: run(cfg), torch, reps, inner) / 1e9 for run, nb in runs]
+        return geomean(rates), cfg, [round(r, 1) for r in rates]
+    results = [score(cfg) for cfg in stage1(batched)]
     results.sort(key=lambda r: -r[0])
-    best_gbs, best = results[0]
-    esize = H.element_size()
-    key = (0, esize, w.shape[3] * w.shape[4], w.shape[2])
-    full = full_config(lf, w.shape, dt, best)
-    return key, [full[f] for f in FIELDS], {"workload": name, "best_gbs": round(best_gbs, 1), "config": full,
-                                            "runner_up": [(round(g, 1), c) for g, c in results[1:4]]}
+    results += [score(cfg) for cfg in stage2(results[0][1])]
+    results.sort(key=lambda r: -r[0])
+    return results[0][0], results[0][1], results
+
+
+def tune_class(lf, torch, esize, cls, reps):
+    shapes = CLASS_SHAPES[(esize, cls)]
+    dt = torch.float32 if esize == 4 else torch.float16
+    Hs = [random_psf(torch, s, dt) for s in shapes]
+    Hts = [torch.empty_like(H) for H in Hs]
+    runs = [((lambda c, H=H, Ht=Ht: lf.compute_Ht_into(H, Ht, config=c)), 2 * H.numel() * H.element_size())
+            for H, Ht in zip(Hs, Hts)]
+    best_gbs, best, results = sweep(runs, torch, reps, 5, False)
+    default = [nb / _time(lambda: run(None), torch, reps) / 1e9 for run, nb in runs]
+    kept_default = best_gbs < MIN_GAIN * geomean(default)
+    if kept_default:
+        best, best_gbs = {}, geomean(default)
+    for H, Ht in zip(Hs, Hts):
+        ref = torch.empty_like(H)
+        lf.compute_Ht_into(H, ref)                     # built-in default
+        lf.compute_Ht_into(H, Ht, config=best)
+        torch.cuda.synchronize()
+        if not same_bits(torch, Ht, ref):
+            raise RuntimeError(f"class {cls} ({list(H.shape)}): the winning configuration's H' differs from "
+                               "the default's")
+    full = full_config(lf, shapes[0], dt, best)
+    info = {"class": [esize, cls], "shapes": [list(s) for s in shapes], "best_gbs": round(best_gbs, 1),
+            "best_per_shape": results[0][2], "config": full, "default_gbs": round(geomean(default), 1),
+            "default_per_shape": [round(r, 1) for r in default],
+            "kept_default": kept_default, "runner_up": [(round(g, 1), c) for g, c, _ in results[1:4]]}
+    del Hs, Hts
+    torch.cuda.empty_cache()
+    return (0, esize, cls), [full[f] for f in FIELDS], info
 
 
 def tune_batched(lf, torch, lfsynth, reps):
-    Hs = []
-    for w in lfsynth.BATCHED_SETS:
-        h = torch.empty(w.shape, dtype=torch.float32, device="cuda")
-        h.view(torch.int32).random_(0, 1 << 15)
-        Hs.append(h)
+    Hs = [random_psf(torch, w.shape, torch.float32) for w in lfsynth.BATCHED_SETS]
     outs = [torch.empty_like(h) for h in Hs]
     nbytes = sum(2 * h.numel() * 4 for h in Hs)
-    results = []
-    for cfg in candidates(True):
-        t = _time(lambda: lf.compute_Ht_batched(Hs, outs, config=cfg), torch, max(3, reps // 2), inner=2)
-        results.append((nbytes / t / 1e9, cfg))
+    best_gbs, best, results = sweep([(lambda c: lf.compute_Ht_batched(Hs, outs, config=c), nbytes)], torch,
+                                    max(3, reps // 2), 2, True)
+    refs = [torch.empty_like(h) for h in Hs]
+    for h, r in zip(Hs, refs):
+        lf.compute_Ht_into(h, r)
+    lf.compute_Ht_batched(Hs, outs, config=best)
+    torch.cuda.synchronize()
+    if not all(same_bits(torch, o, r) for o, r in zip(outs, refs)):
+        raise RuntimeError("batched: the winning configuration's H' differs from the plain calls'")
     lf.release_plans()
-    results.sort(key=lambda r: -r[0])
-    best_gbs, best = results[0]
     big = max(lfsynth.BATCHED_SETS, key=lambda w: w.elements)
-    key = (1, 4, big.shape[3] * big.shape[4], big.shape[2])
     full = full_config(lf, big.shape, torch.float32, best)
+    key = (1, 4, row_class(big.shape, 4))
     return key, [full[f] for f in FIELDS], {"workload": "batched", "best_gbs": round(best_gbs, 1), "config": full,
-                                            "runner_up": [(round(g, 1), c) for g, c in results[1:4]]}
+                                            "runner_up": [(round(g, 1), c) for g, c, _ in results[1:4]]}
+
+
+def time_shapes(lf, torch, spec: str, reps: int):
+    """Rate of the library's own choice on each shape of spec."""
+    out = []
+    for item in spec.split(";"):
+        dims, _, dts = item.partition(":")
+        shape = tuple(int(v) for v in dims.split(","))
+        dt = torch.float16 if dts == "f16" else torch.float32
+        H = random_psf(torch, shape, dt)
+        Ht = torch.empty_like(H)
+        t = _time(lambda: lf.compute_Ht_into(H, Ht), torch, reps)
+        out.append({"shape": list(shape), "dtype": "f16" if dt == torch.float16 else "f32",
+                    "row_class": row_class(shape, H.element_size()), "config": lf.default_config(shape, dt),
+                    "GBs": round(2 * H.numel() * H.element_size() / t / 1e9, 1)})
+        del H, Ht
+        torch.cuda.empty_cache()
+    return out
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("--workloads", default="microscope,camera,camera-f16,batched")
+    ap.add_argument("--classes", default=",".join(f"{'f32' if e == 4 else 'f16'}:{c}" for e, c in CLASS_SHAPES))
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-only", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--out", default=DEFAULT_TABLE)
     ap.add_argument("--reps", type=int, default=7)
+    ap.add_argument("--time-shapes", default=None)
     args = ap.parse_args(argv)
-    # Tune against the built-in defaults, not an older table.
-    os.environ["LFBP_TUNE_TABLE"] = os.path.join(HERE, "_no_table_")
     sys.path.insert(0, os.path.dirname(HERE))
+    if args.time_shapes:
+        import torch
+        import paper_2003_09133_amd as lf
+        print(json.dumps(time_shapes(lf, torch, args.time_shapes, args.reps)), flush=True)
+        return
+    if args.batched_only:
+        # child process: the library has read the plain entries from $LFBP_TUNE_TABLE
+        import torch
+        import lfsynth
+        import paper_2003_09133_amd as lf
+        entries = read_table(args.out)
+        key, vals, info = tune_batched(lf, torch, lfsynth, args.reps)
+        entries[key] = vals
+        print(json.dumps(info), flush=True)
+        write_table(args.out, entries, [f"batched: {info['best_gbs']} GB/s on {torch.cuda.get_device_name(0)}"])
+        return
+    # Tune the plain classes against the built-in defaults, not an older table.
+    os.environ["LFBP_TUNE_TABLE"] = os.path.join(HERE, "_no_table_")
     import torch
-    import lfsynth
     import paper_2003_09133_amd as lf
 
-    entries = read_table(args.out)
+    entries = {k: v for k, v in read_table(args.out).items() if k[0] == 0}
     notes = []
-    for name in args.workloads.split(","):
-        if name == "batched":
-            key, vals, info = tune_batched(lf, torch, lfsynth, args.reps)
-        else:
-            key, vals, info = tune_plain(lf, torch, lfsynth, name, args.reps)
+    for item in args.classes.split(","):
+        if not item:
+            continue
+        dts, _, cls = item.partition(":")
+        esize = 2 if dts == "f16" else 4
+        key, vals, info = tune_class(lf, torch, esize, int(cls), args.reps)
         entries[key] = vals
-        notes.append(f"{info['workload']}: {info['best_gbs']} GB/s on {torch.cuda.get_device_name(0)}")
+        notes.append(f"{dts} class {cls}: {info['best_gbs']} GB/s geometric mean over {info['shapes']} "
+                     f"(built-in default {info['default_gbs']}) on {torch.cuda.get_device_name(0)}")
         print(json.dumps(info), flush=True)
     write_table(args.out, entries, notes)
+    if not args.no_batched:
+        env = dict(os.environ, LFBP_TUNE_TABLE=args.out)
+        r = subprocess.run([sys.executable, "-m", "paper_2003_09133_amd.autotune", "--batched-only", "--out",
+                            args.out, "--reps", str(args.reps)], env=env, cwd=os.path.dirname(HERE))
+        if r.returncode != 0:
+            raise SystemExit(r.returncode)
+        # keep the plain notes beside the batched one
+        entries = read_table(args.out)
+        with open(args.out) as fh:
+            bnotes = [l[2:].strip() for l in fh if l.startswith("# batched:")]
+        write_table(args.out, entries, notes + bnotes)
     print(f"wrote {args.out}", flush=True)
 
 

@@ -34,6 +34,7 @@ namespace {
 std::once_flag g_init_once;
 hipError_t g_init_err = hipSuccess;
 int g_max_lds = 65536;  // dynamic LDS a workgroup may use (device limit, read at init)
+int g_cu_lds = 65536;   // LDS of one compute unit (read at init)
 int g_cus = 256;
 
 }  // namespace
@@ -62,6 +63,11 @@ hipError_t ensure_init()
             g_max_lds = lds;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
             g_cus = cus;
+        int cu_lds = 0;
+        if (hipDeviceGetAttribute(&cu_lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess &&
+            cu_lds > 0)
+            g_cu_lds = cu_lds;
+        g_cu_lds = std::max(g_cu_lds, g_max_lds);
         g_init_err = set_smem_limits(g_max_lds);
         if (g_init_err != hipSuccess && g_max_lds > 65536) {
             (void)hipGetLastError();
@@ -91,8 +97,21 @@ lfbp_gather_config resolve_config(const lfbp_shape& s, int esize, const lfbp_gat
         if (user->nontemporal) c.nontemporal = user->nontemporal;
         if (user->persistent) c.persistent = user->persistent;
         if (user->grid) c.grid = user->grid;
+        if (user->waves_per_eu) c.waves_per_eu = user->waves_per_eu;
+        if (user->schedule) c.schedule = user->schedule;
     }
     return c;
+}
+
+// LDS a workgroup of config c reserves so that at most c.waves_per_eu
+// wavefronts run per SIMD: k = 4*waves_per_eu*64/threads workgroups per CU
+// (4 SIMDs), enforced by reserving just over 1/(k+1) of the CU's LDS each.
+int occupancy_lds(int lds, const lfbp_gather_config& c)
+{
+    if (c.waves_per_eu >= 8) return lds;
+    const int k = std::max(1, 4 * c.waves_per_eu * 64 / c.block_threads);
+    const int pad = round16(int64_t(g_cu_lds) / (k + 1) + 1);
+    return std::max(lds, std::min(pad, g_max_lds));
 }
 
 // Rows per work unit and dynamic LDS of config c for rows of W elements.
@@ -276,6 +295,7 @@ lfbp_status layout_batch(const lfbp_problem* probs, int32_t count, int es, const
     }
     if (c.variant == LFBP_GATHER_WIDE) lds += ntab * int(max_rows) * 16;
     if (lds > g_max_lds) return LFBP_ESHAPE;
+    lds = occupancy_lds(lds, c);
     L.descs.resize(static_cast<size_t>(count));
     for (int32_t k = 0; k < count; ++k) {
         const lfbp_problem& pb = probs[order[size_t(k)]];
@@ -284,20 +304,36 @@ lfbp_status layout_batch(const lfbp_problem* probs, int32_t count, int es, const
     BatchArgs& a = L.args;
     std::memset(&a, 0, sizeof(a));
     L.xstart.assign(size_t(kXcds) * (size_t(count) + 1), 0);
-    uint64_t slots = 0;
-    for (uint32_t x = 0; x < kXcds; ++x) {
+    a.linear = c.schedule == 2 ? 1 : 0;
+    uint64_t nslots = 0;
+    if (a.linear) {
+        // one walk over every unit in launch order (row 0 of the prefix table)
         uint64_t cum = 0;
         for (int32_t k = 0; k < count; ++k) {
-            L.xstart[x * (size_t(count) + 1) + size_t(k)] = uint32_t(cum);
-            cum += xcd_share(L.descs[size_t(k)].nunits, x);
-            if (cum >= (uint64_t(1) << 28)) return LFBP_ESHAPE;  // kXcds * slots < 2^31
+            L.xstart[size_t(k)] = uint32_t(cum);
+            cum += L.descs[size_t(k)].nunits;
+            if (cum >= (uint64_t(1) << 31)) return LFBP_ESHAPE;
         }
-        L.xstart[x * (size_t(count) + 1) + size_t(count)] = uint32_t(cum);
-        a.xtotal[x] = uint32_t(cum);
-        slots = std::max(slots, cum);
+        L.xstart[size_t(count)] = uint32_t(cum);
+        a.xtotal[0] = uint32_t(cum);
+        nslots = cum;
+    } else {
+        uint64_t slots = 0;
+        for (uint32_t x = 0; x < kXcds; ++x) {
+            uint64_t cum = 0;
+            for (int32_t k = 0; k < count; ++k) {
+                L.xstart[x * (size_t(count) + 1) + size_t(k)] = uint32_t(cum);
+                cum += xcd_share(L.descs[size_t(k)].nunits, x);
+                if (cum >= (uint64_t(1) << 28)) return LFBP_ESHAPE;  // kXcds * slots < 2^31
+            }
+            L.xstart[x * (size_t(count) + 1) + size_t(count)] = uint32_t(cum);
+            a.xtotal[x] = uint32_t(cum);
+            slots = std::max(slots, cum);
+        }
+        nslots = uint64_t(kXcds) * slots;
     }
     a.count = uint32_t(count);
-    a.slots = uint32_t(slots);
+    a.nslots = uint32_t(nslots);
     a.max_rows = max_rows;
     a.nt = c.nontemporal == 1 ? 1 : 0;
     if (uint32_t(count) <= kInlineProblems) {
@@ -306,7 +342,6 @@ lfbp_status layout_batch(const lfbp_problem* probs, int32_t count, int es, const
             for (int32_t k = 0; k <= count; ++k) a.xstart[x][k] = L.xstart[x * (size_t(count) + 1) + size_t(k)];
     }
     LaunchPlan lp = make_plan(c, lds);
-    const uint64_t nslots = uint64_t(kXcds) * slots;
     if (c.persistent != 1) {
         lp.grid = int(std::min<uint64_t>(nslots, max_grid(lp.threads)));
     } else {
@@ -585,7 +620,7 @@ lfbp_status lfbp_default_config(lfbp_shape shape, lfbp_dtype dtype, lfbp_gather_
     const uint32_t W = uint32_t(shape.ny * shape.nz);
     decompose(W, es, c, rows, lds);
     const GatherDesc d = make_desc(nullptr, nullptr, shape, es, rows);
-    LaunchPlan p = make_plan(c, lds);
+    LaunchPlan p = make_plan(c, occupancy_lds(lds, c));
     c.grid = grid_for(c, p, d.nunits, W, es, false);
     *cfg = c;
     return LFBP_OK;
@@ -605,8 +640,9 @@ lfbp_status lfbp_compute_Ht_config(const void* H, void* Ht, lfbp_shape shape, lf
     int lds = 0;
     const uint32_t W = uint32_t(shape.ny * shape.nz);
     decompose(W, es, c, rows, lds);
-    const GatherDesc d = make_desc(H, Ht, shape, es, rows);
-    LaunchPlan p = make_plan(c, lds);
+    GatherDesc d = make_desc(H, Ht, shape, es, rows);
+    d.xcd_remap = c.schedule == 2 ? 0 : 1;
+    LaunchPlan p = make_plan(c, occupancy_lds(lds, c));
     p.grid = grid_for(c, p, d.nunits, W, es, false);
     return launch_gather(d, es, p, static_cast<hipStream_t>(stream)) == hipSuccess ? LFBP_OK : LFBP_EDEVICE;
 }

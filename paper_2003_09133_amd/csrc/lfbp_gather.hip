@@ -461,8 +461,8 @@ __global__ void __launch_bounds__(512) k_wide_persist(GatherDesc d, int nt)
         lu = u;
         return true;
     };
-    wide_pipeline<T, M>(persistent_first(blockIdx.x, gridDim.x), gridDim.x, d.nunits, get, tab0, tab1, tile,
-                        nt != 0);
+    wide_pipeline<T, M>(d.xcd_remap ? persistent_first(blockIdx.x, gridDim.x) : blockIdx.x, gridDim.x, d.nunits,
+                        get, tab0, tab1, tile, nt != 0);
 }
 
 // A descriptor read from a device table (word by word, through a global
@@ -478,18 +478,20 @@ __device__ __forceinline__ GatherDesc load_desc(gptr<const GatherDesc> p)
     return d;
 }
 
-// Problem and problem-local unit of slot b of a batched launch: slot b is
-// unit l = b / kXcds of the walk of XCD x = b mod kXcds (the XCD that
-// workgroup b runs on), which takes an even share of every problem in turn.
-// The first slot of each problem in each XCD's walk is a prefix table: up to
-// kInlineProblems problems it travels in the kernel arguments with the
-// descriptors (a branch-free scalar count over one row of it), larger
-// batches use a device table searched by bisection.  Returns false for the
-// slots past the end of the XCD's walk (d is then a valid descriptor of the
-// batch and local 0, so that callers may run it with no rows).
+// Problem and problem-local unit of slot b of a batched launch.  In the
+// XCD schedule, slot b is unit l = b / kXcds of the walk of XCD
+// x = b mod kXcds (the XCD that workgroup b runs on), which takes an even
+// share of every problem in turn; in the linear schedule slot b is unit b of
+// one walk over all problems (row 0 of the prefix table).  The prefix table
+// (first slot of each problem in each walk) travels in the kernel arguments
+// with the descriptors for up to kInlineProblems problems (a branch-free
+// scalar count over one row of it); larger batches use a device table
+// searched by bisection.  Returns false for the slots past the end of a walk
+// (d is then a valid descriptor of the batch and local 0, so that callers may
+// run it with no rows).
 __device__ __forceinline__ bool batch_slot(const BatchArgs& a, uint32_t b, GatherDesc& d, uint32_t& local)
 {
-    const uint32_t x = b & (kXcds - 1), l = b / kXcds;
+    const uint32_t x = a.linear ? 0u : b & (kXcds - 1), l = a.linear ? b : b / kXcds;
     const gptr<const GatherDesc> table = (gptr<const GatherDesc>)a.table;
     if (l >= a.xtotal[x]) {
         d = a.table == nullptr ? a.d[0] : load_desc(table);
@@ -502,7 +504,7 @@ __device__ __forceinline__ bool batch_slot(const BatchArgs& a, uint32_t b, Gathe
 #pragma unroll
         for (uint32_t i = 1; i < kInlineProblems; ++i) p += (i < a.count && xs[i] <= l) ? 1u : 0u;
         d = a.d[p];
-        local = xcd_first(d.nunits, x) + (l - xs[p]);
+        local = (a.linear ? 0u : xcd_first(d.nunits, x)) + (l - xs[p]);
     } else {
         const gptr<const uint32_t> xs = (gptr<const uint32_t>)a.table_xstart + size_t(x) * (a.count + 1);
         uint32_t lo = 0, hi = a.count;  // xs[lo] <= l < xs[hi]
@@ -514,7 +516,7 @@ __device__ __forceinline__ bool batch_slot(const BatchArgs& a, uint32_t b, Gathe
                 hi = mid;
         }
         d = load_desc(table + lo);
-        local = xcd_first(d.nunits, x) + (l - xs[lo]);
+        local = (a.linear ? 0u : xcd_first(d.nunits, x)) + (l - xs[lo]);
     }
     return true;
 }
@@ -522,7 +524,7 @@ __device__ __forceinline__ bool batch_slot(const BatchArgs& a, uint32_t b, Gathe
 template <typename T, int S, int U>
 __global__ void __launch_bounds__(512) k_direct_batched(BatchArgs a)
 {
-    for (uint32_t b = blockIdx.x; b < kXcds * a.slots; b += gridDim.x) {
+    for (uint32_t b = blockIdx.x; b < a.nslots; b += gridDim.x) {
         GatherDesc d;
         uint32_t lu;
         if (batch_slot(a, b, d, lu)) direct_unit<T, S, U>(d, lu, a.nt != 0);
@@ -534,7 +536,7 @@ __global__ void __launch_bounds__(512) k_staged_batched(BatchArgs a)
 {
     extern __shared__ u32x4 smem[];
     T* lds = reinterpret_cast<T*>(smem);
-    for (uint32_t b = blockIdx.x; b < kXcds * a.slots; b += gridDim.x) {
+    for (uint32_t b = blockIdx.x; b < a.nslots; b += gridDim.x) {
         GatherDesc d;
         uint32_t lu;
         if (batch_slot(a, b, d, lu)) staged_unit<T, S, U>(d, lu, lds, a.nt != 0);
@@ -548,7 +550,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(M >= 8
     extern __shared__ u32x4 smem[];
     RowEnt* tab = reinterpret_cast<RowEnt*>(smem);
     T* tile = reinterpret_cast<T*>(smem + a.max_rows);
-    for (uint32_t b = blockIdx.x; b < kXcds * a.slots; b += gridDim.x) {
+    for (uint32_t b = blockIdx.x; b < a.nslots; b += gridDim.x) {
         GatherDesc d;
         uint32_t lu;
         if (batch_slot(a, b, d, lu)) wide_unit<T, M>(d, lu, tab, tile, a.nt != 0);
@@ -571,7 +573,7 @@ __global__ void __launch_bounds__(512) k_wide_batched_persist(BatchArgs a)
     const BatchArgs& ka = *reinterpret_cast<const BatchArgs*>(
         reinterpret_cast<uintptr_t>(__builtin_amdgcn_kernarg_segment_ptr()));
     auto get = [&](uint32_t u, GatherDesc& dd, uint32_t& lu) { return batch_slot(ka, u, dd, lu); };
-    wide_pipeline<T, M>(blockIdx.x, gridDim.x, kXcds * a.slots, get, tab0, tab1, tile, a.nt != 0);
+    wide_pipeline<T, M>(blockIdx.x, gridDim.x, a.nslots, get, tab0, tab1, tile, a.nt != 0);
 }
 
 // Device-side copy of up to kPutWords words carried in the kernel arguments.

@@ -117,7 +117,8 @@ struct BatchArgs {
     const GatherDesc* table;      // device descriptor table, or nullptr
     const uint32_t* table_xstart; // device [kXcds][count+1]: first slot of each problem in each XCD's walk
     uint32_t count;               // problems
-    uint32_t slots;               // longest XCD walk; slots b < kXcds*slots cover every unit
+    uint32_t nslots;              // slots b < nslots cover every unit
+    uint32_t linear;              // 1: one walk over all units in launch order (row 0 of the prefix table)
     uint32_t max_rows;            // largest rows_per_unit (LDS table size)
     uint32_t nt;                  // 1: streaming stores
     uint32_t xtotal[kXcds];       // units in each XCD's walk

@@ -5,8 +5,12 @@
 
 namespace lfbp {
 
-// The configuration for one problem: an entry of the tuning table when one
-// matches (batched or plain, element size, W = ny*nz, nx), else the built-in
+// Row class of a shape: floor(log2(ny*nz*esize)), the size class of one
+// x-row in bytes, which keys the tuning table.
+int row_class(const lfbp_shape& s, int esize);
+
+// The configuration for one problem: the tuning-table entry of its row class
+// (batched or plain) or of the nearest class present, else the built-in
 // defaults.  Every field is set except grid, which may be 0 (= one workgroup
 // per unit, or every workgroup slot of the device when persistent).
 lfbp_gather_config tuned_config(const lfbp_shape& s, int esize, bool batched);

@@ -80,6 +80,8 @@ lfbp_status check_config(const lfbp_gather_config* c)
     if (c->nontemporal < 0 || c->nontemporal > 2) return LFBP_EINVAL;
     if (c->persistent < 0 || c->persistent > 2) return LFBP_EINVAL;
     if (c->grid < 0) return LFBP_EINVAL;
+    if (c->waves_per_eu < 0 || c->waves_per_eu > 8) return LFBP_EINVAL;
+    if (c->schedule < 0 || c->schedule > 2) return LFBP_EINVAL;
     return LFBP_OK;
 }
 

@@ -1,9 +1,10 @@
 """NumPy mirror of the batched launch's slot arithmetic (csrc/lfbp_gather.hip
 batch_slot, csrc/lfbp_internal.h xcd_share/xcd_first, csrc/lfbp_api.cpp
-layout_batch), on the CPU: over the slots b < 8*slots of a launch, every unit
-of every problem is visited exactly once, each XCD's share of a problem is one
-contiguous run of its units, and the XCD walks differ in length by at most one
-unit per problem."""
+layout_batch), on the CPU: over the slots b < nslots of a launch, every unit
+of every problem is visited exactly once; in the XCD schedule each XCD's share
+of a problem is one contiguous run of its units and the XCD walks differ in
+length by at most one unit per problem; in the linear schedule slot b is unit
+b of the problems laid end to end."""
 import numpy as np
 import pytest
 
@@ -27,24 +28,27 @@ def layout(nunits):
     return xstart
 
 
-def slot_inline(nunits, xtotal, b):
-    """The scalar scan used when the descriptors travel in the kernel arguments."""
-    x, l = b % XCDS, b // XCDS
-    if l >= xtotal[x]:
+def layout_linear(nunits):
+    """Prefix sums of the one linear walk (row 0 of the table; other rows unused)."""
+    xstart = np.zeros((XCDS, len(nunits) + 1), dtype=np.int64)
+    xstart[0, 1:] = np.cumsum(nunits)
+    return xstart
+
+
+def slot_inline(nunits, xstart, b, linear=False):
+    """The branch-free scalar count used when the descriptors and the prefix
+    table travel in the kernel arguments."""
+    x, l = (0, b) if linear else (b % XCDS, b // XCDS)
+    if l >= xstart[x, -1]:
         return None
-    base, p = 0, None
-    for i, n in enumerate(nunits):
-        c = share(n, x)
-        if l < base + c:
-            p = i
-            break
-        base += c
-    return p, first(nunits[p], x) + (l - base)
+    xs = xstart[x]
+    p = sum(1 for i in range(1, 16) if i < len(nunits) and xs[i] <= l)
+    return p, (0 if linear else first(nunits[p], x)) + (l - xs[p])
 
 
-def slot_table(nunits, xstart, b):
+def slot_table(nunits, xstart, b, linear=False):
     """The bisection used with a device descriptor table."""
-    x, l = b % XCDS, b // XCDS
+    x, l = (0, b) if linear else (b % XCDS, b // XCDS)
     if l >= xstart[x, -1]:
         return None
     lo, hi = 0, len(nunits)
@@ -54,7 +58,7 @@ def slot_table(nunits, xstart, b):
             lo = mid
         else:
             hi = mid
-    return lo, first(nunits[lo], x) + (l - xstart[x, lo])
+    return lo, (0 if linear else first(nunits[lo], x)) + (l - xstart[x, lo])
 
 
 @pytest.mark.parametrize("seed", range(12))
@@ -72,7 +76,7 @@ def test_slots_cover_every_unit_once(seed):
     for b in range(XCDS * slots):
         got = slot_table(nunits, xstart, b)
         if count <= 16:
-            assert got == slot_inline(nunits, xtotal, b)
+            assert got == slot_inline(nunits, xstart, b)
         if got is None:
             continue
         p, u = got
@@ -91,3 +95,19 @@ def test_shares_partition_each_problem():
         assert runs[0][0] == 0 and runs[-1][1] == n
         assert all(runs[i][1] == runs[i + 1][0] for i in range(XCDS - 1))
         assert max(share(n, x) for x in range(XCDS)) - min(share(n, x) for x in range(XCDS)) <= 1
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_linear_slots_are_the_units_end_to_end(seed):
+    rng = np.random.default_rng(100 + seed)
+    count = int(rng.integers(1, 40))
+    nunits = sorted((int(v) for v in rng.choice([1, 2, 3, 7, 9, 16, 17, 100, 1001], size=count)), reverse=True)
+    xstart = layout_linear(nunits)
+    order = [(p, u) for p, n in enumerate(nunits) for u in range(n)]
+    nslots = int(xstart[0, -1])
+    assert nslots == len(order)
+    for b in range(nslots + 9):                      # slots past the end are holes
+        got = slot_table(nunits, xstart, b, linear=True)
+        if count <= 16:
+            assert got == slot_inline(nunits, xstart, b, linear=True)
+        assert got == (order[b] if b < nslots else None)

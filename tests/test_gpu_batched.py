@@ -17,6 +17,10 @@ BATCH_CONFIGS = [
     {"variant": lf.GATHER_STAGED, "persistent": 1, "tile_bytes": 8192},
     {"variant": lf.GATHER_STAGED, "persistent": 2},
     {"variant": lf.GATHER_DIRECT, "persistent": 1, "grid": 11, "rows_in_flight": 1},
+    {"variant": lf.GATHER_WIDE, "persistent": 2, "schedule": 2, "waves_per_eu": 4},
+    {"variant": lf.GATHER_WIDE, "persistent": 1, "schedule": 2, "grid": 13, "vec_per_thread": 2},
+    {"variant": lf.GATHER_STAGED, "persistent": 2, "schedule": 2, "waves_per_eu": 2},
+    {"variant": lf.GATHER_DIRECT, "persistent": 1, "schedule": 2, "grid": 5},
 ]
 
 
@@ -187,7 +191,9 @@ def test_batch_beyond_inline_descriptors(n):
     Hs = [lfsynth.bits(s, 7 * i + 1, np.float32) for i, s in enumerate(shapes)]
     dHs = [to_dev(H) for H in Hs]
     for cfg in (None, {"variant": lf.GATHER_WIDE, "persistent": 2}, {"variant": lf.GATHER_STAGED},
-                {"variant": lf.GATHER_DIRECT, "persistent": 1, "grid": 9}):
+                {"variant": lf.GATHER_DIRECT, "persistent": 1, "grid": 9},
+                {"variant": lf.GATHER_WIDE, "persistent": 2, "schedule": 2},
+                {"variant": lf.GATHER_WIDE, "persistent": 1, "schedule": 2, "grid": 24}):
         outs = lf.compute_Ht_batched(dHs, config=cfg)
         torch.cuda.synchronize()
         for i, (o, H) in enumerate(zip(outs, Hs)):

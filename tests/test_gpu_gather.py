@@ -29,6 +29,9 @@ CONFIGS = [
     {"variant": lf.GATHER_WIDE, "vec_per_thread": 8, "block_threads": 512, "nontemporal": 2},
     {"variant": lf.GATHER_WIDE, "vec_per_thread": 4, "persistent": 1, "grid": 7},
     {"variant": lf.GATHER_WIDE, "vec_per_thread": 2, "persistent": 1, "block_threads": 128},
+    {"variant": lf.GATHER_WIDE, "vec_per_thread": 4, "schedule": 2, "waves_per_eu": 3},
+    {"variant": lf.GATHER_WIDE, "vec_per_thread": 2, "persistent": 1, "schedule": 2, "waves_per_eu": 1},
+    {"variant": lf.GATHER_STAGED, "waves_per_eu": 2, "schedule": 2},
 ]
 
 

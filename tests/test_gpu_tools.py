@@ -21,21 +21,43 @@ def run(args, env=None, timeout=240):
 
 
 def test_autotuner_writes_a_table_the_library_uses(tmp_path):
+    """One row class tuned into a fresh table: a shape of that class that the
+    tuner never ran (and a shape of another class, through the nearest-class
+    rule) then runs the tuned configuration."""
     table = tmp_path / "tune.txt"
-    out = run(["-m", "paper_2003_09133_amd.autotune", "--workloads", "microscope", "--reps", "1",
+    out = run(["-m", "paper_2003_09133_amd.autotune", "--classes", "f32:10", "--no-batched", "--reps", "1",
                "--out", str(table)])
     report = json.loads([l for l in out.splitlines() if l.startswith("{")][-1])
-    assert report["workload"] == "microscope" and report["best_gbs"] > 0
+    assert report["class"] == [4, 10] and report["best_gbs"] > 0 and report["default_gbs"] > 0
     rows = [l.split() for l in table.read_text().splitlines() if l.strip() and not l.startswith("#")]
-    assert len(rows) == 1 and len(rows[0]) == 12
-    key, cfg = [int(v) for v in rows[0][:4]], [int(v) for v in rows[0][4:]]
-    assert key == [0, 4, 15 * 21, 15]                        # plain, float32, W = ny*nz, nx
+    assert len(rows) == 1 and len(rows[0]) == 13
+    key, cfg = [int(v) for v in rows[0][:3]], [int(v) for v in rows[0][3:]]
+    assert key == [0, 4, 10]                                  # plain, float32, rows of 1024..2047 bytes
+    unseen = [(45, 45, 9, 9, 31), (209, 209, 11, 11, 22)]    # rows of 1116 B (class 10) and 968 B (class 9)
     probe = ("import json, sys; sys.path.insert(0, %r); import torch, paper_2003_09133_amd as lf; "
-             "print(json.dumps(lf.default_config((165, 165, 15, 15, 21), torch.float32)))" % ROOT)
+             "print(json.dumps([lf.default_config(s, torch.float32) for s in %r]))" % (ROOT, unseen))
     used = json.loads(run(["-c", probe], env={"LFBP_TUNE_TABLE": str(table)}).strip().splitlines()[-1])
     fields = ("variant", "block_threads", "rows_in_flight", "tile_bytes", "vec_per_thread", "nontemporal",
-              "persistent")
-    assert [used[f] for f in fields] == cfg[:7]
+              "persistent", "grid", "waves_per_eu", "schedule")
+    want = dict(zip(fields, cfg))
+    for u in used:
+        assert {f: u[f] for f in fields if f != "grid"} == {f: want[f] for f in fields if f != "grid"}
+
+
+def test_shipped_table_against_builtin_default_on_unseen_shapes():
+    """Three PSF shapes that no table entry was tuned on (sets of the 16-set
+    table, three row classes), timed with the shipped table's choice and with
+    the built-in default: the class entries serve them, and the gap is
+    printed (the tuned choice is not allowed to be much slower)."""
+    spec = "165,165,15,15,35;209,209,11,11,22;285,285,19,19,20"
+    tuned = json.loads(run(["-m", "paper_2003_09133_amd.autotune", "--time-shapes", spec, "--reps", "5"]
+                           ).strip().splitlines()[-1])
+    default = json.loads(run(["-m", "paper_2003_09133_amd.autotune", "--time-shapes", spec, "--reps", "5"],
+                             env={"LFBP_TUNE_TABLE": os.path.join(ROOT, "_no_table_")}).strip().splitlines()[-1])
+    for t, d in zip(tuned, default):
+        print(f"{t['shape']} class {t['row_class']}: tuned {t['GBs']} GB/s, built-in default {d['GBs']} GB/s "
+              f"({t['GBs'] / d['GBs']:.3f}x)")
+        assert t["GBs"] > 0.9 * d["GBs"], (t, d)
 
 
 def test_bench_line_carries_every_field():

@@ -1,9 +1,12 @@
 """The tuning table reader of liblfbp.so (csrc/lfbp_tune.cpp), on the CPU:
-entries keyed by (batched, element size, W = ny*nz, nx) replace the built-in
-kernel choice; comments, malformed lines and entries with invalid fields are
-skipped.  Each case runs in a fresh process, since the library reads the table
-once per process (from $LFBP_TUNE_TABLE here)."""
+entries keyed by (batched, element size, row class = floor(log2(ny*nz*esize)))
+replace the built-in kernel choice for every shape of their class, a shape
+whose class has no entry takes the nearest class's entry, and comments,
+malformed lines and entries with invalid fields are skipped.  Each case runs
+in a fresh process, since the library reads the table once per process (from
+$LFBP_TUNE_TABLE here)."""
 import json
+import math
 import os
 import subprocess
 import sys
@@ -15,33 +18,82 @@ import json, sys
 sys.path.insert(0, {root!r})
 import torch
 import paper_2003_09133_amd as lf
-print(json.dumps([lf.default_config(s, torch.float32) for s in {shapes!r}]))
+dt = {{2: torch.float16, 4: torch.float32}}
+print(json.dumps([lf.default_config(s, dt[e]) for s, e in {cases!r}]))
 """
+FIELDS = ("variant", "block_threads", "rows_in_flight", "tile_bytes", "vec_per_thread", "nontemporal",
+          "persistent", "waves_per_eu", "schedule")
 
 
-def configs_with_table(table: str, shapes, tmp_path):
+def row_class(shape, esize):
+    return int(math.floor(math.log2(shape[3] * shape[4] * esize)))
+
+
+def configs_with_table(table: str, cases, tmp_path):
     path = tmp_path / "tune.txt"
     path.write_text(table)
     env = dict(os.environ, LFBP_TUNE_TABLE=str(path))
-    r = subprocess.run([sys.executable, "-c", PROBE.format(root=ROOT, shapes=[list(s) for s in shapes])],
+    r = subprocess.run([sys.executable, "-c", PROBE.format(root=ROOT, cases=[(list(s), e) for s, e in cases])],
                        capture_output=True, text=True, env=env, timeout=300)
     assert r.returncode == 0, r.stderr
-    return json.loads(r.stdout.strip().splitlines()[-1])
+    return [{k: c[k] for k in FIELDS} for c in json.loads(r.stdout.strip().splitlines()[-1])]
 
 
-def test_entries_replace_the_default_and_bad_lines_are_skipped(tmp_path):
-    micro = (165, 165, 15, 15, 21)           # W = 315, nx = 15
-    other = (45, 45, 9, 9, 7)                # W = 63, nx = 9
-    third = (21, 21, 7, 7, 5)                # W = 35, nx = 7
+def entry(batched, esize, cls, variant, threads, rows, tile, vec, nt, persistent, waves, schedule):
+    return f"{batched} {esize} {cls} {variant} {threads} {rows} {tile} {vec} {nt} {persistent} 0 {waves} {schedule}"
+
+
+def as_cfg(line):
+    v = [int(x) for x in line.split()]
+    return dict(zip(FIELDS, v[3:10] + v[11:13]))
+
+
+def test_class_entries_replace_the_default_and_bad_lines_are_skipped(tmp_path):
+    micro = (165, 165, 15, 15, 21)           # row 1260 B: class 10
+    same_class = (45, 45, 9, 9, 31)          # row 1116 B: class 10, another shape
+    other = (45, 45, 9, 9, 7)                # row 252 B: class 7
+    assert row_class(micro, 4) == row_class(same_class, 4) == 10 and row_class(other, 4) == 7
+    e10 = entry(0, 4, 10, 2, 128, 1, 8192, 2, 2, 2, 6, 2)
     table = "\n".join([
-        "# batched esize W nx variant threads rows tile vec nt persistent grid",
-        "0 4 315 15 2 128 1 8192 2 2 2 0   # a staged choice for the microscope key",
-        "0 4 63 9 3 100 2 16384 4 1 2 0    # 100 threads: invalid, skipped",
-        "0 4 35 7 3 256",                      # malformed, skipped
-        "1 4 315 15 1 64 2 0 2 1 1 0       # batched key: not used by plain calls",
+        "# batched esize class variant threads rows tile vec nt persistent grid waves schedule",
+        e10 + "   # a staged choice for class 10",
+        entry(0, 4, 7, 3, 100, 2, 16384, 4, 1, 2, 8, 1) + "   # 100 threads: invalid, skipped",
+        entry(0, 4, 7, 3, 256, 2, 16384, 4, 1, 2, 9, 1) + "   # 9 waves per SIMD: invalid, skipped",
+        "0 4 7 3 256 2 16384 4 1 2 0",                              # malformed (old format), skipped
+        "0 4 315 15 3 256 2 16384 4 1 2 0",                         # old exact-shape key, skipped
+        entry(1, 4, 7, 1, 64, 2, 0, 2, 1, 1, 8, 1) + "   # batched: not used by plain calls",
     ]) + "\n"
-    got = configs_with_table(table, [micro, other, third], tmp_path)
-    assert {k: got[0][k] for k in ("variant", "block_threads", "rows_in_flight", "tile_bytes", "nontemporal")} == \
-        {"variant": 2, "block_threads": 128, "rows_in_flight": 1, "tile_bytes": 8192, "nontemporal": 2}
-    default = configs_with_table("", [other, third], tmp_path)
-    assert got[1] == default[0] and got[2] == default[1]
+    got = configs_with_table(table, [(micro, 4), (same_class, 4), (other, 4)], tmp_path)
+    assert got[0] == as_cfg(e10) and got[1] == as_cfg(e10)
+    # class 7 has no valid plain entry: the nearest class (10) serves it
+    assert got[2] == as_cfg(e10)
+    default = configs_with_table("", [(other, 4)], tmp_path)
+    assert default[0] != as_cfg(e10)
+
+
+def test_nearest_class_and_element_size(tmp_path):
+    small = (45, 45, 9, 9, 7)                # f32 row 252 B: class 7
+    mid = (165, 165, 15, 15, 21)             # f32 class 10, f16 (630 B) class 9
+    big = (21, 21, 3, 3, 2000)               # f32 row 24000 B: class 14
+    e7 = entry(0, 4, 7, 3, 128, 2, 16384, 2, 2, 2, 8, 1)
+    e11 = entry(0, 4, 11, 3, 512, 2, 16384, 4, 1, 2, 4, 2)
+    e9h = entry(0, 2, 9, 2, 256, 2, 32768, 4, 2, 2, 8, 1)
+    table = "\n".join([e7, e11, e9h]) + "\n"
+    got = configs_with_table(table, [(small, 4), (mid, 4), (big, 4), (mid, 2), (small, 2)], tmp_path)
+    assert got[0] == as_cfg(e7)               # its own class
+    assert got[1] == as_cfg(e11)              # class 10: 11 is one step away, 7 three (and 9 is f16)
+    assert got[2] == as_cfg(e11)              # class 14: nearest is 11
+    assert got[3] == as_cfg(e9h)              # f16 class 9: its own class and element size
+    # f16 class 6: f32 class 7 (one step, other size: 3) beats f16 class 9 (three steps: 6)
+    assert row_class(small, 2) == 6 and got[4] == as_cfg(e7)
+
+
+def test_batched_entries_serve_batched_calls_only(tmp_path):
+    """The plain default is unchanged by a batched entry, and a plain entry
+    does not become a batched call's configuration (checked through
+    default_config, which reports the plain choice)."""
+    shape = (165, 165, 15, 15, 21)
+    eb = entry(1, 4, 10, 3, 512, 2, 16384, 8, 1, 2, 8, 2)
+    got = configs_with_table(eb + "\n", [(shape, 4)], tmp_path)
+    default = configs_with_table("", [(shape, 4)], tmp_path)
+    assert got == default
