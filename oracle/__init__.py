@@ -53,6 +53,8 @@ def _load():
             "oracle_backward": [vp, vp, vp, i64, i64, vp, i32],
             "oracle_backward_at": [vp, vp, vp, i64, i64, vp, i64, vp, i32],
             "oracle_forward_d": [vp, vp, vp, i64, i64, vp, i32],
+            "oracle_forward_sparse": [vp, vp, vp, i64, i64, vp, i32],
+            "oracle_backward_sparse": [vp, vp, vp, i64, i64, vp, i32],
             "oracle_backward_d": [vp, vp, vp, i64, i64, vp, i32],
             "oracle_grad_psf": [vp, vp, vp, i64, i64, vp, i32],
             "oracle_grad_psf_at": [vp, vp, vp, i64, i64, vp, i64, vp, i32],
@@ -188,6 +190,28 @@ def backward_at(H: np.ndarray, f: np.ndarray, voxels: np.ndarray, nthreads: int 
                                       vox.ctypes.data, len(vox), out.ctypes.data, nthreads),
            "oracle_backward_at")
     return out
+
+
+def forward_sparse(H: np.ndarray, g: np.ndarray, nthreads: int = 0) -> np.ndarray:
+    """f = A g in float64, summed over the nonzero entries of H only (the same
+    entries of A read from the H side; cost scales with the nonzeros)."""
+    H, g = _f32(H), _f32(g)
+    nz, R, C = g.shape
+    assert nz == H.shape[4]
+    f = np.empty((R, C), dtype=np.float64)
+    _check(_load().oracle_forward_sparse(H.ctypes.data, _dims(H).ctypes.data, g.ctypes.data, R, C,
+                                         f.ctypes.data, nthreads), "oracle_forward_sparse")
+    return f
+
+
+def backward_sparse(H: np.ndarray, f: np.ndarray, nthreads: int = 0) -> np.ndarray:
+    """A^T f in float64 from H, summed over the nonzero entries of H only."""
+    H, f = _f32(H), _f32(f)
+    R, C = f.shape
+    g = np.empty((H.shape[4], R, C), dtype=np.float64)
+    _check(_load().oracle_backward_sparse(H.ctypes.data, _dims(H).ctypes.data, f.ctypes.data, R, C,
+                                          g.ctypes.data, nthreads), "oracle_backward_sparse")
+    return g
 
 
 def forward64(H: np.ndarray, g: np.ndarray, nthreads: int = 0) -> np.ndarray:

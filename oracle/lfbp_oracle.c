@@ -396,6 +396,123 @@ static double grad_psf_entry(const oshape* h, const float* w, const float* g, in
     return acc;
 }
 
+/*
+ * The two projections again, summed over the nonzero entries of H only.  Read
+ * from the H side, entry H[s][t][x][y][z] of the pattern of cell position
+ * (x,y) links every voxel (z,P,Q) with P mod nx = x and Q mod ny = y to the
+ * pixel (P+s-hs, Q+t-ht) when that pixel lies in the image: the same entries
+ * of A as above.  A zero entry of H adds nothing to either sum, so skipping it
+ * leaves A g and A^T f unchanged up to the order of the float64 additions; the
+ * cost scales with the nonzeros of H, which makes full projector-sized images
+ * affordable.
+ */
+static int64_t nonzero_entries(const oshape* h, const float* H, int64_t** idx)
+{
+    const int64_t E = h->ns * h->nt * h->nx * h->ny * h->nz;
+    int64_t n = 0;
+    for (int64_t k = 0; k < E; ++k) n += H[k] != 0.0f;
+    *idx = (int64_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    if (!*idx) return -1;
+    n = 0;
+    for (int64_t k = 0; k < E; ++k)
+        if (H[k] != 0.0f) (*idx)[n++] = k;
+    return n;
+}
+
+/* f[R][C] = A g over the nonzero entries of H; each thread sums its share of
+ * the entries into an image of its own, and the images are added in thread
+ * order. */
+int oracle_forward_sparse(const float* H, const int64_t* dims, const float* g, int64_t R, int64_t C, double* f,
+                          int nthreads)
+{
+    const oshape h = mkshape(dims);
+    const int64_t hs = (h.ns - 1) / 2, ht = (h.nt - 1) / 2;
+    int64_t* nz_idx = NULL;
+    const int64_t n = nonzero_entries(&h, H, &nz_idx);
+    if (n < 0) return -3;
+    const int T = nthreads_or_default(nthreads);
+    double* part = (double*)calloc((size_t)T * (size_t)(R * C), sizeof(double));
+    if (!part) {
+        free(nz_idx);
+        return -3;
+    }
+#pragma omp parallel num_threads(T)
+    {
+        const int tid = omp_get_thread_num();
+        double* fp = part + (size_t)tid * (size_t)(R * C);
+#pragma omp for schedule(static)
+        for (int64_t e = 0; e < n; ++e) {
+            int64_t k = nz_idx[e];
+            const double v = (double)H[k];
+            const int64_t z = k % h.nz;
+            k /= h.nz;
+            const int64_t y = k % h.ny;
+            k /= h.ny;
+            const int64_t x = k % h.nx;
+            k /= h.nx;
+            const int64_t t = k % h.nt;
+            const int64_t s = k / h.nt;
+            for (int64_t P = x; P < R; P += h.nx) {
+                const int64_t p = P + s - hs;
+                if (p < 0 || p >= R) continue;
+                for (int64_t Q = y; Q < C; Q += h.ny) {
+                    const int64_t q = Q + t - ht;
+                    if (q < 0 || q >= C) continue;
+                    fp[p * C + q] += v * (double)g[(z * R + P) * C + Q];
+                }
+            }
+        }
+    }
+    for (int64_t i = 0; i < R * C; ++i) {
+        double acc = 0.0;
+        for (int t = 0; t < T; ++t) acc += part[(size_t)t * (size_t)(R * C) + (size_t)i];
+        f[i] = acc;
+    }
+    free(part);
+    free(nz_idx);
+    return 0;
+}
+
+/* g[nz][R][C] = A^T f over the nonzero entries of H; each depth plane is
+ * summed by one thread. */
+int oracle_backward_sparse(const float* H, const int64_t* dims, const float* f, int64_t R, int64_t C, double* g,
+                           int nthreads)
+{
+    const oshape h = mkshape(dims);
+    const int64_t hs = (h.ns - 1) / 2, ht = (h.nt - 1) / 2;
+    int64_t* nz_idx = NULL;
+    const int64_t n = nonzero_entries(&h, H, &nz_idx);
+    if (n < 0) return -3;
+    memset(g, 0, (size_t)(h.nz * R * C) * sizeof(double));
+#pragma omp parallel for num_threads(nthreads_or_default(nthreads)) schedule(dynamic, 1)
+    for (int64_t z = 0; z < h.nz; ++z) {
+        double* gz = g + z * R * C;
+        for (int64_t e = 0; e < n; ++e) {
+            int64_t k = nz_idx[e];
+            if (k % h.nz != z) continue;
+            const double v = (double)H[k];
+            k /= h.nz;
+            const int64_t y = k % h.ny;
+            k /= h.ny;
+            const int64_t x = k % h.nx;
+            k /= h.nx;
+            const int64_t t = k % h.nt;
+            const int64_t s = k / h.nt;
+            for (int64_t P = x; P < R; P += h.nx) {
+                const int64_t p = P + s - hs;
+                if (p < 0 || p >= R) continue;
+                for (int64_t Q = y; Q < C; Q += h.ny) {
+                    const int64_t q = Q + t - ht;
+                    if (q < 0 || q >= C) continue;
+                    gz[P * C + Q] += v * (double)f[p * C + q];
+                }
+            }
+        }
+    }
+    free(nz_idx);
+    return 0;
+}
+
 int oracle_grad_psf(const int64_t* dims, const float* w, const float* g, int64_t R, int64_t C, double* dH,
                     int nthreads)
 {

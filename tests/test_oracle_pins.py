@@ -293,6 +293,38 @@ def test_backprojection_through_Ht_is_the_adjoint(shape, R, C):
     assert np.array_equal(backproject_with_Ht(oracle.Ht_rows(H), f), oracle.backward(H, f))
 
 
+@pytest.mark.parametrize("shape,R,C", [((5, 5, 3, 3, 2), 9, 12), ((7, 9, 3, 5, 1), 8, 11),
+                                       ((9, 7, 1, 1, 3), 10, 7)])
+def test_sparse_projectors_are_the_dense_matrix(shape, R, C):
+    """The nonzero-entry forms (for full-size images) against the dense
+    measurement matrix, on PSFs with most entries zero, and against the
+    pixel/voxel forms with the sums exact (small integers): bit for bit."""
+    H = lfsynth.uniform_f32(shape, 16)
+    H[H < 0.7] = 0.0
+    g = lfsynth.uniform_f32((shape[4], R, C), 17)
+    f = lfsynth.uniform_f32((R, C), 18)
+    A = oracle.A_dense(H, R, C).astype(np.float64)
+    for nth in (1, 3):
+        assert np.allclose(oracle.forward_sparse(H, g, nth).ravel(), A @ g.astype(np.float64).ravel(),
+                           rtol=1e-13, atol=1e-13)
+        assert np.allclose(oracle.backward_sparse(H, f, nth).ravel(), A.T @ f.astype(np.float64).ravel(),
+                           rtol=1e-13, atol=1e-13)
+    Hi = lfsynth.small_int_f32(shape, 19, 8)
+    Hi[::2] = 0.0
+    gi = lfsynth.small_int_f32((shape[4], R, C), 20, 8)
+    fi = lfsynth.small_int_f32((R, C), 21, 8)
+    assert np.array_equal(oracle.forward_sparse(Hi, gi, 2), oracle.forward(Hi, gi))
+    assert np.array_equal(oracle.backward_sparse(Hi, fi, 2), oracle.backward(Hi, fi))
+
+
+def test_sparse_projectors_all_zero_and_scatter():
+    shape, R, C = (9, 9, 3, 3, 2), 11, 13
+    g = lfsynth.uniform_f32((shape[4], R, C), 22)
+    assert not oracle.forward_sparse(np.zeros(shape, np.float32), g).any()
+    H = lfsynth.uniform_f32(shape, 23)
+    assert np.allclose(oracle.forward_sparse(H, g), scatter_forward(H, g), rtol=1e-13, atol=1e-13)
+
+
 def test_forward_at_and_backward_at_match_full():
     shape, R, C = (9, 9, 3, 3, 2), 12, 15
     H = lfsynth.uniform_f32(shape, 9)
