@@ -560,7 +560,8 @@ def bench_projector(args, torch):
 
 def bench_rl(args, torch):
     """One step = one Richardson-Lucy update (Eq. 2) of a 21 x 600 x 600 volume
-    from a 600 x 600 image: forward projection ending in the quotient,
+    from a 600 x 600 shot-noise image (Poisson counts, 50 photons per pixel on
+    average): forward projection ending in the quotient,
     backprojection through H' ending in the update, on an operator prepared
     once as richardson_lucy does (lfbp_rl_step_op).  The preparation time and
     the step time of lfbp_rl_step, which packs H and H' on every call, are
@@ -575,7 +576,13 @@ def bench_rl(args, torch):
     dev = torch.device("cuda:0")
     dH = torch.from_numpy(H).to(dev)
     dHt = lf.compute_Ht(dH)
-    f = torch.from_numpy(lfsynth.uniform_f32((R, C), pw.g_seed + 1) + np.float32(0.5)).to(dev)
+    # shot-noise data f = Poisson(H g_true), 50 photons per pixel on average;
+    # the noise-free image comes from the library's own forward projection
+    g_true = torch.from_numpy(lfsynth.uniform_f32((pw.psf.shape[4], R, C), pw.g_seed + 1) ** 4).to(dev)
+    mean = lf.forward(dH, g_true).double()
+    lam = (mean * (50.0 / mean.mean())).cpu().numpy()
+    f = torch.from_numpy(lfsynth.poisson_counts(lam, pw.g_seed + 2)).to(dev)
+    del g_true, mean
     g = torch.ones((pw.psf.shape[4], R, C), device=dev)
     ws = torch.empty(lf.rl_workspace_size(H.shape, R, C), dtype=torch.uint8, device=dev)
     norm = lf.rl_norm(dHt, R, C, workspace=ws)

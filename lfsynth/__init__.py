@@ -21,7 +21,7 @@ _SO = os.path.join(_HERE, "liblfsynth.so")
 _lib = None
 
 __all__ = ["build", "gauss_f32", "bits_u32", "bits_u16", "bits", "uniform_f32",
-           "small_int_f32", "word", "Workload", "TINY", "MICROSCOPE", "CAMERA",
+           "small_int_f32", "poisson_counts", "word", "Workload", "TINY", "MICROSCOPE", "CAMERA",
            "PROJECTOR", "BATCHED_SETS", "SMALL_SETS", "TABLE1_SHAPES", "batched_set", "small_set", "table1_workload", "make_H"]
 
 
@@ -114,6 +114,15 @@ def small_int_f32(shape, seed: int, k: int, nthreads: int = 0) -> np.ndarray:
     out = np.empty(shape, dtype=np.float32)
     _load().lfsynth_small_int_f32(out.size, int(seed), int(k), out.ctypes.data, int(nthreads))
     return out
+
+
+def poisson_counts(mean: np.ndarray, seed: int) -> np.ndarray:
+    """Photon counts: one Poisson draw per element with the given means
+    (numpy's seeded PCG64 generator), as float32.  The shot noise of a
+    light-field image f = Poisson(H g) is what the Richardson-Lucy update of
+    Eq. 2 is the maximum-likelihood iteration for."""
+    rng = np.random.default_rng(seed)
+    return rng.poisson(np.asarray(mean, dtype=np.float64)).astype(np.float32)
 
 
 def make_H(w: Workload, dtype=np.float32, nthreads: int = 0, out: np.ndarray | None = None):

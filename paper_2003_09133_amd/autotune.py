@@ -2,27 +2,30 @@
 and writes the winners to the tuning table that liblfbp.so reads at start-up
 (paper_2003_09133_amd/lfbp_tune.txt, or $LFBP_TUNE_TABLE).
 
-    python -m paper_2003_09133_amd.autotune [--classes f32:7,...,f16:10] [--no-batched]
-                                            [--out PATH] [--reps N]
+    python -m paper_2003_09133_amd.autotune [--classes f32:7,...,f16:10] [--shapes camera,...]
+                                            [--no-batched] [--out PATH] [--reps N]
     python -m paper_2003_09133_amd.autotune --time-shapes "ns,nt,nx,ny,nz[:f16];..."
 
-A table entry is keyed by (batched, element size, row class), the row class
-of a shape being floor(log2(ny*nz*esize)): the kernels cut H into units of
-whole x-rows, so the size of a row decides the work decomposition and with it
-the best configuration; a shape with no entry of its own class takes the
-nearest class's entry.  Each class is tuned on four representative PSF
-shapes (table CLASS_SHAPES), scored by the geometric mean of their rates, in
-two stages: kernel variant, workgroup size, loads per thread and store kind
-first, then occupancy cap (waves per SIMD) and the order in which units meet
-the XCDs for the best of those.  The winner's output is compared bit for bit
-with the output of the built-in default before it is written; a class whose
-best candidate does not beat the built-in default by MIN_GAIN keeps the
-default.  The batched entry is tuned on the 16-set table, in a
-child process that reads the freshly written plain entries (a batch cuts each
-problem into units of its plain class's size).  Inputs are random payloads
-(the kernels' cost does not depend on the values).  Only the library's C ABI
-is called.  --time-shapes prints, for each shape, the configuration the
-library picks and its rate (GB/s), as one JSON line.
+The table holds two kinds of entries.  A class entry is keyed by (batched,
+element size, row class), the row class of a shape being
+floor(log2(ny*nz*esize)): the kernels cut H into units of whole x-rows, so the
+size of a row decides the work decomposition; a shape with no entry of its
+own takes its class's entry, or the nearest class's.  A shape entry serves
+one exact shape: the named PSF workloads (SHAPE_WORKLOADS), and the batched
+16-set table (keyed by its largest problem).  Every sweep has two stages:
+kernel variant, workgroup size, loads per thread and store kind first, then
+occupancy cap (waves per SIMD) and the order in which units meet the XCDs for
+the best of those.  Each class is tuned on five or six representative PSF
+shapes whose rows span the class (CLASS_SHAPES): a candidate that is more than 2% slower than the built-in
+default on any of them is passed over, the others are ranked by the geometric
+mean of their rates, and a class whose best candidate does not beat the
+default by MIN_GAIN keeps the default.  Every winner's output is compared
+bit for bit with the built-in default's before it is written.  The batched
+entry is tuned in a child process that reads the freshly written plain
+entries (a batch cuts each problem into units of its plain entry's size).
+Inputs are random payloads (the kernels' cost does not depend on the values).
+Only the library's C ABI is called.  --time-shapes prints, for each shape,
+the configuration the library picks and its rate (GB/s), as one JSON line.
 """
 from __future__ import annotations
 
@@ -41,24 +44,43 @@ FIELDS = ("variant", "block_threads", "rows_in_flight", "tile_bytes", "vec_per_t
 
 # Representative PSF shapes (ns, nt, nx, ny, nz) of each (element size, row
 # class): odd cells and patches of an odd number of whole lenslets, 0.2 to
-# 5.5 GB per array, different cell sizes and depth counts.  A configuration is
+# 5.5 GB per array, different cell sizes and depth counts, with rows from the
+# low to the high end of the class.  A configuration is
 # scored by the geometric mean of its rates over the class's shapes, so that
 # the entry serves the whole class rather than one shape.
 CLASS_SHAPES = {
-    (4, 7): [(497, 497, 7, 7, 7), (405, 405, 9, 9, 6), (693, 693, 11, 11, 5), (385, 385, 7, 7, 9)],
-    (4, 8): [(405, 405, 9, 9, 11), (735, 735, 7, 7, 12), (253, 253, 11, 11, 9), (165, 165, 15, 15, 8)],
-    (4, 9): [(275, 275, 11, 11, 20), (525, 525, 15, 15, 10), (245, 245, 7, 7, 30), (165, 165, 15, 15, 15)],
-    (4, 10): [(165, 165, 15, 15, 21), (171, 171, 19, 19, 25), (297, 297, 11, 11, 30), (135, 135, 15, 15, 30)],
-    (4, 11): [(345, 345, 15, 15, 51), (225, 225, 15, 15, 45), (209, 209, 11, 11, 60), (135, 135, 15, 15, 40)],
-    (4, 12): [(171, 171, 19, 19, 80), (135, 135, 15, 15, 100), (99, 99, 11, 11, 120), (75, 75, 15, 15, 90)],
-    (4, 13): [(105, 105, 15, 15, 200), (57, 57, 19, 19, 150), (77, 77, 11, 11, 300), (45, 45, 15, 15, 250)],
-    (4, 14): [(45, 45, 15, 15, 300), (57, 57, 19, 19, 300), (31, 31, 31, 31, 200), (75, 75, 15, 15, 400)],
-    (2, 9): [(165, 165, 15, 15, 21), (171, 171, 19, 19, 25), (297, 297, 11, 11, 30), (135, 135, 15, 15, 30)],
-    (2, 10): [(345, 345, 15, 15, 51), (225, 225, 15, 15, 45), (209, 209, 11, 11, 60), (135, 135, 15, 15, 40)],
+    (4, 7): [(497, 497, 7, 7, 7), (405, 405, 9, 9, 6), (693, 693, 11, 11, 5), (385, 385, 7, 7, 9),
+             (495, 495, 11, 11, 3)],
+    (4, 8): [(405, 405, 9, 9, 11), (735, 735, 7, 7, 12), (253, 253, 11, 11, 9), (165, 165, 15, 15, 8),
+             (325, 325, 13, 13, 5), (385, 385, 7, 7, 18)],
+    (4, 9): [(275, 275, 11, 11, 20), (525, 525, 15, 15, 10), (245, 245, 7, 7, 30), (165, 165, 15, 15, 15),
+             (275, 275, 11, 11, 12), (245, 245, 7, 7, 36)],
+    (4, 10): [(165, 165, 15, 15, 21), (171, 171, 19, 19, 25), (297, 297, 11, 11, 30), (135, 135, 15, 15, 30),
+              (195, 195, 13, 13, 20), (165, 165, 15, 15, 34)],
+    (4, 11): [(345, 345, 15, 15, 51), (225, 225, 15, 15, 45), (209, 209, 11, 11, 60), (135, 135, 15, 15, 40),
+              (195, 195, 15, 15, 35), (135, 135, 15, 15, 68)],
+    (4, 12): [(171, 171, 19, 19, 80), (135, 135, 15, 15, 100), (99, 99, 11, 11, 120), (75, 75, 15, 15, 90),
+              (135, 135, 15, 15, 69), (75, 75, 15, 15, 136)],
+    (4, 13): [(105, 105, 15, 15, 200), (57, 57, 19, 19, 150), (77, 77, 11, 11, 300), (45, 45, 15, 15, 250),
+              (75, 75, 15, 15, 137), (45, 45, 15, 15, 272)],
+    (4, 14): [(45, 45, 15, 15, 300), (57, 57, 19, 19, 300), (31, 31, 31, 31, 200), (75, 75, 15, 15, 400),
+              (75, 75, 15, 15, 274), (45, 45, 15, 15, 545)],
+    (2, 9): [(165, 165, 15, 15, 21), (171, 171, 19, 19, 25), (297, 297, 11, 11, 30), (135, 135, 15, 15, 30),
+             (195, 195, 13, 13, 20), (165, 165, 15, 15, 34)],
+    (2, 10): [(345, 345, 15, 15, 51), (225, 225, 15, 15, 45), (209, 209, 11, 11, 60), (135, 135, 15, 15, 40),
+              (195, 195, 15, 15, 35), (135, 135, 15, 15, 68)],
 }
-# A tuned entry must beat the built-in default by this factor (geometric mean
-# over the class's shapes); otherwise the class keeps the default.
+# A tuned class entry must beat the built-in default by this factor (geometric
+# mean over the class's shapes), and may be at most MAX_LOSS slower than it on
+# any one of them; otherwise the class keeps the default.
 MIN_GAIN = 1.005
+MAX_LOSS = 0.98
+# Named PSF workloads tuned for their exact shape: (name, shape, element size).
+SHAPE_WORKLOADS = {
+    "camera": ((345, 345, 15, 15, 51), 4),
+    "camera-f16": ((345, 345, 15, 15, 51), 2),
+    "microscope": ((165, 165, 15, 15, 21), 4),
+}
 
 
 def row_class(shape, esize: int) -> int:
@@ -113,24 +135,30 @@ def full_config(lf, shape, dtype, cfg):
 
 
 def read_table(path):
+    """Entries of a table file: {key: config fields}, key = ("class", batched,
+    esize, class) or ("shape", batched, esize, ns, nt, nx, ny, nz)."""
     entries = {}
     if os.path.exists(path):
         with open(path) as fh:
             for line in fh:
-                line = line.split("#", 1)[0].split()
-                if len(line) == 13:
-                    entries[tuple(int(v) for v in line[:3])] = [int(v) for v in line[3:]]
+                f = line.split("#", 1)[0].split()
+                if f and f[0] == "class" and len(f) == 14:
+                    entries[("class", *(int(v) for v in f[1:4]))] = [int(v) for v in f[4:]]
+                elif f and f[0] == "shape" and len(f) == 18:
+                    entries[("shape", *(int(v) for v in f[1:8]))] = [int(v) for v in f[8:]]
     return entries
 
 
 def write_table(path, entries, notes):
     with open(path + ".tmp", "w") as fh:
         fh.write("# Tuning table of liblfbp.so, written by paper_2003_09133_amd/autotune.py.\n")
-        fh.write("# batched esize row_class | variant threads rows_in_flight tile_bytes vec_per_thread "
-                 "nontemporal persistent grid waves_per_eu schedule\n")
+        fh.write("# shape batched esize ns nt nx ny nz | config\n")
+        fh.write("# class batched esize row_class | config\n")
+        fh.write("# config = variant threads rows_in_flight tile_bytes vec_per_thread nontemporal persistent grid "
+                 "waves_per_eu schedule\n")
         for n in notes:
             fh.write(f"# {n}\n")
-        for key in sorted(entries):
+        for key in sorted(entries, key=lambda k: (k[0] != "shape", k[1:])):
             fh.write(" ".join(str(v) for v in (*key, *entries[key])) + "\n")
     os.replace(path + ".tmp", path)
 
@@ -153,48 +181,74 @@ def geomean(v):
     return p ** (1.0 / len(v))
 
 
-def sweep(runs, torch, reps, inner, batched):
+def sweep(runs, torch, reps, inner, batched, floor=None):
     """Two-stage sweep over (run(cfg), bytes) pairs, scored by the geometric
-    mean of the rates; returns (best score in GB/s, best config, ranked
-    results as (score, config, per-run GB/s))."""
+    mean of the rates; with `floor` (per-run GB/s), a candidate slower than
+    floor on any run is passed over.  Returns (best score in GB/s, best
+    config, ranked results as (score, config, per-run GB/s)); the config is
+    None when every candidate was passed over."""
     def score(cfg):
         rates = [nb / _time(lambda: run(cfg), torch, reps, inner) / 1e9 for run, nb in runs]
-        return geomean(rates), cfg, [round(r, 1) for r in rates]
+        ok = floor is None or all(r >= f for r, f in zip(rates, floor))
+        return (geomean(rates) if ok else 0.0), cfg, [round(r, 1) for r in rates]
     results = [score(cfg) for cfg in stage1(batched)]
     results.sort(key=lambda r: -r[0])
-    results += [score(cfg) for cfg in stage2(results[0][1])]
-    results.sort(key=lambda r: -r[0])
+    if results[0][0] > 0:
+        results += [score(cfg) for cfg in stage2(results[0][1])]
+        results.sort(key=lambda r: -r[0])
+    if results[0][0] <= 0:
+        return 0.0, None, results
     return results[0][0], results[0][1], results
 
 
-def tune_class(lf, torch, esize, cls, reps):
-    shapes = CLASS_SHAPES[(esize, cls)]
-    dt = torch.float32 if esize == 4 else torch.float16
-    Hs = [random_psf(torch, s, dt) for s in shapes]
-    Hts = [torch.empty_like(H) for H in Hs]
-    runs = [((lambda c, H=H, Ht=Ht: lf.compute_Ht_into(H, Ht, config=c)), 2 * H.numel() * H.element_size())
-            for H, Ht in zip(Hs, Hts)]
-    best_gbs, best, results = sweep(runs, torch, reps, 5, False)
-    default = [nb / _time(lambda: run(None), torch, reps) / 1e9 for run, nb in runs]
-    kept_default = best_gbs < MIN_GAIN * geomean(default)
-    if kept_default:
-        best, best_gbs = {}, geomean(default)
+def check_bits(lf, torch, Hs, Hts, best, what):
     for H, Ht in zip(Hs, Hts):
         ref = torch.empty_like(H)
         lf.compute_Ht_into(H, ref)                     # built-in default
         lf.compute_Ht_into(H, Ht, config=best)
         torch.cuda.synchronize()
         if not same_bits(torch, Ht, ref):
-            raise RuntimeError(f"class {cls} ({list(H.shape)}): the winning configuration's H' differs from "
-                               "the default's")
+            raise RuntimeError(f"{what} ({list(H.shape)}): the winning configuration's H' differs from the "
+                               "default's")
+
+
+def tune_shapes(lf, torch, shapes, esize, reps, robust):
+    """Tune over `shapes` (one dtype); robust: the class rules (floor and
+    minimum gain against the built-in default)."""
+    dt = torch.float32 if esize == 4 else torch.float16
+    Hs = [random_psf(torch, s, dt) for s in shapes]
+    Hts = [torch.empty_like(H) for H in Hs]
+    runs = [((lambda c, H=H, Ht=Ht: lf.compute_Ht_into(H, Ht, config=c)), 2 * H.numel() * H.element_size())
+            for H, Ht in zip(Hs, Hts)]
+    default = [nb / _time(lambda: run(None), torch, reps) / 1e9 for run, nb in runs]
+    floor = [MAX_LOSS * d for d in default] if robust else None
+    best_gbs, best, results = sweep(runs, torch, reps, 5, False, floor)
+    kept_default = best is None or (robust and best_gbs < MIN_GAIN * geomean(default))
+    if kept_default:
+        best, best_gbs = {}, geomean(default)
+    check_bits(lf, torch, Hs, Hts, best, "tuning")
     full = full_config(lf, shapes[0], dt, best)
-    info = {"class": [esize, cls], "shapes": [list(s) for s in shapes], "best_gbs": round(best_gbs, 1),
-            "best_per_shape": results[0][2], "config": full, "default_gbs": round(geomean(default), 1),
-            "default_per_shape": [round(r, 1) for r in default],
-            "kept_default": kept_default, "runner_up": [(round(g, 1), c) for g, c, _ in results[1:4]]}
+    info = {"shapes": [list(s) for s in shapes], "esize": esize, "best_gbs": round(best_gbs, 1),
+            "best_per_shape": results[0][2] if not kept_default else [round(r, 1) for r in default],
+            "config": full, "default_gbs": round(geomean(default), 1),
+            "default_per_shape": [round(r, 1) for r in default], "kept_default": kept_default,
+            "runner_up": [(round(g, 1), c) for g, c, _ in results[1:4]]}
     del Hs, Hts
     torch.cuda.empty_cache()
-    return (0, esize, cls), [full[f] for f in FIELDS], info
+    return [full[f] for f in FIELDS], info
+
+
+def tune_class(lf, torch, esize, cls, reps):
+    vals, info = tune_shapes(lf, torch, CLASS_SHAPES[(esize, cls)], esize, reps, True)
+    info["class"] = [esize, cls]
+    return ("class", 0, esize, cls), vals, info
+
+
+def tune_named(lf, torch, name, reps):
+    shape, esize = SHAPE_WORKLOADS[name]
+    vals, info = tune_shapes(lf, torch, [shape], esize, reps, False)
+    info["workload"] = name
+    return ("shape", 0, esize, *shape), vals, info
 
 
 def tune_batched(lf, torch, lfsynth, reps):
@@ -203,6 +257,8 @@ def tune_batched(lf, torch, lfsynth, reps):
     nbytes = sum(2 * h.numel() * 4 for h in Hs)
     best_gbs, best, results = sweep([(lambda c: lf.compute_Ht_batched(Hs, outs, config=c), nbytes)], torch,
                                     max(3, reps // 2), 2, True)
+    if best is None:
+        best = {}
     refs = [torch.empty_like(h) for h in Hs]
     for h, r in zip(Hs, refs):
         lf.compute_Ht_into(h, r)
@@ -213,7 +269,7 @@ def tune_batched(lf, torch, lfsynth, reps):
     lf.release_plans()
     big = max(lfsynth.BATCHED_SETS, key=lambda w: w.elements)
     full = full_config(lf, big.shape, torch.float32, best)
-    key = (1, 4, row_class(big.shape, 4))
+    key = ("shape", 1, 4, *big.shape)
     return key, [full[f] for f in FIELDS], {"workload": "batched", "best_gbs": round(best_gbs, 1), "config": full,
                                             "runner_up": [(round(g, 1), c) for g, c, _ in results[1:4]]}
 
@@ -239,6 +295,7 @@ def time_shapes(lf, torch, spec: str, reps: int):
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--classes", default=",".join(f"{'f32' if e == 4 else 'f16'}:{c}" for e, c in CLASS_SHAPES))
+    ap.add_argument("--shapes", default=",".join(SHAPE_WORKLOADS))
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-only", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--out", default=DEFAULT_TABLE)
@@ -267,8 +324,17 @@ def main(argv=None):
     import torch
     import paper_2003_09133_amd as lf
 
-    entries = {k: v for k, v in read_table(args.out).items() if k[0] == 0}
+    entries = {k: v for k, v in read_table(args.out).items() if k[1] == 0}
     notes = []
+    dev = torch.cuda.get_device_name(0)
+    for name in args.shapes.split(","):
+        if not name:
+            continue
+        key, vals, info = tune_named(lf, torch, name, args.reps)
+        entries[key] = vals
+        notes.append(f"{name} {info['shapes'][0]}: {info['best_gbs']} GB/s (built-in default "
+                     f"{info['default_gbs']}) on {dev}")
+        print(json.dumps(info), flush=True)
     for item in args.classes.split(","):
         if not item:
             continue
@@ -277,7 +343,7 @@ def main(argv=None):
         key, vals, info = tune_class(lf, torch, esize, int(cls), args.reps)
         entries[key] = vals
         notes.append(f"{dts} class {cls}: {info['best_gbs']} GB/s geometric mean over {info['shapes']} "
-                     f"(built-in default {info['default_gbs']}) on {torch.cuda.get_device_name(0)}")
+                     f"(built-in default {info['default_gbs']}{', kept' if info['kept_default'] else ''}) on {dev}")
         print(json.dumps(info), flush=True)
     write_table(args.out, entries, notes)
     if not args.no_batched:

@@ -1,17 +1,19 @@
 // Tuning table of the re-arrangement kernels.
 //
 // The table is a text file written by the autotuner
-// (paper_2003_09133_amd/autotune.py): one entry per line,
-//   <batched 0|1> <esize> <row class> <variant> <threads> <rows_in_flight>
-//   <tile_bytes> <vec_per_thread> <nontemporal> <persistent> <grid>
-//   <waves_per_eu> <schedule>
-// '#' starts a comment.  The row class of a shape is floor(log2(ny*nz*esize)),
-// the size class of an x-row in bytes: the kernels' work decomposition, and so
-// their best configuration, follows the row size.  A shape takes the entry of
-// its own class, else the entry of the nearest class (same batched flag; a
-// class step counts twice as much as a different element size), else the
-// built-in defaults below.  The table is read once, from $LFBP_TUNE_TABLE if
-// set, else from lfbp_tune.txt next to liblfbp.so.
+// (paper_2003_09133_amd/autotune.py), one entry per line, of two kinds:
+//   shape <batched 0|1> <esize> <ns> <nt> <nx> <ny> <nz> <config>
+//   class <batched 0|1> <esize> <row class> <config>
+// where <config> is <variant> <threads> <rows_in_flight> <tile_bytes>
+// <vec_per_thread> <nontemporal> <persistent> <grid> <waves_per_eu>
+// <schedule>.  '#' starts a comment.  A shape entry serves that exact shape
+// (for a batch: the shape of its largest problem).  The row class of a shape
+// is floor(log2(ny*nz*esize)), the size class of an x-row in bytes: the
+// kernels' work decomposition follows the row size.  A shape with no entry of
+// its own takes the entry of its row class, else the entry of the nearest
+// class (same batched flag; a class step counts twice as much as a different
+// element size), else the built-in defaults below.  The table is read once,
+// from $LFBP_TUNE_TABLE if set, else from lfbp_tune.txt next to liblfbp.so.
 #include "lfbp_tune.h"
 
 #include <dlfcn.h>
@@ -30,7 +32,8 @@ namespace lfbp {
 namespace {
 
 struct Entry {
-    int batched, esize, cls;
+    int batched, esize, cls;  // cls < 0: a shape entry
+    int64_t dims[5];
     lfbp_gather_config cfg;
 };
 
@@ -50,6 +53,19 @@ std::string table_path()
     return "lfbp_tune.txt";
 }
 
+// Parse the ten configuration fields at p; true if all are present, valid
+// and nothing follows them.
+bool parse_config(const char* p, lfbp_gather_config& c)
+{
+    int extra = 0;
+    const int n = std::sscanf(p, "%d %d %d %d %d %d %d %d %d %d %d", &c.variant, &c.block_threads,
+                              &c.rows_in_flight, &c.tile_bytes, &c.vec_per_thread, &c.nontemporal, &c.persistent,
+                              &c.grid, &c.waves_per_eu, &c.schedule, &extra);
+    return n == 10 && c.variant >= LFBP_GATHER_DIRECT && c.variant <= LFBP_GATHER_WIDE && c.block_threads > 0 &&
+           c.rows_in_flight > 0 && c.vec_per_thread > 0 && c.nontemporal > 0 && c.persistent > 0 &&
+           c.waves_per_eu > 0 && c.schedule > 0 && check_config(&c) == LFBP_OK;
+}
+
 void load_table()
 {
     FILE* fh = std::fopen(table_path().c_str(), "r");
@@ -60,18 +76,24 @@ void load_table()
         if (hash) *hash = 0;
         Entry e;
         std::memset(&e, 0, sizeof(e));
-        lfbp_gather_config& c = e.cfg;
-        int extra = 0;
-        const int n = std::sscanf(line, "%d %d %d %d %d %d %d %d %d %d %d %d %d %d", &e.batched, &e.esize, &e.cls,
-                                  &c.variant, &c.block_threads, &c.rows_in_flight, &c.tile_bytes,
-                                  &c.vec_per_thread, &c.nontemporal, &c.persistent, &c.grid, &c.waves_per_eu,
-                                  &c.schedule, &extra);
-        if (n != 13) continue;
-        const bool ok = (e.batched == 0 || e.batched == 1) && (e.esize == 2 || e.esize == 4) && e.cls >= 0 &&
-                        e.cls < 64 && c.variant >= LFBP_GATHER_DIRECT && c.variant <= LFBP_GATHER_WIDE &&
-                        c.block_threads > 0 && c.rows_in_flight > 0 && c.vec_per_thread > 0 && c.nontemporal > 0 &&
-                        c.persistent > 0 && c.waves_per_eu > 0 && c.schedule > 0 && check_config(&c) == LFBP_OK;
-        if (ok) g_table.push_back(e);
+        char kind[16] = {0};
+        int used = 0;
+        if (std::sscanf(line, "%15s %d %d%n", kind, &e.batched, &e.esize, &used) != 3) continue;
+        if ((e.batched != 0 && e.batched != 1) || (e.esize != 2 && e.esize != 4)) continue;
+        const char* rest = line + used;
+        int more = 0;
+        if (std::strcmp(kind, "class") == 0) {
+            if (std::sscanf(rest, "%d%n", &e.cls, &more) != 1 || e.cls < 0 || e.cls >= 64) continue;
+        } else if (std::strcmp(kind, "shape") == 0) {
+            long long d[5];
+            if (std::sscanf(rest, "%lld %lld %lld %lld %lld%n", &d[0], &d[1], &d[2], &d[3], &d[4], &more) != 5)
+                continue;
+            for (int i = 0; i < 5; ++i) e.dims[i] = d[i];
+            e.cls = -1;
+        } else {
+            continue;
+        }
+        if (parse_config(rest + more, e.cfg)) g_table.push_back(e);
     }
     std::fclose(fh);
 }
@@ -92,11 +114,15 @@ int row_class(const lfbp_shape& s, int esize)
 lfbp_gather_config tuned_config(const lfbp_shape& s, int esize, bool batched)
 {
     std::call_once(g_once, load_table);
+    const int64_t dims[5] = {s.ns, s.nt, s.nx, s.ny, s.nz};
+    for (const Entry& e : g_table)
+        if (e.cls < 0 && e.batched == int(batched) && e.esize == esize && std::memcmp(e.dims, dims, sizeof(dims)) == 0)
+            return e.cfg;
     const int cls = row_class(s, esize);
     const Entry* best = nullptr;
     int best_score = 0;
     for (const Entry& e : g_table) {
-        if (e.batched != int(batched)) continue;
+        if (e.cls < 0 || e.batched != int(batched)) continue;
         const int score = 2 * (e.cls > cls ? e.cls - cls : cls - e.cls) + (e.esize != esize ? 1 : 0);
         if (!best || score < best_score) {
             best = &e;

@@ -171,6 +171,25 @@ def _full_size_check(w, dtype, full_compare: bool):
     assert gpu_equal_bits(lf.compute_Ht(Htb), dHb)
 
 
+def test_r29_shape_sampled():
+    """The shape of the paper's experimental R29 PSF (Sec. 5, Table 1 last row:
+    a 95 x 55 hexagonal-grid cell, 181 x 181 px patches, 11 depths; 7.5 GB in
+    float32), row-major, random payloads: 3 million sampled elements and
+    whole x-rows at the array's ends and middle against the oracle."""
+    shape = (181, 181, 95, 55, 11)
+    H = lfsynth.bits(shape, 29, np.float32)
+    dH = to_dev(H)
+    Ht = lf.compute_Ht(dH)
+    del dH
+    ns, nt, nx, ny, nz = shape
+    W = ny * nz
+    rows = [0, 1, nx - 1, nx, (ns * nt // 2) * nx + 47, ns * nt * nx - 1]
+    idx = np.concatenate([sample_indices(H.size, 3_000_000, 29)] +
+                         [np.arange(r * W, (r + 1) * W, dtype=np.int64) for r in rows])
+    got = Ht.view(-1)[torch.from_numpy(idx).to(DEV)].cpu().numpy()
+    assert_same_bits(got, oracle.Ht_at(H, idx), "R29 shape sampled")
+
+
 def test_microscope_full_size():
     _full_size_check(lfsynth.MICROSCOPE, np.float32, full_compare=True)
 

@@ -35,24 +35,40 @@ def test_inplace_equals_oracle_and_involution(shape, dtype):
     assert_same_bits(d.cpu().numpy(), H, f"{shape} twice")
 
 
-def test_inplace_microscope_equals_out_of_place():
+def test_inplace_microscope_equals_oracle():
+    """The microscope PSF (random bit payloads), whole array: in place against
+    the oracle, and against the out-of-place kernel."""
     w = lfsynth.MICROSCOPE
-    d = to_dev(lfsynth.bits(w.shape, w.seed, np.float32))
+    H = lfsynth.bits(w.shape, w.seed, np.float32)
+    d = to_dev(H)
     ref = lf.compute_Ht(d)
     lf.compute_Ht_inplace(d)
+    assert_same_bits(d.cpu().numpy(), oracle.Ht_rows(H), "microscope in place")
     assert gpu_equal_bits(d, ref)
 
 
-def test_inplace_camera_f16_equals_out_of_place():
+def test_inplace_camera_f16_equals_oracle():
+    """The camera PSF in float16 (random bit payloads): in place against the
+    oracle at 3 million sampled elements and at whole x-rows of the first,
+    middle and last blocks, then against the out-of-place kernel everywhere;
+    a second call restores H."""
+    from gpu_util import sample_indices
     w = lfsynth.CAMERA
-    d = to_dev(lfsynth.bits(w.shape, w.seed, np.float16))
+    H = lfsynth.bits(w.shape, w.seed, np.float16)
+    d = to_dev(H)
     ref = lf.compute_Ht(d)
     lf.compute_Ht_inplace(d)
+    ns, nt, nx, ny, nz = w.shape
+    W = ny * nz
+    rows = [0, nx - 1, (ns * nt // 2) * nx + 3, ns * nt * nx - 1]
+    idx = np.concatenate([sample_indices(H.size, 3_000_000, 41)] +
+                         [np.arange(r * W, (r + 1) * W, dtype=np.int64) for r in rows])
+    got = d.view(-1)[torch.from_numpy(idx).to(DEV)].cpu().numpy()
+    assert_same_bits(got, oracle.Ht_at(H, idx), "camera f16 in place, sampled")
     assert gpu_equal_bits(d, ref)
     del ref
     lf.compute_Ht_inplace(d)
-    back = to_dev(lfsynth.bits(w.shape, w.seed, np.float16))
-    assert gpu_equal_bits(d, back)
+    assert gpu_equal_bits(d, to_dev(H))
 
 
 def test_inplace_on_a_view_and_stream_order():

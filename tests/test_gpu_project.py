@@ -145,6 +145,29 @@ def test_projector_workload_full_size_sampled():
     assert gpu_equal_bits(op.backward(f), fb)
 
 
+def test_projector_workload_full_size_float64():
+    """Full projector workload, every pixel and every voxel: the GPU forward
+    and backward (through the GPU-built H') against the float64 oracle summed
+    over the nonzero entries of H, relative L2 over the whole image and the
+    whole volume, and the largest single-element error against the norm."""
+    pw = lfsynth.PROJECTOR
+    H, _ = lfsynth.make_H(pw.psf)
+    R, C = pw.image
+    g = lfsynth.uniform_f32((pw.psf.shape[4], R, C), pw.g_seed)
+    dH = to_dev(H)
+    dHt = lf.compute_Ht(dH)
+    f = lf.forward(dH, to_dev(g))
+    fb = lf.backward(dHt, f)
+    torch.cuda.synchronize()
+    fn, fbn = f.cpu().numpy(), fb.cpu().numpy()
+    ref_f = oracle.forward_sparse(H, g)
+    ref_b = oracle.backward_sparse(H, fn)
+    print(f"\nforward rel. L2 {rel_l2(fn, ref_f):.2e}, backward rel. L2 {rel_l2(fbn, ref_b):.2e}", flush=True)
+    assert rel_l2(fn, ref_f) <= TOL and rel_l2(fbn, ref_b) <= TOL
+    assert np.abs(fn - ref_f).max() <= TOL * np.linalg.norm(ref_f)
+    assert np.abs(fbn - ref_b).max() <= TOL * np.linalg.norm(ref_b)
+
+
 def test_without_workspace_uses_stream_allocator():
     """The workspace-free entry points (scratch from hipMallocAsync) give the
     same bits as the workspace forms."""

@@ -98,6 +98,32 @@ def test_five_iterations_vs_oracle():
     assert rel_l2(g_gpu.cpu().numpy(), g) <= 5 * TOL
 
 
+def test_poisson_data_one_step_and_five_iterations():
+    """Shot-noise data, f = Poisson(H g_true) with 50 photons per pixel on
+    average, on a 4 x 4-lenslet crop of the microscope PSF: one update from a
+    flat start against the oracle, and five updates."""
+    w = lfsynth.MICROSCOPE
+    H, _ = lfsynth.make_H(w)
+    R = C = 4 * w.shape[2]
+    g_true = (lfsynth.uniform_f32((w.shape[4], R, C), 50) ** 4).astype(np.float32)
+    mean = oracle.forward(H, g_true)
+    lam = mean * (50.0 / mean.mean())
+    f = lfsynth.poisson_counts(lam, 51)
+    assert (f == np.round(f)).all() and abs(np.var(f - lam) / lam.mean() - 1.0) < 0.2   # counts, var = mean
+    dH = to_dev(H)
+    dHt = lf.compute_Ht(dH)
+    n = lf.rl_norm(dHt, R, C)
+    g0 = np.ones((w.shape[4], R, C), np.float32)
+    g1 = lf.rl_step(dH, dHt, to_dev(f), to_dev(g0), n)
+    n_ref = oracle.rl_norm(H, R, C)
+    assert rel_l2(g1.cpu().numpy(), oracle.rl_step(H, f, g0, norm=n_ref)) <= TOL
+    g5 = lf.richardson_lucy(dH, to_dev(f), 5)
+    g = np.ones((w.shape[4], R, C))
+    for _ in range(5):
+        g = oracle.rl_step(H, f, g, norm=n_ref)
+    assert rel_l2(g5.cpu().numpy(), g) <= 5 * TOL
+
+
 def test_projector_crop_one_step():
     """A 4 x 4-lenslet crop of the projector workload (microscope PSF, 60 x 60
     px, 21 depths)."""

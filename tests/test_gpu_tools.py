@@ -25,14 +25,14 @@ def test_autotuner_writes_a_table_the_library_uses(tmp_path):
     tuner never ran (and a shape of another class, through the nearest-class
     rule) then runs the tuned configuration."""
     table = tmp_path / "tune.txt"
-    out = run(["-m", "paper_2003_09133_amd.autotune", "--classes", "f32:10", "--no-batched", "--reps", "1",
-               "--out", str(table)])
+    out = run(["-m", "paper_2003_09133_amd.autotune", "--classes", "f32:10", "--shapes", "", "--no-batched",
+               "--reps", "1", "--out", str(table)])
     report = json.loads([l for l in out.splitlines() if l.startswith("{")][-1])
     assert report["class"] == [4, 10] and report["best_gbs"] > 0 and report["default_gbs"] > 0
     rows = [l.split() for l in table.read_text().splitlines() if l.strip() and not l.startswith("#")]
-    assert len(rows) == 1 and len(rows[0]) == 13
-    key, cfg = [int(v) for v in rows[0][:3]], [int(v) for v in rows[0][3:]]
-    assert key == [0, 4, 10]                                  # plain, float32, rows of 1024..2047 bytes
+    assert len(rows) == 1 and len(rows[0]) == 14
+    key, cfg = rows[0][:4], [int(v) for v in rows[0][4:]]
+    assert key == ["class", "0", "4", "10"]                   # plain, float32, rows of 1024..2047 bytes
     unseen = [(45, 45, 9, 9, 31), (209, 209, 11, 11, 22)]    # rows of 1116 B (class 10) and 968 B (class 9)
     probe = ("import json, sys; sys.path.insert(0, %r); import torch, paper_2003_09133_amd as lf; "
              "print(json.dumps([lf.default_config(s, torch.float32) for s in %r]))" % (ROOT, unseen))

@@ -1,8 +1,9 @@
 """The tuning table reader of liblfbp.so (csrc/lfbp_tune.cpp), on the CPU:
-entries keyed by (batched, element size, row class = floor(log2(ny*nz*esize)))
-replace the built-in kernel choice for every shape of their class, a shape
-whose class has no entry takes the nearest class's entry, and comments,
-malformed lines and entries with invalid fields are skipped.  Each case runs
+class entries keyed by (batched, element size, row class =
+floor(log2(ny*nz*esize))) replace the built-in kernel choice for every shape
+of their class, a shape whose class has no entry takes the nearest class's
+entry, a shape entry serves its exact shape before any class entry, and
+comments, malformed lines and entries with invalid fields are skipped.  Each case runs
 in a fresh process, since the library reads the table once per process (from
 $LFBP_TUNE_TABLE here)."""
 import json
@@ -40,12 +41,19 @@ def configs_with_table(table: str, cases, tmp_path):
 
 
 def entry(batched, esize, cls, variant, threads, rows, tile, vec, nt, persistent, waves, schedule):
-    return f"{batched} {esize} {cls} {variant} {threads} {rows} {tile} {vec} {nt} {persistent} 0 {waves} {schedule}"
+    return (f"class {batched} {esize} {cls} {variant} {threads} {rows} {tile} {vec} {nt} {persistent} 0 "
+            f"{waves} {schedule}")
+
+
+def shape_entry(batched, esize, shape, variant, threads, rows, tile, vec, nt, persistent, waves, schedule):
+    return (f"shape {batched} {esize} {' '.join(map(str, shape))} {variant} {threads} {rows} {tile} {vec} {nt} "
+            f"{persistent} 0 {waves} {schedule}")
 
 
 def as_cfg(line):
-    v = [int(x) for x in line.split()]
-    return dict(zip(FIELDS, v[3:10] + v[11:13]))
+    v = line.split()
+    v = [int(x) for x in v[4:]] if v[0] == "class" else [int(x) for x in v[8:]]
+    return dict(zip(FIELDS, v[0:7] + v[8:10]))
 
 
 def test_class_entries_replace_the_default_and_bad_lines_are_skipped(tmp_path):
@@ -59,8 +67,10 @@ def test_class_entries_replace_the_default_and_bad_lines_are_skipped(tmp_path):
         e10 + "   # a staged choice for class 10",
         entry(0, 4, 7, 3, 100, 2, 16384, 4, 1, 2, 8, 1) + "   # 100 threads: invalid, skipped",
         entry(0, 4, 7, 3, 256, 2, 16384, 4, 1, 2, 9, 1) + "   # 9 waves per SIMD: invalid, skipped",
-        "0 4 7 3 256 2 16384 4 1 2 0",                              # malformed (old format), skipped
-        "0 4 315 15 3 256 2 16384 4 1 2 0",                         # old exact-shape key, skipped
+        "class 0 4 7 3 256 2 16384 4 1 2 0",                        # malformed (too short), skipped
+        "0 4 315 15 3 256 2 16384 4 1 2 0",                         # no entry kind, skipped
+        "class 0 4 7 3 256 2 16384 4 1 2 0 8 1 5",                  # a field too many, skipped
+        "shape 0 4 45 45 9 9 3 256 2 16384 4 1 2 0 8 1",            # shape with four dimensions, skipped
         entry(1, 4, 7, 1, 64, 2, 0, 2, 1, 1, 8, 1) + "   # batched: not used by plain calls",
     ]) + "\n"
     got = configs_with_table(table, [(micro, 4), (same_class, 4), (other, 4)], tmp_path)
@@ -97,3 +107,17 @@ def test_batched_entries_serve_batched_calls_only(tmp_path):
     got = configs_with_table(eb + "\n", [(shape, 4)], tmp_path)
     default = configs_with_table("", [(shape, 4)], tmp_path)
     assert got == default
+
+
+def test_shape_entries_come_before_class_entries(tmp_path):
+    camera = (345, 345, 15, 15, 51)           # f32 class 11
+    near = (345, 345, 15, 15, 49)             # same class, not the same shape
+    e11 = entry(0, 4, 11, 3, 256, 2, 16384, 2, 1, 2, 8, 1)
+    ecam = shape_entry(0, 4, camera, 3, 128, 2, 16384, 4, 2, 2, 6, 1)
+    ecam16 = shape_entry(0, 2, camera, 2, 512, 1, 32768, 4, 2, 2, 8, 2)
+    ebat = shape_entry(1, 4, camera, 3, 512, 2, 16384, 8, 1, 2, 8, 2)
+    table = "\n".join([e11, ecam, ecam16, ebat]) + "\n"
+    got = configs_with_table(table, [(camera, 4), (near, 4), (camera, 2)], tmp_path)
+    assert got[0] == as_cfg(ecam)             # the exact shape, f32
+    assert got[1] == as_cfg(e11)              # another shape of class 11: the class entry
+    assert got[2] == as_cfg(ecam16)           # the exact shape, f16 (the batched shape entry is not used)
