@@ -292,6 +292,8 @@ def batched_vs_sequential(args, torch, lf, lfsynth, sets, rng):
         Hts.append(torch.empty_like(Hs[-1]))
     nbytes = sum(2 * h.numel() * h.element_size() for h in Hs)
     batched = lf.BatchedHt(Hs, Hts)
+    batched_graph = lf.BatchedHt(Hs, Hts, use_graph=True)
+    batched_persist = lf.BatchedHt(Hs, Hts, config={"persistent": 1})
     L = _abi.lib()
     plain_args = [(h.data_ptr(), o.data_ptr(), _abi.Shape.of(h.shape)) for h, o in zip(Hs, Hts)]
     stream = torch.cuda.current_stream().cuda_stream
@@ -306,15 +308,21 @@ def batched_vs_sequential(args, torch, lf, lfsynth, sets, rng):
     for _ in range(2):
         per_seq += time_each(sequential, args.steps, args.warmup, torch)[2]
         per_bat += time_each(batched, args.steps, args.warmup, torch)[2]
+    # the same table replayed from the plan's captured graph, and the
+    # persistent (pipelined) kernel, beside the default direct launch
+    per_graph = time_each(batched_graph, args.steps, args.warmup, torch)[2]
+    per_pers = time_each(batched_persist, args.steps, args.warmup, torch)[2]
+    lf.release_plans()
     checks = []
     for i, (H, o) in enumerate(zip(Hs_host, Hts)):          # outputs of the last (batched) call
         idx = rng.integers(0, H.size, 200_000)
         checks.append((f"batched set {i} {list(H.shape)}", H, idx, gpu_sample(torch, o, idx)))
-    del Hs, Hts, batched
+    del Hs, Hts, batched, batched_graph, batched_persist
     s_seq, s_bat = spread_ms(per_seq), spread_ms(per_bat)
     figures = {
         "sets": len(sets), "bytes_per_step": nbytes, "steps_per_form": len(per_bat),
         "batched_ms": s_bat, "sequential_ms": s_seq,
+        "batched_graph_replay_ms": spread_ms(per_graph), "batched_persistent_ms": spread_ms(per_pers),
         "batched_GBs_median": round(nbytes / (s_bat["median"] * 1e-3) / 1e9, 1),
         "speedup_median": round(s_seq["median"] / s_bat["median"], 4),
         "speedup_min": round(s_seq["min"] / s_bat["min"], 4),
@@ -436,6 +444,7 @@ def bench_batched(args, torch):
     from paper_2003_09133_amd import _abi
     batched = lf.BatchedHt(Hs, Hts)
     batched_graph = lf.BatchedHt(Hs, Hts, use_graph=True)
+    batched_persist = lf.BatchedHt(Hs, Hts, config={"persistent": 1})
     L = _abi.lib()
     plain_args = [(h.data_ptr(), o.data_ptr(), _abi.Shape.of(h.shape)) for h, o in zip(Hs, Hts)]
     stream = torch.cuda.current_stream().cuda_stream
@@ -455,6 +464,7 @@ def bench_batched(args, torch):
                 raise RuntimeError("lfbp_compute_Ht failed during graph capture")
     t_seqg, _ = time_steps(seq_graph.replay, args.steps, args.warmup, torch)
     t_graph, _ = time_steps(batched_graph, args.steps, args.warmup, torch)
+    t_pers, _ = time_steps(batched_persist, args.steps, args.warmup, torch)
     t_bat, wall = time_steps(batched, args.steps, args.warmup, torch)
     sec = t_bat / args.steps
     gbs = bytes_step / sec / 1e9
@@ -468,6 +478,7 @@ def bench_batched(args, torch):
                    "sequential_ms_per_step": round(t_seq / args.steps * 1e3, 4),
                    "sequential_in_one_graph_ms_per_step": round(t_seqg / args.steps * 1e3, 4),
                    "batched_graph_replay_ms_per_step": round(t_graph / args.steps * 1e3, 4),
+                   "batched_persistent_ms_per_step": round(t_pers / args.steps * 1e3, 4),
                    "batched_vs_sequential_speedup": round(t_seq / t_bat, 4),
                    "batched_vs_sequential_in_one_graph_speedup": round(t_seqg / t_bat, 4),
                    "wall_s": round(wall, 3)},

@@ -163,9 +163,10 @@ class BatchedHt:
     """A batch prepared once: the tensors are checked and the problem table is
     built here, so that each call costs one C call (for repeated H' builds of
     the same buffers, e.g. in a loop that refreshes the PSFs in place).
-    use_graph: replay the launch from a hipGraph captured with the plan."""
+    use_graph: replay the launch from a hipGraph captured with the plan;
+    config: an explicit kernel choice (dict of lfbp_gather_config fields)."""
 
-    def __init__(self, Hs, outs=None, use_graph: bool = False):
+    def __init__(self, Hs, outs=None, use_graph: bool = False, config=None):
         self.Hs = list(Hs)
         if not self.Hs:
             raise ValueError("empty batch")
@@ -184,9 +185,11 @@ class BatchedHt:
                                                  for H, o in zip(self.Hs, self.outs)])
         self._dtype = _DTYPES[self.Hs[0].dtype]
         self._graph = 1 if use_graph else 0
+        self._cfg = _config(config)
+        self._cfg_ref = ctypes.byref(self._cfg) if self._cfg is not None else None
 
     def __call__(self, stream=None):
-        _abi.check(_abi.lib().lfbp_compute_Ht_batched_config(self._probs, len(self.Hs), self._dtype, None,
+        _abi.check(_abi.lib().lfbp_compute_Ht_batched_config(self._probs, len(self.Hs), self._dtype, self._cfg_ref,
                                                              self._graph, _stream(stream)),
                    "lfbp_compute_Ht_batched")
         return self.outs
