@@ -44,7 +44,8 @@ typedef enum {
     LFBP_EDEVICE = -5, /* a HIP call failed (launch error, no device) */
     LFBP_ENOMEM = -6,  /* the library could not allocate its own device or host memory */
     LFBP_EALIGN = -7,  /* a pointer is not aligned to its element size */
-    LFBP_ECAPTURE = -8 /* the call would have to allocate, and its stream is being captured into a graph */
+    LFBP_ECAPTURE = -8, /* the call would have to allocate, and its stream is being captured into a graph */
+    LFBP_ESCRATCH = -9  /* the call needs more than the library's fixed device scratch holds */
 } lfbp_status;
 
 typedef enum { LFBP_F32 = 0, LFBP_F16 = 1 } lfbp_dtype;
@@ -187,6 +188,28 @@ LFBP_API lfbp_status lfbp_compute_Ht_inplace(void* H, lfbp_shape shape, lfbp_dty
  */
 LFBP_API lfbp_status lfbp_compute_Ht_colmajor(const void* H, void* Ht, lfbp_shape shape, lfbp_dtype dtype,
                                               void* stream);
+
+/*
+ * lfbp_compute_Ht_batched_noalloc -- lfbp_compute_Ht_batched for callers that
+ * cannot allocate device memory: code being captured into a graph, tight
+ * serving loops, harnesses that forbid allocation.  Same problems, same
+ * results (bit-identical), same kernels and tuned choice; no plan is kept.
+ *
+ * Scratch  Batches of more than 16 problems need a device descriptor table;
+ *          here it lives in a fixed array compiled into the library (one per
+ *          GPU, held until the process ends, LFBP_NOALLOC_MAX_PROBLEMS
+ *          problems, about 160 KB), written by small kernels on `stream`
+ *          before the gather kernel reads it.  Every call on one GPU uses the
+ *          same array, so calls that overlap in time on one GPU (two streams,
+ *          two threads) race: order them on one stream or synchronise between
+ *          them.  Nothing in the array needs to start at zero.
+ * Errors   as lfbp_compute_Ht_batched (checked before anything is launched),
+ *          and ESCRATCH when count > LFBP_NOALLOC_MAX_PROBLEMS.  Calls no
+ *          hipMalloc, hipFree or other device allocator, and never blocks.
+ */
+#define LFBP_NOALLOC_MAX_PROBLEMS 1024
+LFBP_API lfbp_status lfbp_compute_Ht_batched_noalloc(const lfbp_problem* problems, int32_t count,
+                                                     lfbp_dtype dtype, void* stream);
 
 /* Same as lfbp_compute_Ht_batched with an explicit kernel choice shared by
  * every problem, and graph use: use_graph = 1 captures the launch into a

@@ -11,13 +11,14 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("LFBP_LIB", os.path.join(HERE, "liblfbp.so"))
 
-OK, EINVAL, ESHAPE, EDTYPE, EALIAS, EDEVICE, ENOMEM, EALIGN, ECAPTURE = 0, -1, -2, -3, -4, -5, -6, -7, -8
+OK, EINVAL, ESHAPE, EDTYPE, EALIAS, EDEVICE, ENOMEM, EALIGN, ECAPTURE, ESCRATCH = 0, -1, -2, -3, -4, -5, -6, -7, -8, -9
+NOALLOC_MAX_PROBLEMS = 1024
 F32, F16 = 0, 1
 GATHER_AUTO, GATHER_DIRECT, GATHER_STAGED, GATHER_WIDE = 0, 1, 2, 3
 
 STATUS_NAMES = {OK: "LFBP_OK", EINVAL: "LFBP_EINVAL", ESHAPE: "LFBP_ESHAPE", EDTYPE: "LFBP_EDTYPE",
                 EALIAS: "LFBP_EALIAS", EDEVICE: "LFBP_EDEVICE", ENOMEM: "LFBP_ENOMEM", EALIGN: "LFBP_EALIGN",
-                ECAPTURE: "LFBP_ECAPTURE"}
+                ECAPTURE: "LFBP_ECAPTURE", ESCRATCH: "LFBP_ESCRATCH"}
 
 
 class Shape(ctypes.Structure):
@@ -70,6 +71,7 @@ def lib():
             "lfbp_compute_Ht_colmajor": (st, [vp, vp, Shape, i32, vp]),
             "lfbp_default_config": (st, [Shape, i32, ctypes.POINTER(GatherConfig)]),
             "lfbp_compute_Ht_batched": (st, [ctypes.POINTER(Problem), i32, i32, vp]),
+            "lfbp_compute_Ht_batched_noalloc": (st, [ctypes.POINTER(Problem), i32, i32, vp]),
             "lfbp_compute_Ht_batched_config": (st, [ctypes.POINTER(Problem), i32, i32,
                                                     ctypes.POINTER(GatherConfig), i32, vp]),
             "lfbp_forward": (st, [vp, Shape, vp, i64, i64, vp, vp]),

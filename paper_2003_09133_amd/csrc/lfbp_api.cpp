@@ -21,6 +21,7 @@ hipError_t launch_gather(const GatherDesc& d, int esize, const LaunchPlan& p, hi
 hipError_t launch_gather_batched(const BatchArgs& a, uint32_t maxW, int esize, const LaunchPlan& p,
                                  hipStream_t stream);
 hipError_t put_words(uint32_t* dst, const uint32_t* src, size_t n, hipStream_t stream);
+hipError_t noalloc_scratch(void** ptr, size_t* bytes);
 hipError_t set_gather_smem_limits(int max_bytes);
 hipError_t set_inplace_smem_limits(int max_bytes);
 hipError_t launch_inplace(void* H, const lfbp_shape& s, int esize, int max_lds, hipStream_t stream);
@@ -358,10 +359,7 @@ lfbp_status layout_batch(const lfbp_problem* probs, int32_t count, int es, const
 // Upload a layout's descriptor table and per-XCD walks into `table` (device
 // memory of table_bytes(count) bytes) on `stream`, and point the launch
 // arguments at it.
-size_t table_bytes(int32_t count)
-{
-    return sizeof(GatherDesc) * size_t(count) + sizeof(uint32_t) * size_t(kXcds) * (size_t(count) + 1);
-}
+size_t table_bytes(int32_t count) { return batch_table_bytes(size_t(count)); }
 
 hipError_t upload_table(BatchLayout& L, void* table, hipStream_t stream)
 {
@@ -598,6 +596,7 @@ const char* lfbp_status_string(lfbp_status s)
         case LFBP_ENOMEM: return "out of memory";
         case LFBP_EALIGN: return "pointer not aligned to its element size";
         case LFBP_ECAPTURE: return "the call would allocate while its stream is being captured";
+        case LFBP_ESCRATCH: return "the call needs more than the library's fixed device scratch holds";
         default: return "unknown status";
     }
 }
@@ -712,6 +711,29 @@ lfbp_status lfbp_compute_Ht_batched(const lfbp_problem* problems, int32_t count,
     // a direct launch: replaying the plan's one-kernel graph costs more host
     // time per call than launching the kernel (measured on small tables)
     return lfbp_compute_Ht_batched_config(problems, count, dtype, nullptr, 0, stream);
+}
+
+lfbp_status lfbp_compute_Ht_batched_noalloc(const lfbp_problem* problems, int32_t count, lfbp_dtype dtype,
+                                             void* stream)
+{
+    lfbp_status st = validate_batch(problems, count, dtype);
+    if (st != LFBP_OK) return st;
+    if (count > LFBP_NOALLOC_MAX_PROBLEMS) return LFBP_ESCRATCH;
+    if (ensure_init() != hipSuccess) return LFBP_EDEVICE;
+    const int es = dtype_size(dtype);
+    BatchLayout L;
+    st = layout_batch(problems, count, es, nullptr, L);
+    if (st != LFBP_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (uint32_t(count) > kInlineProblems) {
+        // the descriptor table goes to the library's fixed device scratch
+        void* table = nullptr;
+        size_t bytes = 0;
+        if (noalloc_scratch(&table, &bytes) != hipSuccess) return LFBP_EDEVICE;
+        if (table_bytes(count) > bytes) return LFBP_ESCRATCH;
+        if (upload_table(L, table, s) != hipSuccess) return LFBP_EDEVICE;
+    }
+    return launch_gather_batched(L.args, L.maxW, es, L.plan, s) == hipSuccess ? LFBP_OK : LFBP_EDEVICE;
 }
 
 lfbp_status lfbp_compute_Ht_inplace(void* H, lfbp_shape shape, lfbp_dtype dtype, void* stream)

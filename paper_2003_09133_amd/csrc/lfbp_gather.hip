@@ -35,7 +35,10 @@
 #include <algorithm>
 #include <cstring>
 #include <iterator>
+#include <mutex>
 #include <vector>
+
+#include "lfbp.h"
 
 #include "lfbp_internal.h"
 
@@ -686,6 +689,38 @@ hipError_t launch_gather(const GatherDesc& d, int esize, const LaunchPlan& p, hi
     PlainFn fn = pick_plain_any(p, d.W, esize);
     hipLaunchKernelGGL(fn, dim3(p.grid), dim3(p.threads), size_t(p.lds_bytes), stream, d, p.nontemporal == 1 ? 1 : 0);
     return hipGetLastError();
+}
+
+// Device scratch of lfbp_compute_Ht_batched_noalloc: the descriptor table of
+// one batch of up to LFBP_NOALLOC_MAX_PROBLEMS problems, compiled into the
+// library (each GPU holds its own copy until the process ends).  In host code
+// `scratch` names a host-side stand-in, not device memory: kernels receive the
+// device address that noalloc_scratch() looks up per device.
+constexpr size_t kScratchBytes = batch_table_bytes(LFBP_NOALLOC_MAX_PROBLEMS);
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+// Device address of this GPU's `scratch` (the current device's), looked up
+// once per device with that device current.
+hipError_t noalloc_scratch(void** ptr, size_t* bytes)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    *bytes = kScratchBytes;
+    return hipSuccess;
 }
 
 // Write n words from host memory to device memory dst, ordered on stream:

@@ -2,6 +2,7 @@
 // liblfbp.so.  Not part of the public ABI.
 #pragma once
 
+#include <stddef.h>
 #include <stdint.h>
 
 #include "lfbp.h"
@@ -125,6 +126,13 @@ struct BatchArgs {
     GatherDesc d[kInlineProblems];
     uint32_t xstart[kXcds][kInlineProblems + 1];  // inline batches: first slot of each problem per XCD
 };
+
+// Bytes of a batched descriptor table for n problems: the descriptors, then
+// the per-XCD prefix table [kXcds][n+1].
+constexpr size_t batch_table_bytes(size_t n)
+{
+    return sizeof(GatherDesc) * n + sizeof(uint32_t) * size_t(kXcds) * (n + 1);
+}
 
 // Words written into device memory by one launch of the table-writer kernel
 // (descriptor tables travel to the device as kernel arguments, so uploading

@@ -41,8 +41,8 @@ def test_library_exports_every_declared_symbol():
 
 def test_status_strings():
     L = _abi.lib()
-    for code in range(0, -8, -1):
-        assert L.lfbp_status_string(code)
+    for code in range(0, -10, -1):
+        assert L.lfbp_status_string(code) and b"unknown" not in L.lfbp_status_string(code)
     assert b"unknown" in L.lfbp_status_string(-99)
     assert L.lfbp_version().startswith(b"lfbp")
 
@@ -74,7 +74,8 @@ def test_bad_config_fields():
     L = _abi.lib()
     for field, val in [("variant", 4), ("block_threads", 96), ("block_threads", 1024),
                        ("rows_in_flight", 3), ("tile_bytes", 70000), ("vec_per_thread", 3),
-                       ("vec_per_thread", 16), ("nontemporal", 3), ("persistent", 3), ("grid", -1)]:
+                       ("vec_per_thread", 16), ("nontemporal", 3), ("persistent", 3), ("grid", -1),
+                       ("waves_per_eu", 9), ("waves_per_eu", -1), ("schedule", 3), ("schedule", -1)]:
         c = GatherConfig()
         setattr(c, field, val)
         assert L.lfbp_compute_Ht_config(P1, P2, GOOD, _abi.F32, ctypes.byref(c), None) == _abi.EINVAL, field
@@ -361,3 +362,20 @@ def test_operator_validation_before_launch():
     assert L.lfbp_rl_step_op(op, opb, shape, f, R, C, g, n, g, g - 256, wsb, None) == _abi.EALIAS
     assert L.lfbp_rl_norm_op(op, opb, shape, R, C, ws + 256, ws, wsb, None) == _abi.EALIAS
     assert L.lfbp_rl_norm_op(op, opb, shape, R, C, None, ws, wsb, None) == _abi.EINVAL
+
+
+def test_noalloc_batch_limit_and_checks_before_any_hip_call():
+    """lfbp_compute_Ht_batched_noalloc refuses a batch larger than its fixed
+    scratch (ESCRATCH) and every bad table, all before touching a device."""
+    L = _abi.lib()
+    n = _abi.NOALLOC_MAX_PROBLEMS + 1
+    nbytes = 15 * 15 * 3 * 3 * 3 * 4
+    probs = (Problem * n)(*[Problem(P1, P2 + i * nbytes, GOOD) for i in range(n)])
+    assert L.lfbp_compute_Ht_batched_noalloc(probs, n, _abi.F32, None) == _abi.ESCRATCH
+    assert L.lfbp_compute_Ht_batched_noalloc(probs, 0, _abi.F32, None) == _abi.EINVAL
+    assert L.lfbp_compute_Ht_batched_noalloc(None, 3, _abi.F32, None) == _abi.EINVAL
+    bad = (Problem * 2)(Problem(P1, P2, GOOD), Problem(P1, P2, Shape(15, 14, 3, 3, 3)))
+    assert L.lfbp_compute_Ht_batched_noalloc(bad, 2, _abi.F32, None) == _abi.ESHAPE
+    alias = (Problem * 2)(Problem(P1, P2, GOOD), Problem(P1, P2 + 8, GOOD))
+    assert L.lfbp_compute_Ht_batched_noalloc(alias, 2, _abi.F32, None) == _abi.EALIAS
+    assert L.lfbp_compute_Ht_batched_noalloc(probs, 2, 9, None) == _abi.EDTYPE
