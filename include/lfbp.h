@@ -9,6 +9,22 @@
  * is launched and the status says why.  No C++ exception and no abort crosses
  * this interface.  Calls may be made from several threads at once.
  *
+ * Memory the library takes for itself, by call:
+ *   none        lfbp_compute_Ht(_config), lfbp_compute_Ht_inplace,
+ *               lfbp_compute_Ht_colmajor, lfbp_compute_Ht_batched_noalloc, and
+ *               every _ws and _op projector call (the caller passes the
+ *               workspace);
+ *   plan cache  lfbp_compute_Ht_batched(_config): a plan per distinct problem
+ *               table; one hipMalloc per plan only for a table of more than 16
+ *               problems (descriptor table) and a captured graph only when
+ *               asked for; at most 32 plans; freed by lfbp_release_plans;
+ *   stream-ordered workspace  lfbp_forward, lfbp_backward, lfbp_rl_step,
+ *               lfbp_grad_psf: the operand records of their matrix-core
+ *               products (hundreds of MB at projector sizes) come from
+ *               hipMallocAsync on `stream` and are returned with hipFreeAsync
+ *               on the same stream, so these calls stay stream-ordered and
+ *               never block; callers that cannot allocate use the _ws forms.
+ *
  * Arrays are row-major with the last axis fastest:
  *   PSF array H and backprojection array H'   [ns][nt][nx][ny][nz]
  *       s,t = pixel row/column inside a pattern cut-out (ns x nt pixels),
