@@ -72,7 +72,7 @@ constexpr int kHalf = 11;            // MFMA steps per stage (two reduction indi
 constexpr int kStageK = 2 * kHalf;   // reduction indices per stage
 constexpr int kRec = 24;             // floats per record (halves at 0 and 12)
 constexpr int kRecVec = kRec / 4;    // 16-byte vectors per record (3 per half)
-constexpr int kFold = 32;            // stages between folds of the MFMA accumulators
+constexpr int kFoldGroups = 11;      // groups of three stages between folds of the MFMA accumulators
 constexpr int kXcds = 8;
 constexpr int kTargetBlocks = 512;
 
@@ -81,7 +81,7 @@ struct ProjGeom {
     int Lr, Lc;   // lenslets per image side (ceil(R/nx), ceil(C/ny))
     int M;        // Lr*Lc
     int Kr, Kc;   // ns+nx-1, nt+ny-1
-    FastDiv fKc, fny, fnz, fLc;
+    FastDiv fKc, fnx, fny, fnz, fLc;
 };
 
 ProjGeom make_geom(const lfbp_shape& s, int64_t R, int64_t C)
@@ -102,6 +102,7 @@ ProjGeom make_geom(const lfbp_shape& s, int64_t R, int64_t C)
     g.Kr = g.ns + g.nx - 1;
     g.Kc = g.nt + g.ny - 1;
     g.fKc = make_fastdiv(uint32_t(g.Kc));
+    g.fnx = make_fastdiv(uint32_t(g.nx));
     g.fny = make_fastdiv(uint32_t(g.ny));
     g.fnz = make_fastdiv(uint32_t(g.nz));
     g.fLc = make_fastdiv(uint32_t(g.Lc));
@@ -149,6 +150,19 @@ __device__ __forceinline__ int col_of_class(const ClassBoxes& c, int u, int v)
     return (bi * c.nbv + bj) * 64 + (u - bi * c.bu) * c.bv + (v - bj * c.bv);
 }
 
+// Forward walk of a box's window, Rw patch-row shifts by Cw patch-column
+// shifts (times the depth chunks, fastest): the column shifts are taken by
+// residue b modulo ny, and within a residue class all Rw row shifts, each with
+// the class's column shifts b, b + ny, b + 2 ny, ... innermost.  Consecutive
+// stages then read the same phase plane of g one lenslet apart, so they share
+// all but one of their A records.  The first r0 residues hold q1 = q0 + 1
+// column shifts, the others q0 (Cw = ny q0 + r0); n1 = r0 Rw q1 window
+// positions belong to the first group.
+struct WindowWalk {
+    int n1, r0, q0, q1;
+    FastDiv fRq1, fRq0, fq1, fq0;   // by Rw q1, Rw q0, q1, q0 (divisors of 0 stored as 1)
+};
+
 struct GemmArgs {
     const float* A;   // left operand records
     const float* B;   // right operand records [stage][Npad][kRec]
@@ -165,6 +179,7 @@ struct GemmArgs {
     int nzc, LRp, LCp, padP, padQ;
     FastDiv fnzc;
     ClassBoxes cb;    // forward column layout
+    WindowWalk walk;  // forward order of a box's window
 };
 
 // Geometry of the forward depth chunking and of the phase-split copy of g.
@@ -270,6 +285,16 @@ __device__ __forceinline__ void mma_stage(const Frag& f, f32x16 (&acc)[2][2])
         asm volatile("" ::"v"(f.a[i][2]));
         asm volatile("" ::"v"(f.b[i][2]));
     }
+    // Spread the scalar work of the region (the next stage's record
+    // addresses) between the MFMAs: a wavefront issues it while its own MFMAs
+    // run, instead of in one block during which neither of the two wavefronts
+    // sharing the SIMD, which the shared matrix core keeps in step, has an
+    // MFMA ready.
+#pragma unroll
+    for (int s = 0; s < 4 * kHalf; ++s) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one MFMA
+        __builtin_amdgcn_sched_group_barrier(0x004, 3, 0);   // up to three scalar ALU instructions
+    }
 }
 
 // T[tile][quad][lane] += accumulator registers 4*quad .. 4*quad+3; acc = 0.
@@ -326,13 +351,13 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2
     const int nb = ntile * kNT + 64 * wave;
 
     // This wavefront's window: the stages whose B records can be nonzero in
-    // its columns, w_cnt of them, window index i -> stage stage_of(i).
+    // its columns, w_cnt of them (window index i: forward position fwd_pos(i),
+    // otherwise stage w_base + i).
     // Forward: the box's patch shifts, s' + u inside [0, ns) and t' + v
     // inside [0, nt) for some class (u, v) of the box, in a window of the
     // full box size for every box (a box cut short by the cell edge pads it
-    // at the far end), walked with the depth chunk fastest, then the patch
-    // row s', then t': wavefronts whose boxes share their v then stay within
-    // a few stages of one another and share the A records.  Backward: the
+    // at the far end), walked in the order WindowWalk describes (consecutive
+    // stages share their A records).  Backward: the
     // reduction pairs with r + cx inside [0, ns) for some column of the
     // workgroup, a contiguous run of stages (columns are (cx, cy, z) with z
     // fastest, so a workgroup spans few cx).  Gradient with respect to H:
@@ -374,12 +399,6 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2
         const int xlo = nlo / g.nz / g.ny, xhi = nhi / g.nz / g.ny;
         if (m0 >= a.M || rhi < xlo || rlo - xhi > g.ns - 1) w_cnt = 0;
     }
-    auto stage_of = [&](int i) -> int {
-        if (!kFwd) return w_base + i;
-        const int j = i / a.nzc, zc = i - j * a.nzc;
-        const int ic = j / Rw, ir = j - ic * Rw;
-        return ((sr0 + ir) * g.Kc + tc0 + ic) * a.nzc + zc;
-    };
     const int s_begin = int(int64_t(w_cnt) * split / a.splits);
     const int s_end = int(int64_t(w_cnt) * (split + 1) / a.splits);
     const int li = lane & 31, lk = lane >> 5;
@@ -406,13 +425,35 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2
     const char* B1 = reinterpret_cast<const char*>(a.B);
     const uint32_t ablock = uint32_t(16 * kRecVec * arows), bblock = uint32_t(16 * kRecVec * a.Npad);
 
-    auto a_rsrc = [&](int s) -> Rsrc {
-        if (!kFwd) return make_rsrc(A1 + int64_t(s) * ablock, ablock);
-        // block (phase plane, depth chunk), shifted by the stage's lenslet offset
-        const FwdStage t = fwd_stage(g, a.fnzc, a.nzc, s);
-        const uint32_t shift = uint32_t(32 * ((t.dP + a.padP) * a.LCp + t.dQ + a.padQ));
-        return make_rsrc(A1 + int64_t(t.px * g.ny + t.py) * a.nzc * ablock + int64_t(t.zc) * ablock + shift,
-                         ablock - shift);
+    // Forward window index i -> shifted patch row and column sr = s' + nx - 1,
+    // tc = t' + ny - 1 and depth chunk zc (stage (sr * Kc + tc) * nzc + zc).
+    struct FwdPos {
+        int sr, tc, zc;
+    };
+    auto fwd_pos = [&](int i) -> FwdPos {
+        const WindowWalk& w = a.walk;
+        const int j = int(fdiv(uint32_t(i), a.fnzc)), zc = i - j * a.nzc;
+        const bool first = j < w.n1;
+        const int jr = first ? j : j - w.n1, q = first ? w.q1 : w.q0;
+        const int bq = int(fdiv(uint32_t(jr), first ? w.fRq1 : w.fRq0));
+        const int rem = jr - bq * Rw * q;
+        const int ir = int(fdiv(uint32_t(rem), first ? w.fq1 : w.fq0)), k = rem - ir * q;
+        const int ic = (first ? bq : w.r0 + bq) + k * g.ny;
+        return FwdPos{sr0 + ir, tc0 + ic, zc};
+    };
+    // Forward A block of a window position: the phase plane px = (hs - s') mod
+    // nx, py = (ht - t') mod ny and depth chunk zc, shifted by the lenslet
+    // offset dP = floor((hs - s') / nx), dQ likewise.  hs - s' + nx ns =
+    // hs + nx - 1 - sr + nx ns is never negative, so unsigned division finds
+    // both (and dP = quotient - ns).
+    auto a_rsrc_fwd = [&](const FwdPos& p) -> Rsrc {
+        const uint32_t ep = uint32_t(g.hs + g.nx - 1 - p.sr + g.nx * g.ns);
+        const uint32_t fq = uint32_t(g.ht + g.ny - 1 - p.tc + g.ny * g.nt);
+        const int qp = int(fdiv(ep, g.fnx)), qq = int(fdiv(fq, g.fny));
+        const int px = int(ep) - qp * g.nx, py = int(fq) - qq * g.ny;
+        const int dP = qp - g.ns, dQ = qq - g.nt;
+        const uint32_t shift = uint32_t(32 * ((dP + a.padP) * a.LCp + dQ + a.padQ));
+        return make_rsrc(A1 + (int64_t(px * g.ny + py) * a.nzc + p.zc) * ablock + shift, ablock - shift);
     };
 
 #pragma unroll
@@ -426,41 +467,59 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2
     // is clamped) so that the wait before a stage's MFMAs only covers that
     // stage's loads, never the prefetch behind it.
     const int s_last = max(s_begin, s_end - 1);
-    auto load = [&](int s, Frag& f) {
-        const int sc = stage_of(min(s, s_last));
-        load_frag(a_rsrc(sc), make_rsrc(B1 + int64_t(sc) * bblock, bblock), oa, ob, uint32_t(32 * arows),
-                  uint32_t(32 * a.Npad), f);
+    // The buffer resources of stage s's records; computed one stage before
+    // its loads are issued, among the MFMAs of the stage in flight.
+    struct StageRsrc {
+        Rsrc ra, rb;
+    };
+    auto rsrc_of = [&](int s) -> StageRsrc {
+        const int i = min(s, s_last);
+        if (kFwd) {
+            const FwdPos p = fwd_pos(i);
+            return StageRsrc{a_rsrc_fwd(p),
+                             make_rsrc(B1 + int64_t((p.sr * g.Kc + p.tc) * a.nzc + p.zc) * bblock, bblock)};
+        }
+        return StageRsrc{make_rsrc(A1 + int64_t(w_base + i) * ablock, ablock),
+                         make_rsrc(B1 + int64_t(w_base + i) * bblock, bblock)};
+    };
+    auto load = [&](const StageRsrc& r, Frag& f) {
+        load_frag(r.ra, r.rb, oa, ob, uint32_t(32 * arows), uint32_t(32 * a.Npad), f);
         // keep the prefetch ahead of the MFMAs that follow (compiler barrier for
         // the optimiser, scheduling barrier for the back end)
         asm volatile("" ::: "memory");
         __builtin_amdgcn_sched_barrier(0);
     };
     Frag f0, f1, f2;
-    int since = 0;
-    auto step = [&](const Frag& f) {
-        mma_stage(f, acc);
-        if (++since == kFold) {
-            fold(acc, T, lane);
-            since = 0;
-        }
-    };
     if (s_begin < s_end) {
         // Whole groups of three stages in a loop with one path through it (so
         // the wait analysis sees the same loads in flight on every entry),
         // then the zero to two stages left, whose loads the last group issued.
-        load(s_begin, f0);
-        load(s_begin + 1, f1);
+        StageRsrc nr = rsrc_of(s_begin);
+        load(nr, f0);
+        nr = rsrc_of(s_begin + 1);
+        load(nr, f1);
+        nr = rsrc_of(s_begin + 2);
         int s = s_begin;
+        // (no branch inside a group: the scheduling regions between the loads
+        // hold one stage's MFMAs and the next stage's address arithmetic)
+        int groups = 0;
         for (const int s3 = s_begin + (s_end - s_begin) / 3 * 3; s < s3; s += 3) {
-            load(s + 2, f2);
-            step(f0);
-            load(s + 3, f0);
-            step(f1);
-            load(s + 4, f1);
-            step(f2);
+            load(nr, f2);
+            nr = rsrc_of(s + 3);
+            mma_stage(f0, acc);
+            load(nr, f0);
+            nr = rsrc_of(s + 4);
+            mma_stage(f1, acc);
+            load(nr, f1);
+            nr = rsrc_of(s + 5);
+            mma_stage(f2, acc);
+            if (++groups == kFoldGroups) {
+                fold(acc, T, lane);
+                groups = 0;
+            }
         }
-        if (s < s_end) step(f0);
-        if (s + 1 < s_end) step(f1);
+        if (s < s_end) mma_stage(f0, acc);
+        if (s + 1 < s_end) mma_stage(f1, acc);
     }
     fold(acc, T, lane);
 
@@ -883,6 +942,21 @@ PackArgs pack_args(const ProjGeom& g, int N, int Npad, int Mpad, int stages)
 
 unsigned blocks_for(int64_t items) { return unsigned((items + 255) / 256); }
 
+WindowWalk window_walk(const ProjGeom& g, const ClassBoxes& cb)
+{
+    const int Rw = g.ns + cb.bu - 1, Cw = g.nt + cb.bv - 1;
+    WindowWalk w;
+    w.q0 = Cw / g.ny;
+    w.r0 = Cw - w.q0 * g.ny;
+    w.q1 = w.q0 + 1;
+    w.n1 = w.r0 * Rw * w.q1;
+    w.fRq1 = make_fastdiv(uint32_t(Rw * w.q1));
+    w.fRq0 = make_fastdiv(uint32_t(std::max(1, Rw * w.q0)));
+    w.fq1 = make_fastdiv(uint32_t(w.q1));
+    w.fq0 = make_fastdiv(uint32_t(std::max(1, w.q0)));
+    return w;
+}
+
 }  // namespace
 
 // Workspace of the forward projection: g with depth innermost, the A and B
@@ -962,6 +1036,7 @@ hipError_t forward_impl(const float* H, const lfbp_shape& s, const float* gin, i
     a.padQ = P.L.padQ;
     a.fnzc = p.fnzc;
     a.cb = P.cb;
+    a.walk = window_walk(g, P.cb);
     hipLaunchKernelGGL(k_gemm<kModeFwd>, dim3(unsigned(P.mtiles * P.ntiles * P.splits)), dim3(kThreads), 0, stream,
                        a);
     if ((e = hipGetLastError()) != hipSuccess) return e;

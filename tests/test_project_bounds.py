@@ -84,8 +84,10 @@ def col_of_class(cb, u, v):
 
 def fwd_window(g, p, ntile, wave):
     """The wavefront's stages (k_gemm, forward), in window order: the box's
-    (ns + bu - 1) x (nt + bv - 1) patch shifts, depth chunk fastest, then s',
-    then t'."""
+    Rw x Cw = (ns + bu - 1) x (nt + bv - 1) patch shifts, depth chunk
+    fastest; the column shifts by residue b modulo ny, within a residue all
+    row shifts, each with the residue's column shifts b, b + ny, ...
+    innermost."""
     cb = p['cb']
     b = ntile * (kNT // 64) + wave
     if b >= cb['boxes']:
@@ -95,12 +97,18 @@ def fwd_window(g, p, ntile, wave):
     sr0, tc0 = g['nx'] - 1 - u1, g['ny'] - 1 - v1
     Rw, Cw = g['ns'] + cb['bu'] - 1, g['nt'] + cb['bv'] - 1
     assert sr0 >= 0 and tc0 >= 0 and sr0 + Rw <= g['Kr'] and tc0 + Cw <= g['Kc']
-    out = []
-    for i in range(Rw * Cw * p['nzc']):
-        j, zc = divmod(i, p['nzc'])
-        ic, ir = divmod(j, Rw)
-        out.append(((sr0 + ir) * g['Kc'] + tc0 + ic) * p['nzc'] + zc)
-    return out
+    ny = g['ny']
+    order = [(ir, b + k * ny) for b in range(min(ny, Cw)) for ir in range(Rw) for k in range((Cw - b + ny - 1) // ny)]
+    assert sorted(order) == [(ir, ic) for ir in range(Rw) for ic in range(Cw)]
+    # the kernel's closed form of the same order (WindowWalk)
+    q0, r0 = divmod(Cw, ny)
+    q1, n1 = q0 + 1, r0 * Rw * (q0 + 1)
+    for j, (ir, ic) in enumerate(order):
+        first = j < n1
+        jr, q = (j, q1) if first else (j - n1, q0)
+        bq, rem = divmod(jr, Rw * q)
+        assert (rem // q, (bq if first else r0 + bq) + (rem % q) * ny) == (ir, ic)
+    return [((sr0 + ir) * g['Kc'] + tc0 + ic) * p['nzc'] + zc for ir, ic in order for zc in range(p['nzc'])]
 
 
 def bwd_window(g, N, stages, ntile):
