@@ -220,6 +220,19 @@ def cpu_oracle_rate(H, nthreads, budget_s):
     return 2.0 * H.nbytes / dt / 1e9, reps + 1, dt, out
 
 
+def budget_sample(run, pilot_n, total_n, budget_s):
+    """Time run(n) on a pilot of pilot_n items, then on as many items as fill
+    about budget_s seconds (at most total_n).  Returns (items, seconds) of the
+    second run."""
+    t0 = time.perf_counter()
+    run(pilot_n)
+    pilot = max(time.perf_counter() - t0, 1e-4)
+    n = int(min(total_n, max(pilot_n, pilot_n * budget_s / pilot)))
+    t0 = time.perf_counter()
+    run(n)
+    return n, time.perf_counter() - t0
+
+
 def paper_method_rates(H, nthreads):
     """The paper's own method (oracle.paper_Ht: Eqs. 4-9 looped as in Fig. 10)
     on the host, one pass on one core and one on `nthreads`: GB/s of (read +
@@ -558,13 +571,13 @@ def bench_projector(args, torch):
         import oracle
         nth = cores_used()
         rng = np.random.default_rng(0)
-        pix = rng.integers(0, [R, C], size=(400, 2))
-        t0 = time.perf_counter()
-        oracle.forward_at(H, g.cpu().numpy(), pix, nthreads=nth)
-        dt = time.perf_counter() - t0
-        per_proj = dt * (R * C) / len(pix)
+        pix = rng.integers(0, [R, C], size=(R * C, 2))
+        gh = g.cpu().numpy()
+        n, dt = budget_sample(lambda k: oracle.forward_at(H, gh, pix[:k], nthreads=nth), 400, R * C,
+                              args.cpu_seconds)
+        per_proj = dt * (R * C) / n
         out["cpu_baseline"] = {"value": round(1.0 / (2 * per_proj), 6), "unit": "pairs/s", "cores": nth,
-                               "kind": "oracle", "sample": f"float64 oracle forward at {len(pix)} random pixels "
+                               "kind": "oracle", "sample": f"float64 oracle forward at {n} random pixels "
                                                            f"({dt:.2f} s), scaled to a full forward+backward pair"}
     return out
 
@@ -631,14 +644,13 @@ def bench_rl(args, torch):
         import oracle
         nth = cores_used()
         rng = np.random.default_rng(0)
-        pix = rng.integers(0, [R, C], size=(400, 2))
+        pix = rng.integers(0, [R, C], size=(R * C, 2))
         gh = g.cpu().numpy()
-        t0 = time.perf_counter()
-        oracle.forward_at(H, gh, pix, nthreads=nth)
-        dt = time.perf_counter() - t0
-        per_step = 2 * dt * (R * C) / len(pix)
+        n, dt = budget_sample(lambda k: oracle.forward_at(H, gh, pix[:k], nthreads=nth), 400, R * C,
+                              args.cpu_seconds)
+        per_step = 2 * dt * (R * C) / n
         out["cpu_baseline"] = {"value": round(1.0 / per_step, 6), "unit": "iterations/s", "cores": nth,
-                               "kind": "oracle", "sample": f"float64 oracle forward at {len(pix)} random pixels "
+                               "kind": "oracle", "sample": f"float64 oracle forward at {n} random pixels "
                                                            f"({dt:.2f} s), scaled to a forward and a backward "
                                                            f"projection of the whole volume"}
     return out
@@ -677,13 +689,14 @@ def bench_grad_psf(args, torch):
     if not args.no_cpu_baseline:
         import oracle
         nth = cores_used()
-        idx = np.random.default_rng(0).integers(0, int(np.prod(shape)), 20000)
-        t0 = time.perf_counter()
-        oracle.grad_psf_at(shape, w.cpu().numpy(), g.cpu().numpy(), idx, nthreads=nth)
-        dt = time.perf_counter() - t0
-        per = dt * np.prod(shape) / len(idx)
+        total = int(np.prod(shape))
+        idx = np.random.default_rng(0).integers(0, total, min(total, 50_000_000))
+        wh, gh = w.cpu().numpy(), g.cpu().numpy()
+        n, dt = budget_sample(lambda k: oracle.grad_psf_at(shape, wh, gh, idx[:k], nthreads=nth), 20000, idx.size,
+                              args.cpu_seconds)
+        per = dt * total / n
         out["cpu_baseline"] = {"value": round(1.0 / per, 6), "unit": "gradients/s", "cores": nth, "kind": "oracle",
-                               "sample": f"float64 oracle at {len(idx)} random entries of dH ({dt:.2f} s), "
+                               "sample": f"float64 oracle at {n} random entries of dH ({dt:.2f} s), "
                                          f"scaled to the whole array"}
     return out
 
