@@ -85,3 +85,22 @@ def test_inplace_on_a_view_and_stream_order():
     torch.cuda.synchronize()
     assert gpu_equal_bits(out, view)                  # bit patterns (the payloads include NaNs)
     assert torch.all(buf[:3] == -1.0) and torch.all(buf[3 + n:] == -1.0)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float16])
+@pytest.mark.parametrize("offset", [1, 2, 3, 5, 7])
+@pytest.mark.parametrize("shape", [(11, 7, 1, 1, 2), (5, 5, 9, 1, 3), (9, 7, 3, 5, 2), (7, 9, 3, 1, 1)])
+def test_inplace_unaligned_views(shape, offset, dtype):
+    """Arrays starting `offset` elements into a buffer (every position of the
+    first element in a 16-byte vector), rows shorter than a vector among
+    them: equal to the oracle, canaries untouched."""
+    n = int(np.prod(shape))
+    H = lfsynth.bits(shape, 29, dtype)
+    tdt = torch.float32 if dtype == np.float32 else torch.float16
+    buf = torch.full((n + 16,), -1.0, device=DEV, dtype=tdt)
+    view = buf[offset:offset + n].view(shape)
+    view.copy_(torch.from_numpy(H))
+    lf.compute_Ht_inplace(view)
+    torch.cuda.synchronize()
+    assert_same_bits(view.cpu().numpy(), oracle.Ht_rows(H), f"{shape} offset {offset} {dtype.__name__}")
+    assert torch.all(buf[:offset] == -1.0) and torch.all(buf[offset + n:] == -1.0)
