@@ -196,6 +196,49 @@ def time_each(fn, steps, warmup, torch):
     return ev[0].elapsed_time(ev[steps]) / 1000.0, wall, per
 
 
+def time_flushed(fn, steps, warmup, torch, mode):
+    """`steps` calls of fn, each after a 1 GiB buffer is written (mode
+    "written": the 256 MB MALL then holds dirty lines of the buffer, which the
+    call must evict) or read ("read": it holds clean lines only), with HIP
+    events around each call alone.  Returns the per-call seconds."""
+    buf = torch.empty(1 << 28, dtype=torch.float32, device=torch.device("cuda:0"))
+    buf.zero_()
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    evs = []
+    for i in range(steps):
+        if mode == "written":
+            buf.fill_(float(i))
+        else:
+            buf.sum()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        evs.append((e0, e1))
+    torch.cuda.synchronize()
+    del buf
+    torch.cuda.empty_cache()
+    return [a.elapsed_time(b) / 1000.0 for a, b in evs]
+
+
+def flushed_figures(torch, lf, H, steps, warmup):
+    """The plain build of H timed after a 1 GiB buffer is written and after it
+    is read: GB/s at the median call and the call-time spread, per mode."""
+    dH = torch.from_numpy(H).to(torch.device("cuda:0"))
+    dHt = torch.empty_like(dH)
+    out = {}
+    for mode in ("written", "read"):
+        per = time_flushed(lambda: lf.compute_Ht_into(dH, dHt), steps, warmup, torch, mode)
+        med = sorted(per)[len(per) // 2]
+        out[mode] = {"GBs_at_median": round(2 * H.nbytes / med / 1e9, 1), "step_ms": spread_ms(per)}
+    del dH, dHt
+    torch.cuda.empty_cache()
+    return out
+
+
 def spread_ms(per):
     """min / median / mean of per-step seconds, in ms."""
     import statistics
@@ -393,6 +436,10 @@ def bench_plain(args, torch):
                                  else traffic_from_profile(args.workload))},
     }
     checks = [] if got is None else [(out["config"]["workload"], H, None, got)]
+    if args.workload == "microscope" and not (args.copy or args.inplace):
+        # H and H' (0.5 GB each) are twice the 256 MB MALL: also timed with the cache state between calls
+        # set by a 1 GiB buffer
+        out["config"]["after_1GiB_buffer"] = flushed_figures(torch, lf, H, args.steps, args.warmup)
     if args.workload == "camera" and not (args.copy or args.inplace or args.no_extras):
         rng = np.random.default_rng(2003)
         also = {}
@@ -415,7 +462,8 @@ def bench_plain(args, torch):
         torch.cuda.empty_cache()
         gm = 2 * Hm.nbytes / (tm / args.steps) / 1e9
         also["microscope"] = {"GBs": round(gm, 1), "frac": round(gm / HBM_PEAK_GBS, 4), "step_ms": spread_ms(perm),
-                              "traffic": traffic_from_profile("microscope")}
+                              "traffic": traffic_from_profile("microscope"),
+                              "after_1GiB_buffer": flushed_figures(torch, lf, Hm, args.steps, args.warmup)}
         # 16 PSF sets: one batched launch against 16 per-set launches
         also["batched-16"], bchecks = batched_vs_sequential(args, torch, lf, lfsynth, lfsynth.BATCHED_SETS, rng)
         checks += bchecks
