@@ -224,6 +224,37 @@ def time_flushed(fn, steps, warmup, torch, mode):
     return [a.elapsed_time(b) / 1000.0 for a, b in evs]
 
 
+def memcpy_figures(torch, nbytes, steps, warmup):
+    """hipMemcpyAsync device to device of nbytes on the current stream (the
+    HIP runtime's own copy, as a ceiling for a read-once write-once pass):
+    GB/s of (read + write) over `steps` back-to-back copies."""
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipMemcpyAsync.restype = ctypes.c_int
+    hip.hipMemcpyAsync.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p]
+    dev = torch.device("cuda:0")
+    src = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    src.fill_(7)
+    stream = torch.cuda.current_stream().cuda_stream
+    status = []
+
+    def step():
+        status.append(hip.hipMemcpyAsync(dst.data_ptr(), src.data_ptr(), nbytes, 3, stream))  # device to device
+
+    total, _, per = time_each(step, steps, warmup, torch)
+    ok = all(r == 0 for r in status) and bool(torch.equal(dst[:4096], src[:4096]))
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"GBs": round(2 * nbytes / (total / steps) / 1e9, 1), "step_ms": spread_ms(per), "ok": ok}
+
+
+def device_figures(torch):
+    p = torch.cuda.get_device_properties(0)
+    return {"name": p.name, "arch": getattr(p, "gcnArchName", None), "compute_units": p.multi_processor_count,
+            "memory_GiB": round(p.total_memory / 2**30, 1)}
+
+
 def flushed_figures(torch, lf, H, steps, warmup):
     """The plain build of H timed after a 1 GiB buffer is written and after it
     is read: GB/s at the median call and the call-time spread, per mode."""
@@ -428,6 +459,7 @@ def bench_plain(args, torch):
         "scaling": "weak", "vs_baseline": None, "dtype": dt, "data": "synthetic",
         "config": {"workload": f"{w.name} H{list(w.shape)} {dt}", "shape": list(w.shape),
                    "bytes_per_step": bytes_step, "zero_fraction": round(zf, 4), "step_ms": spread_ms(per),
+                   "device": device_figures(torch),
                    "kernel": ("torch copy_ (reference)" if args.copy else
                               "k_inplace (H' over H)" if args.inplace else resolved), "wall_s": round(wall, 3)},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -464,6 +496,10 @@ def bench_plain(args, torch):
         also["microscope"] = {"GBs": round(gm, 1), "frac": round(gm / HBM_PEAK_GBS, 4), "step_ms": spread_ms(perm),
                               "traffic": traffic_from_profile("microscope"),
                               "after_1GiB_buffer": flushed_figures(torch, lf, Hm, args.steps, args.warmup)}
+        # the HIP runtime's device-to-device copy of the same bytes
+        mc = memcpy_figures(torch, H.nbytes, args.steps, args.warmup)
+        mc["gather_over_memcpy"] = round(gbs / mc["GBs"], 4)
+        also["hipMemcpyAsync-d2d"] = mc
         # 16 PSF sets: one batched launch against 16 per-set launches
         also["batched-16"], bchecks = batched_vs_sequential(args, torch, lf, lfsynth, lfsynth.BATCHED_SETS, rng)
         checks += bchecks
