@@ -75,3 +75,24 @@ def test_bench_line_carries_every_field():
     assert abs(r["frac"] - r["achieved"] / r["peak"]) < 1e-3
     c = d["cpu_baseline"]
     assert c["kind"] == "oracle" and c["cores"] >= 1 and c["value"] > 0 and c["sample"]
+
+
+def test_default_config_reports_what_a_launch_runs():
+    """In a fresh process, the configuration lfbp_default_config reports for a
+    shape with rows over 32 KB (whose work decomposition depends on the
+    device's LDS size) is the same before and after the first build, grid
+    included, and the build with that configuration passed explicitly equals
+    the default build bit for bit."""
+    probe = ("import json, sys; sys.path.insert(0, %r); import torch, paper_2003_09133_amd as lf\n"
+             "shape = (3, 3, 3, 3, 3001)\n"
+             "before = lf.default_config(shape, torch.float32)\n"
+             "H = torch.rand(shape, device='cuda')\n"
+             "ref = lf.compute_Ht(H)\n"
+             "after = lf.default_config(shape, torch.float32)\n"
+             "got = lf.compute_Ht(H, config=after)\n"
+             "print(json.dumps([before, after, bool(torch.equal(ref.view(torch.int32), got.view(torch.int32)))]))"
+             % ROOT)
+    before, after, same = json.loads(run(["-c", probe]).strip().splitlines()[-1])
+    assert 3 * 3001 * 4 > 32 * 1024
+    assert before == after, (before, after)
+    assert same
