@@ -47,7 +47,13 @@ def fwd_stage(g, nzc, s):
     sp, tp = sr - (g['nx'] - 1), tc - (g['ny'] - 1)
     e, f = g['hs'] - sp, g['ht'] - tp
     px, py = e % g['nx'], f % g['ny']
-    return sp, tp, zc, px, py, (e - px) // g['nx'], (f - py) // g['ny']
+    dP, dQ = (e - px) // g['nx'], (f - py) // g['ny']
+    # the GEMM's form of the same (a_rsrc_fwd): unsigned division of a biased, never negative index
+    ep = g['hs'] + g['nx'] - 1 - sr + g['nx'] * g['ns']
+    fq = g['ht'] + g['ny'] - 1 - tc + g['ny'] * g['nt']
+    assert 0 <= ep < 2 ** 32 and 0 <= fq < 2 ** 32
+    assert (ep % g['nx'], ep // g['nx'] - g['ns']) == (px, dP) and (fq % g['ny'], fq // g['ny'] - g['nt']) == (py, dQ)
+    return sp, tp, zc, px, py, dP, dQ
 
 
 def class_boxes(g):
