@@ -75,6 +75,20 @@ def test_bench_line_carries_every_field():
     assert abs(r["frac"] - r["achieved"] / r["peak"]) < 1e-3
     c = d["cpu_baseline"]
     assert c["kind"] == "oracle" and c["cores"] >= 1 and c["value"] > 0 and c["sample"]
+    dev = d["config"]["device"]
+    assert dev["compute_units"] > 0 and dev["arch"].startswith("gfx")
+
+
+def test_bench_microscope_line_after_a_buffer_between_calls():
+    """The microscope line carries the build timed after a 1 GiB buffer is
+    written and after it is read between calls, and its output matches the
+    oracle bit for bit."""
+    out = run(["bench.py", "--workload", "microscope", "--steps", "3", "--warmup", "1", "--cpu-seconds", "1"])
+    d = json.loads([l for l in out.splitlines() if l.startswith("{")][-1])
+    fl = d["config"]["after_1GiB_buffer"]
+    for mode in ("written", "read"):
+        assert fl[mode]["GBs_at_median"] > 0 and fl[mode]["step_ms"]["min"] > 0
+    assert all(v["mismatches"] == 0 for v in d["config"]["bit_exact_vs_oracle"].values())
 
 
 def test_default_config_reports_what_a_launch_runs():
