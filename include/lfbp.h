@@ -396,7 +396,8 @@ LFBP_API lfbp_status lfbp_grad_psf_ws(const float* w, const float* g, lfbp_shape
 LFBP_API int64_t lfbp_operator_size(lfbp_shape shape, int64_t R, int64_t C);
 LFBP_API int64_t lfbp_operator_workspace_size(lfbp_shape shape, int64_t R, int64_t C);
 
-/* Pack H (forward) and H' (backward) into op. */
+/* Pack H (forward) and H' (backward) into op, with the forward's work table
+ * (which row tile and split each workgroup takes; it depends on the shapes only). */
 LFBP_API lfbp_status lfbp_operator_prepare(const float* H, const float* Ht, lfbp_shape shape, int64_t R, int64_t C,
                                            void* op, int64_t op_bytes, void* stream);
 

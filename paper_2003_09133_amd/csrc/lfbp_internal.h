@@ -23,7 +23,7 @@ struct FastDiv {
     uint32_t d, m, s1, s2;
 };
 
-inline FastDiv make_fastdiv(uint32_t d)
+LFBP_HD inline FastDiv make_fastdiv(uint32_t d)
 {
     uint32_t l = 0;
     while (l < 32 && (uint64_t(1) << l) < d) ++l;  // l = ceil(log2 d)

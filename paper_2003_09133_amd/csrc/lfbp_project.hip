@@ -55,10 +55,13 @@
 
 #include <algorithm>
 #include <cstdlib>
+#include <vector>
 
 #include "lfbp_internal.h"
 
 namespace lfbp {
+
+hipError_t put_words(uint32_t* dst, const uint32_t* src, size_t n, hipStream_t stream);
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -157,10 +160,11 @@ __device__ __forceinline__ int col_of_class(const ClassBoxes& c, int u, int v)
 // stages then read the same phase plane of g one lenslet apart, so they share
 // all but one of their A records.  The first r0 residues hold q1 = q0 + 1
 // column shifts, the others q0 (Cw = ny q0 + r0); n1 = r0 Rw q1 window
-// positions belong to the first group.
+// positions belong to the first group (n1 and the divisors by Rw q1, Rw q0
+// are taken per wavefront, whose Rw is the count of rows its row tile needs).
 struct WindowWalk {
-    int n1, r0, q0, q1;
-    FastDiv fRq1, fRq0, fq1, fq0;   // by Rw q1, Rw q0, q1, q0 (divisors of 0 stored as 1)
+    int r0, q0, q1;
+    FastDiv fq1, fq0;   // by q1, q0 (a divisor of 0 stored as 1)
 };
 
 struct GemmArgs {
@@ -180,6 +184,11 @@ struct GemmArgs {
     FastDiv fnzc;
     ClassBoxes cb;    // forward column layout
     WindowWalk walk;  // forward order of a box's window
+    // forward work table: tab[mt] (mt <= mtiles) is the first partial-sum slot
+    // of row tile mt (its splits: tab[mt+1] - tab[mt]), and
+    // tab[mtiles + 1 + L] = ((mt * ntiles + nt) << 6) | split for workgroup L
+    const uint32_t* tab;
+    int nwg;
 };
 
 // Geometry of the forward depth chunking and of the phase-split copy of g.
@@ -223,6 +232,24 @@ __device__ __forceinline__ FwdStage fwd_stage(const ProjGeom& g, const FastDiv& 
     t.dP = (e - t.px) / g.nx;   // exact: floor(e / nx)
     t.dQ = (f - t.py) / g.ny;
     return t;
+}
+
+// The window rows of forward box `box` that row tile mt needs: a window row
+// ir is the patch-row shift s' = ir - u1 (u1 the box's last class row), and
+// its A records are all zero (every lenslet row of the tile sees a source
+// row P = nx Lp + hs - s' outside the image) unless s' lies in
+// [nx Lp_lo + hs - (R - 1), nx Lp_hi + hs].  Returns the count, and the first
+// row in ir_lo.  The host sizes the splits of each row tile with it, the
+// GEMM walks only these rows.
+__host__ __device__ inline int fwd_tile_rows(const ProjGeom& g, const ClassBoxes& cb, int mt, int box, int& ir_lo)
+{
+    const int bi = box / cb.nbv;
+    const int u1 = min(g.nx, (bi + 1) * cb.bu) - 1, Rw = g.ns + cb.bu - 1;
+    const int m_lo = mt * kMT, m_hi = min(g.M - 1, mt * kMT + kMT - 1);
+    const int lp_lo = m_lo / g.Lc, lp_hi = m_hi / g.Lc;
+    ir_lo = max(0, g.nx * lp_lo + g.hs - (g.R - 1) + u1);
+    const int ir_hi = min(Rw - 1, g.nx * lp_hi + g.hs + u1);
+    return max(0, ir_hi - ir_lo + 1);
 }
 
 // --------------------------------------------------------------- GEMM kernel
@@ -340,8 +367,22 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2
 {
     constexpr bool kFwd = kMode == kModeFwd;
     __shared__ f32x4 tot[kThreads / 64][4][4][64];   // per wave: 4 tiles x 16 sums x 64 lanes
-    int mt, ntile, split;
-    tile_of_block(a, mt, ntile, split);
+    int mt, ntile, split, splits = a.splits, slot = 0;
+    if (kFwd) {
+        // logical workgroup L (consecutive L on one XCD, as in tile_of_block)
+        // -> its row tile, column tile and split, from the work table
+        const int b = int(blockIdx.x), x = b % kXcds, q = a.nwg / kXcds, r = a.nwg % kXcds;
+        const int L = x * q + min(x, r) + b / kXcds;
+        const uint32_t e = a.tab[a.mtiles + 1 + L];
+        const int tile = int(e >> 6);
+        split = int(e & 63u);
+        mt = tile / a.ntiles;
+        ntile = tile - mt * a.ntiles;
+        slot = int(a.tab[mt]) + split;
+        splits = int(a.tab[mt + 1] - a.tab[mt]);
+    } else {
+        tile_of_block(a, mt, ntile, split);
+    }
     const ProjGeom& g = a.g;
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6), lane = int(threadIdx.x) & 63;
     // This wavefront's 64 x 64 output block at rows m0, columns nb: a
@@ -356,8 +397,9 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2
     // Forward: the box's patch shifts, s' + u inside [0, ns) and t' + v
     // inside [0, nt) for some class (u, v) of the box, in a window of the
     // full box size for every box (a box cut short by the cell edge pads it
-    // at the far end), walked in the order WindowWalk describes (consecutive
-    // stages share their A records).  Backward: the
+    // at the far end), less the patch rows whose A records are zero for the
+    // whole row tile (fwd_tile_rows), walked in the order WindowWalk
+    // describes (consecutive stages share their A records).  Backward: the
     // reduction pairs with r + cx inside [0, ns) for some column of the
     // workgroup, a contiguous run of stages (columns are (cx, cy, z) with z
     // fastest, so a workgroup spans few cx).  Gradient with respect to H:
@@ -370,9 +412,10 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2
         } else {
             const int bi = b / a.cb.nbv, bj = b - bi * a.cb.nbv;
             const int u1 = min(g.nx, (bi + 1) * a.cb.bu) - 1, v1 = min(g.ny, (bj + 1) * a.cb.bv) - 1;
-            sr0 = g.nx - 1 - u1;   // s' from -u1 (shifted by nx - 1)
+            int ir_lo;
+            Rw = fwd_tile_rows(g, a.cb, mt, b, ir_lo);   // the rows with nonzero A records
+            sr0 = g.nx - 1 - u1 + ir_lo;   // s' from -u1 + ir_lo (shifted by nx - 1)
             tc0 = g.ny - 1 - v1;
-            Rw = g.ns + a.cb.bu - 1;
             w_cnt = Rw * (g.nt + a.cb.bv - 1) * a.nzc;
         }
     } else if (kMode == kModeBwd) {
@@ -399,8 +442,8 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2
         const int xlo = nlo / g.nz / g.ny, xhi = nhi / g.nz / g.ny;
         if (m0 >= a.M || rhi < xlo || rlo - xhi > g.ns - 1) w_cnt = 0;
     }
-    const int s_begin = int(int64_t(w_cnt) * split / a.splits);
-    const int s_end = int(int64_t(w_cnt) * (split + 1) / a.splits);
+    const int s_begin = int(int64_t(w_cnt) * split / splits);
+    const int s_end = int(int64_t(w_cnt) * (split + 1) / splits);
     const int li = lane & 31, lk = lane >> 5;
     f32x4 (*T)[4][64] = tot[wave];
 
@@ -430,12 +473,16 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2
     struct FwdPos {
         int sr, tc, zc;
     };
+    // the walk's divisors by this wavefront's row count
+    const int n1 = kFwd ? a.walk.r0 * Rw * a.walk.q1 : 0;
+    const FastDiv fRq1 = make_fastdiv(uint32_t(kFwd ? max(1, Rw * a.walk.q1) : 1));
+    const FastDiv fRq0 = make_fastdiv(uint32_t(kFwd ? max(1, Rw * a.walk.q0) : 1));
     auto fwd_pos = [&](int i) -> FwdPos {
         const WindowWalk& w = a.walk;
         const int j = int(fdiv(uint32_t(i), a.fnzc)), zc = i - j * a.nzc;
-        const bool first = j < w.n1;
-        const int jr = first ? j : j - w.n1, q = first ? w.q1 : w.q0;
-        const int bq = int(fdiv(uint32_t(jr), first ? w.fRq1 : w.fRq0));
+        const bool first = j < n1;
+        const int jr = first ? j : j - n1, q = first ? w.q1 : w.q0;
+        const int bq = int(fdiv(uint32_t(jr), first ? fRq1 : fRq0));
         const int rem = jr - bq * Rw * q;
         const int ir = int(fdiv(uint32_t(rem), first ? w.fq1 : w.fq0)), k = rem - ir * q;
         const int ic = (first ? bq : w.r0 + bq) + k * g.ny;
@@ -524,7 +571,8 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2
     fold(acc, T, lane);
 
     if (kFwd) {
-        float* out = a.out + size_t(split) * a.Mpad * a.Npad;
+        // the workgroup's partial-sum slot: the tile's 64 rows x Npad columns
+        float* out = a.out + size_t(slot) * kMT * a.Npad;
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -534,8 +582,8 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2
                     const f32x4 v = T[2 * i + j][q][lane];
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
-                        const int m = m0 + 32 * i + 8 * q + 4 * lk + e;
-                        out[size_t(m) * a.Npad + nb + 32 * j + li] = v[e];
+                        const int r = 32 * i + 8 * q + 4 * lk + e;
+                        out[size_t(r) * a.Npad + nb + 32 * j + li] = v[e];
                     }
                 }
     } else if (kMode == kModeGradH) {
@@ -828,7 +876,7 @@ __global__ void __launch_bounds__(256) k_pack_gh_b(const float* gv, PackArgs p, 
 // f[p][q] = sum over splits of the partial tile entry of (lenslet, class).
 // With fmeas set (Richardson-Lucy, Eq. 2), the quotient fmeas / f is written
 // instead, 0 where f is not positive.
-__global__ void __launch_bounds__(256) k_fwd_reduce(const float* partial, int splits, int Mpad, int Npad,
+__global__ void __launch_bounds__(256) k_fwd_reduce(const float* partial, const uint32_t* tab, int Npad,
                                                      ProjGeom g, ClassBoxes cb, const float* fmeas, float* f)
 {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -836,8 +884,11 @@ __global__ void __launch_bounds__(256) k_fwd_reduce(const float* partial, int sp
     const int p = int(i / g.C), q = int(i - int64_t(p) * g.C);
     const int m = (p / g.nx) * g.Lc + q / g.ny;
     const int n = col_of_class(cb, p % g.nx, q % g.ny);
+    // the row tile's partial-sum slots, in split order
+    const int mt = m / kMT, r = m - mt * kMT;
+    const uint32_t first = tab[mt], last = tab[mt + 1];
     double acc = 0.0;
-    for (int s = 0; s < splits; ++s) acc += double(partial[(size_t(s) * Mpad + m) * Npad + n]);
+    for (uint32_t s = first; s < last; ++s) acc += double(partial[(size_t(s) * kMT + r) * Npad + n]);
     if (fmeas)
         f[i] = acc > 0.0 ? float(double(fmeas[i]) / acc) : 0.0f;
     else
@@ -851,9 +902,12 @@ size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 struct FwdPlan {
     ProjGeom g;
     FwdLayout L;
-    int N, Npad, Mpad, mtiles, ntiles, splits;
+    int N, Npad, Mpad, mtiles, ntiles;
+    int splits;                  // of a row tile that needs every window row
+    int slots, nwg;              // partial-sum slots (64 rows each), workgroups
+    std::vector<uint32_t> tab;   // the work table (GemmArgs::tab)
     ClassBoxes cb;
-    size_t gT_bytes, gS_bytes, B_bytes, part_bytes;
+    size_t gT_bytes, gS_bytes, B_bytes, part_bytes, tab_bytes;
 };
 
 // Box shape of the forward columns: at most 64 classes a box, the shape that
@@ -891,15 +945,50 @@ FwdPlan fwd_plan(const lfbp_shape& s, int64_t R, int64_t C)
     P.ntiles = (P.cb.boxes * 64 + kNT - 1) / kNT;
     P.Mpad = P.mtiles * kMT;
     P.Npad = P.ntiles * kNT;
-    // About kTargetBlocks workgroups (one round at two per CU on 256 CUs).  The
-    // split count depends on the shape only, so the workspace size and the
-    // order of the float64 reduction do not depend on the device.
-    const int want = kTargetBlocks / (P.mtiles * P.ntiles);
-    P.splits = std::max(1, std::min({want, 64, std::max(1, P.L.stages / 64)}));
+    // Splits.  Row tiles near the top and bottom of the image need fewer
+    // window rows (fwd_tile_rows), so each row tile gets splits in proportion
+    // to the rows its busiest box needs and every workgroup has about the
+    // same work: count(c, mt) = ceil(rows(mt) c / rows_max), with the largest
+    // c (at most 64, and at most one per 64 stages) whose workgroups fit one
+    // round of kTargetBlocks (two per CU on 256 CUs).  The counts depend on
+    // the shape only, so the workspace size and the order of the float64
+    // reduction do not depend on the device.
+    std::vector<int> rows(size_t(P.mtiles), 0);
+    int rows_max = 0;
+    for (int mt = 0; mt < P.mtiles; ++mt) {
+        for (int b = 0; b < P.cb.boxes; ++b) {
+            int lo;
+            rows[size_t(mt)] = std::max(rows[size_t(mt)], fwd_tile_rows(P.g, P.cb, mt, b, lo));
+        }
+        rows_max = std::max(rows_max, rows[size_t(mt)]);
+    }
+    auto count = [&](int c, int mt) {
+        return rows_max == 0 ? 1 : std::max(1, int((int64_t(rows[size_t(mt)]) * c + rows_max - 1) / rows_max));
+    };
+    const int cap = std::max(1, std::min(64, P.L.stages / 64));
+    P.splits = 1;
+    for (int c = 2; c <= cap; ++c) {
+        int64_t total = 0;
+        for (int mt = 0; mt < P.mtiles; ++mt) total += count(c, mt);
+        if (total * P.ntiles > kTargetBlocks) break;
+        P.splits = c;
+    }
+    // the work table: first slot of every row tile, then the workgroups in
+    // the order (split, column tile, row tile), so that the row tiles of one
+    // split and column tile, which walk the same stages, run on one XCD
+    P.tab.assign(size_t(P.mtiles) + 1, 0u);
+    for (int mt = 0; mt < P.mtiles; ++mt) P.tab[size_t(mt) + 1] = P.tab[size_t(mt)] + uint32_t(count(P.splits, mt));
+    P.slots = int(P.tab[size_t(P.mtiles)]);
+    for (int j = 0; j < P.splits; ++j)
+        for (int nt = 0; nt < P.ntiles; ++nt)
+            for (int mt = 0; mt < P.mtiles; ++mt)
+                if (j < count(P.splits, mt)) P.tab.push_back((uint32_t(mt * P.ntiles + nt) << 6) | uint32_t(j));
+    P.nwg = int(P.tab.size()) - (P.mtiles + 1);
     P.gT_bytes = align256(size_t(P.g.nz) * P.g.R * P.g.C * sizeof(float));
     P.gS_bytes = align256(size_t(P.N) * P.L.LRp * P.L.LCp * P.L.nzc * kRec * sizeof(float));
     P.B_bytes = align256(size_t(P.L.stages) * P.Npad * kRec * sizeof(float));
-    P.part_bytes = size_t(P.splits) * P.Mpad * P.Npad * sizeof(float);
+    P.tab_bytes = align256(P.tab.size() * sizeof(uint32_t));
+    P.part_bytes = align256(size_t(P.slots) * kMT * P.Npad * sizeof(float)) + P.tab_bytes;   // partials, table
     return P;
 }
 
@@ -944,14 +1033,11 @@ unsigned blocks_for(int64_t items) { return unsigned((items + 255) / 256); }
 
 WindowWalk window_walk(const ProjGeom& g, const ClassBoxes& cb)
 {
-    const int Rw = g.ns + cb.bu - 1, Cw = g.nt + cb.bv - 1;
+    const int Cw = g.nt + cb.bv - 1;
     WindowWalk w;
     w.q0 = Cw / g.ny;
     w.r0 = Cw - w.q0 * g.ny;
     w.q1 = w.q0 + 1;
-    w.n1 = w.r0 * Rw * w.q1;
-    w.fRq1 = make_fastdiv(uint32_t(Rw * w.q1));
-    w.fRq0 = make_fastdiv(uint32_t(std::max(1, Rw * w.q0)));
     w.fq1 = make_fastdiv(uint32_t(w.q1));
     w.fq0 = make_fastdiv(uint32_t(std::max(1, w.q0)));
     return w;
@@ -980,15 +1066,26 @@ namespace {
 // pack them into the workspace.  Workspace: g with depth innermost, the A
 // records, the B records unless prepared, the split partial tiles.
 hipError_t forward_impl(const float* H, const lfbp_shape& s, const float* gin, int64_t R, int64_t C,
-                        const float* fmeas, float* f, void* ws, const float* Bpre, hipStream_t stream)
+                        const float* fmeas, float* f, void* ws, const float* Bpre, const uint32_t* tabpre,
+                        hipStream_t stream)
 {
     const FwdPlan P = fwd_plan(s, R, C);
     const ProjGeom& g = P.g;
+    if (int64_t(P.mtiles) * P.ntiles >= (int64_t(1) << 26)) return hipErrorInvalidValue;   // work table entries
     char* w = static_cast<char*>(ws);
     float* gT = reinterpret_cast<float*>(w);
     float* gS = reinterpret_cast<float*>(w + P.gT_bytes);
     float* Bp = reinterpret_cast<float*>(w + P.gT_bytes + P.gS_bytes);
     float* part = reinterpret_cast<float*>(w + P.gT_bytes + P.gS_bytes + (Bpre ? 0 : P.B_bytes));
+    // the work table: prepared with the operator, else written into the
+    // workspace after the partial sums (stream-ordered, no allocation)
+    const uint32_t* tab = tabpre;
+    if (!tab) {
+        uint32_t* t = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(part) + (P.part_bytes - P.tab_bytes));
+        const hipError_t et = put_words(t, P.tab.data(), P.tab.size(), stream);
+        if (et != hipSuccess) return et;
+        tab = t;
+    }
 
     PackArgs p = pack_args(g, P.N, P.Npad, P.Mpad, P.L.stages);
     p.nzc = P.L.nzc;
@@ -1037,12 +1134,13 @@ hipError_t forward_impl(const float* H, const lfbp_shape& s, const float* gin, i
     a.fnzc = p.fnzc;
     a.cb = P.cb;
     a.walk = window_walk(g, P.cb);
-    hipLaunchKernelGGL(k_gemm<kModeFwd>, dim3(unsigned(P.mtiles * P.ntiles * P.splits)), dim3(kThreads), 0, stream,
-                       a);
+    a.tab = tab;
+    a.nwg = P.nwg;
+    hipLaunchKernelGGL(k_gemm<kModeFwd>, dim3(unsigned(P.nwg)), dim3(kThreads), 0, stream, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int64_t npix = int64_t(g.R) * g.C;
-    hipLaunchKernelGGL(k_fwd_reduce, dim3(blocks_for(npix)), dim3(256), 0, stream, part, P.splits, P.Mpad, P.Npad, g,
-                       P.cb, fmeas, f);
+    hipLaunchKernelGGL(k_fwd_reduce, dim3(blocks_for(npix)), dim3(256), 0, stream, part, tab, P.Npad, g, P.cb, fmeas,
+                       f);
     return hipGetLastError();
 }
 
@@ -1093,7 +1191,7 @@ hipError_t backward_impl(const float* Ht, const lfbp_shape& s, const float* f, i
 hipError_t launch_forward_ws(const float* H, const lfbp_shape& s, const float* gin, int64_t R, int64_t C, float* f,
                              void* ws, hipStream_t stream)
 {
-    return forward_impl(H, s, gin, R, C, nullptr, f, ws, nullptr, stream);
+    return forward_impl(H, s, gin, R, C, nullptr, f, ws, nullptr, nullptr, stream);
 }
 
 hipError_t launch_backward_ws(const float* Ht, const lfbp_shape& s, const float* f, int64_t R, int64_t C, float* g,
@@ -1197,7 +1295,7 @@ hipError_t launch_rl_step_ws(const float* H, const float* Ht, const lfbp_shape& 
 {
     float* ratio = reinterpret_cast<float*>(
         static_cast<char*>(ws) + align256(std::max(forward_workspace_bytes(s, R, C), backward_workspace_bytes(s, R, C))));
-    hipError_t e = forward_impl(H, s, g, R, C, fmeas, ratio, ws, nullptr, stream);
+    hipError_t e = forward_impl(H, s, g, R, C, fmeas, ratio, ws, nullptr, nullptr, stream);
     if (e != hipSuccess) return e;
     return backward_impl(Ht, s, ratio, R, C, g, norm, g_out, ws, nullptr, stream);
 }
@@ -1262,10 +1360,12 @@ hipError_t launch_backward(const float* Ht, const lfbp_shape& s, const float* f,
 
 // A prepared operator holds the B records of H (forward) and of H'
 // (backward), which depend on the PSF only, so that a loop over volumes and
-// images with one PSF (Richardson-Lucy, Eq. 2) packs them once.
+// images with one PSF (Richardson-Lucy, Eq. 2) packs them once, and the
+// forward's work table, which depends on the shapes only.
 size_t operator_bytes(const lfbp_shape& s, int64_t R, int64_t C)
 {
-    return align256(fwd_plan(s, R, C).B_bytes) + align256(bwd_plan(s, R, C).B_bytes);
+    const FwdPlan F = fwd_plan(s, R, C);
+    return align256(F.B_bytes) + align256(bwd_plan(s, R, C).B_bytes) + F.tab_bytes;
 }
 
 // Workspace of every call on a prepared operator (forward, backward, one
@@ -1286,6 +1386,12 @@ const float* op_fwd_b(const void* op) { return static_cast<const float*>(op); }
 const float* op_bwd_b(const void* op, const lfbp_shape& s, int64_t R, int64_t C)
 {
     return reinterpret_cast<const float*>(static_cast<const char*>(op) + align256(fwd_plan(s, R, C).B_bytes));
+}
+
+const uint32_t* op_fwd_tab(const void* op, const lfbp_shape& s, int64_t R, int64_t C)
+{
+    return reinterpret_cast<const uint32_t*>(static_cast<const char*>(op) + align256(fwd_plan(s, R, C).B_bytes) +
+                                             align256(bwd_plan(s, R, C).B_bytes));
 }
 
 float* op_image(void* ws, const lfbp_shape& s, int64_t R, int64_t C)
@@ -1315,6 +1421,8 @@ hipError_t launch_operator_prepare(const float* H, const float* Ht, const lfbp_s
                        const_cast<float*>(op_fwd_b(op)));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    e = put_words(const_cast<uint32_t*>(op_fwd_tab(op, s, R, C)), F.tab.data(), F.tab.size(), stream);
+    if (e != hipSuccess) return e;
     const BwdPlan Bw = bwd_plan(s, R, C);
     const PackArgs pb = pack_args(Bw.g, Bw.N, Bw.Npad, Bw.Mpad, Bw.stages);
     hipLaunchKernelGGL(k_pack_bwd_b, dim3(unsigned(Bw.stages), blocks_for(int64_t(Bw.Npad) * kRecVec)), dim3(256), 0,
@@ -1325,7 +1433,7 @@ hipError_t launch_operator_prepare(const float* H, const float* Ht, const lfbp_s
 hipError_t launch_forward_op(const void* op, const lfbp_shape& s, const float* g, int64_t R, int64_t C, float* f,
                              void* ws, hipStream_t stream)
 {
-    return forward_impl(nullptr, s, g, R, C, nullptr, f, ws, op_fwd_b(op), stream);
+    return forward_impl(nullptr, s, g, R, C, nullptr, f, ws, op_fwd_b(op), op_fwd_tab(op, s, R, C), stream);
 }
 
 hipError_t launch_backward_op(const void* op, const lfbp_shape& s, const float* f, int64_t R, int64_t C, float* g,
@@ -1338,7 +1446,7 @@ hipError_t launch_rl_step_op(const void* op, const lfbp_shape& s, const float* f
                              const float* g, const float* norm, float* g_out, void* ws, hipStream_t stream)
 {
     float* ratio = op_image(ws, s, R, C);
-    hipError_t e = forward_impl(nullptr, s, g, R, C, fmeas, ratio, ws, op_fwd_b(op), stream);
+    hipError_t e = forward_impl(nullptr, s, g, R, C, fmeas, ratio, ws, op_fwd_b(op), op_fwd_tab(op, s, R, C), stream);
     if (e != hipSuccess) return e;
     return backward_impl(nullptr, s, ratio, R, C, g, norm, g_out, ws, op_bwd_b(op, s, R, C), stream);
 }

@@ -7,6 +7,7 @@ its array, that the workgroup -> tile map is a bijection, and, by running the
 mirrored records through a float64 matrix product, that the formulation gives
 the oracle's f = H g and g = H' f.  Keep it in step with the kernels.
 """
+import functools
 import itertools
 
 import numpy as np
@@ -88,12 +89,27 @@ def col_of_class(cb, u, v):
     return (bi * cb['nbv'] + bj) * 64 + (u - bi * cb['bu']) * cb['bv'] + (v - bj * cb['bv'])
 
 
-def fwd_window(g, p, ntile, wave):
+def fwd_tile_rows(g, cb, mt, box):
+    """(count, first) of the window rows box `box` needs for row tile mt
+    (mirror of fwd_tile_rows): the rows whose patch-row shift s' = ir - u1
+    puts a source row P = nx Lp + hs - s' inside the image for some lenslet
+    row Lp of the tile."""
+    bi = box // cb['nbv']
+    u1 = min(g['nx'], (bi + 1) * cb['bu']) - 1
+    Rw = g['ns'] + cb['bu'] - 1
+    m_lo, m_hi = mt * kMT, min(g['M'] - 1, mt * kMT + kMT - 1)
+    lp_lo, lp_hi = m_lo // g['Lc'], m_hi // g['Lc']
+    ir_lo = max(0, g['nx'] * lp_lo + g['hs'] - (g['R'] - 1) + u1)
+    ir_hi = min(Rw - 1, g['nx'] * lp_hi + g['hs'] + u1)
+    return max(0, ir_hi - ir_lo + 1), ir_lo
+
+
+def fwd_window(g, p, ntile, wave, mt=None):
     """The wavefront's stages (k_gemm, forward), in window order: the box's
-    Rw x Cw = (ns + bu - 1) x (nt + bv - 1) patch shifts, depth chunk
-    fastest; the column shifts by residue b modulo ny, within a residue all
-    row shifts, each with the residue's column shifts b, b + ny, ...
-    innermost."""
+    Rw x Cw = (ns + bu - 1) x (nt + bv - 1) patch shifts (only the rows row
+    tile mt needs, when mt is given), depth chunk fastest; the column shifts
+    by residue b modulo ny, within a residue all row shifts, each with the
+    residue's column shifts b, b + ny, ... innermost."""
     cb = p['cb']
     b = ntile * (kNT // 64) + wave
     if b >= cb['boxes']:
@@ -103,10 +119,21 @@ def fwd_window(g, p, ntile, wave):
     sr0, tc0 = g['nx'] - 1 - u1, g['ny'] - 1 - v1
     Rw, Cw = g['ns'] + cb['bu'] - 1, g['nt'] + cb['bv'] - 1
     assert sr0 >= 0 and tc0 >= 0 and sr0 + Rw <= g['Kr'] and tc0 + Cw <= g['Kc']
-    ny = g['ny']
+    if mt is not None:
+        Rw, ir_lo = fwd_tile_rows(g, cb, mt, b)
+        sr0 += ir_lo
+        assert Rw == 0 or sr0 + Rw <= g['Kr']
+    order = walk_order(Rw, Cw, g['ny'])
+    return [((sr0 + ir) * g['Kc'] + tc0 + ic) * p['nzc'] + zc for ir, ic in order for zc in range(p['nzc'])]
+
+
+@functools.lru_cache(maxsize=None)
+def walk_order(Rw, Cw, ny):
+    """Window positions (ir, ic) in walk order, checked against the kernel's
+    closed form (WindowWalk, with n1 and the divisors by Rw q taken per
+    wavefront)."""
     order = [(ir, b + k * ny) for b in range(min(ny, Cw)) for ir in range(Rw) for k in range((Cw - b + ny - 1) // ny)]
     assert sorted(order) == [(ir, ic) for ir in range(Rw) for ic in range(Cw)]
-    # the kernel's closed form of the same order (WindowWalk)
     q0, r0 = divmod(Cw, ny)
     q1, n1 = q0 + 1, r0 * Rw * (q0 + 1)
     for j, (ir, ic) in enumerate(order):
@@ -114,7 +141,7 @@ def fwd_window(g, p, ntile, wave):
         jr, q = (j, q1) if first else (j - n1, q0)
         bq, rem = divmod(jr, Rw * q)
         assert (rem // q, (bq if first else r0 + bq) + (rem % q) * ny) == (ir, ic)
-    return [((sr0 + ir) * g['Kc'] + tc0 + ic) * p['nzc'] + zc for ir, ic in order for zc in range(p['nzc'])]
+    return tuple(order)
 
 
 def bwd_window(g, N, stages, ntile):
@@ -132,16 +159,37 @@ def bwd_window(g, N, stages, ntile):
 
 
 def fwd_plan(g, target_blocks=512):
+    """Mirror of fwd_plan: row-tile split counts in proportion to the window
+    rows each tile needs, the work table (first slot per row tile, then the
+    workgroups as (row tile, column tile, split))."""
     N = g['nx'] * g['ny']
     cb = class_boxes(g)
     mtiles, ntiles = -(-g['M'] // kMT), -(-(cb['boxes'] * 64) // kNT)
     nzc = -(-g['nz'] // kStageK)
     stages = g['Kr'] * g['Kc'] * nzc
-    want = target_blocks // (mtiles * ntiles)
-    splits = max(1, min(want, 64, max(1, stages // 64)))
+    rows = [max(fwd_tile_rows(g, cb, mt, b)[0] for b in range(cb['boxes'])) for mt in range(mtiles)]
+    rmax = max(rows)
+
+    def count(c, mt):
+        return 1 if rmax == 0 else max(1, -(-rows[mt] * c // rmax))
+
+    cap = max(1, min(64, stages // 64))
+    splits = 1
+    for c in range(2, cap + 1):
+        if sum(count(c, mt) for mt in range(mtiles)) * ntiles > target_blocks:
+            break
+        splits = c
+    prefix = [0]
+    for mt in range(mtiles):
+        prefix.append(prefix[-1] + count(splits, mt))
+    wgs = [(mt, nt, j) for j in range(splits) for nt in range(ntiles) for mt in range(mtiles) if j < count(splits, mt)]
+    assert splits <= 64 and mtiles * ntiles < 1 << 26          # the table's (tile << 6) | split words
+    assert sorted(wgs) == sorted((mt, nt, j) for mt in range(mtiles) for nt in range(ntiles)
+                                 for j in range(prefix[mt + 1] - prefix[mt]))
     padP, padQ = (g['hs'] + g['nx'] - 1) // g['nx'], (g['ht'] + g['ny'] - 1) // g['ny']
     return dict(N=N, mtiles=mtiles, ntiles=ntiles, Mpad=mtiles * kMT, Npad=ntiles * kNT, nzc=nzc, stages=stages,
-                splits=splits, padP=padP, padQ=padQ, LRp=g['Lr'] + 2 * padP, LCp=g['Lc'] + 2 * padQ, cb=cb)
+                splits=splits, prefix=prefix, wgs=wgs, slots=prefix[-1], padP=padP, padQ=padQ,
+                LRp=g['Lr'] + 2 * padP, LCp=g['Lc'] + 2 * padQ, cb=cb)
 
 
 def check_blocks(mtiles, ntiles, splits):
@@ -210,15 +258,13 @@ def forward_mirror(H, gvol, target_blocks=512):
     idx = np.where(okb, (su * nt + tv) * cell + (pxs[S] * ny + pys[S]) * nz + zz, 0)
     assert idx.min() >= 0 and idx.max() < H.size
     Bp = to_blocks(np.where(okb, Hf[idx], 0.0))          # blocks = stages, Npad records each
-    # GEMM: every workgroup's lanes and stages
-    check_blocks(p['mtiles'], p['ntiles'], p['splits'])
+    # GEMM: every workgroup's lanes and stages, from the work table
     m = np.arange(p['Mpad'])
     mc = np.minimum(m, g['M'] - 1)
     lane_a = (mc // g['Lc']) * p['LCp'] + mc % g['Lc']             # record of the lane's lenslet
     abase = ((pxs * ny + pys) * p['nzc'] + zcs) * kRecVec * arows + 2 * ((dP + p['padP']) * p['LCp'] + dQ + p['padQ'])
     lane_b = np.arange(p['Npad'])
     use = SLOT_K >= 0                                               # the MFMA steps read slots 0-10 and 12-22
-    partial = np.zeros((p['splits'], p['Mpad'], p['Npad']))
     okb_s = okb.any(axis=2)                                         # [stage][column] holds a nonzero slot
     for ntile in range(p['ntiles']):
         for wave in range(kNT // 64):
@@ -228,17 +274,34 @@ def forward_mirror(H, gvol, target_blocks=512):
             outside = np.ones(p['stages'], bool)
             outside[win] = False
             assert not okb_s[np.ix_(outside, cols)].any(), "nonzero B record outside the window"
-            for sidx, (b, e) in enumerate(split_ranges(len(win), p['splits'])):
-                for s in win[b:e]:
-                    Arec = read_records(gS, abase[s], lane_a, 2 * arows)
-                    Brec = read_records(Bp, s * kRecVec * p['Npad'], lane_b[cols], 2 * p['Npad'])
-                    partial[sidx][:, cols] += Arec[:, use] @ Brec[:, use].T
-    # k_fwd_reduce
+            for mt in range(p['mtiles']):
+                # the rows a row tile drops hold only zero A records for its lenslets
+                rows_t = lane_a[mt * kMT:(mt + 1) * kMT]
+                kept = set(fwd_window(g, p, ntile, wave, mt))
+                assert kept <= set(win)
+                for st in set(win) - kept:
+                    assert not read_records(gS, abase[st], rows_t, 2 * arows).any(), "dropped row with nonzero A"
+    partial = np.zeros((p['slots'], kMT, p['Npad']))
+    for mt, ntile, j in p['wgs']:
+        nsplit = p['prefix'][mt + 1] - p['prefix'][mt]
+        slot = p['prefix'][mt] + j
+        assert 0 <= j < nsplit and slot < p['slots']
+        rows_t = lane_a[mt * kMT:(mt + 1) * kMT]
+        for wave in range(kNT // 64):
+            cols = np.arange(ntile * kNT + 64 * wave, ntile * kNT + 64 * wave + 64)
+            win = fwd_window(g, p, ntile, wave, mt)
+            b, e = len(win) * j // nsplit, len(win) * (j + 1) // nsplit
+            for st in win[b:e]:
+                Arec = read_records(gS, abase[st], rows_t, 2 * arows)
+                Brec = read_records(Bp, st * kRecVec * p['Npad'], lane_b[cols], 2 * p['Npad'])
+                partial[slot][:, cols] += Arec[:, use] @ Brec[:, use].T
+    # k_fwd_reduce: a pixel's lenslet row m sums its row tile's slots
     pp, qq = np.meshgrid(np.arange(R), np.arange(C), indexing='ij')
     mm = (pp // nx) * g['Lc'] + qq // ny
     nn = np.vectorize(lambda a, b: col_of_class(p['cb'], a, b))(pp % nx, qq % ny)
     assert mm.max() < p['Mpad'] and nn.max() < p['Npad']
-    return partial.sum(axis=0)[mm, nn]
+    tiles = np.array([partial[p['prefix'][mt]:p['prefix'][mt + 1]].sum(axis=0) for mt in range(p['mtiles'])])
+    return tiles[mm // kMT, mm % kMT, nn]
 
 
 def backward_mirror(Ht, f):
@@ -305,7 +368,8 @@ def backward_mirror(Ht, f):
     return out
 
 
-SHAPES = [((15, 15, 3, 3, 3), 21, 21), ((15, 15, 3, 3, 3), 20, 23), ((9, 7, 3, 5, 2), 12, 10),
+SHAPES = [((15, 15, 3, 3, 2), 12, 200), ((9, 9, 1, 1, 2), 10, 70), ((11, 9, 3, 3, 3), 9, 140),
+          ((15, 15, 3, 3, 3), 21, 21), ((15, 15, 3, 3, 3), 20, 23), ((9, 7, 3, 5, 2), 12, 10),
           ((5, 5, 5, 5, 1), 7, 8), ((7, 9, 1, 1, 3), 11, 9), ((1, 1, 1, 1, 2), 4, 5), ((3, 3, 7, 7, 2), 14, 21),
           ((21, 21, 3, 3, 9), 8, 7), ((5, 5, 3, 3, 2), 9, 12), ((3, 3, 1, 1, 2), 5, 6),
           ((9, 9, 3, 3, 30), 10, 10), ((5, 5, 3, 3, 45), 6, 7), ((3, 3, 3, 3, 23), 7, 5), ((7, 5, 3, 1, 22), 9, 4),
@@ -357,7 +421,14 @@ def test_large_shapes_record_addresses(shape, R, C):
     # the shift never carries a lane's record out of its (px, py, zc) block
     blk = ((px * shape[3] + py) * p['nzc'] + zc) * kRecVec * arows
     assert np.all(base - blk + lane.max() + 1 < 2 * arows) and np.all(base - blk + lane.min() >= 0)
-    check_blocks(p['mtiles'], p['ntiles'], p['splits'])
+    # the work table (checked in fwd_plan): every workgroup's slot inside the partial sums
+    assert all(p['prefix'][mt] + j < p['slots'] for mt, _, j in p['wgs'])
+    if shape == (165, 165, 15, 15, 21) and (R, C) == (600, 600):
+        # the projector workload: 21 splits for the 19 row tiles that need every window row, 14, 18 and 20
+        # for the three at either edge, 503 workgroups in one round of 512
+        assert p['splits'] == 21 and len(p['wgs']) == 503
+        counts = [p['prefix'][mt + 1] - p['prefix'][mt] for mt in range(p['mtiles'])]
+        assert counts == [14, 18, 20] + [21] * 19 + [20, 18, 14]
 
 
 def grad_mirror(shape, w, gv):
