@@ -403,7 +403,9 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2
     // reduction pairs with r + cx inside [0, ns) for some column of the
     // workgroup, a contiguous run of stages (columns are (cx, cy, z) with z
     // fastest, so a workgroup spans few cx).  Gradient with respect to H:
-    // every stage, or none for a tile none of whose entries is kept.
+    // the run of stages (22 lenslets each) over the lenslet rows whose image
+    // rows the tile's r reach, or none for a tile none of whose entries is
+    // kept.
     int w_cnt = a.stages, w_base = 0, sr0 = 0, tc0 = 0, Rw = 1;
     if (kFwd) {
         const int b = ntile * (kNT / 64) + wave;
@@ -440,7 +442,23 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2
         const int rlo = m0 / g.Kc, rhi = min(m0 + kMT - 1, a.M - 1) / g.Kc;
         const int nlo = ntile * kNT, nhi = min(nlo + kNT - 1, a.N - 1);
         const int xlo = nlo / g.nz / g.ny, xhi = nhi / g.nz / g.ny;
-        if (m0 >= a.M || rhi < xlo || rlo - xhi > g.ns - 1) w_cnt = 0;
+        if (m0 >= a.M || rhi < xlo || rlo - xhi > g.ns - 1) {
+            w_cnt = 0;
+        } else {
+            // only the lenslet rows LP whose image row nx LP + r - hs lies
+            // inside the image for some r of the tile give nonzero A records:
+            // nx LP in [hs - rhi, R - 1 + hs - rlo]; their lenslets
+            // [LP_lo Lc, (LP_hi + 1) Lc) are a contiguous run of stages
+            const int d = g.hs - rhi, e = g.R - 1 + g.hs - rlo;
+            const int lp_lo = d > 0 ? (d + g.nx - 1) / g.nx : 0;
+            const int lp_hi = e < 0 ? -1 : min(g.Lr - 1, e / g.nx);
+            if (lp_lo > lp_hi) {
+                w_cnt = 0;
+            } else {
+                w_base = lp_lo * g.Lc / kStageK;
+                w_cnt = (min(g.M, (lp_hi + 1) * g.Lc) + kStageK - 1) / kStageK - w_base;
+            }
+        }
     }
     const int s_begin = int(int64_t(w_cnt) * split / splits);
     const int s_end = int(int64_t(w_cnt) * (split + 1) / splits);

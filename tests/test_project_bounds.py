@@ -431,6 +431,29 @@ def test_large_shapes_record_addresses(shape, R, C):
         assert counts == [14, 18, 20] + [21] * 19 + [20, 18, 14]
 
 
+def grad_window(g, Mg, N, mt, nt_, stages):
+    """The stages of gradient tile (mt, nt_) (k_gemm, gradient with respect
+    to H): none when no entry of the tile is kept (no pair 0 <= r - x < ns),
+    else the run of stages over the lenslet rows LP with nx LP in
+    [hs - rhi, R - 1 + hs - rlo]."""
+    nx, ny, nz, ns = g['nx'], g['ny'], g['nz'], g['ns']
+    m0, nlo = mt * kMT, nt_ * kNT
+    rlo, rhi = m0 // g['Kc'], min(m0 + kMT - 1, Mg - 1) // g['Kc']
+    nhi = min(nlo + kNT - 1, N - 1)
+    xlo, xhi = nlo // nz // ny, nhi // nz // ny
+    if m0 >= Mg or rhi < xlo or rlo - xhi > ns - 1:
+        return []
+    d, e = g['hs'] - rhi, g['R'] - 1 + g['hs'] - rlo
+    lp_lo = (d + nx - 1) // nx if d > 0 else 0
+    lp_hi = -1 if e < 0 else min(g['Lr'] - 1, e // nx)
+    if lp_lo > lp_hi:
+        return []
+    base = lp_lo * g['Lc'] // kStageK
+    end = -(-min(g['M'], (lp_hi + 1) * g['Lc']) // kStageK)
+    assert 0 <= base <= end <= stages
+    return list(range(base, end))
+
+
 def grad_mirror(shape, w, gv):
     """Records, GEMM and epilogue of the gradient with respect to H."""
     ns, nt, nx, ny, nz = shape
@@ -470,20 +493,22 @@ def grad_mirror(shape, w, gv):
     check_blocks(mtiles, ntiles, 1)
     use = SLOT_K >= 0
     E = np.zeros((Mpad, Npad))
-    for s in range(stages):
-        Arec = read_records(Ap, s * kRecVec * Mpad, np.arange(Mpad), 2 * Mpad)
-        Brec = read_records(Bp, s * kRecVec * Npad, np.arange(Npad), 2 * Npad)
-        E += Arec[:, use] @ Brec[:, use].T
-    # k_gemm skips a tile (64 rows, the workgroup's 256 columns) with no pair
-    # 0 <= r - x < ns: its entries stay zero and none of them is kept below
     for mt in range(mtiles):
         for nt_ in range(ntiles):
             m0, nlo = mt * kMT, nt_ * kNT
+            rows, cols = np.arange(m0, m0 + kMT), np.arange(nlo, nlo + kNT)
+            win = grad_window(g, Mg, N, mt, nt_, stages)
+            # the stages outside the window hold only zero A records for the tile's rows (a tile
+            # with no kept entry computes nothing, and none of its entries is kept below)
             rlo, rhi = m0 // g['Kc'], min(m0 + kMT - 1, Mg - 1) // g['Kc']
-            nhi = min(nlo + kNT - 1, N - 1)
-            xlo, xhi = nlo // nz // ny, nhi // nz // ny
-            if m0 >= Mg or rhi < xlo or rlo - xhi > ns - 1:
-                E[m0:m0 + kMT, nlo:nlo + kNT] = 0.0
+            xlo, xhi = nlo // nz // ny, min(nlo + kNT - 1, N - 1) // nz // ny
+            if not (m0 >= Mg or rhi < xlo or rlo - xhi > ns - 1):
+                for st in sorted(set(range(stages)) - set(win)):
+                    assert not read_records(Ap, st * kRecVec * Mpad, rows, 2 * Mpad).any(), "skipped stage with nonzero A"
+            for st in win:
+                Arec = read_records(Ap, st * kRecVec * Mpad, rows, 2 * Mpad)
+                Brec = read_records(Bp, st * kRecVec * Npad, cols, 2 * Npad)
+                E[m0:m0 + kMT, nlo:nlo + kNT] += Arec[:, use] @ Brec[:, use].T
     # epilogue: (m, n) -> dH[r - x][r2 - y][x][y][z] when inside the patch
     dH = np.full(shape, np.nan)
     mm, nn = np.meshgrid(np.arange(Mg), np.arange(N), indexing='ij')
@@ -497,7 +522,8 @@ def grad_mirror(shape, w, gv):
     return dH
 
 
-@pytest.mark.parametrize("shape,R,C", [((15, 15, 3, 3, 3), 21, 21), ((9, 7, 3, 5, 2), 12, 10), ((5, 5, 5, 5, 1), 7, 8),
+@pytest.mark.parametrize("shape,R,C", [((9, 9, 3, 3, 2), 90, 60), ((15, 15, 1, 1, 2), 40, 50),
+                                       ((15, 15, 3, 3, 3), 21, 21), ((9, 7, 3, 5, 2), 12, 10), ((5, 5, 5, 5, 1), 7, 8),
                                        ((7, 9, 1, 1, 3), 11, 9), ((21, 21, 17, 17, 2), 40, 36),
                                        ((3, 3, 7, 7, 2), 14, 21), ((9, 9, 3, 3, 30), 10, 10)])
 def test_grad_psf_mirror(shape, R, C):
