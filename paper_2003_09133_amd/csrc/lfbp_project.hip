@@ -50,7 +50,11 @@
 // splits the reduction over workgroups (partials added in a fixed order, in
 // float64, by a second kernel, so results are deterministic); the backward
 // needs no split.  Workgroups that read the same operand slab are placed on
-// the same XCD (L2).
+// the same XCD (L2).  Stages whose A records are zero for a whole row tile
+// (source pixels outside the image) are not run: the forward drops such patch
+// rows and gives each row tile splits in proportion to what is left (a work
+// table maps workgroups to row tiles, column tiles and splits); the gradient
+// with respect to H drops such lenslet rows.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
