@@ -26,7 +26,10 @@ SMALL = [((15, 15, 3, 3, 3), 21, 21), ((15, 15, 3, 3, 3), 20, 23), ((9, 7, 3, 5,
          # several depth chunks of 22, a ragged last chunk, and one chunk exactly full
          ((9, 9, 3, 3, 30), 10, 10), ((5, 5, 3, 3, 45), 6, 7), ((3, 3, 3, 3, 23), 7, 5), ((7, 5, 3, 1, 22), 9, 4),
          # more classes than one 256-column tile (nx*ny = 289), and a backward with several column tiles
-         ((21, 21, 17, 17, 2), 40, 36), ((11, 13, 5, 7, 30), 23, 30)]
+         ((21, 21, 17, 17, 2), 40, 36), ((11, 13, 5, 7, 30), 23, 30),
+         # wide images: row tiles within one or two lenslet rows, whose edge tiles drop the patch rows that
+         # only see pixels outside the image and take fewer splits
+         ((15, 15, 3, 3, 2), 12, 200), ((9, 9, 1, 1, 2), 10, 70), ((11, 9, 3, 3, 3), 9, 140)]
 
 
 @pytest.mark.parametrize("shape,R,C", SMALL)
