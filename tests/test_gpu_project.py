@@ -214,3 +214,38 @@ def test_workspace_reuse_across_shapes():
         torch.cuda.synchronize()
         assert rel_l2(fg.cpu().numpy(), oracle.forward(H, g)) <= TOL
         assert rel_l2(bg.cpu().numpy(), oracle.backward(H, f)) <= TOL
+
+
+def random_projector_cases(seed, n):
+    """Seeded odd PSF shapes with images from a few pixels to many lenslets
+    wide or tall, so that row tiles span one to many lenslet rows."""
+    rng = np.random.default_rng(seed)
+    odd = lambda lo, hi: int(rng.integers(lo, hi + 1)) | 1
+    cases = []
+    for _ in range(n):
+        shape = (odd(1, 21), odd(1, 21), odd(1, 9), odd(1, 9), int(rng.integers(1, 30)))
+        R, C = int(rng.integers(1, 90)), int(rng.integers(1, 90))
+        if rng.random() < 0.5:
+            R, C = (R, 3 * C) if rng.random() < 0.5 else (3 * R, C)
+        cases.append((shape, R, C))
+    return cases
+
+
+@pytest.mark.parametrize("shape,R,C", random_projector_cases(2003, 12))
+def test_random_shapes_forward_gradient_and_operator(shape, R, C):
+    """Forward (plain and on a prepared operator, bit-identical), backprojection
+    and gradient with respect to H against the float64 oracle."""
+    H = lfsynth.uniform_f32(shape, 71)
+    g = lfsynth.uniform_f32((shape[4], R, C), 72)
+    f = lfsynth.uniform_f32((R, C), 73)
+    dH, dg = to_dev(H), to_dev(g)
+    dHt = lf.compute_Ht(dH)
+    fg = lf.forward(dH, dg)
+    op = lf.LFOperator(dH, R, C, Ht=dHt)
+    assert gpu_equal_bits(op.forward(dg), fg)
+    bg = lf.backward(dHt, to_dev(f))
+    dPsf = lf.grad_psf(to_dev(f), dg, shape)
+    torch.cuda.synchronize()
+    assert rel_l2(fg.cpu().numpy(), oracle.forward(H, g)) <= TOL
+    assert rel_l2(bg.cpu().numpy(), oracle.backward(H, f)) <= TOL
+    assert rel_l2(dPsf.cpu().numpy(), oracle.grad_psf(shape, f, g)) <= TOL
