@@ -41,11 +41,19 @@ def _stream(stream=None) -> int:
     return int(stream.cuda_stream)
 
 
+def _check_device(t: torch.Tensor, name: str):
+    # The library launches on the current device's stream with raw pointers,
+    # so a tensor of another device would be read through the wrong mapping.
+    if t.device.index != torch.cuda.current_device():
+        raise ValueError(f"{name} lives on {t.device}, not on the current device cuda:{torch.cuda.current_device()}")
+
+
 def _check_psf(H: torch.Tensor, name: str = "H"):
     if not isinstance(H, torch.Tensor) or H.dim() != 5:
         raise ValueError(f"{name} must be a 5-D tensor [ns, nt, nx, ny, nz]")
     if not H.is_cuda:
         raise ValueError(f"{name} must live on a GPU")
+    _check_device(H, name)
     if not H.is_contiguous():
         raise ValueError(f"{name} must be contiguous (row-major, depth fastest)")
     if H.dtype not in _DTYPES:
@@ -114,6 +122,7 @@ def compute_Ht_colmajor(H: torch.Tensor, out=None, stream=None) -> torch.Tensor:
         raise ValueError("H must be a 5-D tensor [ns, nt, nx, ny, nz]")
     if not H.is_cuda:
         raise ValueError("H must live on a GPU")
+    _check_device(H, "H")
     if H.dtype not in _DTYPES:
         raise TypeError(f"H must be float32 or float16, got {H.dtype}")
     if not _is_colmajor(H):
@@ -122,6 +131,8 @@ def compute_Ht_colmajor(H: torch.Tensor, out=None, stream=None) -> torch.Tensor:
         out = torch.empty(tuple(reversed(H.shape)), dtype=H.dtype, device=H.device).permute(4, 3, 2, 1, 0)
     elif out.shape != H.shape or out.dtype != H.dtype or not out.is_cuda or not _is_colmajor(out):
         raise ValueError("out must be a column-major GPU tensor of H's shape and dtype")
+    else:
+        _check_device(out, "out")
     _abi.check(_abi.lib().lfbp_compute_Ht_colmajor(H.data_ptr(), out.data_ptr(), Shape.of(H.shape),
                                                    _DTYPES[H.dtype], _stream(stream)), "lfbp_compute_Ht_colmajor")
     return out
@@ -208,6 +219,7 @@ def _check_f32(t: torch.Tensor, name: str, dim: int):
         raise ValueError(f"{name} must be a {dim}-D tensor")
     if not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
         raise ValueError(f"{name} must be a contiguous float32 GPU tensor")
+    _check_device(t, name)
 
 
 def forward_workspace_size(shape, R: int, C: int) -> int:
@@ -243,6 +255,7 @@ def _workspace(workspace, need, device):
         workspace = torch.empty(need, dtype=torch.uint8, device=device)
     if workspace.numel() * workspace.element_size() < need or not workspace.is_cuda:
         raise ValueError(f"workspace must be a GPU tensor of at least {need} bytes")
+    _check_device(workspace, "workspace")
     return workspace
 
 
