@@ -278,6 +278,7 @@ def test_new_table_used_from_a_second_stream_at_once():
     lf.release_plans()
 
 
+@pytest.mark.filterwarnings("ignore:The CUDA Graph is empty")  # the first capture is refused on purpose
 def test_table_of_many_problems_first_made_under_capture():
     """A 20-problem table submitted first inside a caller's stream capture
     needs a device table, which cannot be allocated there: the call returns
