@@ -6,8 +6,11 @@
 Prints ONE JSON line.  The default workload is the camera PSF
 H[345,345,15,15,51] in float32, the largest single-GPU configuration; its line
 also carries, measured in the same run, the camera PSF in float16 storage, the
-microscope PSF, and the 16-set batched table against 16 per-set launches
-(minimum and median step times of both), and, from the oracle leg, a bit-exact
+microscope PSF, the 16-set batched table against 16 per-set launches
+(minimum and median step times of both), the projector pair, the
+Richardson-Lucy update, the gradient with respect to H, the in-place build and
+the column-major Table 1 sizes (each as its own line times it), and, from the
+oracle leg, a bit-exact
 comparison of every timed output with the CPU oracle (whole arrays for the
 float32 PSFs, samples for the others).
 
@@ -49,7 +52,7 @@ def parse():
     ap.add_argument("--variant", default=None, choices=[None, "direct", "staged"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="camera workload: skip the camera-f16, microscope and batched figures")
+                    help="camera workload: skip the figures of the other workloads")
     ap.add_argument("--inplace", action="store_true",
                     help="plain workloads: time lfbp_compute_Ht_inplace (H' written over H)")
     ap.add_argument("--copy", action="store_true",
@@ -432,6 +435,25 @@ def batched_vs_sequential(args, torch, lf, lfsynth, sets, rng):
     return figures, checks
 
 
+def other_lines(args, torch):
+    """The projector pair, the Richardson-Lucy update, the gradient with
+    respect to H, the in-place build of the camera PSF and the column-major
+    Table 1 sizes, each run as its own workload line runs it (same steps and
+    warm-up, no CPU leg), summarised by value, step time and roofline."""
+    runs = (("projector-pair", "projector", False, bench_projector), ("rl-update", "rl", False, bench_rl),
+            ("grad-psf", "grad-psf", False, bench_grad_psf), ("inplace-camera", "camera", True, bench_plain),
+            ("colmajor-table1", "table1", False, bench_table1))
+    res = {}
+    for name, workload, inplace, fn in runs:
+        sub = argparse.Namespace(**vars(args))
+        sub.workload, sub.inplace, sub.no_cpu_baseline, sub.no_extras = workload, inplace, True, True
+        d = fn(sub, torch)
+        res[name] = {"workload": d["config"]["workload"], "value": d["value"], "unit": d["unit"],
+                     "ms_per_step": d["ms_per_step"], "roofline": d["roofline"]}
+        torch.cuda.empty_cache()
+    return res
+
+
 def bench_plain(args, torch):
     import numpy as np
     import lfsynth
@@ -516,6 +538,8 @@ def bench_plain(args, torch):
         also["batched-16"], bchecks = batched_vs_sequential(args, torch, lf, lfsynth, lfsynth.BATCHED_SETS, rng)
         checks += bchecks
         torch.cuda.empty_cache()
+        # the rest of the path, each timed as its own line does (without its CPU leg)
+        also.update(other_lines(args, torch))
         out["config"]["also"] = also
     if not args.no_cpu_baseline and not args.copy and not args.inplace:
         nth = cores_used()
