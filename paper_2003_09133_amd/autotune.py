@@ -23,6 +23,8 @@ default by MIN_GAIN keeps the default.  Every winner's output is compared
 bit for bit with the built-in default's before it is written.  The batched
 entry is tuned in a child process that reads the freshly written plain
 entries (a batch cuts each problem into units of its plain entry's size).
+A run over some of the shapes and classes keeps the table's other entries (and
+the batched entry under --no-batched) and their notes.
 Inputs are random payloads (the kernels' cost does not depend on the values).
 Only the library's C ABI is called.  --time-shapes prints, for each shape,
 the configuration the library picks and its rate (GB/s), as one JSON line.
@@ -147,6 +149,34 @@ def read_table(path):
                 elif f and f[0] == "shape" and len(f) == 18:
                     entries[("shape", *(int(v) for v in f[1:8]))] = [int(v) for v in f[8:]]
     return entries
+
+
+HEADER_LINES = 4   # fixed comment lines at the top of a table file (written by write_table)
+
+
+def read_notes(path):
+    """The note lines of a table file (comments after the fixed header), in order."""
+    if not os.path.exists(path):
+        return []
+    with open(path) as fh:
+        comments = [l[1:].strip() for l in fh if l.startswith("#")]
+    return comments[HEADER_LINES:]
+
+
+def merge_notes(old, new):
+    """Notes of a partial re-tune: a new note replaces the old note on the same
+    subject (the text before its first colon) in place; other old notes stay,
+    and new subjects follow them."""
+    subject = lambda n: n.split(":", 1)[0]
+    fresh = {subject(n): n for n in new}
+    out = [fresh.pop(subject(n), n) for n in old]
+    return out + [n for n in new if subject(n) in fresh]
+
+
+def kept_entries(entries, retune_batched):
+    """Entries of an existing table that a run keeps before it adds its own:
+    every plain entry, and the batched entry unless the run re-tunes it."""
+    return {k: v for k, v in entries.items() if k[1] == 0 or not retune_batched}
 
 
 def write_table(path, entries, notes):
@@ -324,7 +354,8 @@ def main(argv=None):
     import torch
     import paper_2003_09133_amd as lf
 
-    entries = {k: v for k, v in read_table(args.out).items() if k[1] == 0}
+    entries = kept_entries(read_table(args.out), not args.no_batched)
+    old_notes = [n for n in read_notes(args.out) if args.no_batched or not n.startswith("batched:")]
     notes = []
     dev = torch.cuda.get_device_name(0)
     for name in args.shapes.split(","):
@@ -345,6 +376,7 @@ def main(argv=None):
         notes.append(f"{dts} class {cls}: {info['best_gbs']} GB/s geometric mean over {info['shapes']} "
                      f"(built-in default {info['default_gbs']}{', kept' if info['kept_default'] else ''}) on {dev}")
         print(json.dumps(info), flush=True)
+    notes = merge_notes(old_notes, notes)
     write_table(args.out, entries, notes)
     if not args.no_batched:
         env = dict(os.environ, LFBP_TUNE_TABLE=args.out)

@@ -121,3 +121,24 @@ def test_shape_entries_come_before_class_entries(tmp_path):
     assert got[0] == as_cfg(ecam)             # the exact shape, f32
     assert got[1] == as_cfg(e11)              # another shape of class 11: the class entry
     assert got[2] == as_cfg(ecam16)           # the exact shape, f16 (the batched shape entry is not used)
+
+
+def test_partial_retune_keeps_other_entries_and_notes(tmp_path):
+    """The autotuner's table bookkeeping (no GPU): a run over a subset keeps the
+    other entries, keeps the batched entry only when it does not re-tune it,
+    and replaces the note of each re-tuned subject in place."""
+    sys.path.insert(0, ROOT)
+    from paper_2003_09133_amd import autotune as at
+    path = str(tmp_path / "tune.txt")
+    cfg = [3, 256, 2, 16384, 4, 1, 2, 0, 8, 1]
+    entries = {("class", 0, 4, 10): cfg, ("class", 0, 2, 9): cfg, ("shape", 1, 4, 399, 399, 19, 19, 39): cfg}
+    notes = ["camera [345, 345, 15, 15, 51]: 6072.4 GB/s", "f32 class 10: 5908.2 GB/s", "batched: 5980.8 GB/s"]
+    at.write_table(path, entries, notes)
+    assert at.read_table(path) == entries
+    assert at.read_notes(path) == notes
+    assert at.kept_entries(at.read_table(path), retune_batched=False) == entries
+    assert ("shape", 1, 4, 399, 399, 19, 19, 39) not in at.kept_entries(at.read_table(path), retune_batched=True)
+    merged = at.merge_notes(notes, ["f32 class 10: 5950.0 GB/s", "f16 class 12: 5800.0 GB/s"])
+    assert merged == ["camera [345, 345, 15, 15, 51]: 6072.4 GB/s", "f32 class 10: 5950.0 GB/s",
+                      "batched: 5980.8 GB/s", "f16 class 12: 5800.0 GB/s"]
+    assert at.merge_notes([], ["a: 1"]) == ["a: 1"] and at.merge_notes(["a: 1"], []) == ["a: 1"]
