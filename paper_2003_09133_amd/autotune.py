@@ -67,11 +67,10 @@ CLASS_SHAPES = {
               (75, 75, 15, 15, 137), (45, 45, 15, 15, 272)],
     (4, 14): [(45, 45, 15, 15, 300), (57, 57, 19, 19, 300), (31, 31, 31, 31, 200), (75, 75, 15, 15, 400),
               (75, 75, 15, 15, 274), (45, 45, 15, 15, 545)],
-    (2, 9): [(165, 165, 15, 15, 21), (171, 171, 19, 19, 25), (297, 297, 11, 11, 30), (135, 135, 15, 15, 30),
-             (195, 195, 13, 13, 20), (165, 165, 15, 15, 34)],
-    (2, 10): [(345, 345, 15, 15, 51), (225, 225, 15, 15, 45), (209, 209, 11, 11, 60), (135, 135, 15, 15, 40),
-              (195, 195, 15, 15, 35), (135, 135, 15, 15, 68)],
 }
+# float16 rows of a shape are half as long as its float32 rows: the float16
+# class c is tuned on the shapes of the float32 class c + 1.
+CLASS_SHAPES.update({(2, c): CLASS_SHAPES[(4, c + 1)] for c in range(6, 14)})
 # A tuned class entry must beat the built-in default by this factor (geometric
 # mean over the class's shapes), and may be at most MAX_LOSS slower than it on
 # any one of them; otherwise the class keeps the default.
