@@ -197,3 +197,33 @@ def test_microscope_full_size():
 @pytest.mark.parametrize("dtype", [np.float32, np.float16])
 def test_camera_full_size(dtype):
     _full_size_check(lfsynth.CAMERA, dtype, full_compare=False)
+
+
+def table_classes():
+    """(element size, row class) of every class entry in the shipped tuning table."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2003_09133_amd",
+                        "lfbp_tune.txt")
+    out = []
+    for line in open(path):
+        f = line.split("#", 1)[0].split()
+        if f and f[0] == "class" and f[1] == "0":
+            out.append((int(f[2]), int(f[3])))
+    return sorted(out)
+
+
+@pytest.mark.parametrize("esize,cls", table_classes())
+def test_default_choice_of_every_table_class(esize, cls):
+    """Each class entry of the shipped tuning table, as the default path picks
+    it, on two shapes of its row class (rows just above the class's lower
+    bound and just below its upper bound, several work units, a ragged tail)."""
+    dtype = np.float32 if esize == 4 else np.float16
+    ny = 3
+    low, high = -(-2 ** cls // (ny * esize)), (2 ** (cls + 1) - 1) // (ny * esize)
+    for k, nz in enumerate((low, high)):
+        W = ny * nz * esize
+        assert 2 ** cls <= W < 2 ** (cls + 1), (cls, W)
+        shape = (11, 9, 5, ny, nz)
+        H = lfsynth.bits(shape, 97 * cls + k, dtype)
+        cfg = lf.default_config(shape, torch.float32 if esize == 4 else torch.float16)
+        assert_same_bits(run(H), oracle.Ht_rows(H), f"class {cls} esize {esize} shape {shape} {cfg}")
