@@ -59,6 +59,7 @@
 
 #include <algorithm>
 #include <cstdlib>
+#include <cstring>
 #include <vector>
 
 #include "lfbp_internal.h"
@@ -69,6 +70,7 @@ hipError_t put_words(uint32_t* dst, const uint32_t* src, size_t n, hipStream_t s
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x3 __attribute__((ext_vector_type(3)));
 
 namespace {
 
@@ -1065,12 +1067,557 @@ WindowWalk window_walk(const ProjGeom& g, const ClassBoxes& cb)
     return w;
 }
 
+
+// ------------------------------------------- forward with 16-column class boxes
+//
+// The forward GEMM above tiles the nx * ny classes in 64-column boxes of
+// 32 x 32 x 2 matrix-core steps, so 225 classes take 256 columns, and each
+// box walks the window of its 8 x 8 classes.  This form takes boxes of 3 x 5
+// classes in 16 columns (v_mfma_f32_16x16x4_f32): a wavefront holds up to five
+// boxes stacked along u in one strip of five class columns (64 lenslet rows x
+// 80 columns), and the four reduction indices of a step are four column
+// shifts t', t' + ny, t' + 2 ny, t' + 3 ny of one residue (one per group of 16
+// lanes), so a stage is four window positions at seven depths.  A box runs
+// only the row shifts it needs: the shared A records feed every box whose
+// window holds the stage's rows.  The partial sums of each split go to their
+// own slot; a second kernel adds the slots in split order in float64.
+//
+// Records (8 floats, the last 0): A16[px][py][chunk][LP'][LQ'] holds depths
+// 7 chunk .. 7 chunk + 6 of g at pixel (nx (LP' - padP) + px, ny (LQ' - padQ) +
+// py), 0 outside the image; B16[s' + nx - 1][t' + ny - 1][chunk][strip][box][n]
+// holds those depths of H[s' + u][t' + v][(hs - s') mod nx][(ht - t') mod ny]
+// for class (u, v) = (3 box + n / 5, 5 strip + n mod 5), 0 outside the patch,
+// for n = 15 and for classes past the cell.
+constexpr int kBU = 3, kBV = 5, kWaveBoxes = 5, kCh = 7, kF16Fold = 24;
+constexpr uint32_t kOob = 0x7FFFFFF0u;   // a byte offset past every record block: reads zeros
+
+struct Fwd16Item {      // one wavefront: row tile, strip, box group, the window rows it needs, stages, slot
+    int mt, j, h, r_lo, nrows, st_begin, st_end, slot;
+};
+
+struct Fwd16Args {
+    const float* A;
+    const float* B;
+    float* out;                 // partial tiles [slot][64][ncols]
+    const Fwd16Item* items;
+    uint32_t A_bytes, B_bytes;
+    int nitems, nwg;
+    int ns, nt, nx, ny, hs, ht, M, Lc, LRp, LCp, padP, padQ, Kt;
+    int nch, nstrips, nbox, ncols;
+    FastDiv fnx, fny;
+};
+
+__device__ __forceinline__ f32x3 ld3(Rsrc r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(f32x3, __builtin_amdgcn_raw_buffer_load_b96(r, int(voff), int(soff), 0));
+}
+
+__device__ __forceinline__ float rec_at(const f32x4& x, const f32x3& y, int d) { return d < 4 ? x[d] : y[d - 4]; }
+
+struct Fwd16Walk {      // wavefront-uniform: residue, group of four positions, depth chunk
+    int rho, g, c, ncols, groups, tfirst, P;
+    FastDiv fcols;
+};
+
+__device__ __forceinline__ void f16_residue(Fwd16Walk& w, int rho, int nrows, int ny, int c_lo, int c_hi)
+{
+    w.rho = rho;
+    w.tfirst = c_lo + imod(rho - c_lo, ny);
+    w.ncols = w.tfirst <= c_hi ? (c_hi - w.tfirst) / ny + 1 : 0;
+    w.P = nrows * w.ncols;
+    w.groups = (w.P + 3) / 4;
+    w.fcols = make_fastdiv(uint32_t(max(1, w.ncols)));
+}
+
+struct Fwd16Set {
+    f32x4 a0[4];
+    f32x3 a1[4];
+    f32x4 b0[kWaveBoxes];
+    f32x3 b1[kWaveBoxes];
+    int mask;
+};
+
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) k_fwd16(Fwd16Args a)
+{
+    __shared__ float tot[kThreads / 64][4 * kWaveBoxes * 4][64];   // per wave: 80 sums x 64 lanes
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6), lane = int(threadIdx.x) & 63;
+    // logical workgroup (consecutive ones on one XCD) -> its four items
+    const int b = int(blockIdx.x), x = b % kXcds, qq = a.nwg / kXcds, rr = a.nwg % kXcds;
+    const int it = (x * qq + min(x, rr) + b / kXcds) * 4 + wave;
+    if (it >= a.nitems) return;
+    const Fwd16Item I = a.items[it];
+    const int mt = __builtin_amdgcn_readfirstlane(I.mt), j = __builtin_amdgcn_readfirstlane(I.j);
+    const int h = __builtin_amdgcn_readfirstlane(I.h), r_lo = __builtin_amdgcn_readfirstlane(I.r_lo);
+    const int nrows = __builtin_amdgcn_readfirstlane(I.nrows);
+    const int st0 = __builtin_amdgcn_readfirstlane(I.st_begin), st1 = __builtin_amdgcn_readfirstlane(I.st_end);
+    const int slot = __builtin_amdgcn_readfirstlane(I.slot);
+    const int q = lane >> 4, n = lane & 15;
+    const Rsrc ra = make_rsrc(reinterpret_cast<const char*>(a.A), a.A_bytes);
+    const Rsrc rb = make_rsrc(reinterpret_cast<const char*>(a.B), a.B_bytes);
+    int lb[4];   // this lane's lenslet (row 16 k + n of the tile) in the padded grid, -1 past M
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int m = kMT * mt + 16 * k + n;
+        const int Lp = m / a.Lc, Lq = m - Lp * a.Lc;
+        lb[k] = m < a.M ? Lp * a.LCp + Lq : -1;
+    }
+    const int c_lo = -min(a.ny - 1, kBV * j + kBV - 1), c_hi = a.nt - 1 - kBV * j;
+    Fwd16Walk w;
+    {   // the first stage: skip whole residues, then groups and chunks
+        int rem = st0, rho = 0;
+        f16_residue(w, 0, nrows, a.ny, c_lo, c_hi);
+        while (rho < a.ny && rem >= a.nch * w.groups) {
+            rem -= a.nch * w.groups;
+            if (++rho < a.ny) f16_residue(w, rho, nrows, a.ny, c_lo, c_hi);
+        }
+        w.g = rem / a.nch;
+        w.c = rem - w.g * a.nch;
+    }
+    for (int e = 0; e < 4 * kWaveBoxes * 4; ++e) tot[wave][e][lane] = 0.f;
+    f32x4 acc[4][kWaveBoxes];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int i = 0; i < kWaveBoxes; ++i) acc[k][i] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    // this lane's position in the residue's row-major sequence, and the record
+    // offsets of the current group of four positions (chunk 0)
+    const uint32_t CA = uint32_t(a.LRp) * uint32_t(a.LCp) * 32u;
+    const uint32_t CB = uint32_t(a.nstrips) * uint32_t(a.nbox) * 16u * 32u;
+    int pos = 0, ri = 0, ci = 0, gmask = 0;
+    uint32_t gA[4], gB = kOob;
+    auto start_residue = [&]() {
+        pos = 4 * w.g + q;
+        ri = int(fdiv(uint32_t(pos), w.fcols));
+        ci = pos - ri * w.ncols;
+    };
+    auto group_offsets = [&]() {
+        const bool ok = pos < w.P;
+        const int sp = r_lo + ri, tp = w.tfirst + a.ny * ci;
+        const uint32_t es = uint32_t(a.hs - sp + a.nx * a.padP), et = uint32_t(a.ht - tp + a.ny * a.padQ);
+        const int qs = int(fdiv(es, a.fnx)), qt = int(fdiv(et, a.fny));
+        const int px = int(es) - qs * a.nx, py = int(et) - qt * a.ny;
+        const int plane = (px * a.ny + py) * a.nch * a.LRp * a.LCp + qs * a.LCp + qt;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) gA[k] = (ok && lb[k] >= 0) ? uint32_t(plane + lb[k]) * 32u : kOob;
+        const int pidx = (sp + a.nx - 1) * a.Kt + (tp + a.ny - 1);
+        gB = ok ? uint32_t(((pidx * a.nch * a.nstrips + j) * a.nbox + kWaveBoxes * h) * 16 + n) * 32u : kOob;
+        int mask = 0;
+        if (w.P > 0) {
+            const int p3 = min(4 * w.g + 3, w.P - 1);
+            const int smin = r_lo + int(fdiv(uint32_t(4 * w.g), w.fcols));
+            const int smax = r_lo + int(fdiv(uint32_t(p3), w.fcols));
+#pragma unroll
+            for (int i = 0; i < kWaveBoxes; ++i) {
+                const int bi = kWaveBoxes * h + i;
+                if (bi < a.nbox && smin <= a.ns - 1 - kBU * bi && smax >= -min(a.nx - 1, kBU * bi + kBU - 1))
+                    mask |= 1 << i;
+            }
+        }
+        gmask = __builtin_amdgcn_readfirstlane(mask);
+    };
+    start_residue();
+    group_offsets();
+    auto fill = [&](Fwd16Set& S, bool live) {
+        const uint32_t sa = uint32_t(w.c) * CA, sb = uint32_t(w.c) * CB;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t off = live ? gA[k] : kOob;
+            S.a0[k] = load_vec(ra, off, sa);
+            S.a1[k] = ld3(ra, off + 16u, sa);
+        }
+        const uint32_t ob = live ? gB : kOob;
+#pragma unroll
+        for (int i = 0; i < kWaveBoxes; ++i) {
+            S.b0[i] = load_vec(rb, ob + 512u * i, sb);
+            S.b1[i] = ld3(rb, ob + 512u * i + 16u, sb);
+        }
+        S.mask = live ? gmask : 0;
+        if (++w.c == a.nch) {   // next group of positions
+            w.c = 0;
+            if (++w.g >= w.groups) {
+                w.g = 0;
+                int rho = w.rho + 1;
+                while (rho < a.ny) {
+                    f16_residue(w, rho, nrows, a.ny, c_lo, c_hi);
+                    if (w.groups > 0) break;
+                    ++rho;
+                }
+                if (rho >= a.ny) w.rho = a.ny;
+                start_residue();
+            } else {
+                pos += 4;
+                ci += 4;
+                while (ci >= w.ncols) {
+                    ci -= w.ncols;
+                    ++ri;
+                }
+            }
+            group_offsets();
+        }
+    };
+    auto mma = [&](const Fwd16Set& S) {
+#pragma unroll
+        for (int i = 0; i < kWaveBoxes; ++i) {
+            if (S.mask & (1 << i)) {
+#pragma unroll
+                for (int d = 0; d < kCh; ++d)
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        acc[k][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(rec_at(S.a0[k], S.a1[k], d),
+                                                                         rec_at(S.b0[i], S.b1[i], d), acc[k][i], 0, 0, 0);
+            }
+        }
+    };
+    auto fold = [&]() {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int i = 0; i < kWaveBoxes; ++i)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    tot[wave][(k * kWaveBoxes + i) * 4 + r][lane] += acc[k][i][r];
+                    acc[k][i][r] = 0.f;
+                }
+    };
+    // two register sets: the next stage's records load while the matrix
+    // cores take the current one (an odd count ends with a dead stage: zero
+    // records, no steps)
+    Fwd16Set s0, s1;
+    fill(s0, st0 < st1);
+    int since = 0;
+    for (int st = st0; st < st1; st += 2) {
+        fill(s1, st + 1 < st1);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(s0);
+        __builtin_amdgcn_sched_barrier(0);
+        fill(s0, st + 2 < st1);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(s1);
+        __builtin_amdgcn_sched_barrier(0);
+        if ((since += 2) >= kF16Fold) {
+            fold();
+            since = 0;
+        }
+    }
+    fold();
+    float* o = a.out + size_t(slot) * kMT * a.ncols;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int i = 0; i < kWaveBoxes; ++i) {
+            const int bi = kWaveBoxes * h + i;
+            if (bi < a.nbox) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    o[(16 * k + 4 * q + r) * a.ncols + (j * a.nbox + bi) * 16 + n] = tot[wave][(k * kWaveBoxes + i) * 4 + r][lane];
+            }
+        }
+}
+
+struct Fwd16Pack {
+    ProjGeom g;
+    int nch, nstrips, nbox, padP, padQ, LRp, LCp, Kt;
+    FastDiv f16, f5;
+};
+
+// A16 records from g with depth innermost (gT[P][Q][z]): one record per thread.
+__global__ void __launch_bounds__(256) k_pack16_a(const float* gT, Fwd16Pack p, float* A16, int64_t nrec)
+{
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= nrec) return;
+    const ProjGeom& g = p.g;
+    const int64_t cell = int64_t(p.LRp) * p.LCp;
+    const int64_t pl = i / cell;
+    const int rest = int(i - pl * cell);
+    const int LP = rest / p.LCp, LQ = rest - LP * p.LCp;
+    const int c = int(pl % p.nch), pxy = int(pl / p.nch);
+    const int px = pxy / g.ny, py = pxy - px * g.ny;
+    const int P = g.nx * (LP - p.padP) + px, Q = g.ny * (LQ - p.padQ) + py;
+    const bool ok = unsigned(P) < unsigned(g.R) && unsigned(Q) < unsigned(g.C);
+    const float* src = gT + (ok ? (int64_t(P) * g.C + Q) * g.nz : 0);
+    float v[8];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) v[d] = (ok && d < kCh && kCh * c + d < g.nz) ? src[kCh * c + d] : 0.f;
+    f32x4* dst = reinterpret_cast<f32x4*>(A16) + 2 * i;
+    dst[0] = f32x4{v[0], v[1], v[2], v[3]};
+    dst[1] = f32x4{v[4], v[5], v[6], v[7]};
+}
+
+// B16 records from H: one record per thread.
+__global__ void __launch_bounds__(256) k_pack16_b(const float* H, Fwd16Pack p, float* B16, int64_t nrec)
+{
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= nrec) return;
+    const ProjGeom& g = p.g;
+    const int n = int(i & 15);
+    int64_t r = i >> 4;
+    const int bi = int(r % p.nbox);
+    r /= p.nbox;
+    const int j = int(r % p.nstrips);
+    r /= p.nstrips;
+    const int c = int(r % p.nch);
+    const int64_t pidx = r / p.nch;
+    const int sr = int(pidx / p.Kt), tc = int(pidx - int64_t(sr) * p.Kt);
+    const int sp = sr - (g.nx - 1), tp = tc - (g.ny - 1);
+    const int u = kBU * bi + n / kBV, v = kBV * j + n % kBV;
+    const bool ok = n < kBU * kBV && u < g.nx && v < g.ny && unsigned(sp + u) < unsigned(g.ns) &&
+                    unsigned(tp + v) < unsigned(g.nt);
+    const int x = imod(g.hs - sp, g.nx), y = imod(g.ht - tp, g.ny);
+    const float* src = H + (ok ? ((((int64_t(sp + u) * g.nt + (tp + v)) * g.nx + x) * g.ny + y) * g.nz) : 0);
+    float vals[8];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) vals[d] = (ok && d < kCh && kCh * c + d < g.nz) ? src[kCh * c + d] : 0.f;
+    f32x4* dst = reinterpret_cast<f32x4*>(B16) + 2 * i;
+    dst[0] = f32x4{vals[0], vals[1], vals[2], vals[3]};
+    dst[1] = f32x4{vals[4], vals[5], vals[6], vals[7]};
+}
+
+// f[p][q] = sum over the row tile's slots (in split order, float64) of the
+// partial entry of (lenslet, class); with fmeas set (Richardson-Lucy, Eq. 2),
+// the quotient fmeas / f instead, 0 where f is not positive.
+__global__ void __launch_bounds__(256) k_fwd16_reduce(const float* partial, const uint32_t* tab, int ncols, int nbox,
+                                                       ProjGeom g, const float* fmeas, float* f)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= int64_t(g.R) * g.C) return;
+    const int p = int(i / g.C), qc = int(i - int64_t(p) * g.C);
+    const int Lp = p / g.nx, u = p - Lp * g.nx, Lq = qc / g.ny, v = qc - Lq * g.ny;
+    const int m = Lp * g.Lc + Lq, mt = m / kMT, r = m - mt * kMT;
+    const int bi = u / kBU, j = v / kBV;
+    const int col = (j * nbox + bi) * 16 + (u - kBU * bi) * kBV + (v - kBV * j);
+    double acc = 0.0;
+    for (uint32_t s = tab[mt]; s < tab[mt + 1]; ++s) acc += double(partial[(size_t(s) * kMT + r) * ncols + col]);
+    if (fmeas)
+        f[i] = acc > 0.0 ? float(double(fmeas[i]) / acc) : 0.0f;
+    else
+        f[i] = float(acc);
+}
+
+// Plan of the 16-column forward: record and partial-sum geometry, the
+// wavefront items and the slot table, from the shapes only (so the workspace
+// and the order of the float64 sums do not depend on the device).
+struct Fwd16Plan {
+    ProjGeom g;
+    bool ok;                        // record blocks within 32-bit byte offsets
+    int nch, nstrips, nbox, ngroups, padP, padQ, LRp, LCp, Kt, ncols, mtiles, slots, nitems, nwg;
+    std::vector<Fwd16Item> items;   // wavefront items, in launch order
+    std::vector<uint32_t> tab;      // first slot of every row tile (mtiles + 1 entries)
+    size_t gT_bytes, A_bytes, B_bytes, part_bytes, items_bytes, tab_bytes;
+};
+
+Fwd16Plan fwd16_plan(const lfbp_shape& s, int64_t R, int64_t C)
+{
+    Fwd16Plan P;
+    const ProjGeom g = make_geom(s, R, C);
+    P.g = g;
+    P.nch = (g.nz + kCh - 1) / kCh;
+    P.nstrips = (g.ny + kBV - 1) / kBV;
+    P.nbox = (g.nx + kBU - 1) / kBU;
+    P.ngroups = (P.nbox + kWaveBoxes - 1) / kWaveBoxes;
+    P.padP = (g.ns - 1 - g.hs + g.nx - 1) / g.nx;   // lenslet offsets floor((hs - s') / nx) >= -padP
+    P.padQ = (g.nt - 1 - g.ht + g.ny - 1) / g.ny;
+    P.LRp = g.Lr + P.padP + (g.hs + g.nx - 1) / g.nx;
+    P.LCp = g.Lc + P.padQ + (g.ht + g.ny - 1) / g.ny;
+    P.Kt = g.nt + g.ny - 1;
+    P.ncols = P.nstrips * P.nbox * 16;
+    P.mtiles = (g.M + kMT - 1) / kMT;
+    const uint64_t A_raw = uint64_t(g.nx) * g.ny * P.nch * uint64_t(P.LRp) * P.LCp * 32u;
+    const uint64_t B_raw = uint64_t(g.Kr) * P.Kt * P.nch * uint64_t(P.nstrips) * P.nbox * 16u * 32u;
+    P.ok = A_raw <= 0x7FFF0000u && B_raw <= 0x7FFF0000u;
+    P.gT_bytes = align256(size_t(g.nz) * g.R * g.C * sizeof(float));
+    P.A_bytes = align256(size_t(A_raw));
+    P.B_bytes = align256(size_t(B_raw));
+    // window rows of every (row tile, box group): the group's patch-row
+    // shifts less those whose A records are zero for the whole tile
+    std::vector<int> rlo(size_t(P.mtiles) * P.ngroups), nrow(size_t(P.mtiles) * P.ngroups), rows(size_t(P.mtiles), 0);
+    int rows_max = 0;
+    for (int mt = 0; mt < P.mtiles; ++mt) {
+        const int lp_lo = (kMT * mt) / g.Lc, lp_hi = std::min(g.M - 1, kMT * mt + kMT - 1) / g.Lc;
+        for (int h = 0; h < P.ngroups; ++h) {
+            const int lo = std::max(-std::min(g.nx - 1, kBU * kWaveBoxes * h + kBU * kWaveBoxes - 1),
+                                    g.nx * lp_lo + g.hs - (g.R - 1));
+            const int hi = std::min(g.ns - 1 - kBU * kWaveBoxes * h, g.nx * lp_hi + g.hs);
+            rlo[size_t(mt) * P.ngroups + h] = lo;
+            nrow[size_t(mt) * P.ngroups + h] = std::max(0, hi - lo + 1);
+            rows[size_t(mt)] = std::max(rows[size_t(mt)], std::max(0, hi - lo + 1));
+        }
+        rows_max = std::max(rows_max, rows[size_t(mt)]);
+    }
+    auto stages = [&](int mt, int j, int h) {   // the walk of one item: residues, groups of four, chunks
+        const int nr = nrow[size_t(mt) * P.ngroups + h];
+        const int c_lo = -std::min(g.ny - 1, kBV * j + kBV - 1), c_hi = g.nt - 1 - kBV * j;
+        int64_t T = 0;
+        for (int rho = 0; rho < g.ny; ++rho) {
+            const int tfirst = c_lo + ((rho - c_lo) % g.ny + g.ny) % g.ny;
+            const int ncols = tfirst <= c_hi ? (c_hi - tfirst) / g.ny + 1 : 0;
+            T += int64_t(P.nch) * ((int64_t(nr) * ncols + 3) / 4);
+        }
+        return T;
+    };
+    int64_t Tmax = 0;
+    for (int mt = 0; mt < P.mtiles; ++mt)
+        for (int h = 0; h < P.ngroups; ++h) Tmax = std::max(Tmax, stages(mt, 0, h));
+    auto count = [&](int c, int mt) {
+        return rows_max == 0 ? 1 : std::max(1, int((int64_t(rows[size_t(mt)]) * c + rows_max - 1) / rows_max));
+    };
+    // splits: the most (at most 64, at most one per 64 stages) whose
+    // wavefronts fill one round of kTargetBlocks workgroups
+    const int per = P.nstrips * P.ngroups;
+    const int cap = int(std::max<int64_t>(1, std::min<int64_t>(64, Tmax / 64)));
+    int S = 1;
+    for (int c = 2; c <= cap; ++c) {
+        int64_t waves = 0;
+        for (int mt = 0; mt < P.mtiles; ++mt) waves += int64_t(count(c, mt)) * per;
+        if ((waves + 3) / 4 > kTargetBlocks) break;
+        S = c;
+    }
+    P.tab.assign(size_t(P.mtiles) + 1, 0u);
+    int cmax = 0;
+    for (int mt = 0; mt < P.mtiles; ++mt) {
+        P.tab[size_t(mt) + 1] = P.tab[size_t(mt)] + uint32_t(count(S, mt));
+        cmax = std::max(cmax, count(S, mt));
+    }
+    P.slots = int(P.tab[size_t(P.mtiles)]);
+    // items in the order (split, strip, box group, row tile): the row tiles of
+    // one split and strip walk the same stages and share their B records
+    for (int k = 0; k < cmax; ++k)
+        for (int j = 0; j < P.nstrips; ++j)
+            for (int h = 0; h < P.ngroups; ++h)
+                for (int mt = 0; mt < P.mtiles; ++mt) {
+                    const int cnt = count(S, mt);
+                    if (k >= cnt) continue;
+                    const int64_t T = stages(mt, j, h);
+                    Fwd16Item it;
+                    it.mt = mt;
+                    it.j = j;
+                    it.h = h;
+                    it.r_lo = rlo[size_t(mt) * P.ngroups + h];
+                    it.nrows = nrow[size_t(mt) * P.ngroups + h];
+                    it.st_begin = int(T * k / cnt);
+                    it.st_end = int(T * (k + 1) / cnt);
+                    it.slot = int(P.tab[size_t(mt)]) + k;
+                    P.items.push_back(it);
+                }
+    P.nitems = int(P.items.size());
+    P.nwg = (P.nitems + 3) / 4;
+    if (Tmax >= (int64_t(1) << 31) || P.nitems >= (1 << 24) ||
+        uint64_t(P.slots) * kMT * uint64_t(P.ncols) >= (uint64_t(1) << 31))
+        P.ok = false;
+    P.part_bytes = align256(size_t(P.slots) * kMT * P.ncols * sizeof(float));
+    P.items_bytes = align256(size_t(P.nitems) * sizeof(Fwd16Item));
+    P.tab_bytes = align256(P.tab.size() * sizeof(uint32_t));
+    return P;
+}
+
+// Items, then the slot table, as words (written by put_words).
+std::vector<uint32_t> fwd16_words(const Fwd16Plan& P)
+{
+    std::vector<uint32_t> w(P.items_bytes / 4 + P.tab.size(), 0u);
+    std::memcpy(w.data(), P.items.data(), P.items.size() * sizeof(Fwd16Item));
+    std::memcpy(w.data() + P.items_bytes / 4, P.tab.data(), P.tab.size() * sizeof(uint32_t));
+    return w;
+}
+
+Fwd16Pack fwd16_pack(const Fwd16Plan& P)
+{
+    Fwd16Pack p{};
+    p.g = P.g;
+    p.nch = P.nch;
+    p.nstrips = P.nstrips;
+    p.nbox = P.nbox;
+    p.padP = P.padP;
+    p.padQ = P.padQ;
+    p.LRp = P.LRp;
+    p.LCp = P.LCp;
+    p.Kt = P.Kt;
+    return p;
+}
+
+hipError_t pack16_b(const float* H, const Fwd16Plan& P, float* B16, hipStream_t stream)
+{
+    const int64_t nrec = int64_t(P.B_bytes / 32);
+    hipLaunchKernelGGL(k_pack16_b, dim3(unsigned((nrec + 255) / 256)), dim3(256), 0, stream, H, fwd16_pack(P), B16,
+                       nrec);
+    return hipGetLastError();
+}
+
+// tables: the items and the slot table (prepared with an operator), or null
+// to write them into the workspace after the partial sums.
+hipError_t forward16_impl(const float* H, const Fwd16Plan& P, const float* gin, const float* fmeas, float* f,
+                          void* ws, const float* Bpre, const uint32_t* tables, hipStream_t stream)
+{
+    const ProjGeom& g = P.g;
+    char* w = static_cast<char*>(ws);
+    float* gT = reinterpret_cast<float*>(w);
+    float* A16 = reinterpret_cast<float*>(w + P.gT_bytes);
+    float* B16 = reinterpret_cast<float*>(w + P.gT_bytes + P.A_bytes);
+    float* part = reinterpret_cast<float*>(w + P.gT_bytes + P.A_bytes + (Bpre ? 0 : P.B_bytes));
+    hipError_t e;
+    if (!tables) {
+        uint32_t* t = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(part) + P.part_bytes);
+        const std::vector<uint32_t> words = fwd16_words(P);
+        if ((e = put_words(t, words.data(), words.size(), stream)) != hipSuccess) return e;
+        tables = t;
+    }
+    const int plane = g.R * g.C;
+    hipLaunchKernelGGL(k_depth_last, dim3(unsigned((plane + 31) / 32), unsigned((g.nz + 31) / 32)), dim3(256), 0,
+                       stream, gin, g.nz, plane, gT);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int64_t nrec_a = int64_t(P.A_bytes / 32);
+    hipLaunchKernelGGL(k_pack16_a, dim3(unsigned((nrec_a + 255) / 256)), dim3(256), 0, stream, gT, fwd16_pack(P), A16,
+                       nrec_a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (Bpre)
+        B16 = const_cast<float*>(Bpre);
+    else if ((e = pack16_b(H, P, B16, stream)) != hipSuccess)
+        return e;
+    Fwd16Args a{};
+    a.A = A16;
+    a.B = B16;
+    a.out = part;
+    a.items = reinterpret_cast<const Fwd16Item*>(tables);
+    a.A_bytes = uint32_t(P.A_bytes);
+    a.B_bytes = uint32_t(P.B_bytes);
+    a.nitems = P.nitems;
+    a.nwg = P.nwg;
+    a.ns = g.ns;
+    a.nt = g.nt;
+    a.nx = g.nx;
+    a.ny = g.ny;
+    a.hs = g.hs;
+    a.ht = g.ht;
+    a.M = g.M;
+    a.Lc = g.Lc;
+    a.LRp = P.LRp;
+    a.LCp = P.LCp;
+    a.padP = P.padP;
+    a.padQ = P.padQ;
+    a.Kt = P.Kt;
+    a.nch = P.nch;
+    a.nstrips = P.nstrips;
+    a.nbox = P.nbox;
+    a.ncols = P.ncols;
+    a.fnx = make_fastdiv(uint32_t(g.nx));
+    a.fny = make_fastdiv(uint32_t(g.ny));
+    if (P.nwg > 0) {
+        hipLaunchKernelGGL(k_fwd16, dim3(unsigned(P.nwg)), dim3(kThreads), 0, stream, a);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    const uint32_t* tab = tables + P.items_bytes / 4;
+    hipLaunchKernelGGL(k_fwd16_reduce, dim3(blocks_for(int64_t(g.R) * g.C)), dim3(256), 0, stream, part, tab, P.ncols,
+                       P.nbox, g, fmeas, f);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 // Workspace of the forward projection: g with depth innermost, the A and B
 // records, then the split partial tiles.
 size_t forward_workspace_bytes(const lfbp_shape& s, int64_t R, int64_t C)
 {
+    const Fwd16Plan Q = fwd16_plan(s, R, C);
+    if (Q.ok) return Q.gT_bytes + Q.A_bytes + Q.B_bytes + Q.part_bytes + Q.items_bytes + Q.tab_bytes;
     const FwdPlan P = fwd_plan(s, R, C);
     return P.gT_bytes + P.gS_bytes + P.B_bytes + P.part_bytes;
 }
@@ -1091,6 +1638,10 @@ hipError_t forward_impl(const float* H, const lfbp_shape& s, const float* gin, i
                         const float* fmeas, float* f, void* ws, const float* Bpre, const uint32_t* tabpre,
                         hipStream_t stream)
 {
+    {
+        const Fwd16Plan Q = fwd16_plan(s, R, C);
+        if (Q.ok) return forward16_impl(H, Q, gin, fmeas, f, ws, Bpre, tabpre, stream);
+    }
     const FwdPlan P = fwd_plan(s, R, C);
     const ProjGeom& g = P.g;
     if (int64_t(P.mtiles) * P.ntiles >= (int64_t(1) << 26)) return hipErrorInvalidValue;   // work table entries
@@ -1384,10 +1935,36 @@ hipError_t launch_backward(const float* Ht, const lfbp_shape& s, const float* f,
 // (backward), which depend on the PSF only, so that a loop over volumes and
 // images with one PSF (Richardson-Lucy, Eq. 2) packs them once, and the
 // forward's work table, which depends on the shapes only.
+namespace {
+
+// The forward's part of a prepared operator: its B records, and its tables.
+size_t op_fwd_b_bytes(const lfbp_shape& s, int64_t R, int64_t C)
+{
+    const Fwd16Plan Q = fwd16_plan(s, R, C);
+    return align256(Q.ok ? Q.B_bytes : fwd_plan(s, R, C).B_bytes);
+}
+
+size_t op_fwd_tab_bytes(const lfbp_shape& s, int64_t R, int64_t C)
+{
+    const Fwd16Plan Q = fwd16_plan(s, R, C);
+    return Q.ok ? Q.items_bytes + Q.tab_bytes : fwd_plan(s, R, C).tab_bytes;
+}
+
+// Workspace of a forward call on a prepared operator: g with depth
+// innermost, the A records, the partial sums.
+size_t op_fwd_call_bytes(const lfbp_shape& s, int64_t R, int64_t C)
+{
+    const Fwd16Plan Q = fwd16_plan(s, R, C);
+    if (Q.ok) return Q.gT_bytes + Q.A_bytes + Q.part_bytes;
+    const FwdPlan F = fwd_plan(s, R, C);
+    return F.gT_bytes + F.gS_bytes + F.part_bytes;
+}
+
+}  // namespace
+
 size_t operator_bytes(const lfbp_shape& s, int64_t R, int64_t C)
 {
-    const FwdPlan F = fwd_plan(s, R, C);
-    return align256(F.B_bytes) + align256(bwd_plan(s, R, C).B_bytes) + F.tab_bytes;
+    return op_fwd_b_bytes(s, R, C) + align256(bwd_plan(s, R, C).B_bytes) + op_fwd_tab_bytes(s, R, C);
 }
 
 // Workspace of every call on a prepared operator (forward, backward, one
@@ -1395,10 +1972,8 @@ size_t operator_bytes(const lfbp_shape& s, int64_t R, int64_t C)
 // them, one image.
 size_t operator_workspace_bytes(const lfbp_shape& s, int64_t R, int64_t C)
 {
-    const FwdPlan F = fwd_plan(s, R, C);
     const BwdPlan Bw = bwd_plan(s, R, C);
-    return align256(std::max(F.gT_bytes + F.gS_bytes + F.part_bytes, Bw.A_bytes)) +
-           align256(size_t(R) * size_t(C) * sizeof(float));
+    return align256(std::max(op_fwd_call_bytes(s, R, C), Bw.A_bytes)) + align256(size_t(R) * size_t(C) * sizeof(float));
 }
 
 namespace {
@@ -1407,21 +1982,19 @@ const float* op_fwd_b(const void* op) { return static_cast<const float*>(op); }
 
 const float* op_bwd_b(const void* op, const lfbp_shape& s, int64_t R, int64_t C)
 {
-    return reinterpret_cast<const float*>(static_cast<const char*>(op) + align256(fwd_plan(s, R, C).B_bytes));
+    return reinterpret_cast<const float*>(static_cast<const char*>(op) + op_fwd_b_bytes(s, R, C));
 }
 
 const uint32_t* op_fwd_tab(const void* op, const lfbp_shape& s, int64_t R, int64_t C)
 {
-    return reinterpret_cast<const uint32_t*>(static_cast<const char*>(op) + align256(fwd_plan(s, R, C).B_bytes) +
+    return reinterpret_cast<const uint32_t*>(static_cast<const char*>(op) + op_fwd_b_bytes(s, R, C) +
                                              align256(bwd_plan(s, R, C).B_bytes));
 }
 
 float* op_image(void* ws, const lfbp_shape& s, int64_t R, int64_t C)
 {
-    const FwdPlan F = fwd_plan(s, R, C);
     const BwdPlan Bw = bwd_plan(s, R, C);
-    return reinterpret_cast<float*>(static_cast<char*>(ws) +
-                                    align256(std::max(F.gT_bytes + F.gS_bytes + F.part_bytes, Bw.A_bytes)));
+    return reinterpret_cast<float*>(static_cast<char*>(ws) + align256(std::max(op_fwd_call_bytes(s, R, C), Bw.A_bytes)));
 }
 
 }  // namespace
@@ -1429,6 +2002,19 @@ float* op_image(void* ws, const lfbp_shape& s, int64_t R, int64_t C)
 hipError_t launch_operator_prepare(const float* H, const float* Ht, const lfbp_shape& s, int64_t R, int64_t C,
                                    void* op, hipStream_t stream)
 {
+    const Fwd16Plan Q = fwd16_plan(s, R, C);
+    if (Q.ok) {
+        hipError_t e = pack16_b(H, Q, const_cast<float*>(op_fwd_b(op)), stream);
+        if (e != hipSuccess) return e;
+        const std::vector<uint32_t> words = fwd16_words(Q);
+        e = put_words(const_cast<uint32_t*>(op_fwd_tab(op, s, R, C)), words.data(), words.size(), stream);
+        if (e != hipSuccess) return e;
+        const BwdPlan Bw = bwd_plan(s, R, C);
+        const PackArgs pb = pack_args(Bw.g, Bw.N, Bw.Npad, Bw.Mpad, Bw.stages);
+        hipLaunchKernelGGL(k_pack_bwd_b, dim3(unsigned(Bw.stages), blocks_for(int64_t(Bw.Npad) * kRecVec)), dim3(256),
+                           0, stream, Ht, pb, const_cast<float*>(op_bwd_b(op, s, R, C)));
+        return hipGetLastError();
+    }
     const FwdPlan F = fwd_plan(s, R, C);
     PackArgs p = pack_args(F.g, F.N, F.Npad, F.Mpad, F.L.stages);
     p.nzc = F.L.nzc;
