@@ -1102,9 +1102,11 @@ struct Fwd16Args {
     const Fwd16Item* items;
     uint32_t A_bytes, B_bytes;
     int nitems, nwg;
-    int ns, nt, nx, ny, hs, ht, M, Lc, LRp, LCp, padP, padQ, Kt;
-    int nch, nstrips, nbox, ncols;
-    FastDiv fnx, fny;
+    int ns, nt, nx, ny, M, Lc, LCp, Kt;
+    int hsb, htb;          // hs + nx padP, ht + ny padQ: the biased shifts floor(/ nx) and floor(/ ny) take
+    int PL;                // records of one (px, py) block: nch * LRp * LCp
+    int nch, nbx, nbox, ncols;   // depth chunks, B records per (position, chunk): nstrips * nbox * 16
+    uint32_t mnx, mny;     // division magics of nx and ny (mdiv)
 };
 
 __device__ __forceinline__ f32x3 ld3(Rsrc r, uint32_t voff, uint32_t soff)
@@ -1114,9 +1116,18 @@ __device__ __forceinline__ f32x3 ld3(Rsrc r, uint32_t voff, uint32_t soff)
 
 __device__ __forceinline__ float rec_at(const f32x4& x, const f32x3& y, int d) { return d < 4 ? x[d] : y[d - 4]; }
 
+// n / d for n < 2^32 / d, with m = ceil(2^32 / d) (one multiply-high), or n
+// itself for d = 1 (m = 0).
+__host__ __device__ inline uint32_t div_magic(uint32_t d)
+{
+    return d <= 1 ? 0u : uint32_t(((uint64_t(1) << 32) + d - 1) / d);
+}
+
+__device__ __forceinline__ uint32_t mdiv(uint32_t n, uint32_t m) { return m ? __umulhi(n, m) : n; }
+
 struct Fwd16Walk {      // wavefront-uniform: residue, group of four positions, depth chunk
     int rho, g, c, ncols, groups, tfirst, P;
-    FastDiv fcols;
+    uint32_t mcols;
 };
 
 __device__ __forceinline__ void f16_residue(Fwd16Walk& w, int rho, int nrows, int ny, int c_lo, int c_hi)
@@ -1126,7 +1137,7 @@ __device__ __forceinline__ void f16_residue(Fwd16Walk& w, int rho, int nrows, in
     w.ncols = w.tfirst <= c_hi ? (c_hi - w.tfirst) / ny + 1 : 0;
     w.P = nrows * w.ncols;
     w.groups = (w.P + 3) / 4;
-    w.fcols = make_fastdiv(uint32_t(max(1, w.ncols)));
+    w.mcols = div_magic(uint32_t(max(1, w.ncols)));
 }
 
 struct Fwd16Set {
@@ -1182,31 +1193,31 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2
 
     // this lane's position in the residue's row-major sequence, and the record
     // offsets of the current group of four positions (chunk 0)
-    const uint32_t CA = uint32_t(a.LRp) * uint32_t(a.LCp) * 32u;
-    const uint32_t CB = uint32_t(a.nstrips) * uint32_t(a.nbox) * 16u * 32u;
+    const uint32_t CA = uint32_t(a.PL / a.nch) * 32u;
+    const uint32_t CB = uint32_t(a.nbx) * 32u;
     int pos = 0, ri = 0, ci = 0, gmask = 0;
     uint32_t gA[4], gB = kOob;
     auto start_residue = [&]() {
         pos = 4 * w.g + q;
-        ri = int(fdiv(uint32_t(pos), w.fcols));
+        ri = int(mdiv(uint32_t(pos), w.mcols));
         ci = pos - ri * w.ncols;
     };
     auto group_offsets = [&]() {
         const bool ok = pos < w.P;
         const int sp = r_lo + ri, tp = w.tfirst + a.ny * ci;
-        const uint32_t es = uint32_t(a.hs - sp + a.nx * a.padP), et = uint32_t(a.ht - tp + a.ny * a.padQ);
-        const int qs = int(fdiv(es, a.fnx)), qt = int(fdiv(et, a.fny));
+        const uint32_t es = uint32_t(a.hsb - sp), et = uint32_t(a.htb - tp);
+        const int qs = int(mdiv(es, a.mnx)), qt = int(mdiv(et, a.mny));
         const int px = int(es) - qs * a.nx, py = int(et) - qt * a.ny;
-        const int plane = (px * a.ny + py) * a.nch * a.LRp * a.LCp + qs * a.LCp + qt;
+        const int plane = (px * a.ny + py) * a.PL + qs * a.LCp + qt;
 #pragma unroll
         for (int k = 0; k < 4; ++k) gA[k] = (ok && lb[k] >= 0) ? uint32_t(plane + lb[k]) * 32u : kOob;
         const int pidx = (sp + a.nx - 1) * a.Kt + (tp + a.ny - 1);
-        gB = ok ? uint32_t(((pidx * a.nch * a.nstrips + j) * a.nbox + kWaveBoxes * h) * 16 + n) * 32u : kOob;
+        gB = ok ? uint32_t((pidx * a.nch * a.nbx + (j * a.nbox + kWaveBoxes * h) * 16 + n)) * 32u : kOob;
         int mask = 0;
         if (w.P > 0) {
             const int p3 = min(4 * w.g + 3, w.P - 1);
-            const int smin = r_lo + int(fdiv(uint32_t(4 * w.g), w.fcols));
-            const int smax = r_lo + int(fdiv(uint32_t(p3), w.fcols));
+            const int smin = r_lo + int(mdiv(uint32_t(4 * w.g), w.mcols));
+            const int smax = r_lo + int(mdiv(uint32_t(p3), w.mcols));
 #pragma unroll
             for (int i = 0; i < kWaveBoxes; ++i) {
                 const int bi = kWaveBoxes * h + i;
@@ -1375,23 +1386,30 @@ __global__ void __launch_bounds__(256) k_pack16_b(const float* H, Fwd16Pack p, f
 
 // f[p][q] = sum over the row tile's slots (in split order, float64) of the
 // partial entry of (lenslet, class); with fmeas set (Richardson-Lucy, Eq. 2),
-// the quotient fmeas / f instead, 0 where f is not positive.
+// the quotient fmeas / f instead, 0 where f is not positive.  One thread per
+// partial entry (row tile, row, column), so that the reads of a slot coalesce.
 __global__ void __launch_bounds__(256) k_fwd16_reduce(const float* partial, const uint32_t* tab, int ncols, int nbox,
                                                        ProjGeom g, const float* fmeas, float* f)
 {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= int64_t(g.R) * g.C) return;
-    const int p = int(i / g.C), qc = int(i - int64_t(p) * g.C);
-    const int Lp = p / g.nx, u = p - Lp * g.nx, Lq = qc / g.ny, v = qc - Lq * g.ny;
-    const int m = Lp * g.Lc + Lq, mt = m / kMT, r = m - mt * kMT;
-    const int bi = u / kBU, j = v / kBV;
-    const int col = (j * nbox + bi) * 16 + (u - kBU * bi) * kBV + (v - kBV * j);
+    const int64_t per = int64_t(kMT) * ncols;
+    const int mt = int(i / per);
+    const int rest = int(i - int64_t(mt) * per), r = rest / ncols, col = rest - r * ncols;
+    const int m = kMT * mt + r;
+    if (m >= g.M) return;
+    const int n = col & 15, box = col >> 4, j = box / nbox, bi = box - j * nbox;
+    const int u = kBU * bi + n / kBV, v = kBV * j + n % kBV;
+    if (n >= kBU * kBV || u >= g.nx || v >= g.ny) return;
+    const int Lp = m / g.Lc, Lq = m - Lp * g.Lc;
+    const int p = g.nx * Lp + u, q = g.ny * Lq + v;
+    if (p >= g.R || q >= g.C) return;
     double acc = 0.0;
     for (uint32_t s = tab[mt]; s < tab[mt + 1]; ++s) acc += double(partial[(size_t(s) * kMT + r) * ncols + col]);
+    const int64_t o = int64_t(p) * g.C + q;
     if (fmeas)
-        f[i] = acc > 0.0 ? float(double(fmeas[i]) / acc) : 0.0f;
+        f[o] = acc > 0.0 ? float(double(fmeas[o]) / acc) : 0.0f;
     else
-        f[i] = float(acc);
+        f[o] = float(acc);
 }
 
 // Plan of the 16-column forward: record and partial-sum geometry, the
@@ -1501,6 +1519,11 @@ Fwd16Plan fwd16_plan(const lfbp_shape& s, int64_t R, int64_t C)
                 }
     P.nitems = int(P.items.size());
     P.nwg = (P.nitems + 3) / 4;
+    // the multiply-high divisions of the kernel are exact below 2^32 / d:
+    // positions (at most Kr rows times Kt / ny + 1 columns) by their column
+    // count, and the biased shifts by nx and ny
+    const uint64_t cmaxcols = uint64_t(P.Kt) / g.ny + 1;
+    if (uint64_t(g.Kr) * cmaxcols * cmaxcols >= (uint64_t(1) << 32)) P.ok = false;
     if (Tmax >= (int64_t(1) << 31) || P.nitems >= (1 << 24) ||
         uint64_t(P.slots) * kMT * uint64_t(P.ncols) >= (uint64_t(1) << 31))
         P.ok = false;
@@ -1585,28 +1608,26 @@ hipError_t forward16_impl(const float* H, const Fwd16Plan& P, const float* gin, 
     a.nt = g.nt;
     a.nx = g.nx;
     a.ny = g.ny;
-    a.hs = g.hs;
-    a.ht = g.ht;
     a.M = g.M;
     a.Lc = g.Lc;
-    a.LRp = P.LRp;
     a.LCp = P.LCp;
-    a.padP = P.padP;
-    a.padQ = P.padQ;
     a.Kt = P.Kt;
+    a.hsb = g.hs + g.nx * P.padP;
+    a.htb = g.ht + g.ny * P.padQ;
+    a.PL = P.nch * P.LRp * P.LCp;
     a.nch = P.nch;
-    a.nstrips = P.nstrips;
+    a.nbx = P.nstrips * P.nbox * 16;
     a.nbox = P.nbox;
     a.ncols = P.ncols;
-    a.fnx = make_fastdiv(uint32_t(g.nx));
-    a.fny = make_fastdiv(uint32_t(g.ny));
+    a.mnx = div_magic(uint32_t(g.nx));
+    a.mny = div_magic(uint32_t(g.ny));
     if (P.nwg > 0) {
         hipLaunchKernelGGL(k_fwd16, dim3(unsigned(P.nwg)), dim3(kThreads), 0, stream, a);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     const uint32_t* tab = tables + P.items_bytes / 4;
-    hipLaunchKernelGGL(k_fwd16_reduce, dim3(blocks_for(int64_t(g.R) * g.C)), dim3(256), 0, stream, part, tab, P.ncols,
-                       P.nbox, g, fmeas, f);
+    hipLaunchKernelGGL(k_fwd16_reduce, dim3(blocks_for(int64_t(P.mtiles) * kMT * P.ncols)), dim3(256), 0, stream, part,
+                       tab, P.ncols, P.nbox, g, fmeas, f);
     return hipGetLastError();
 }
 
