@@ -135,7 +135,8 @@ def projector_traffic():
         t = json.load(fh)
     if t.get("kernel_source_sha") != projector_source_sha():
         return None
-    return t.get("kernels", {}).get("k_gemm<0>", {}).get("hbm_bytes_per_launch")
+    kern = t.get("kernels", {})
+    return kern.get("k_fwd16", kern.get("k_gemm<0>", {})).get("hbm_bytes_per_launch")
 
 
 def step_traffic(workload: str):
