@@ -1088,7 +1088,7 @@ WindowWalk window_walk(const ProjGeom& g, const ClassBoxes& cb)
 // holds those depths of H[s' + u][t' + v][(hs - s') mod nx][(ht - t') mod ny]
 // for class (u, v) = (3 box + n / 5, 5 strip + n mod 5), 0 outside the patch,
 // for n = 15 and for classes past the cell.
-constexpr int kBU = 3, kBV = 5, kWaveBoxes = 5, kCh = 7, kF16Fold = 24;
+constexpr int kBU = 3, kBV = 5, kWaveBoxes = 5, kCh = 7, kF16Fold = 48;
 constexpr uint32_t kOob = 0x7FFFFFF0u;   // a byte offset past every record block: reads zeros
 
 struct Fwd16Item {      // one wavefront: row tile, strip, box group, the window rows it needs, stages, slot
