@@ -381,8 +381,15 @@ LFBP_API lfbp_status lfbp_grad_psf_ws(const float* w, const float* g, lfbp_shape
  * records depend on the PSF and the image size only, so a loop that applies
  * one PSF to many volumes or images -- the Richardson-Lucy iteration of Eq. 2,
  * which uses H and H' unchanged in every update -- can pack them once into a
- * caller buffer (the "operator") and pass it to the _op calls below.  Results
- * are bit-identical to the unprepared calls.
+ * caller buffer (the "operator") and pass it to the _op calls below.  The
+ * backprojection and the normaliser are bit-identical to the unprepared
+ * calls.  The forward projection (also inside lfbp_rl_step_op) runs on
+ * records of 16-column class boxes that only a prepared operator holds (3 x 5
+ * classes in 16 matrix-core columns, which pay off once the records are
+ * packed), so it agrees with lfbp_forward to float32 rounding (a different
+ * summation order; both within the relative L2 bound of 1e-5 of the float64
+ * result) rather than bit for bit; every call on one operator gives the same
+ * bits.
  *
  * op        DEVICE buffer of lfbp_operator_size() bytes, 256-byte aligned,
  *           owned by the caller; valid while H and H' are unchanged.

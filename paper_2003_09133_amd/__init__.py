@@ -372,7 +372,9 @@ def rl_step(H: torch.Tensor, Ht: torch.Tensor, f: torch.Tensor, g: torch.Tensor,
 class LFOperator:
     """H and H' packed once for R x C images (a prepared operator): forward
     projections, backprojections and Richardson-Lucy updates on it skip the
-    per-call packing of the PSF and give bit-identical results.  The packed
+    per-call packing of the PSF; the backprojection is bit-identical to the
+    unprepared call, the forward projection (on 16-column class-box records
+    only an operator holds) agrees with it to float32 rounding.  The packed
     records are copies: H and H' may be freed or changed afterwards (a changed
     PSF needs a new operator).  One workspace serves every call, so calls on
     one operator must not run concurrently on different streams."""

@@ -31,6 +31,19 @@ def gpu_equal_bits(a: torch.Tensor, b: torch.Tensor) -> bool:
     return bool(torch.equal(a.view(it), b.view(it)))
 
 
+def gpu_rel_l2(a: torch.Tensor, b: torch.Tensor) -> float:
+    """Relative L2 distance of two device tensors, in float64."""
+    a, b = a.double(), b.double()
+    return float((a - b).norm() / b.norm())
+
+
+# The prepared operator's forward (16-column class boxes) and the per-call
+# forward (64-column boxes) sum in different orders in float32, and each adds
+# its float32 partial sums in float64: they agree far inside the 1e-5 bound
+# both keep against the float64 oracle.
+SAME_SUM_TOL = 1e-6
+
+
 def sample_indices(n: int, k: int, seed: int) -> np.ndarray:
     """k flat indices in [0, n): both ends, then random."""
     rng = np.random.default_rng(seed)

@@ -8,7 +8,7 @@ import torch
 import lfsynth
 import oracle
 import paper_2003_09133_amd as lf
-from gpu_util import DEV, gpu_equal_bits, to_dev
+from gpu_util import DEV, SAME_SUM_TOL, gpu_equal_bits, gpu_rel_l2, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -142,9 +142,13 @@ def test_projector_workload_full_size_sampled():
                                            rng.integers(0, R, 1500), rng.integers(0, C, 1500)]),
                           np.array([(0, 0, 0), (20, R - 1, C - 1), (10, 0, C - 1)])])
     assert rel_l2(fbn[vox[:, 0], vox[:, 1], vox[:, 2]], oracle.backward_at(H, fn, vox)) <= TOL
-    # the prepared operator the benchmark times gives the same bits
+    # the prepared operator the benchmark times: its forward (16-column class
+    # boxes) against the oracle at the same pixels and against the per-call
+    # forward, its backprojection bit for bit
     op = lf.LFOperator(dH, R, C, Ht=dHt)
-    assert gpu_equal_bits(op.forward(to_dev(g)), f)
+    fo = op.forward(to_dev(g))
+    assert rel_l2(fo.cpu().numpy()[pix[:, 0], pix[:, 1]], oracle.forward_at(H, g, pix)) <= TOL
+    assert gpu_rel_l2(fo, f) <= SAME_SUM_TOL
     assert gpu_equal_bits(op.backward(f), fb)
 
 
@@ -233,8 +237,8 @@ def random_projector_cases(seed, n):
 
 @pytest.mark.parametrize("shape,R,C", random_projector_cases(2003, 12))
 def test_random_shapes_forward_gradient_and_operator(shape, R, C):
-    """Forward (plain and on a prepared operator, bit-identical), backprojection
-    and gradient with respect to H against the float64 oracle."""
+    """Forward (plain and on a prepared operator), backprojection and gradient
+    with respect to H against the float64 oracle."""
     H = lfsynth.uniform_f32(shape, 71)
     g = lfsynth.uniform_f32((shape[4], R, C), 72)
     f = lfsynth.uniform_f32((R, C), 73)
@@ -242,7 +246,9 @@ def test_random_shapes_forward_gradient_and_operator(shape, R, C):
     dHt = lf.compute_Ht(dH)
     fg = lf.forward(dH, dg)
     op = lf.LFOperator(dH, R, C, Ht=dHt)
-    assert gpu_equal_bits(op.forward(dg), fg)
+    fo = op.forward(dg)
+    assert gpu_rel_l2(fo, fg) <= SAME_SUM_TOL
+    assert rel_l2(fo.cpu().numpy(), oracle.forward(H, g)) <= TOL
     bg = lf.backward(dHt, to_dev(f))
     dPsf = lf.grad_psf(to_dev(f), dg, shape)
     torch.cuda.synchronize()
