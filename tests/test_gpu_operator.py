@@ -99,3 +99,23 @@ def test_operator_projection_is_differentiable():
     assert gpu_rel_l2(f.detach(), lf.forward(dH, g.detach())) <= SAME_SUM_TOL
     (f * w).sum().backward()
     assert gpu_equal_bits(g.grad, lf.backward(dHt, w))
+
+
+def test_operator_past_the_16_column_record_limit():
+    """H[165,165,15,15,70]: its 16-column B records would pass 2 GB (179 x 179
+    positions x 10 depth chunks x 240 columns x 32 bytes), so the operator holds
+    the 64-column records and its forward is the per-call forward, bit for bit,
+    and meets the float64 oracle at sampled pixels."""
+    shape, R, C = (165, 165, 15, 15, 70), 60, 45
+    assert (165 + 14) * (165 + 14) * 10 * 240 * 32 > 0x7FFF0000
+    H = lfsynth.uniform_f32(shape, 80)
+    g = lfsynth.uniform_f32((shape[4], R, C), 81)
+    dH, dg = to_dev(H), to_dev(g)
+    op = lf.LFOperator(dH, R, C)
+    fo = op.forward(dg)
+    assert gpu_equal_bits(fo, lf.forward(dH, dg))
+    rng = np.random.default_rng(82)
+    pix = np.concatenate([rng.integers(0, [R, C], size=(24, 2)), np.array([(0, 0), (R - 1, C - 1)])])
+    ref = oracle.forward_at(H, g, pix)
+    got = fo.cpu().numpy()[pix[:, 0], pix[:, 1]]
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-5
